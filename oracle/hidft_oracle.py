@@ -1,0 +1,382 @@
+"""FP64 CPU oracle for the homogeneous-support DFT (arXiv 2211.15299).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  The product path
+(the C-ABI library and its Python binding) never calls it, and this module
+shares no code, tables or constants with the HIP path.
+
+Everything here is written from the paper's definitions, slowly and plainly:
+
+* index work (pivots, the homogeneity predicate, the pivoted sampling pattern,
+  the plan orders and the butterfly twiddle exponents) follows the definitions
+  of Sections VI-VIII with exact integer arithmetic;
+* coefficients are obtained by the paper's "trivial" route of Section V-A:
+  build the k x k submatrix F^{-1}(I, J) of the inverse DFT and solve the
+  linear system f_I = F^{-1}(I, J) c by LU with partial pivoting, in complex128.
+  For large k the algebraically identical adjoint form c = (N/k) F(J, I) f_I is
+  used (Lemma 1 makes F(J, I_r) a scaled unitary matrix), see
+  ``adjoint_coefficients``.
+
+Conventions (Section II and Section IV): N = 2^M, omega = exp(-2 pi i / N),
+(Ff)(m) = sum_n f(n) omega^{mn} (no normalisation) and
+(F^{-1} c)(n) = (1/N) sum_m c(m) omega^{-mn}.
+
+Readings of passages the text leaves garbled (each is also pinned by a test):
+
+* The Hi-DFT identity F_J^0 f = |J| (Ff)_J drops the 1/N of the inverse DFT;
+  with the paper's own DFT/IDFT conventions the correct statement is
+  F(J, I_r) f_I = (k/N) (Ff)_J.  The factor 2 in the radix-2 split (Lemma 3) is
+  likewise absent from the derivation in its proof.
+* Algorithm 1 uses exp(+2 pi i a/N); the forward DFT sign of Lemma 3
+  (omega_{r+1} = exp(-2 pi i / 2^{r+1})) is the one that reproduces (Ff)_J.
+* Rows of the block factorisation of Corollary 2 are ordered by the recursion
+  of the sampling pattern (I_r = I_{r-} followed by its translate); columns by
+  q(j) = sum_u bit_{r_u}(j) 2^{u-1}.  The 4x4 matrix printed for
+  J = {84, 305, 725, 992} reproduces entry for entry in this order.
+"""
+from __future__ import annotations
+
+import math
+from typing import Iterable, Sequence
+
+import numpy as np
+import scipy.linalg
+
+
+# ---------------------------------------------------------------------------
+# 2-adic index work (Section VI: congruence trees, pivots, homogeneity)
+# ---------------------------------------------------------------------------
+
+def nu2(x: int) -> int:
+    """2-adic valuation of a nonzero integer (largest e with 2^e | x).
+
+    Remark 1(1): the lowest common ancestor of two leaves of the congruence
+    tree sits at level nu2(j_a - j_b).
+    """
+    x = int(x)
+    if x == 0:
+        raise ValueError("nu2 of zero is undefined")
+    e = 0
+    while x % 2 == 0:
+        x //= 2
+        e += 1
+    return e
+
+
+def check_index_set(M: int, J: Sequence[int]) -> list[int]:
+    """Return J as a list of Python ints after the problem-statement checks:
+    every index lies in Z_N (Section II) and indices are distinct."""
+    N = 1 << M
+    out = [int(j) for j in J]
+    for j in out:
+        if j < 0 or j >= N:
+            raise ValueError(f"index {j} outside Z_N with N = 2^{M}")
+    if len(set(out)) != len(out):
+        raise ValueError("duplicate index in J")
+    return out
+
+
+def pivots(M: int, J: Sequence[int]) -> list[int]:
+    """Pivot set P(J), sorted ascending, by brute force over all pairs.
+
+    Remark 2 (pivot as gcd): level e is a pivot iff 2^e is the largest power of
+    two dividing j_1 - j_2 for some j_1 != j_2 in J.  Differences are taken in
+    Z_N (mod 2^M), which does not change nu2 for levels below M.
+    """
+    J = check_index_set(M, J)
+    N = 1 << M
+    arr = np.array(J, dtype=np.uint64)
+    # O(k^2) pairs, one row at a time.  For a nonzero difference d the lowest
+    # set bit d & -d equals 2^{nu2(d)}; OR-ing these powers of two over all
+    # pairs leaves exactly the bits of the pivot levels.
+    levels = 0
+    with np.errstate(over="ignore"):
+        for a in range(len(arr) - 1):
+            d = (arr[a + 1:] - arr[a]) & np.uint64(N - 1)
+            low = d & (~d + np.uint64(1))
+            levels |= int(np.bitwise_or.reduce(low))
+    return [e for e in range(M) if (levels >> e) & 1]
+
+
+def is_power_of_two(k: int) -> bool:
+    return k >= 1 and (k & (k - 1)) == 0
+
+
+def is_homogeneous(M: int, J: Sequence[int]) -> bool:
+    """Definition (homogeneous): T(J) has exactly log2 |J| pivots.
+
+    Proposition 1 says there are always at least log2 |J| pivots, so this is the
+    extreme case; it forces |J| to be a power of two.
+    """
+    J = check_index_set(M, J)
+    k = len(J)
+    if not is_power_of_two(k):
+        return False
+    return len(pivots(M, J)) == k.bit_length() - 1
+
+
+def congruence_tree_levels(M: int, J: Sequence[int]) -> list[dict[int, list[int]]]:
+    """The congruence tree T(J) level by level (Section VI).
+
+    Level l holds the nonempty classes of J modulo 2^l, keyed by residue; the
+    root (level 0) is J itself and the leaves (level M) are singletons.
+    """
+    J = check_index_set(M, J)
+    levels = []
+    for l in range(M + 1):
+        nodes: dict[int, list[int]] = {}
+        for j in J:
+            nodes.setdefault(j % (1 << l), []).append(j)
+        levels.append(nodes)
+    return levels
+
+
+def homogeneous_by_tree(M: int, J: Sequence[int]) -> bool:
+    """Homogeneity through Proposition 2(2), checked on the explicit tree.
+
+    Every split is into two children of equal weight, and if one node at a
+    level splits, every node at that level splits.  Independent of ``pivots``.
+    """
+    levels = congruence_tree_levels(M, J)
+    for l in range(M):
+        splits = []
+        for res, members in levels[l].items():
+            children = [c for c in (res, res + (1 << l)) if c in levels[l + 1]]
+            if len(children) == 2:
+                w0 = len(levels[l + 1][children[0]])
+                w1 = len(levels[l + 1][children[1]])
+                if w0 != w1:
+                    return False
+                splits.append(True)
+            else:
+                splits.append(False)
+        if any(splits) and not all(splits):
+            return False
+    return True
+
+
+def pivots_by_tree(M: int, J: Sequence[int]) -> list[int]:
+    """Pivots as levels of T(J) that hold a node with two children
+    (Definition of pivots, Section VI)."""
+    levels = congruence_tree_levels(M, J)
+    out = []
+    for l in range(M):
+        if any(((res + (1 << l)) in levels[l + 1]) and (res in levels[l + 1])
+               for res in levels[l]):
+            out.append(l)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Pivoted sampling pattern (Section VII, Definition of I_r)
+# ---------------------------------------------------------------------------
+
+def sample_pattern_recursive(M: int, r: Sequence[int]) -> list[int]:
+    """I_r from its recursive definition, in recursion order.
+
+    I_() = {0};  I_r = I_{r-} followed by I_{r-} translated by 2^{M-1-r_max}.
+    The listing order (first the smaller pattern, then its translate) is the
+    row order of the block factorisation of Corollary 2.
+    """
+    r = list(r)
+    if r != sorted(r) or len(set(r)) != len(r):
+        raise ValueError("pivot vector must be strictly ascending")
+    if r and (r[0] < 0 or r[-1] >= M):
+        raise ValueError("pivots must lie in [0, M)")
+    pattern = [0]
+    for u in range(len(r)):
+        shift = 1 << (M - 1 - r[u])
+        pattern = pattern + [x + shift for x in pattern]
+    return pattern
+
+
+def sample_pattern_closed_form(M: int, r: Sequence[int]) -> set[int]:
+    """I_r from the non-recursive form: all sums of distinct 2^{M-1-r_u}."""
+    s = len(r)
+    out = set()
+    for b in range(1 << s):
+        out.add(sum((1 << (M - 1 - r[u])) for u in range(s) if (b >> u) & 1))
+    return out
+
+
+def sample_set(M: int, J: Sequence[int]) -> list[int]:
+    """The k sample locations I_r for a homogeneous J, ascending."""
+    if not is_homogeneous(M, J):
+        raise ValueError("J is not homogeneous")
+    return sorted(sample_pattern_recursive(M, pivots(M, J)))
+
+
+# ---------------------------------------------------------------------------
+# Plan orders and twiddle exponents (Lemma 3, Corollary 2, Algorithm 1)
+# ---------------------------------------------------------------------------
+
+def frequency_position(j: int, r: Sequence[int]) -> int:
+    """q(j) = sum_u bit_{r_u}(j) 2^{u-1}: the column order of Corollary 2.
+
+    The first half (q < k/2) is the left branch J_1 of the top split, the
+    second half the right branch J_2; recursively inside each half.
+    """
+    return sum(((int(j) >> r[u]) & 1) << u for u in range(len(r)))
+
+
+def frequency_positions(M: int, J: Sequence[int]) -> list[int]:
+    """q(J[t]) for every t, in the caller's order of J."""
+    r = pivots(M, J)
+    return [frequency_position(j, r) for j in J]
+
+
+def twiddle_exponents(M: int, J: Sequence[int]) -> list[tuple[int, int, int, int]]:
+    """Butterfly twiddles of the radix-2 split, as exact integers.
+
+    Lemma 3 combines the height-(n+1) Hi-DFT of f and of its translate by
+    a = 2^{M-1-r} with the factor omega_{r+1}^{j} = exp(-2 pi i j / 2^{r+1})
+    taken at the left descendant j (bit r of j is 0); the right descendant gets
+    the negated factor.  Counting stages upward from the leaves (stage u uses
+    pivot r_u), the butterflies of stage u are indexed by q_lo < 2^{u-1}, the
+    frequency position of the node's low pivot bits, and the factor is
+    exp(-i pi m / 2^{r_u}) with m = j mod 2^{r_u} for any j in J whose first
+    u-1 pivot bits spell q_lo.
+
+    Returns (u, q_lo, m, r_u) for u = 1..s and q_lo < 2^{u-1}, i.e. k-1 entries
+    in the order stage-major, q_lo-minor.
+    """
+    J = check_index_set(M, J)
+    r = pivots(M, J)
+    s = len(r)
+    if (1 << s) != len(J):
+        raise ValueError("J is not homogeneous")
+    by_q = {frequency_position(j, r): j for j in J}
+    if len(by_q) != len(J):
+        raise ValueError("q(j) is not a bijection: J is not homogeneous")
+    out = []
+    for u in range(1, s + 1):
+        ru = r[u - 1]
+        for q_lo in range(1 << (u - 1)):
+            j = by_q[q_lo]
+            out.append((u, q_lo, j % (1 << ru), ru))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Fourier submatrices and the coefficient solve (Section V-A, Eq. submatrix)
+# ---------------------------------------------------------------------------
+
+def _phase_fraction(M: int, rows: Iterable[int], cols: Iterable[int]) -> np.ndarray:
+    """((row * col) mod N) / N for every pair, with the product reduced exactly.
+
+    uint64 products wrap modulo 2^64, and N = 2^M divides 2^64, so masking the
+    wrapped product with N-1 gives the exact residue for every M <= 63.
+    """
+    N = 1 << M
+    rows_a = np.array(list(rows), dtype=np.uint64)
+    cols_a = np.array(list(cols), dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        prod = (rows_a[:, None] * cols_a[None, :]) & np.uint64(N - 1)
+    return prod.astype(np.float64) / float(N)
+
+
+def dft_submatrix(M: int, rows: Sequence[int], cols: Sequence[int]) -> np.ndarray:
+    """F(rows, cols) with entries exp(-2 pi i row col / N)   (Section II)."""
+    return np.exp(-2j * np.pi * _phase_fraction(M, rows, cols))
+
+
+def idft_submatrix(M: int, rows: Sequence[int], cols: Sequence[int]) -> np.ndarray:
+    """F^{-1}(rows, cols) with entries (1/N) exp(+2 pi i row col / N) (Section IV)."""
+    N = 1 << M
+    return np.exp(2j * np.pi * _phase_fraction(M, rows, cols)) / N
+
+
+def synthesize_samples(M: int, J: Sequence[int], c: np.ndarray,
+                       I: Sequence[int]) -> np.ndarray:
+    """Samples f(i), i in I, of the signal in B^J whose DFT on J is c.
+
+    f = F^{-1}(Z_N, J) (Ff)_J (Section V-A), evaluated only on the rows I.
+    ``c`` may be (k,) or (batch, k); the result has the matching shape.
+    """
+    A = idft_submatrix(M, I, J)
+    c = np.asarray(c, dtype=np.complex128)
+    return c @ A.T if c.ndim == 2 else A @ c
+
+
+def solve_coefficients(M: int, J: Sequence[int], I: Sequence[int],
+                       f_I: np.ndarray) -> np.ndarray:
+    """(Ff)_J from k samples by solving f_I = F^{-1}(I, J) (Ff)_J.
+
+    This is the paper's trivial O(k^2)-per-signal route (Eq. submatrix-method),
+    done with a dense LU factorisation with partial pivoting (LAPACK zgetrf /
+    zgetrs) in complex128.  ``f_I`` may be (k,) or (batch, k).
+    """
+    A = idft_submatrix(M, I, J)
+    f_I = np.asarray(f_I, dtype=np.complex128)
+    lu = scipy.linalg.lu_factor(A, check_finite=True)
+    if f_I.ndim == 1:
+        return scipy.linalg.lu_solve(lu, f_I)
+    return scipy.linalg.lu_solve(lu, f_I.T).T
+
+
+def adjoint_coefficients(M: int, J: Sequence[int], I: Sequence[int],
+                         f_I: np.ndarray) -> np.ndarray:
+    """(Ff)_J = (N/k) F(J, I) f_I for a homogeneous J sampled on I = I_r.
+
+    Lemma 1 shows the aliasing pattern of I_r vanishes on every difference of
+    two distinct elements of J, so F(J, I_r) F(J, I_r)^H = k Id and the inverse
+    of F^{-1}(I_r, J) is (N/k) F(J, I_r): the same answer as the LU solve,
+    without a factorisation.  Valid only for I = I_r of a homogeneous J.
+    """
+    N = 1 << M
+    k = len(J)
+    F = dft_submatrix(M, J, I)
+    f_I = np.asarray(f_I, dtype=np.complex128)
+    scale = N / k
+    if f_I.ndim == 1:
+        return scale * (F @ f_I)
+    return scale * (f_I @ F.T)
+
+
+def coefficient_at(M: int, j: int, I: Sequence[int], f_I: np.ndarray, k: int) -> complex:
+    """One coefficient (Ff)(j) = (N/k) sum_{i in I_r} f(i) omega^{ij}.
+
+    The one-row form of ``adjoint_coefficients``, for spot checks of large
+    transforms one output at a time.
+    """
+    N = 1 << M
+    row = dft_submatrix(M, [j], I)[0]
+    return complex((N / k) * np.dot(row, np.asarray(f_I, dtype=np.complex128)))
+
+
+def coefficients(M: int, J: Sequence[int], f_I: np.ndarray, method: str = "auto") -> np.ndarray:
+    """(Ff)_J for a homogeneous J from samples on I_r (ascending order).
+
+    method: "lu" (dense solve), "adjoint", or "auto" (LU up to k = 4096).
+    """
+    I = sample_set(M, J)
+    if method == "auto":
+        method = "lu" if len(J) <= 4096 else "adjoint"
+    if method == "lu":
+        return solve_coefficients(M, J, I, f_I)
+    if method == "adjoint":
+        return adjoint_coefficients(M, J, I, f_I)
+    raise ValueError(method)
+
+
+# ---------------------------------------------------------------------------
+# Error report (per result)
+# ---------------------------------------------------------------------------
+
+def rel_l2(x: np.ndarray, ref: np.ndarray) -> float:
+    """||x - ref||_2 / ||ref||_2 over the last axis (a float for 1-D input)."""
+    x = np.asarray(x, dtype=np.complex128)
+    ref = np.asarray(ref, dtype=np.complex128)
+    num = np.linalg.norm(x - ref, axis=-1)
+    den = np.linalg.norm(ref, axis=-1)
+    return num / den
+
+
+def max_abs(x: np.ndarray, ref: np.ndarray) -> float:
+    return np.max(np.abs(np.asarray(x) - np.asarray(ref)), axis=-1)
+
+
+def op_count(k: int) -> int:
+    """Theorem 1: 1.5 A log2 A + A arithmetic operations for A = k samples."""
+    s = k.bit_length() - 1
+    return int(1.5 * k * s + k) if k > 1 else 1
