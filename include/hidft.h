@@ -1,0 +1,206 @@
+/*
+ * hidft.h -- C ABI of the homogeneous-support DFT library for AMD MI355X (gfx950).
+ *
+ * Problem (arXiv 2211.15299, Sec. II, "Structured-DFT algorithm"): a signal
+ * f in C^N, N = 2^M, has a known frequency support J (|J| = k): (Ff)(m) = 0
+ * for m outside J, with (Ff)(m) = sum_n f(n) exp(-2 pi i m n / N).  The
+ * algorithm is given J (in binary) and access to entries of f, may preprocess
+ * J, and must return the k coefficients {(Ff)(j)}_{j in J} exactly.
+ *
+ * When J is homogeneous (Sec. VI, Def. homogeneous: the congruence tree of J
+ * has exactly log2 k pivots), the library reads f on the k points of the
+ * pivoted sampling pattern I_r (Sec. VII, Def. pivoted sampling pattern) and
+ * computes the coefficients with the radix-2 recursion of Lemma 3 / Algorithm 1
+ * in O(k log k) operations per signal (Theorem 1, Corollary 1).
+ *
+ * Two layers:
+ *   planner  (host, C++): hidft_analyze, hidft_plan_create and the getters.
+ *            Validates J, finds the pivots, derives I_r, the plan orders of
+ *            Corollary 2 and the twiddle schedule; uploads device tables.
+ *   executor (device, HIP): hidft_execute and its variants map samples to
+ *            coefficients for a batch of signals on a HIP stream.
+ *
+ * Numbers.  Samples and coefficients are complex64: interleaved
+ * (float re, float im) pairs, 8 bytes per value, 8-byte aligned.  Index sets
+ * are uint64.  Arithmetic is FP32 on the device; twiddles are evaluated in
+ * FP64 on the device from exact integer exponents and rounded once to FP32.
+ *
+ * Streams are passed as `void*` holding a hipStream_t (NULL = the legacy
+ * default stream).  Device pointers are plain HIP device addresses on the
+ * device that was current when the plan was created.
+ *
+ * Errors.  Every call returns hidft_status; nothing throws across the ABI.
+ * Argument, index and homogeneity errors are detected synchronously on the
+ * host before any device work is queued.  Device faults surface as HIP errors
+ * at the caller's next synchronisation.  hidft_last_error() returns a
+ * thread-local message describing the most recent failure on this thread.
+ */
+#ifndef HIDFT_H_
+#define HIDFT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hidft_status {
+  HIDFT_OK = 0,
+  HIDFT_ERR_INVALID_ARGUMENT = 1,   /* null pointer, bad size, stride, alignment, device */
+  HIDFT_ERR_INDEX_OUT_OF_RANGE = 2, /* some j >= N = 2^M */
+  HIDFT_ERR_DUPLICATE_INDEX = 3,    /* J lists an index twice */
+  HIDFT_ERR_SIZE_NOT_POW2 = 4,      /* k is not a power of two (cannot be homogeneous) */
+  HIDFT_ERR_NOT_HOMOGENEOUS = 5,    /* k = 2^s but J has more than s pivots */
+  HIDFT_ERR_OUT_OF_MEMORY = 6,      /* host or device allocation failed */
+  HIDFT_ERR_DEVICE = 7,             /* a HIP runtime call failed */
+  HIDFT_ERR_UNSUPPORTED = 8         /* valid request outside what this build executes */
+} hidft_status;
+
+/* Opaque plan: immutable after creation; safe to execute concurrently from
+ * several host threads and streams.  Destroying a plan while executions that
+ * use it are still in flight is the caller's error: synchronise first. */
+typedef struct hidft_plan_s* hidft_plan;
+
+/* Limits of this build. */
+#define HIDFT_MAX_LOG2_N 63u        /* N = 2^M with M <= 63 */
+#define HIDFT_MAX_LOG2_K_HOST 26u   /* planner (HOST_ONLY plans): k <= 2^26 */
+#define HIDFT_MAX_LOG2_K_DEVICE 14u /* executor: one signal is staged whole in LDS */
+
+/* Plan flags. */
+#define HIDFT_PLAN_HOST_ONLY 0x1u   /* derive the schedule on the host only: no
+                                       device tables, no HIP calls; execute
+                                       calls on such a plan are refused. */
+
+/*
+ * hidft_analyze -- pivots and the homogeneity verdict of J.
+ *
+ * Sec. VI, Remark 2 (pivot as gcd): level e is a pivot iff 2^e is the largest
+ * power of two dividing j1 - j2 for some j1 != j2 in J; Def. homogeneous:
+ * exactly log2 |J| pivots (Prop. 1: never fewer).
+ *
+ *   log2_n          M, with N = 2^M, 0 <= M <= 63.
+ *   J[k]            host array of distinct indices in [0, N), any order.
+ *   pivots          host output, capacity 64 entries: pivot levels ascending.
+ *                   May be NULL.
+ *   n_pivots        host output: number of pivots.  May be NULL.
+ *   is_homogeneous  host output: 1 if k = 2^s and there are exactly s pivots.
+ *                   May be NULL.
+ * Returns HIDFT_OK for any valid J, homogeneous or not (the verdict is in
+ * *is_homogeneous); INDEX_OUT_OF_RANGE / DUPLICATE_INDEX / INVALID_ARGUMENT
+ * otherwise.  Host only; O(k log k).
+ */
+hidft_status hidft_analyze(uint32_t log2_n, const uint64_t* J, uint64_t k,
+                           uint32_t* pivots, uint32_t* n_pivots,
+                           int32_t* is_homogeneous);
+
+/*
+ * hidft_plan_create -- plan the transform for (N, J).
+ *
+ * Validates J (range, duplicates, k = 2^s, homogeneity), finds the pivots
+ * r_1 < ... < r_s, derives the sample set I_r (Sec. VII, Def. pivoted sampling
+ * pattern), the frequency order q(j) = sum_u bit_{r_u}(j) 2^{u-1} of
+ * Corollary 2, and the k-1 butterfly twiddles of Lemma 3
+ * (stage u, q_lo < 2^{u-1}: exp(-i pi m / 2^{r_u}), m = j mod 2^{r_u} for the
+ * j in J whose first u-1 pivot bits spell q_lo).
+ * Unless HIDFT_PLAN_HOST_ONLY is set, allocates the device tables on the
+ * current device, generates the twiddles there in FP64 (rounded once to FP32)
+ * on `stream`, and waits for that work before returning.
+ *
+ *   log2_n, J, k  as for hidft_analyze; J is copied, the caller keeps it.
+ *   flags         0 or HIDFT_PLAN_HOST_ONLY.
+ *   stream        hipStream_t used for the table upload (ignored if HOST_ONLY).
+ *   out           receives the plan; set to NULL on failure.
+ * Errors: INVALID_ARGUMENT, INDEX_OUT_OF_RANGE, DUPLICATE_INDEX,
+ * SIZE_NOT_POW2, NOT_HOMOGENEOUS, UNSUPPORTED (device plan with
+ * k > 2^HIDFT_MAX_LOG2_K_DEVICE, or k > 2^HIDFT_MAX_LOG2_K_HOST),
+ * OUT_OF_MEMORY, DEVICE.
+ */
+hidft_status hidft_plan_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
+                               uint32_t flags, void* stream, hidft_plan* out);
+
+/* Releases host and device memory of the plan.  NULL is accepted. */
+hidft_status hidft_plan_destroy(hidft_plan plan);
+
+/* Sizes of the plan: M, k and s = log2 k (any output may be NULL). */
+hidft_status hidft_plan_get_info(hidft_plan plan, uint32_t* log2_n, uint64_t* k,
+                                 uint32_t* n_pivots);
+
+/* The pivot vector r (ascending), s = log2 k entries, into host memory. */
+hidft_status hidft_plan_get_pivots(hidft_plan plan, uint32_t* pivots);
+
+/*
+ * The sample set I_r, ascending, k entries, into host memory.  Sample
+ * position p of the execute calls holds f(sample_idx[p]).
+ * Sec. VII: I_r = { sum_u b_u 2^{M-1-r_u} : b in {0,1}^s }, |I_r| = k.
+ */
+hidft_status hidft_plan_get_samples(hidft_plan plan, uint64_t* sample_idx);
+
+/*
+ * The integer schedule, for exact checks against an independent derivation.
+ *   freq_pos[k]       q(J[t]) for the caller's order of J (Corollary 2 order).
+ *   tw_num[k-1]       m of each twiddle, stage-major, q_lo-minor
+ *                     (stage u = 1..s, q_lo = 0..2^{u-1}-1).
+ *   tw_log2den[k-1]   r_u of each twiddle: the value is exp(-i pi m / 2^{r_u}).
+ * Any output may be NULL.  Host memory.
+ */
+hidft_status hidft_plan_get_schedule(hidft_plan plan, uint32_t* freq_pos,
+                                     uint64_t* tw_num, uint8_t* tw_log2den);
+
+/*
+ * The FP32 twiddles as generated on the device, copied to host memory in the
+ * schedule's order (2*(k-1) floats: re, im).  Synchronous.  Device plans only.
+ */
+hidft_status hidft_plan_get_twiddles(hidft_plan plan, float* twiddles);
+
+/* Device bytes held by the plan (tables), for memory-based admission. */
+hidft_status hidft_plan_device_bytes(hidft_plan plan, size_t* bytes);
+
+/*
+ * hidft_execute -- batched transform, one plan shared by all signals.
+ *
+ * For b < batch: d_coefs[b*ld_out + t] = (F f_b)(J[t]) for t < k, where
+ * d_samples[b*ld_in + p] = f_b(sample_idx[p]) for p < k (ascending I_r).
+ * Coefficients follow the caller's order of J and the DFT of Sec. II exactly
+ * (no normalisation).  Computes (N/k) F(J, I_r) f_I by s = log2 k radix-2
+ * stages (Lemma 3), which equals (Ff)_J for f in B^J (Sec. VII-B, Lemma 1).
+ * One fused kernel launch: each signal is read once from HBM, transformed in
+ * LDS and registers, and written once.
+ *
+ *   d_samples  device, complex64, batch rows of ld_in >= k values.
+ *   d_coefs    device, complex64, batch rows of ld_out >= k values.
+ *              May equal d_samples (in place) when ld_out == ld_in; any other
+ *              overlap is INVALID_ARGUMENT.
+ *   batch      number of signals; 0 is a no-op.
+ *   stream     hipStream_t; the call is asynchronous on it.
+ * Errors: INVALID_ARGUMENT (null plan or pointer, misaligned pointer,
+ * ld < k, bad overlap, current device differs from the plan's, HOST_ONLY
+ * plan), DEVICE (launch failure).
+ */
+hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in,
+                           void* d_coefs, int64_t ld_out, uint64_t batch,
+                           void* stream);
+
+/*
+ * hidft_execute_plain -- the plain per-signal GPU method (baseline).
+ *
+ * Same contract and results as hidft_execute, computed the textbook way:
+ * one kernel launch per signal, one workgroup, the samples permuted into the
+ * recursion order of Algorithm 1 in LDS, then one radix-2 stage of Lemma 3 per
+ * LDS barrier.  Exists to measure the batched and fused forms against.
+ */
+hidft_status hidft_execute_plain(hidft_plan plan, const void* d_samples, int64_t ld_in,
+                                 void* d_coefs, int64_t ld_out, uint64_t batch,
+                                 void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* hidft_status_string(hidft_status status);
+
+/* Message of the most recent failure on the calling thread ("" if none). */
+const char* hidft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIDFT_H_ */

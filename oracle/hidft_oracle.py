@@ -287,15 +287,21 @@ def idft_submatrix(M: int, rows: Sequence[int], cols: Sequence[int]) -> np.ndarr
 
 
 def synthesize_samples(M: int, J: Sequence[int], c: np.ndarray,
-                       I: Sequence[int]) -> np.ndarray:
+                       I: Sequence[int], chunk: int = 2048) -> np.ndarray:
     """Samples f(i), i in I, of the signal in B^J whose DFT on J is c.
 
     f = F^{-1}(Z_N, J) (Ff)_J (Section V-A), evaluated only on the rows I.
-    ``c`` may be (k,) or (batch, k); the result has the matching shape.
+    ``c`` may be (k,) or (batch, k); the result has the matching shape.  The
+    matrix is formed ``chunk`` rows at a time to bound memory.
     """
-    A = idft_submatrix(M, I, J)
+    I = list(I)
     c = np.asarray(c, dtype=np.complex128)
-    return c @ A.T if c.ndim == 2 else A @ c
+    cm = c[None, :] if c.ndim == 1 else c
+    out = np.empty((cm.shape[0], len(I)), dtype=np.complex128)
+    for lo in range(0, len(I), chunk):
+        A = idft_submatrix(M, I[lo:lo + chunk], J)
+        out[:, lo:lo + chunk] = cm @ A.T
+    return out[0] if c.ndim == 1 else out
 
 
 def solve_coefficients(M: int, J: Sequence[int], I: Sequence[int],
@@ -315,22 +321,30 @@ def solve_coefficients(M: int, J: Sequence[int], I: Sequence[int],
 
 
 def adjoint_coefficients(M: int, J: Sequence[int], I: Sequence[int],
-                         f_I: np.ndarray) -> np.ndarray:
+                         f_I: np.ndarray, k: int | None = None,
+                         chunk: int = 2048) -> np.ndarray:
     """(Ff)_J = (N/k) F(J, I) f_I for a homogeneous J sampled on I = I_r.
 
     Lemma 1 shows the aliasing pattern of I_r vanishes on every difference of
     two distinct elements of J, so F(J, I_r) F(J, I_r)^H = k Id and the inverse
     of F^{-1}(I_r, J) is (N/k) F(J, I_r): the same answer as the LU solve,
     without a factorisation.  Valid only for I = I_r of a homogeneous J.
+
+    ``J`` may be any subset of the support (then pass the support size ``k``)
+    to evaluate selected coefficients only.  ``f_I`` may be (k,) or (batch, k).
+    The matrix is formed ``chunk`` rows at a time to bound memory.
     """
     N = 1 << M
-    k = len(J)
-    F = dft_submatrix(M, J, I)
+    J = list(J)
+    k = len(J) if k is None else k
     f_I = np.asarray(f_I, dtype=np.complex128)
-    scale = N / k
-    if f_I.ndim == 1:
-        return scale * (F @ f_I)
-    return scale * (f_I @ F.T)
+    fm = f_I[None, :] if f_I.ndim == 1 else f_I
+    out = np.empty((fm.shape[0], len(J)), dtype=np.complex128)
+    for lo in range(0, len(J), chunk):
+        F = dft_submatrix(M, J[lo:lo + chunk], I)
+        out[:, lo:lo + chunk] = fm @ F.T
+    out *= N / k
+    return out[0] if f_I.ndim == 1 else out
 
 
 def coefficient_at(M: int, j: int, I: Sequence[int], f_I: np.ndarray, k: int) -> complex:

@@ -1,0 +1,333 @@
+// C ABI of the homogeneous-support DFT: argument checks, plan lifecycle and
+// dispatch to the HIP kernels.  Nothing throws across this boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hidft.h"
+#include "launch.h"
+#include "plan_core.h"
+
+struct hidft_plan_s {
+  hidft::PlanCore core;
+  bool host_only = true;
+  int device = -1;
+  float2* d_tw = nullptr;      // k-1 twiddles in a-order (at least one slot)
+  uint16_t* d_src = nullptr;   // k output gather positions
+  size_t device_bytes = 0;
+  float scale = 1.0f;          // N / k
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hidft_status fail(hidft_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+hidft_status ok() {
+  g_last_error.clear();
+  return HIDFT_OK;
+}
+
+hidft_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory)
+    return fail(HIDFT_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
+  return fail(HIDFT_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void release_device(hidft_plan p) {
+  if (p->d_tw) (void)hipFree(p->d_tw);
+  if (p->d_src) (void)hipFree(p->d_src);
+  p->d_tw = nullptr;
+  p->d_src = nullptr;
+}
+
+// Uploads the device tables and generates the twiddles on `stream`.
+hidft_status upload(hidft_plan p, hipStream_t stream) {
+  const hidft::PlanCore& c = p->core;
+  const uint64_t k = c.k;
+  const uint64_t ntw = k - 1;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+
+  // Device order of the twiddle table: entry (2^{u-1}-1) + bitrev_{u-1}(q_lo)
+  // holds the twiddle of stage u, node q_lo.
+  std::vector<uint64_t> num(ntw ? ntw : 1, 0);
+  std::vector<uint8_t> den(ntw ? ntw : 1, 0);
+  for (uint32_t u = 1; u <= c.s; ++u) {
+    const uint64_t off = (1ULL << (u - 1)) - 1;
+    for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
+      const uint64_t h = hidft::bit_reverse(q_lo, u - 1);
+      num[off + h] = c.tw_num[off + q_lo];
+      den[off + h] = c.tw_log2den[off + q_lo];
+    }
+  }
+  std::vector<uint16_t> src(k);
+  for (uint64_t t = 0; t < k; ++t)
+    src[t] = static_cast<uint16_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
+
+  const size_t ntw_alloc = ntw ? ntw : 1;
+  uint64_t* d_num = nullptr;
+  uint8_t* d_den = nullptr;
+  hidft_status st = HIDFT_OK;
+  if ((e = hipMalloc(&p->d_tw, ntw_alloc * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&p->d_src, k * sizeof(uint16_t))) != hipSuccess ||
+      (e = hipMalloc(&d_num, ntw_alloc * sizeof(uint64_t))) != hipSuccess ||
+      (e = hipMalloc(&d_den, ntw_alloc)) != hipSuccess) {
+    st = hip_fail(e, "hipMalloc of plan tables");
+  } else if ((e = hipMemcpyAsync(d_num, num.data(), ntw_alloc * sizeof(uint64_t),
+                                 hipMemcpyHostToDevice, stream)) != hipSuccess ||
+             (e = hipMemcpyAsync(d_den, den.data(), ntw_alloc, hipMemcpyHostToDevice,
+                                 stream)) != hipSuccess ||
+             (e = hipMemcpyAsync(p->d_src, src.data(), k * sizeof(uint16_t),
+                                 hipMemcpyHostToDevice, stream)) != hipSuccess) {
+    st = hip_fail(e, "hipMemcpyAsync of plan tables");
+  } else if ((e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, stream)) !=
+             hipSuccess) {
+    st = hip_fail(e, "twiddle generation launch");
+  } else if ((e = hipStreamSynchronize(stream)) != hipSuccess) {
+    st = hip_fail(e, "hipStreamSynchronize after plan upload");
+  }
+  if (d_num) (void)hipFree(d_num);
+  if (d_den) (void)hipFree(d_den);
+  if (st != HIDFT_OK) {
+    release_device(p);
+    return st;
+  }
+  p->device_bytes = ntw_alloc * sizeof(float2) + k * sizeof(uint16_t);
+  return HIDFT_OK;
+}
+
+// Common argument checks of the execute calls.
+hidft_status check_exec(hidft_plan plan, const void* d_in, int64_t ld_in, const void* d_out,
+                        int64_t ld_out, uint64_t batch, const char* fn) {
+  if (!plan) return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: plan is NULL", fn);
+  if (plan->host_only)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: plan was created HOST_ONLY", fn);
+  if (batch == 0) return HIDFT_OK;
+  const uint64_t k = plan->core.k;
+  if (!d_in || !d_out) return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: NULL buffer", fn);
+  if ((reinterpret_cast<uintptr_t>(d_in) | reinterpret_cast<uintptr_t>(d_out)) & 7u)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: buffers must be 8-byte aligned", fn);
+  if (ld_in < 0 || ld_out < 0 || (uint64_t)ld_in < k || (uint64_t)ld_out < k)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT,
+                "%s: leading dimensions (%lld, %lld) must be >= k = %llu", fn,
+                (long long)ld_in, (long long)ld_out, (unsigned long long)k);
+  if (batch > (1ULL << 40))
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: batch too large", fn);
+  const uint64_t span_in = ((batch - 1) * (uint64_t)ld_in + k) * sizeof(float2);
+  const uint64_t span_out = ((batch - 1) * (uint64_t)ld_out + k) * sizeof(float2);
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(d_in), a1 = a0 + span_in;
+  const uintptr_t b0 = reinterpret_cast<uintptr_t>(d_out), b1 = b0 + span_out;
+  const bool overlap = a0 < b1 && b0 < a1;
+  if (overlap && !(a0 == b0 && ld_in == ld_out))
+    return fail(HIDFT_ERR_INVALID_ARGUMENT,
+                "%s: input and output overlap other than exactly in place", fn);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, fn);
+  if (dev != plan->device)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: current device %d, plan lives on device %d",
+                fn, dev, plan->device);
+  return HIDFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hidft_status_string(hidft_status st) {
+  switch (st) {
+    case HIDFT_OK: return "HIDFT_OK";
+    case HIDFT_ERR_INVALID_ARGUMENT: return "HIDFT_ERR_INVALID_ARGUMENT";
+    case HIDFT_ERR_INDEX_OUT_OF_RANGE: return "HIDFT_ERR_INDEX_OUT_OF_RANGE";
+    case HIDFT_ERR_DUPLICATE_INDEX: return "HIDFT_ERR_DUPLICATE_INDEX";
+    case HIDFT_ERR_SIZE_NOT_POW2: return "HIDFT_ERR_SIZE_NOT_POW2";
+    case HIDFT_ERR_NOT_HOMOGENEOUS: return "HIDFT_ERR_NOT_HOMOGENEOUS";
+    case HIDFT_ERR_OUT_OF_MEMORY: return "HIDFT_ERR_OUT_OF_MEMORY";
+    case HIDFT_ERR_DEVICE: return "HIDFT_ERR_DEVICE";
+    case HIDFT_ERR_UNSUPPORTED: return "HIDFT_ERR_UNSUPPORTED";
+  }
+  return "HIDFT_ERR_UNKNOWN";
+}
+
+const char* hidft_last_error(void) { return g_last_error.c_str(); }
+
+hidft_status hidft_analyze(uint32_t log2_n, const uint64_t* J, uint64_t k, uint32_t* pivots,
+                           uint32_t* n_pivots, int32_t* is_homogeneous) {
+  try {
+    uint64_t mask = 0;
+    std::string err;
+    hidft_status st = hidft::analyze_core(log2_n, J, k, &mask, &err);
+    if (st != HIDFT_OK) return fail(st, "hidft_analyze: %s", err.c_str());
+    uint32_t n = 0;
+    for (uint32_t e = 0; e < 64; ++e)
+      if ((mask >> e) & 1) {
+        if (pivots) pivots[n] = e;
+        ++n;
+      }
+    if (n_pivots) *n_pivots = n;
+    if (is_homogeneous)
+      *is_homogeneous = ((k & (k - 1)) == 0 && (uint32_t)__builtin_ctzll(k) == n) ? 1 : 0;
+    return ok();
+  } catch (const std::bad_alloc&) {
+    return fail(HIDFT_ERR_OUT_OF_MEMORY, "hidft_analyze: host allocation failed");
+  } catch (...) {
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_analyze: unexpected exception");
+  }
+}
+
+hidft_status hidft_plan_create(uint32_t log2_n, const uint64_t* J, uint64_t k, uint32_t flags,
+                               void* stream, hidft_plan* out) {
+  if (!out) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_create: out is NULL");
+  *out = nullptr;
+  if (flags & ~HIDFT_PLAN_HOST_ONLY)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_create: unknown flags 0x%x", flags);
+  const bool host_only = (flags & HIDFT_PLAN_HOST_ONLY) != 0;
+  hidft_plan p = nullptr;
+  try {
+    p = new hidft_plan_s;
+    std::string err;
+    const uint32_t max_s = host_only ? HIDFT_MAX_LOG2_K_HOST : HIDFT_MAX_LOG2_K_DEVICE;
+    hidft_status st = hidft::build_plan_core(log2_n, J, k, max_s, &p->core, &err);
+    if (st != HIDFT_OK) {
+      delete p;
+      return fail(st, "hidft_plan_create: %s", err.c_str());
+    }
+    p->host_only = host_only;
+    p->scale = std::ldexp(1.0f, (int)(p->core.M - p->core.s));
+    if (!host_only) {
+      st = upload(p, static_cast<hipStream_t>(stream));
+      if (st != HIDFT_OK) {
+        std::string msg = g_last_error;
+        delete p;
+        return fail(st, "hidft_plan_create: %s", msg.c_str());
+      }
+    }
+    *out = p;
+    return ok();
+  } catch (const std::bad_alloc&) {
+    if (p) {
+      release_device(p);
+      delete p;
+    }
+    return fail(HIDFT_ERR_OUT_OF_MEMORY, "hidft_plan_create: host allocation failed");
+  } catch (...) {
+    if (p) {
+      release_device(p);
+      delete p;
+    }
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_create: unexpected exception");
+  }
+}
+
+hidft_status hidft_plan_destroy(hidft_plan plan) {
+  if (!plan) return ok();
+  release_device(plan);
+  delete plan;
+  return ok();
+}
+
+hidft_status hidft_plan_get_info(hidft_plan plan, uint32_t* log2_n, uint64_t* k,
+                                 uint32_t* n_pivots) {
+  if (!plan) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_get_info: plan is NULL");
+  if (log2_n) *log2_n = plan->core.M;
+  if (k) *k = plan->core.k;
+  if (n_pivots) *n_pivots = plan->core.s;
+  return ok();
+}
+
+hidft_status hidft_plan_get_pivots(hidft_plan plan, uint32_t* pivots) {
+  if (!plan || !pivots)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_get_pivots: NULL argument");
+  std::memcpy(pivots, plan->core.pivots.data(), plan->core.s * sizeof(uint32_t));
+  return ok();
+}
+
+hidft_status hidft_plan_get_samples(hidft_plan plan, uint64_t* sample_idx) {
+  if (!plan || !sample_idx)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_get_samples: NULL argument");
+  std::memcpy(sample_idx, plan->core.samples.data(), plan->core.k * sizeof(uint64_t));
+  return ok();
+}
+
+hidft_status hidft_plan_get_schedule(hidft_plan plan, uint32_t* freq_pos, uint64_t* tw_num,
+                                     uint8_t* tw_log2den) {
+  if (!plan) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_get_schedule: plan is NULL");
+  const hidft::PlanCore& c = plan->core;
+  if (freq_pos) std::memcpy(freq_pos, c.freq_pos.data(), c.k * sizeof(uint32_t));
+  if (tw_num && c.k > 1) std::memcpy(tw_num, c.tw_num.data(), (c.k - 1) * sizeof(uint64_t));
+  if (tw_log2den && c.k > 1) std::memcpy(tw_log2den, c.tw_log2den.data(), c.k - 1);
+  return ok();
+}
+
+hidft_status hidft_plan_get_twiddles(hidft_plan plan, float* twiddles) {
+  if (!plan || !twiddles)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_get_twiddles: NULL argument");
+  if (plan->host_only)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_get_twiddles: HOST_ONLY plan");
+  const hidft::PlanCore& c = plan->core;
+  if (c.k < 2) return ok();
+  std::vector<float2> dev(c.k - 1);
+  hipError_t e = hipMemcpy(dev.data(), plan->d_tw, (c.k - 1) * sizeof(float2),
+                           hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hidft_plan_get_twiddles");
+  for (uint32_t u = 1; u <= c.s; ++u) {
+    const uint64_t off = (1ULL << (u - 1)) - 1;
+    for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
+      const float2 w = dev[off + hidft::bit_reverse(q_lo, u - 1)];
+      twiddles[2 * (off + q_lo)] = w.x;
+      twiddles[2 * (off + q_lo) + 1] = w.y;
+    }
+  }
+  return ok();
+}
+
+hidft_status hidft_plan_device_bytes(hidft_plan plan, size_t* bytes) {
+  if (!plan || !bytes)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_device_bytes: NULL argument");
+  *bytes = plan->device_bytes;
+  return ok();
+}
+
+hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in,
+                           void* d_coefs, int64_t ld_out, uint64_t batch, void* stream) {
+  hidft_status st = check_exec(plan, d_samples, ld_in, d_coefs, ld_out, batch, "hidft_execute");
+  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
+  hipError_t e = hidft::launch_fused(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
+                                     static_cast<float2*>(d_coefs), ld_out, batch, plan->d_tw,
+                                     plan->d_src, plan->scale, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hidft_execute: kernel launch");
+  return ok();
+}
+
+hidft_status hidft_execute_plain(hidft_plan plan, const void* d_samples, int64_t ld_in,
+                                 void* d_coefs, int64_t ld_out, uint64_t batch, void* stream) {
+  hidft_status st =
+      check_exec(plan, d_samples, ld_in, d_coefs, ld_out, batch, "hidft_execute_plain");
+  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
+  const float2* in = static_cast<const float2*>(d_samples);
+  float2* out = static_cast<float2*>(d_coefs);
+  for (uint64_t b = 0; b < batch; ++b) {
+    hipError_t e = hidft::launch_plain(plan->core.s, in + b * (uint64_t)ld_in,
+                                       out + b * (uint64_t)ld_out, plan->d_tw, plan->d_src,
+                                       plan->scale, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hidft_execute_plain: kernel launch");
+  }
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,29 @@
+// Internal launchers of the HIP kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hidft.h"
+
+namespace hidft {
+
+// Twiddles exp(-i pi num[i] / 2^den[i]) in FP64, rounded to complex64.
+hipError_t launch_twiddle_gen(const uint64_t* d_num, const uint8_t* d_den, float2* d_tw,
+                              uint64_t n, hipStream_t stream);
+
+// Fused batched transform of size 2^s (s <= HIDFT_MAX_LOG2_K_DEVICE).
+hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out,
+                        int64_t ld_out, uint64_t batch, const float2* tw, const uint16_t* src,
+                        float scale, hipStream_t stream);
+
+// LDS bytes of one fused block for size 2^s.
+size_t fused_lds_bytes(uint32_t s);
+
+// Plain method: one signal, one block, one radix-2 stage per barrier.
+hipError_t launch_plain(uint32_t s, const float2* in, float2* out, const float2* tw,
+                        const uint16_t* src, float scale, hipStream_t stream);
+
+}  // namespace hidft

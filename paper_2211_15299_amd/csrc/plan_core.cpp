@@ -1,0 +1,149 @@
+// Host planner: pivots, homogeneity, sample set, plan orders, twiddle schedule.
+//
+// Pivots (Sec. VI, Remark 2): level e is a pivot iff 2^e exactly divides
+// j1 - j2 for some pair in J.  Sorting J by the bit-reversed value lists the
+// leaves of the congruence tree (an LSB-first binary trie) in depth-first
+// order; every branching node is then the lowest common ancestor of two
+// neighbours in that list, and the LCA level of two leaves is the lowest bit
+// in which they differ (Remark 1).  So the pivot set is the set of lowest
+// differing bits of neighbours: O(k log k) instead of the O(k^2) pair scan.
+#include "plan_core.h"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace hidft {
+
+uint64_t bit_reverse(uint64_t x, unsigned nbits) {
+  if (nbits == 0) return 0;
+  x = ((x >> 1) & 0x5555555555555555ULL) | ((x & 0x5555555555555555ULL) << 1);
+  x = ((x >> 2) & 0x3333333333333333ULL) | ((x & 0x3333333333333333ULL) << 2);
+  x = ((x >> 4) & 0x0F0F0F0F0F0F0F0FULL) | ((x & 0x0F0F0F0F0F0F0F0FULL) << 4);
+  x = ((x >> 8) & 0x00FF00FF00FF00FFULL) | ((x & 0x00FF00FF00FF00FFULL) << 8);
+  x = ((x >> 16) & 0x0000FFFF0000FFFFULL) | ((x & 0x0000FFFF0000FFFFULL) << 16);
+  x = (x >> 32) | (x << 32);
+  return x >> (64 - nbits);
+}
+
+static void set_err(std::string* err, const char* fmt, unsigned long long a = 0,
+                    unsigned long long b = 0) {
+  if (!err) return;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, fmt, a, b);
+  *err = buf;
+}
+
+hidft_status analyze_core(uint32_t M, const uint64_t* J, uint64_t k,
+                          uint64_t* pivot_mask, std::string* err) {
+  if (M > HIDFT_MAX_LOG2_N) {
+    set_err(err, "log2_n = %llu exceeds 63", M);
+    return HIDFT_ERR_INVALID_ARGUMENT;
+  }
+  if (k == 0 || J == nullptr) {
+    set_err(err, "J must be a non-null array of k >= 1 indices");
+    return HIDFT_ERR_INVALID_ARGUMENT;
+  }
+  if (M < 64 && k > (1ULL << M)) {
+    set_err(err, "k = %llu exceeds N = 2^%llu", k, M);
+    return HIDFT_ERR_INVALID_ARGUMENT;
+  }
+  const uint64_t limit_mask = (M == 64) ? ~0ULL : ((1ULL << M) - 1);
+  std::vector<uint64_t> key(k);
+  for (uint64_t t = 0; t < k; ++t) {
+    if (J[t] & ~limit_mask) {
+      set_err(err, "J[%llu] = %llu is outside [0, N)", t, J[t]);
+      return HIDFT_ERR_INDEX_OUT_OF_RANGE;
+    }
+    key[t] = bit_reverse(J[t], 64);
+  }
+  std::sort(key.begin(), key.end());
+  uint64_t mask = 0;
+  for (uint64_t t = 1; t < k; ++t) {
+    if (key[t] == key[t - 1]) {
+      set_err(err, "index %llu appears more than once in J", bit_reverse(key[t], 64));
+      return HIDFT_ERR_DUPLICATE_INDEX;
+    }
+    const uint64_t d = bit_reverse(key[t], 64) ^ bit_reverse(key[t - 1], 64);
+    mask |= d & (~d + 1);  // lowest differing bit = 2^{nu2(j_a - j_b)}
+  }
+  *pivot_mask = mask;
+  return HIDFT_OK;
+}
+
+hidft_status build_plan_core(uint32_t M, const uint64_t* J, uint64_t k,
+                             uint32_t max_log2_k, PlanCore* pc, std::string* err) {
+  uint64_t mask = 0;
+  hidft_status st = analyze_core(M, J, k, &mask, err);
+  if (st != HIDFT_OK) return st;
+  if ((k & (k - 1)) != 0) {
+    set_err(err, "k = %llu is not a power of two, so J cannot be homogeneous", k);
+    return HIDFT_ERR_SIZE_NOT_POW2;
+  }
+  const uint32_t s = static_cast<uint32_t>(__builtin_ctzll(k));
+  const uint32_t npiv = static_cast<uint32_t>(__builtin_popcountll(mask));
+  if (npiv != s) {
+    set_err(err, "J has %llu pivots but log2 k = %llu: not homogeneous", npiv, s);
+    return HIDFT_ERR_NOT_HOMOGENEOUS;
+  }
+  if (s > max_log2_k) {
+    set_err(err, "k = 2^%llu exceeds the supported 2^%llu", s, max_log2_k);
+    return HIDFT_ERR_UNSUPPORTED;
+  }
+  pc->M = M;
+  pc->s = s;
+  pc->k = k;
+  pc->J.assign(J, J + k);
+  pc->pivots.clear();
+  for (uint32_t e = 0; e < 64; ++e)
+    if ((mask >> e) & 1) pc->pivots.push_back(e);
+  const std::vector<uint32_t>& r = pc->pivots;
+
+  // Frequency order of Corollary 2: q(j) = sum_u bit_{r_u}(j) 2^{u-1}.
+  // Homogeneity makes it a bijection J -> [0, k): every pivot level splits
+  // every node, so two elements first differ at some pivot level.
+  pc->freq_pos.assign(k, 0);
+  std::vector<uint64_t> j_of_q(k, 0);
+  std::vector<uint8_t> hit(k, 0);
+  for (uint64_t t = 0; t < k; ++t) {
+    uint32_t q = 0;
+    for (uint32_t u = 0; u < s; ++u) q |= static_cast<uint32_t>((J[t] >> r[u]) & 1) << u;
+    if (hit[q]) {
+      set_err(err, "internal: frequency order is not a bijection (q = %llu)", q);
+      return HIDFT_ERR_NOT_HOMOGENEOUS;
+    }
+    hit[q] = 1;
+    pc->freq_pos[t] = q;
+    j_of_q[q] = J[t];
+  }
+
+  // Sample set (Sec. VII): position p of the recursion order holds
+  // i_p = sum_u bit_{u-1}(p) 2^{M-1-r_u}.  The weights decrease with u, so the
+  // ascending order of I_r is the bit-reversed recursion order.
+  pc->samples.assign(k, 0);
+  for (uint64_t a = 0; a < k; ++a) {
+    const uint64_t p = bit_reverse(a, s);
+    uint64_t i = 0;
+    for (uint32_t u = 0; u < s; ++u)
+      if ((p >> u) & 1) i |= 1ULL << (M - 1 - r[u]);
+    pc->samples[a] = i;
+  }
+
+  // Twiddles of Lemma 3, stage u (pivot r_u) and node q_lo < 2^{u-1}: the
+  // factor exp(-2 pi i j / 2^{r_u + 1}) at the left descendant j (bit r_u of
+  // j is 0), i.e. exp(-i pi m / 2^{r_u}) with m = j mod 2^{r_u}.
+  const uint64_t ntw = k - 1;
+  pc->tw_num.assign(ntw, 0);
+  pc->tw_log2den.assign(ntw, 0);
+  for (uint32_t u = 1; u <= s; ++u) {
+    const uint32_t ru = r[u - 1];
+    const uint64_t mmask = (1ULL << ru) - 1;
+    const uint64_t off = (1ULL << (u - 1)) - 1;
+    for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
+      pc->tw_num[off + q_lo] = j_of_q[q_lo] & mmask;
+      pc->tw_log2den[off + q_lo] = static_cast<uint8_t>(ru);
+    }
+  }
+  return HIDFT_OK;
+}
+
+}  // namespace hidft

@@ -1,0 +1,222 @@
+"""ctypes binding of the C ABI in include/hidft.h (argument marshalling only).
+
+Every step of the transform runs in the HIP library; this module only converts
+Python values and torch tensors into the pointers, sizes and stream handles
+the C functions take.  There is no fallback: if the library is missing, every
+call raises.
+
+torch is imported (when installed) before the library is loaded, so the
+library binds to the same HIP runtime instance as torch's tensors and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+try:  # load torch's HIP runtime first: one runtime instance per process
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - the planner still works without torch
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhidft.so")
+
+HIDFT_PLAN_HOST_ONLY = 0x1
+MAX_LOG2_K_DEVICE = 14
+
+STATUS_NAMES = {
+    0: "HIDFT_OK", 1: "HIDFT_ERR_INVALID_ARGUMENT", 2: "HIDFT_ERR_INDEX_OUT_OF_RANGE",
+    3: "HIDFT_ERR_DUPLICATE_INDEX", 4: "HIDFT_ERR_SIZE_NOT_POW2",
+    5: "HIDFT_ERR_NOT_HOMOGENEOUS", 6: "HIDFT_ERR_OUT_OF_MEMORY", 7: "HIDFT_ERR_DEVICE",
+    8: "HIDFT_ERR_UNSUPPORTED",
+}
+
+# (name, restype, argtypes) of every function declared in include/hidft.h
+_u32, _u64, _i32, _i64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
+_vp, _pp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)
+SIGNATURES = [
+    ("hidft_analyze", ctypes.c_int, [_u32, ctypes.POINTER(_u64), _u64, ctypes.POINTER(_u32),
+                                     ctypes.POINTER(_u32), ctypes.POINTER(_i32)]),
+    ("hidft_plan_create", ctypes.c_int, [_u32, ctypes.POINTER(_u64), _u64, _u32, _vp, _pp]),
+    ("hidft_plan_destroy", ctypes.c_int, [_vp]),
+    ("hidft_plan_get_info", ctypes.c_int, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u64),
+                                           ctypes.POINTER(_u32)]),
+    ("hidft_plan_get_pivots", ctypes.c_int, [_vp, ctypes.POINTER(_u32)]),
+    ("hidft_plan_get_samples", ctypes.c_int, [_vp, ctypes.POINTER(_u64)]),
+    ("hidft_plan_get_schedule", ctypes.c_int, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u64),
+                                               ctypes.POINTER(ctypes.c_uint8)]),
+    ("hidft_plan_get_twiddles", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float)]),
+    ("hidft_plan_device_bytes", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    ("hidft_execute", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
+    ("hidft_execute_plain", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
+    ("hidft_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("hidft_last_error", ctypes.c_char_p, []),
+]
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+class HiDFTError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.status_name = STATUS_NAMES.get(status, f"status {status}")
+        super().__init__(f"{self.status_name}: {message}")
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded C library; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library {LIB_PATH} is missing: build it with "
+                "`python -m paper_2211_15299_amd.build` (there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        msg = lib().hidft_last_error().decode(errors="replace")
+        raise HiDFTError(status, msg)
+
+
+def _u64_array(J: Sequence[int]) -> np.ndarray:
+    arr = np.ascontiguousarray(np.asarray(J, dtype=np.uint64))
+    return arr
+
+
+def _ptr(arr: np.ndarray, ctype):
+    return arr.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def analyze(log2_n: int, J: Sequence[int]):
+    """(pivots, is_homogeneous) of J subset of Z_{2^log2_n} (hidft_analyze)."""
+    arr = _u64_array(J)
+    piv = np.zeros(64, dtype=np.uint32)
+    n = _u32(0)
+    hom = _i32(0)
+    _check(lib().hidft_analyze(log2_n, _ptr(arr, _u64), len(arr), _ptr(piv, _u32),
+                               ctypes.byref(n), ctypes.byref(hom)))
+    return [int(x) for x in piv[: n.value]], bool(hom.value)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        if torch is not None and torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Plan:
+    """Owning wrapper of a hidft_plan (hidft_plan_create / hidft_plan_destroy)."""
+
+    def __init__(self, log2_n: int, J: Sequence[int], host_only: bool = False, stream=None):
+        arr = _u64_array(J)
+        self._h = ctypes.c_void_p(None)
+        flags = HIDFT_PLAN_HOST_ONLY if host_only else 0
+        st = None if host_only else _stream_handle(stream)
+        _check(lib().hidft_plan_create(log2_n, _ptr(arr, _u64), len(arr), flags, st,
+                                       ctypes.byref(self._h)))
+        self.host_only = host_only
+        M, k, s = _u32(0), _u64(0), _u32(0)
+        _check(lib().hidft_plan_get_info(self._h, ctypes.byref(M), ctypes.byref(k),
+                                         ctypes.byref(s)))
+        self.log2_n, self.k, self.s = M.value, k.value, s.value
+
+    # -- lifecycle
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().hidft_plan_destroy(self._h))
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h.value:
+            raise HiDFTError(1, "plan has been destroyed")
+        return self._h
+
+    # -- getters
+    def pivots(self) -> list:
+        out = np.zeros(max(self.s, 1), dtype=np.uint32)
+        _check(lib().hidft_plan_get_pivots(self.handle, _ptr(out, _u32)))
+        return [int(x) for x in out[: self.s]]
+
+    def samples(self) -> np.ndarray:
+        out = np.zeros(self.k, dtype=np.uint64)
+        _check(lib().hidft_plan_get_samples(self.handle, _ptr(out, _u64)))
+        return out
+
+    def schedule(self):
+        """(freq_pos[k], tw_num[k-1], tw_log2den[k-1]) as numpy arrays."""
+        fp = np.zeros(self.k, dtype=np.uint32)
+        n = max(self.k - 1, 1)
+        num = np.zeros(n, dtype=np.uint64)
+        den = np.zeros(n, dtype=np.uint8)
+        _check(lib().hidft_plan_get_schedule(self.handle, _ptr(fp, _u32), _ptr(num, _u64),
+                                             _ptr(den, ctypes.c_uint8)))
+        return fp, num[: self.k - 1], den[: self.k - 1]
+
+    def twiddles(self) -> np.ndarray:
+        out = np.zeros(2 * max(self.k - 1, 1), dtype=np.float32)
+        _check(lib().hidft_plan_get_twiddles(self.handle, _ptr(out, ctypes.c_float)))
+        return (out[0::2] + 1j * out[1::2]).astype(np.complex64)[: self.k - 1]
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t(0)
+        _check(lib().hidft_plan_device_bytes(self.handle, ctypes.byref(b)))
+        return b.value
+
+    # -- execution on raw device pointers
+    def execute_ptr(self, d_in: int, ld_in: int, d_out: int, ld_out: int, batch: int,
+                    stream=None, plain: bool = False) -> None:
+        fn = lib().hidft_execute_plain if plain else lib().hidft_execute
+        _check(fn(self.handle, d_in, ld_in, d_out, ld_out, batch, _stream_handle(stream)))
+
+    # -- execution on torch tensors
+    def execute(self, samples, out=None, stream=None, plain: bool = False):
+        """Coefficients (batch, k) complex64 of samples (batch, k) or (k,) on the device."""
+        if torch is None:
+            raise RuntimeError("torch is required for tensor execution")
+        squeeze = samples.dim() == 1
+        x = samples.unsqueeze(0) if squeeze else samples
+        if x.dtype != torch.complex64 or not x.is_cuda:
+            raise HiDFTError(1, "samples must be a complex64 CUDA/HIP tensor")
+        if x.dim() != 2 or x.shape[1] != self.k or x.stride(1) != 1:
+            raise HiDFTError(1, f"samples must be (batch, {self.k}) with unit inner stride")
+        if out is None:
+            out = torch.empty((x.shape[0], self.k), dtype=torch.complex64, device=x.device)
+        y = out.unsqueeze(0) if out.dim() == 1 else out
+        if y.dtype != torch.complex64 or y.dim() != 2 or y.shape != x.shape or y.stride(1) != 1:
+            raise HiDFTError(1, "out must match samples' shape, complex64, unit inner stride")
+        self.execute_ptr(x.data_ptr(), x.stride(0) if x.shape[0] > 1 else self.k,
+                         y.data_ptr(), y.stride(0) if y.shape[0] > 1 else self.k,
+                         x.shape[0], stream, plain)
+        return out
+
+
+def status_string(status: int) -> str:
+    return lib().hidft_status_string(status).decode()
