@@ -67,9 +67,20 @@ __device__ __forceinline__ void butterfly(float2& P, float2& Q, const float2 w) 
   P.y = xi;
 }
 
-// LDS padding: one spare slot after every 16 complex values keeps the strided
-// accesses of the radix-16 groups spread over the 64 LDS banks.
-__device__ __forceinline__ int lds_pad(int a) { return a + (a >> 4); }
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// orders global memory, which makes every wave wait for its outstanding
+// global stores (the previous signal's outputs) before the barrier; the
+// exchanges here only need the LDS writes of the block to be visible.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// LDS padding: one spare slot after every 2^RHO complex values keeps the
+// strided accesses of the radix-2^RHO groups spread over the 64 LDS banks.
+template <int RHO>
+__device__ __forceinline__ int lds_pad(int a) { return a + (a >> RHO); }
 
 template <int S>
 struct FusedShape {
@@ -81,20 +92,125 @@ struct FusedShape {
   static constexpr int THREADS = T * SPB;
   static constexpr int G = S == 0 ? 0 : (S + RHO - 1) / RHO;     // radix groups
   static constexpr int G1 = S == 0 ? 0 : S - (G - 1) * RHO;      // stages in group 1
-  static constexpr int PADK = K + (K >> 4);                      // LDS slots per signal
+  static constexpr int PADK = K + (K >> RHO);                    // LDS slots per signal
   static constexpr size_t LDS_BYTES = (size_t)SPB * PADK * sizeof(float2);
+  // Launch strategy.  PERSIST: a grid of (blocks resident per CU) x (CUs)
+  // walks over the batch, the twiddles of groups 2..G and the gather
+  // positions of a thread are loaded once per block and kept in registers,
+  // and the next signals' samples are loaded while the current ones are
+  // transformed.  Above 2^12 points a block needs 512 or 1024 threads
+  // (128 registers per thread at most) and at least 68 KB of LDS, the
+  // per-thread state would spill, and those sizes run one group of signals
+  // per block.
+  static constexpr bool PERSIST = S <= 12;
+  static constexpr bool PREFETCH = PERSIST;
+  static constexpr bool TW_REGS = PERSIST && (G - 1) * (R - 1) <= 30;
+  static constexpr int NTW = G > 1 ? (TW_REGS ? (G - 1) * (R - 1) : 1) : 1;
 };
 
 // ---------------------------------------------------------------------------
-// Fused batched transform: one signal per T threads, SPB signals per block.
-//
-// Group 1 (stages 1..G1, the top G1 bits of a) runs straight from the global
-// load: thread tau holds a = tau + c*T for c < R, so each load instruction of
-// a wavefront reads 64 consecutive samples.  Every later group takes RHO = 4
-// stages (radix 16) on the next lower four bits, through LDS.  After the last
-// group the block gathers the outputs in the caller's order of J, scales by
-// N/k and stores them coalesced.
+// Fused batched transform.  Each block owns SPB signal slots of T threads.
+// Per signal:
+//   * group 1 (stages 1..G1, the top G1 bits of a) runs straight from the
+//     global load: thread tau holds a = tau + c*T for c < R, so each load
+//     instruction of a wavefront reads 64 consecutive samples;
+//   * every later group takes RHO = 4 stages (radix 16) on the next lower four
+//     bits of a, through LDS; each thread reads and writes back its own 16
+//     slots, so one barrier per group suffices;
+//   * the block gathers the outputs in the caller's order of J (src table),
+//     scales by N/k and stores them coalesced.
+// Up to 2^12 points the grid is persistent (blocks resident per CU times the
+// CU count) and walks over the batch; the twiddles and gather positions a
+// thread needs are then loaded once per block and kept in registers, and
+// (PREFETCH) the next signals' samples are loaded while the current ones are
+// transformed.  Larger sizes run one group of signals per block.
 // ---------------------------------------------------------------------------
+template <int S>
+struct ThreadState {  // per-thread constants of the persistent form
+  using Sh = FusedShape<S>;
+  float2 w1[(1 << Sh::G1) > 1 ? (1 << Sh::G1) - 1 : 1];  // block-uniform (scalar registers)
+  float2 wg[Sh::NTW];
+  uint32_t srcpk[(Sh::R + 1) / 2];  // two 16-bit gather positions per register
+};
+
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float2 make_uniform(float2 w) {
+  w.x = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, w.x)));
+  w.y = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, w.y)));
+  return w;
+}
+
+// Transform the samples in v (this thread's R values of signal slot `slot`)
+// and store the coefficients of signal `sig` (skipped when sig >= batch).
+// HOISTED: twiddles and gather positions come from `ts`, else from memory.
+template <int S, bool HOISTED>
+__device__ __forceinline__ void transform_signal(float2 (&v)[FusedShape<S>::R], float2* L,
+                                                 int tau, uint64_t sig, uint64_t batch,
+                                                 float2* __restrict__ out, int64_t ld_out,
+                                                 const float2* __restrict__ tw,
+                                                 const uint16_t* __restrict__ src, float scale,
+                                                 const ThreadState<S>& ts) {
+  using Sh = FusedShape<S>;
+  constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, G = Sh::G, G1 = Sh::G1;
+
+  // Group 1: stage u pairs bit RHO-u of c; the twiddle index is the top u-1
+  // bits of c, the same for every thread.
+#pragma unroll
+  for (int u = 1; u <= G1; ++u) {
+    const int bit = RHO - u;
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      if (c & (1 << bit)) continue;
+      const int idx = (1 << (u - 1)) - 1 + (c >> (bit + 1));
+      butterfly(v[c], v[c | (1 << bit)], HOISTED ? ts.w1[idx] : tw[idx]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c) L[lds_pad<RHO>(c * T + tau)] = v[c];
+
+  // Groups 2..G on bits [lo, lo + RHO), lo = S - G1 - (g-1)*RHO.
+#pragma unroll
+  for (int g = 2; g <= G; ++g) {
+    const int lo = S - G1 - (g - 1) * RHO;
+    const int a_lo = tau & ((1 << lo) - 1);
+    const int a_hi = tau >> lo;
+    const int base = a_lo + (a_hi << (lo + RHO));
+    lds_barrier();
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(base + (c << lo))];
+#pragma unroll
+    for (int t = 0; t < RHO; ++t) {
+      const int u = S - lo - RHO + 1 + t;
+      const int bit = RHO - 1 - t;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (c & (1 << bit)) continue;
+        const int h = c >> (RHO - t);
+        float2 w;
+        if constexpr (HOISTED && Sh::TW_REGS)
+          w = ts.wg[(g - 2) * (R - 1) + (1 << t) - 1 + h];
+        else
+          w = tw[((1 << (u - 1)) - 1) + (a_hi << t) + h];
+        butterfly(v[c], v[c | (1 << bit)], w);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) L[lds_pad<RHO>(base + (c << lo))] = v[c];
+  }
+  lds_barrier();
+
+  if (sig < batch) {
+    float2* orow = out + sig * (uint64_t)ld_out;
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const int p = HOISTED ? (int)((ts.srcpk[c >> 1] >> (16 * (c & 1))) & 0xffffu)
+                            : (int)src[c * T + tau];
+      const float2 x = L[lds_pad<RHO>(p)];
+      orow[c * T + tau] = make_float2(x.x * scale, x.y * scale);
+    }
+  }
+}
+
 template <int S>
 __global__ void __launch_bounds__(FusedShape<S>::THREADS)
 hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ out,
@@ -107,68 +223,65 @@ hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
   const int tid = threadIdx.x;
   const int slot = tid / T;
   const int tau = tid - slot * T;
-  const uint64_t sig = (uint64_t)blockIdx.x * SPB + slot;
-  const bool valid = sig < batch;
   float2* L = lds + slot * Sh::PADK;
+  const uint64_t n_groups = (batch + SPB - 1) / SPB;
 
-  float2 v[R];
-  {
-    const float2* row = in + (valid ? sig : 0) * (uint64_t)ld_in;
+  float2 vn[R];
+  auto load = [&](uint64_t grp) {
+    const uint64_t sig = grp * SPB + slot;
+    if (sig < batch) {
+      const float2* row = in + sig * (uint64_t)ld_in;
 #pragma unroll
-    for (int c = 0; c < R; ++c) v[c] = valid ? row[c * T + tau] : make_float2(0.f, 0.f);
-  }
-
-  // Group 1: stage u pairs bit RHO-u of c; the twiddle index is the top u-1
-  // bits of c, the same for every thread (scalar loads).
+      for (int c = 0; c < R; ++c) vn[c] = row[c * T + tau];
+    } else {
 #pragma unroll
-  for (int u = 1; u <= G1; ++u) {
-    const int bit = RHO - u;
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      if (c & (1 << bit)) continue;
-      const float2 w = tw[(1 << (u - 1)) - 1 + (c >> (bit + 1))];
-      butterfly(v[c], v[c | (1 << bit)], w);
+      for (int c = 0; c < R; ++c) vn[c] = make_float2(0.f, 0.f);
     }
-  }
-#pragma unroll
-  for (int c = 0; c < R; ++c) L[lds_pad(c * T + tau)] = v[c];
+  };
 
-  // Groups 2..G: bits [lo, lo + RHO) with lo = S - G1 - (g-1)*RHO.  Each
-  // thread reads and writes back the same 16 slots, so one barrier per group
-  // suffices.
+  if constexpr (!Sh::PERSIST) {
+    const uint64_t grp = blockIdx.x;
+    load(grp);
+    ThreadState<S> unused;
+    transform_signal<S, false>(vn, L, tau, grp * SPB + slot, batch, out, ld_out, tw, src, scale,
+                               unused);
+  } else {
+    ThreadState<S> ts;
 #pragma unroll
-  for (int g = 2; g <= G; ++g) {
-    const int lo = S - G1 - (g - 1) * RHO;
-    const int a_lo = tau & ((1 << lo) - 1);
-    const int a_hi = tau >> lo;
-    const int base = a_lo + (a_hi << (lo + RHO));
-    __syncthreads();
+    for (int i = 0; i < (1 << G1) - 1; ++i) ts.w1[i] = make_uniform(tw[i]);
+    if constexpr (Sh::TW_REGS) {
 #pragma unroll
-    for (int c = 0; c < R; ++c) v[c] = L[lds_pad(base + (c << lo))];
+      for (int g = 2; g <= G; ++g) {
+        const int lo = S - G1 - (g - 1) * RHO;
+        const int a_hi = tau >> lo;
 #pragma unroll
-    for (int t = 0; t < RHO; ++t) {
-      const int u = S - lo - RHO + 1 + t;
-      const int bit = RHO - 1 - t;
-      const float2* twu = tw + ((1 << (u - 1)) - 1) + (a_hi << t);
+        for (int t = 0; t < RHO; ++t) {
+          const int u = S - lo - RHO + 1 + t;
 #pragma unroll
-      for (int c = 0; c < R; ++c) {
-        if (c & (1 << bit)) continue;
-        const float2 w = twu[c >> (RHO - t)];
-        butterfly(v[c], v[c | (1 << bit)], w);
+          for (int h = 0; h < (1 << t); ++h)
+            ts.wg[(g - 2) * (R - 1) + (1 << t) - 1 + h] =
+                tw[((1 << (u - 1)) - 1) + (a_hi << t) + h];
+        }
       }
     }
 #pragma unroll
-    for (int c = 0; c < R; ++c) L[lds_pad(base + (c << lo))] = v[c];
-  }
-  __syncthreads();
+    for (int c = 0; c < R; c += 2) {
+      const uint32_t lo16 = src[c * T + tau];
+      const uint32_t hi16 = c + 1 < R ? src[(c + 1) * T + tau] : 0u;
+      ts.srcpk[c >> 1] = lo16 | (hi16 << 16);
+    }
 
-  if (valid) {
-    float2* orow = out + sig * (uint64_t)ld_out;
+    uint64_t grp = blockIdx.x;
+    if (Sh::PREFETCH && grp < n_groups) load(grp);
+    for (; grp < n_groups; grp += gridDim.x) {
+      float2 v[R];
+      if constexpr (!Sh::PREFETCH) load(grp);
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-      const int t = c * T + tau;
-      const float2 x = L[lds_pad((int)src[t])];
-      orow[t] = make_float2(x.x * scale, x.y * scale);
+      for (int c = 0; c < R; ++c) v[c] = vn[c];
+      if (Sh::PREFETCH && grp + gridDim.x < n_groups) load(grp + gridDim.x);
+      transform_signal<S, true>(v, L, tau, grp * SPB + slot, batch, out, ld_out, tw, src, scale,
+                                ts);
+      lds_barrier();  // the next group overwrites these LDS slots
     }
   }
 }
@@ -188,18 +301,29 @@ static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, i
                                  uint64_t batch, const float2* tw, const uint16_t* src,
                                  float scale, hipStream_t stream) {
   using Sh = FusedShape<S>;
-  static bool attr_set = false;  // benign race: every thread sets the same value
-  if (!attr_set) {
+  // Per-kernel launch shape, computed once: blocks that fit on a CU at the
+  // same time (registers and LDS) times the CU count.
+  static int max_grid = 0;  // benign race: every thread computes the same value
+  if (max_grid == 0) {
     hipError_t e = hipFuncSetAttribute((const void*)hidft_fused_kernel<S>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)Sh::LDS_BYTES);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+             &per_cu, (const void*)hidft_fused_kernel<S>, Sh::THREADS, Sh::LDS_BYTES)) !=
+        hipSuccess)
+      return e;
+    max_grid = Sh::PERSIST ? (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1) : 0x7fffffff;
   }
-  const uint64_t blocks = (batch + Sh::SPB - 1) / Sh::SPB;
-  if (blocks > 0x7fffffffULL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(hidft_fused_kernel<S>, dim3((unsigned)blocks), dim3(Sh::THREADS),
-                     Sh::LDS_BYTES, stream, in, ld_in, out, ld_out, batch, tw, src, scale);
+  const uint64_t groups = (batch + Sh::SPB - 1) / Sh::SPB;
+  const unsigned grid = (unsigned)(groups < (uint64_t)max_grid ? groups : (uint64_t)max_grid);
+  hipLaunchKernelGGL(hidft_fused_kernel<S>, dim3(grid), dim3(Sh::THREADS), Sh::LDS_BYTES,
+                     stream, in, ld_in, out, ld_out, batch, tw, src, scale);
   return hipGetLastError();
 }
 
