@@ -16,6 +16,8 @@ timing; its own cost is reported separately as plan_create_ms.
 Prints one JSON line.  Modes for profiling runs:
   --mode copy      a plain device copy of the same byte count (counter scale)
   --mode execute   warmup + steps of the fused kernel only (no baselines)
+  --mode grouped   the uneven configuration: 2048 instances with their own J
+                   (N = 2^12..2^24, k = 2^6..2^14) in one grouped launch
 """
 from __future__ import annotations
 
@@ -45,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", choices=["full", "execute", "copy"], default="full")
+    ap.add_argument("--mode", choices=["full", "execute", "copy", "grouped"], default="full")
     ap.add_argument("--cpu-sample", type=int, default=512,
                     help="signals in the bounded oracle sample (cpu_baseline)")
     ap.add_argument("--plain-signals", type=int, default=4096,
@@ -116,6 +118,11 @@ def main():
         ms = e0.elapsed_time(e1) / args.steps
         print(json.dumps({"mode": "copy", "sets": args.sets, "bytes_per_launch": bytes_per_launch,
                           "ms_per_copy": ms, "GBps": bytes_per_launch / ms / 1e6}), flush=True)
+        return
+
+    if args.mode == "grouped":
+        del xs, ys, x, y
+        print(json.dumps(grouped_bench(args, native, torch, stream)), flush=True)
         return
 
     torch.cuda.synchronize()
@@ -220,6 +227,55 @@ def main():
         result["cpu_baseline"] = cpu_baseline(M, J, f_host, y, args.cpu_sample)
     print(json.dumps(result), flush=True)
     plan.close()
+
+
+def grouped_instances(n):
+    """(M, J) of the uneven configuration: N log-uniform over 2^12..2^24 and
+    k log-uniform over 2^6..2^14 with k <= N/4, each with its own seeded J."""
+    from workloads import homogeneous_support, rng_for
+    out = []
+    for i in range(n):
+        rng = rng_for(3, i)
+        M = int(rng.integers(12, 25))
+        s = int(rng.integers(6, min(14, M - 2) + 1))
+        out.append((M, homogeneous_support(M, s, rng).J.tolist()))
+    return out
+
+
+def grouped_bench(args, native, torch, stream):
+    """Throughput of one grouped launch over 2048 uneven instances."""
+    from workloads import rng_for, sample_values
+    insts = grouped_instances(2048)
+    rng = rng_for(3, 99999)
+    plans = [native.Plan(M, J, stream=stream) for M, J in insts]
+    ks = np.array([p.k for p in plans], dtype=np.int64)
+    total = int(ks.sum())
+    offs = np.concatenate([[0], np.cumsum(ks)])
+    host = np.concatenate([sample_values(M, len(J), 1, rng)[0] for M, J in insts])
+    sets = max(args.sets, 1)
+    xs = [torch.from_numpy(host).cuda()] + []
+    xs += [xs[0].clone() for _ in range(sets - 1)]
+    ys = [torch.empty_like(xs[0]) for _ in range(sets)]
+    groups = []
+    for j in range(sets):
+        items = [(p, xs[j].data_ptr() + 8 * int(offs[i]), p.k, ys[j].data_ptr() + 8 * int(offs[i]),
+                  p.k, 1) for i, p in enumerate(plans)]
+        groups.append(native.Group(items, stream=stream))
+    for i in range(args.warmup):
+        groups[i % sets].execute(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(args.steps):
+        groups[i % sets].execute(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    byts = total * 16
+    return {"mode": "grouped", "instances": len(plans), "points": total, "packs": groups[0].n_packs,
+            "k_min": int(ks.min()), "k_max": int(ks.max()), "ms_per_launch": ms,
+            "transforms_per_s": len(plans) / (ms * 1e-3), "GBps": byts / (ms * 1e-3) / 1e9,
+            "frac_of_8TBps": byts / (ms * 1e-3) / 8e12, "sets": sets}
 
 
 def cpu_baseline(M, J, f_host, y_dev, n_sample):

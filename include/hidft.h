@@ -193,6 +193,46 @@ hidft_status hidft_execute_plain(hidft_plan plan, const void* d_samples, int64_t
                                  void* d_coefs, int64_t ld_out, uint64_t batch,
                                  void* stream);
 
+/*
+ * Grouped execution: an uneven batch (instances with different N, J and k) in
+ * one persistent kernel launch.
+ *
+ * One work item is a plan and `batch` rows of samples and coefficients, with
+ * the same contract as hidft_execute for that plan.  hidft_group_create
+ * validates every item as hidft_execute would, expands the items into
+ * instances (one per row), orders them by size, packs instances of equal size
+ * into units of up to 2^14 points, and uploads the resulting descriptor list
+ * (pointers to rows, plan tables and scales) to the current device, waiting
+ * for the upload on `stream`.  hidft_group_execute then runs the whole group as
+ * one kernel launch on `stream`, asynchronously; it may be called any number
+ * of times (the samples may change between calls; the pointers may not).
+ *
+ * Ownership: the group copies the items; the plans and buffers they name must
+ * outlive every execution of the group.  Outputs of different instances must
+ * not overlap (not checked); an instance may run in place.
+ * Errors: as hidft_execute for each item (the message names the item), plus
+ * INVALID_ARGUMENT for n_items == 0 or more than 2^31 instances, and
+ * OUT_OF_MEMORY / DEVICE for the descriptor upload.
+ */
+typedef struct hidft_work {
+  hidft_plan plan;          /* device plan (not HOST_ONLY) */
+  const void* d_samples;    /* batch rows of ld_in >= k complex64 samples */
+  int64_t ld_in;
+  void* d_coefs;            /* batch rows of ld_out >= k complex64 coefficients */
+  int64_t ld_out;
+  uint64_t batch;           /* rows; 0 contributes nothing */
+} hidft_work;
+
+typedef struct hidft_group_s* hidft_group;
+
+hidft_status hidft_group_create(const hidft_work* items, uint64_t n_items, void* stream,
+                                hidft_group* out);
+hidft_status hidft_group_execute(hidft_group group, void* stream);
+hidft_status hidft_group_destroy(hidft_group group);  /* NULL accepted; synchronise first */
+/* Instances, packs and device bytes of the descriptor list (outputs may be NULL). */
+hidft_status hidft_group_get_info(hidft_group group, uint64_t* n_instances,
+                                  uint64_t* n_packs, size_t* device_bytes);
+
 /* Human-readable name of a status code (static storage). */
 const char* hidft_status_string(hidft_status status);
 

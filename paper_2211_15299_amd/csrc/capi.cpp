@@ -13,6 +13,9 @@
 #include "launch.h"
 #include "plan_core.h"
 
+#include <algorithm>
+#include <vector>
+
 struct hidft_plan_s {
   hidft::PlanCore core;
   bool host_only = true;
@@ -21,6 +24,15 @@ struct hidft_plan_s {
   uint16_t* d_src = nullptr;   // k output gather positions
   size_t device_bytes = 0;
   float scale = 1.0f;          // N / k
+};
+
+struct hidft_group_s {
+  int device = -1;
+  uint64_t n_instances = 0;
+  uint32_t n_packs = 0;
+  hidft::GroupPack* d_packs = nullptr;
+  hidft::GroupSlot* d_slots = nullptr;
+  size_t device_bytes = 0;
 };
 
 namespace {
@@ -327,6 +339,127 @@ hidft_status hidft_execute_plain(hidft_plan plan, const void* d_samples, int64_t
                                        plan->scale, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "hidft_execute_plain: kernel launch");
   }
+  return ok();
+}
+
+hidft_status hidft_group_create(const hidft_work* items, uint64_t n_items, void* stream,
+                                hidft_group* out) {
+  if (!out) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_create: out is NULL");
+  *out = nullptr;
+  if (!items || n_items == 0)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_create: no work items");
+  hidft_group g = nullptr;
+  try {
+    // Validate every item and count instances per size.
+    uint64_t n_inst = 0;
+    int device = -1;
+    std::vector<uint64_t> per_size(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
+    for (uint64_t i = 0; i < n_items; ++i) {
+      const hidft_work& w = items[i];
+      char fn[64];
+      std::snprintf(fn, sizeof fn, "hidft_group_create: item %llu", (unsigned long long)i);
+      hidft_status st = check_exec(w.plan, w.d_samples, w.ld_in, w.d_coefs, w.ld_out, w.batch, fn);
+      if (st != HIDFT_OK) return st;
+      if (w.batch == 0) continue;
+      device = w.plan->device;
+      per_size[w.plan->core.s] += w.batch;
+      n_inst += w.batch;
+    }
+    if (n_inst == 0) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_create: no rows");
+    if (n_inst > (1ULL << 31))
+      return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_create: more than 2^31 instances");
+    // Slots ordered by size, largest first; packs of up to slots_per_pack(s).
+    std::vector<uint64_t> next(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
+    uint64_t off = 0;
+    for (int s = HIDFT_MAX_LOG2_K_DEVICE; s >= 0; --s) {
+      next[s] = off;
+      off += per_size[s];
+    }
+    std::vector<hidft::GroupSlot> slots(n_inst);
+    for (uint64_t i = 0; i < n_items; ++i) {
+      const hidft_work& w = items[i];
+      const hidft_plan p = w.plan;
+      for (uint64_t b = 0; b < w.batch; ++b) {
+        hidft::GroupSlot& d = slots[next[p->core.s]++];
+        d.in = static_cast<const float2*>(w.d_samples) + b * (uint64_t)w.ld_in;
+        d.out = static_cast<float2*>(w.d_coefs) + b * (uint64_t)w.ld_out;
+        d.tw = p->d_tw;
+        d.src = p->d_src;
+        d.scale = p->scale;
+      }
+    }
+    std::vector<hidft::GroupPack> packs;
+    off = 0;
+    for (int s = HIDFT_MAX_LOG2_K_DEVICE; s >= 0; --s) {
+      const uint64_t per = (uint64_t)hidft::grouped_slots_per_pack((uint32_t)s);
+      for (uint64_t first = 0; first < per_size[s]; first += per) {
+        hidft::GroupPack pk;
+        pk.first_slot = (uint32_t)(off + first);
+        pk.log2_k = (uint16_t)s;
+        pk.n_slots = (uint16_t)std::min<uint64_t>(per, per_size[s] - first);
+        packs.push_back(pk);
+      }
+      off += per_size[s];
+    }
+    g = new hidft_group_s;
+    g->device = device;
+    g->n_instances = n_inst;
+    g->n_packs = (uint32_t)packs.size();
+    const size_t pack_bytes = packs.size() * sizeof(hidft::GroupPack);
+    const size_t slot_bytes = slots.size() * sizeof(hidft::GroupSlot);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = hipMalloc(&g->d_packs, pack_bytes)) != hipSuccess ||
+        (e = hipMalloc(&g->d_slots, slot_bytes)) != hipSuccess ||
+        (e = hipMemcpyAsync(g->d_packs, packs.data(), pack_bytes, hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(g->d_slots, slots.data(), slot_bytes, hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+      hidft_status r = hip_fail(e, "hidft_group_create: descriptor upload");
+      hidft_group_destroy(g);
+      return r;
+    }
+    g->device_bytes = pack_bytes + slot_bytes;
+    *out = g;
+    return ok();
+  } catch (const std::bad_alloc&) {
+    if (g) hidft_group_destroy(g);
+    return fail(HIDFT_ERR_OUT_OF_MEMORY, "hidft_group_create: host allocation failed");
+  } catch (...) {
+    if (g) hidft_group_destroy(g);
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_create: unexpected exception");
+  }
+}
+
+hidft_status hidft_group_execute(hidft_group g, void* stream) {
+  if (!g) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_execute: group is NULL");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hidft_group_execute");
+  if (dev != g->device)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT,
+                "hidft_group_execute: current device %d, group lives on device %d", dev,
+                g->device);
+  e = hidft::launch_grouped(g->d_packs, g->n_packs, g->d_slots, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hidft_group_execute: kernel launch");
+  return ok();
+}
+
+hidft_status hidft_group_destroy(hidft_group g) {
+  if (!g) return ok();
+  if (g->d_packs) (void)hipFree(g->d_packs);
+  if (g->d_slots) (void)hipFree(g->d_slots);
+  delete g;
+  return ok();
+}
+
+hidft_status hidft_group_get_info(hidft_group g, uint64_t* n_instances, uint64_t* n_packs,
+                                  size_t* device_bytes) {
+  if (!g) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_get_info: group is NULL");
+  if (n_instances) *n_instances = g->n_instances;
+  if (n_packs) *n_packs = g->n_packs;
+  if (device_bytes) *device_bytes = g->device_bytes;
   return ok();
 }
 

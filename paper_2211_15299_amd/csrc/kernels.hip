@@ -366,6 +366,115 @@ size_t fused_lds_bytes(uint32_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Grouped transform: an uneven batch (each instance with its own plan and
+// size) in one persistent launch.
+//
+// The host packs instances of equal size 2^S into packs of up to 2^14 points:
+// 1024 / T(S) instances per pack, T(S) = 2^{max(S-4, 0)} threads each, so a
+// pack always fills the block's 1024 threads and at most its 136 KB of LDS.
+// Each block walks the pack list with a grid stride; for a pack it loads its
+// slot's descriptor (rows, twiddle and gather tables, scale), then runs the
+// same per-signal transform as the fused kernel, specialised on S by a switch
+// that is uniform over the block.
+// ---------------------------------------------------------------------------
+constexpr int GROUPED_THREADS = 1024;
+constexpr int GROUPED_LDS_SLOTS = (1 << HIDFT_MAX_LOG2_K_DEVICE) + ((1 << HIDFT_MAX_LOG2_K_DEVICE) >> 4);
+
+// A descriptor field that is the same in every lane of the wavefront (a slot
+// spans whole wavefronts when T >= 64), moved to scalar registers.
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p) {
+  const uint64_t x = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return reinterpret_cast<P*>(((uint64_t)hi << 32) | lo);
+}
+
+// One pack of 2^S-point instances.  Not inlined: each size gets a register
+// allocation of its own instead of one shared by the whole switch.
+template <int S>
+__device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restrict__ slots,
+                                                       int n_slots, float2* lds) {
+  using Sh = FusedShape<S>;
+  constexpr int R = Sh::R, T = Sh::T;
+  const int tid = threadIdx.x;
+  const int slot = tid / T;
+  const int tau = tid - slot * T;
+  const bool valid = slot < n_slots;
+  // Threads of empty slots (a partial pack) run the transform on zeros with
+  // slot 0's tables (every pack has at least one slot) and store nothing.
+  GroupSlot d = slots[valid ? slot : 0];
+  if constexpr (T >= 64) {
+    d.in = uniform_ptr(d.in);
+    d.out = uniform_ptr(d.out);
+    d.tw = uniform_ptr(d.tw);
+    d.src = uniform_ptr(d.src);
+    d.scale = __builtin_bit_cast(
+        float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, d.scale)));
+  }
+  float2 v[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) v[c] = valid ? d.in[c * T + tau] : make_float2(0.f, 0.f);
+  ThreadState<S> unused;
+  transform_signal<S, false>(v, lds + slot * Sh::PADK, tau, 0, valid ? 1 : 0, d.out, 0, d.tw,
+                             d.src, d.scale, unused);
+}
+
+__global__ void __launch_bounds__(GROUPED_THREADS)
+hidft_grouped_kernel(const GroupPack* __restrict__ packs, uint32_t n_packs,
+                     const GroupSlot* __restrict__ slots) {
+  extern __shared__ float2 lds[];
+  for (uint32_t p = blockIdx.x; p < n_packs; p += gridDim.x) {
+    const GroupPack pk = packs[p];
+    const GroupSlot* sl = slots + pk.first_slot;
+    switch (pk.log2_k) {
+#define HIDFT_CASE(S) \
+  case S:             \
+    grouped_pack<S>(sl, (int)pk.n_slots, lds); \
+    break;
+      HIDFT_CASE(0) HIDFT_CASE(1) HIDFT_CASE(2) HIDFT_CASE(3) HIDFT_CASE(4) HIDFT_CASE(5)
+      HIDFT_CASE(6) HIDFT_CASE(7) HIDFT_CASE(8) HIDFT_CASE(9) HIDFT_CASE(10) HIDFT_CASE(11)
+      HIDFT_CASE(12) HIDFT_CASE(13) HIDFT_CASE(14)
+#undef HIDFT_CASE
+      default:
+        break;
+    }
+    lds_barrier();  // the next pack overwrites the LDS
+  }
+}
+
+int grouped_slots_per_pack(uint32_t s) {
+  return GROUPED_THREADS >> (s > 4 ? s - 4 : 0);
+}
+
+hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,
+                          hipStream_t stream) {
+  if (n_packs == 0) return hipSuccess;
+  static int max_grid = 0;  // benign race: every thread computes the same value
+  const size_t lds_bytes = (size_t)GROUPED_LDS_SLOTS * sizeof(float2);
+  if (max_grid == 0) {
+    hipError_t e = hipFuncSetAttribute((const void*)hidft_grouped_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+             &per_cu, (const void*)hidft_grouped_kernel, GROUPED_THREADS, lds_bytes)) !=
+        hipSuccess)
+      return e;
+    max_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  }
+  const unsigned grid = n_packs < (uint32_t)max_grid ? n_packs : (unsigned)max_grid;
+  hipLaunchKernelGGL(hidft_grouped_kernel, dim3(grid), dim3(GROUPED_THREADS), lds_bytes, stream,
+                     d_packs, n_packs, d_slots);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Plain per-signal method (baseline): one block per launch, one signal.
 //
 // Samples are permuted into the recursion order p = bitrev_S(a) in LDS, then

@@ -22,6 +22,30 @@ hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out
 // LDS bytes of one fused block for size 2^s.
 size_t fused_lds_bytes(uint32_t s);
 
+// One instance of a grouped launch: a row of samples, its row of coefficients
+// and the plan tables of its size.
+struct GroupSlot {
+  const float2* in;
+  float2* out;
+  const float2* tw;
+  const uint16_t* src;
+  float scale;
+};
+
+// A pack: n_slots consecutive slots of the same size 2^log2_k.
+struct GroupPack {
+  uint32_t first_slot;
+  uint16_t log2_k;
+  uint16_t n_slots;
+};
+
+// Instances of size 2^s that one pack holds (the block's 1024 threads).
+int grouped_slots_per_pack(uint32_t s);
+
+// Grouped persistent launch over n_packs packs.
+hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,
+                          hipStream_t stream);
+
 // Plain method: one signal, one block, one radix-2 stage per barrier.
 hipError_t launch_plain(uint32_t s, const float2* in, float2* out, const float2* tw,
                         const uint16_t* src, float scale, hipStream_t stream);

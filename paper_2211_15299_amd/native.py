@@ -52,6 +52,11 @@ SIGNATURES = [
     ("hidft_plan_device_bytes", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("hidft_execute", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
     ("hidft_execute_plain", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
+    ("hidft_group_create", ctypes.c_int, [_vp, _u64, _vp, _pp]),
+    ("hidft_group_execute", ctypes.c_int, [_vp, _vp]),
+    ("hidft_group_destroy", ctypes.c_int, [_vp]),
+    ("hidft_group_get_info", ctypes.c_int, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
+                                            ctypes.POINTER(ctypes.c_size_t)]),
     ("hidft_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("hidft_last_error", ctypes.c_char_p, []),
 ]
@@ -216,6 +221,48 @@ class Plan:
                          y.data_ptr(), y.stride(0) if y.shape[0] > 1 else self.k,
                          x.shape[0], stream, plain)
         return out
+
+
+class Work(ctypes.Structure):
+    """hidft_work: a plan and `batch` rows of samples / coefficients."""
+    _fields_ = [("plan", ctypes.c_void_p), ("d_samples", ctypes.c_void_p), ("ld_in", ctypes.c_int64),
+                ("d_coefs", ctypes.c_void_p), ("ld_out", ctypes.c_int64), ("batch", ctypes.c_uint64)]
+
+
+class Group:
+    """Owning wrapper of a hidft_group (one persistent launch over uneven work).
+
+    items: sequence of (plan, d_samples, ld_in, d_coefs, ld_out, batch); the
+    plans and buffers must outlive the group.
+    """
+
+    def __init__(self, items, stream=None):
+        arr = (Work * len(items))()
+        self._keep = []
+        for i, (plan, d_in, ld_in, d_out, ld_out, batch) in enumerate(items):
+            arr[i] = Work(plan.handle.value, d_in, ld_in, d_out, ld_out, batch)
+            self._keep.append(plan)
+        self._h = ctypes.c_void_p(None)
+        _check(lib().hidft_group_create(ctypes.cast(arr, ctypes.c_void_p), len(items),
+                                        _stream_handle(stream), ctypes.byref(self._h)))
+        n_inst, n_packs, nbytes = _u64(0), _u64(0), ctypes.c_size_t(0)
+        _check(lib().hidft_group_get_info(self._h, ctypes.byref(n_inst), ctypes.byref(n_packs),
+                                          ctypes.byref(nbytes)))
+        self.n_instances, self.n_packs, self.device_bytes = n_inst.value, n_packs.value, nbytes.value
+
+    def execute(self, stream=None) -> None:
+        _check(lib().hidft_group_execute(self._h, _stream_handle(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().hidft_group_destroy(self._h))
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def status_string(status: int) -> str:

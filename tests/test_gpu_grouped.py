@@ -1,0 +1,158 @@
+"""Uneven batch in one persistent launch (grouped execution) against the oracle.
+
+2048 instances, each with its own seeded homogeneous J: N log-uniform over
+2^12..2^24, k log-uniform over 2^6..2^14 with k <= N/4, plus composite
+supports (direct sums of homogeneous blocks on disjoint bit ranges).  Every
+instance is checked bit-for-bit against the single-plan fused path (itself
+checked against the oracle), every instance on the energy identity, and a
+sample of instances against the FP64 oracle directly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import composite_support, homogeneous_support, rng_for, sample_values
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+native = pytest.importorskip("paper_2211_15299_amd.native")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _instances(n, seed_cfg=3, composites=64):
+    """(M, J list, levels) for n seeded instances of the uneven configuration."""
+    out = []
+    for i in range(n):
+        rng = rng_for(seed_cfg, i)
+        if i < composites:
+            M = int(rng.integers(14, 25))
+            # two or three blocks on disjoint bit ranges
+            widths = [int(rng.integers(3, 7)) for _ in range(3)]
+            blocks, lo = [], 0
+            for w in widths:
+                if lo + w > M:
+                    break
+                blocks.append((lo, w, int(rng.integers(1, w))))
+                lo += w + int(rng.integers(0, 3))
+            sup = composite_support(M, blocks, rng)
+        else:
+            M = int(rng.integers(12, 25))
+            s = int(rng.integers(6, min(14, M - 2) + 1))
+            sup = homogeneous_support(M, s, rng)
+        out.append((M, sup.J.tolist(), sup.levels))
+    return out
+
+
+def _energy_rel(c, f, M, k):
+    N = float(1 << M)
+    return abs(np.sum(np.abs(c) ** 2) - (N * N / k) * np.sum(np.abs(f) ** 2)) / ((N * N / k) * np.sum(np.abs(f) ** 2))
+
+
+def test_config3_uneven_batch_one_launch():
+    insts = _instances(2048)
+    plans, xs, ys = [], [], []
+    rng = rng_for(3, 99999)
+    for M, J, _ in insts:
+        plans.append(native.Plan(M, J))
+        k = len(J)
+        xs.append(torch.from_numpy(sample_values(M, k, 1, rng)[0]).cuda())
+        ys.append(torch.full((k,), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda"))
+    ks = np.array([p.k for p in plans])
+    _say(f"C3: {len(plans)} instances, k from {ks.min()} to {ks.max()}, {ks.sum()} points")
+    items = [(p, x.data_ptr(), p.k, y.data_ptr(), p.k, 1) for p, x, y in zip(plans, xs, ys)]
+    grp = native.Group(items)
+    assert grp.n_instances == 2048
+    grp.execute()
+    torch.cuda.synchronize()
+    _say(f"C3: {grp.n_packs} packs executed")
+    got = [y.cpu().numpy().astype(np.complex128) for y in ys]
+    # fused single-plan path on each instance: bit-identical
+    n_diff = 0
+    for p, x, g in zip(plans, xs, got):
+        z = p.execute(x)
+        torch.cuda.synchronize()
+        n_diff += not np.array_equal(z[0].cpu().numpy().astype(np.complex128), g)
+    assert n_diff == 0, f"{n_diff} instances differ from the fused path"
+    # energy identity on every instance
+    worst = max(_energy_rel(g, x.cpu().numpy(), M, len(J)) for g, x, (M, J, _) in zip(got, xs, insts))
+    assert worst <= 2e-5, worst
+    # oracle on a sample: every instance with k <= 64 plus 40 random others
+    pick = [i for i in range(len(insts)) if ks[i] <= 64]
+    pick += rng_for(3, 12345).choice(len(insts), 40, replace=False).tolist()
+    errs = []
+    for i in sorted(set(pick)):
+        M, J, levels = insts[i]
+        f = xs[i].cpu().numpy().astype(np.complex128)
+        I = plans[i].samples().tolist()
+        assert I == sorted(oracle.sample_pattern_recursive(M, levels))
+        if len(J) <= 2048:
+            want = oracle.adjoint_coefficients(M, J, I, f)
+            errs.append(float(oracle.rel_l2(got[i], want)))
+        else:
+            sel = rng_for(3, 777 + i).choice(len(J), 64, replace=False)
+            want = oracle.adjoint_coefficients(M, [J[t] for t in sel], I, f, k=len(J))
+            errs.append(float(oracle.rel_l2(got[i][sel], want)))
+    _say(f"C3: oracle on {len(errs)} instances, rel-L2 max {max(errs):.3e}")
+    assert max(errs) <= 1e-5
+    grp.close()
+    for p in plans:
+        p.close()
+
+
+def test_grouped_mixed_batches_and_ragged_packs():
+    """Items with several rows, strides, every size 2^0..2^14, partial packs."""
+    rng = rng_for(3, 5000)
+    items, refs, bufs = [], [], []
+    for s in range(0, 15):
+        M = max(s, 1) + int(rng.integers(0, 6))
+        sup = homogeneous_support(M, s, rng)
+        plan = native.Plan(M, sup.J.tolist())
+        k = plan.k
+        batch = int(rng.integers(1, 5))
+        f = sample_values(M, k, batch, rng)
+        ld_in, ld_out = k + int(rng.integers(0, 3)), k + int(rng.integers(0, 3))
+        x = torch.zeros((batch, ld_in), dtype=torch.complex64, device="cuda")
+        x[:, :k] = torch.from_numpy(f).cuda()
+        y = torch.zeros((batch, ld_out), dtype=torch.complex64, device="cuda")
+        items.append((plan, x.data_ptr(), ld_in, y.data_ptr(), ld_out, batch))
+        bufs.append((plan, x, y, f, M, sup.J.tolist(), k))
+    grp = native.Group(items)
+    grp.execute()
+    grp.execute()  # twice: same result
+    torch.cuda.synchronize()
+    for plan, x, y, f, M, J, k in bufs:
+        got = y[:, :k].cpu().numpy().astype(np.complex128)
+        rows = range(f.shape[0]) if k <= 2048 else [0]
+        want = oracle.adjoint_coefficients(M, J, plan.samples().tolist(), f[list(rows)])
+        err = np.max(oracle.rel_l2(got[list(rows)], want))
+        assert err <= 1e-5, (k, err)
+    grp.close()
+
+
+def test_group_argument_errors():
+    M, s = 12, 6
+    sup = homogeneous_support(M, s, rng_for(3, 6000))
+    plan = native.Plan(M, sup.J.tolist())
+    x = torch.zeros((2, plan.k), dtype=torch.complex64, device="cuda")
+    with pytest.raises(native.HiDFTError):
+        native.Group([(plan, x.data_ptr() + 4, plan.k, x.data_ptr(), plan.k, 1)])
+    with pytest.raises(native.HiDFTError):
+        native.Group([(plan, x.data_ptr(), plan.k - 1, x.data_ptr(), plan.k, 1)])
+    with pytest.raises(native.HiDFTError):
+        native.Group([])
