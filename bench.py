@@ -18,6 +18,9 @@ Prints one JSON line.  Modes for profiling runs:
   --mode execute   warmup + steps of the fused kernel only (no baselines)
   --mode grouped   the uneven configuration: 2048 instances with their own J
                    (N = 2^12..2^24, k = 2^6..2^14) in one grouped launch
+  --mode serve     the serving configuration: Poisson arrivals (20k/s) of
+                   requests over 256 supports reused Zipf(1.1), through the
+                   continuous-batching server
 """
 from __future__ import annotations
 
@@ -47,7 +50,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", choices=["full", "execute", "copy", "grouped"], default="full")
+    ap.add_argument("--mode", choices=["full", "execute", "copy", "grouped", "serve"],
+                    default="full")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="duration of the Poisson arrival process (serving)")
+    ap.add_argument("--serve-rate", type=float, default=20000.0, help="arrivals per second")
     ap.add_argument("--cpu-sample", type=int, default=512,
                     help="signals in the bounded oracle sample (cpu_baseline)")
     ap.add_argument("--plain-signals", type=int, default=4096,
@@ -123,6 +130,10 @@ def main():
     if args.mode == "grouped":
         del xs, ys, x, y
         print(json.dumps(grouped_bench(args, native, torch, stream)), flush=True)
+        return
+    if args.mode == "serve":
+        del xs, ys, x, y
+        print(json.dumps(serve_bench(args, native)), flush=True)
         return
 
     torch.cuda.synchronize()
@@ -276,6 +287,98 @@ def grouped_bench(args, native, torch, stream):
             "k_min": int(ks.min()), "k_max": int(ks.max()), "ms_per_launch": ms,
             "transforms_per_s": len(plans) / (ms * 1e-3), "GBps": byts / (ms * 1e-3) / 1e9,
             "frac_of_8TBps": byts / (ms * 1e-3) / 8e12, "sets": sets}
+
+
+def serve_bench(args, native, seconds=None):
+    """Poisson arrivals through the continuous-batching server.
+
+    256 supports (M uniform on 10..22, s uniform on 6..13 with s <= M-2),
+    chosen per request by a Zipf(1.1) law over their rank; one sample vector
+    per support.  Plans are made resident before the clock starts (their
+    creation is timed separately).  Latency is from submit to the
+    coefficients being in the request's host buffer.
+    """
+    from workloads import homogeneous_support, rng_for, sample_values
+    seconds = args.serve_seconds if seconds is None else seconds
+    sups, vecs = [], []
+    for i in range(256):
+        rng = rng_for(5, i)
+        M = int(rng.integers(10, 23))
+        s = int(rng.integers(6, min(13, M - 2) + 1))
+        sup = homogeneous_support(M, s, rng)
+        sups.append((M, np.ascontiguousarray(sup.J, dtype=np.uint64)))
+        vecs.append(sample_values(M, len(sup.J), 1, rng)[0])
+    rng = rng_for(5, 10 ** 6)
+    n = int(args.serve_rate * seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=n))
+    ranks = np.arange(1, 257, dtype=np.float64)
+    pz = ranks ** -1.1
+    which = rng.choice(256, size=n, p=pz / pz.sum())
+    pool_n = 8192
+    pool = np.zeros((pool_n, 1 << 13), dtype=np.complex64)
+    busy = np.zeros(pool_n, dtype=bool)
+    slot_of = {}
+    srv = native.Server(data_bytes=512 << 20, plan_bytes=256 << 20, slots=4, max_batch=1024)
+    t0 = time.perf_counter()
+    for (M, J), f in zip(sups, vecs):  # make every plan resident
+        srv.submit(M, J, f, pool[0, :len(J)])
+        srv.drain()
+    srv.poll()
+    plan_warm_s = time.perf_counter() - t0
+    lat, bsz = [], []
+
+    def collect(wait_us=0):
+        res = srv.poll(wait_us)
+        for r in res:
+            busy[slot_of.pop(int(r["id"]))] = False
+        lat.extend(res["latency_us"].tolist())
+        bsz.extend(res["batch_size"].tolist())
+        return len(res)
+
+    st0 = srv.stats()
+    t_start = time.perf_counter()
+    late = 0
+    for i in range(n):
+        target = t_start + arrivals[i]
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            if target - now > 200e-6:
+                collect()
+        late = max(late, now - target)
+        slot = i % pool_n
+        while busy[slot]:
+            collect(100)
+        M, J = sups[which[i]]
+        rid = srv.submit(M, J, vecs[which[i]], pool[slot, :len(J)])
+        busy[slot] = True
+        slot_of[rid] = slot
+        if (i & 63) == 0:
+            collect()
+    srv.drain()
+    t_end = time.perf_counter()
+    while collect():
+        pass
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    wall = t_end - t_start
+    ks = np.array([len(sups[w][1]) for w in which], dtype=np.int64)
+    return {"mode": "serve", "requests": n, "rate_per_s": args.serve_rate, "seconds": seconds,
+            "completed": int(st["completed"] - st0["completed"]),
+            "rejected": int(st["rejected"] - st0["rejected"]),
+            "transforms_per_s": n / wall, "wall_s": wall,
+            "data_GBps": float(ks.sum()) * 16 / wall / 1e9,
+            "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean()), "max": float(lat.max())},
+            "batch_size_mean": float(np.mean(bsz)), "batches": int(st["batches"] - st0["batches"]),
+            "max_inflight_batches": int(st["max_inflight_batches"]),
+            "plan_hits": int(st["plan_hits"] - st0["plan_hits"]),
+            "plan_misses": int(st["plan_misses"] - st0["plan_misses"]),
+            "plans_resident": int(st["plans_resident"]),
+            "plan_warmup_s": plan_warm_s, "max_submit_lag_us": late * 1e6,
+            "supports": 256, "zipf": 1.1}
 
 
 def cpu_baseline(M, J, f_host, y_dev, n_sample):

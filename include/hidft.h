@@ -233,6 +233,70 @@ hidft_status hidft_group_destroy(hidft_group group);  /* NULL accepted; synchron
 hidft_status hidft_group_get_info(hidft_group group, uint64_t* n_instances,
                                   uint64_t* n_packs, size_t* device_bytes);
 
+/*
+ * Request server (continuous batching).
+ *
+ * Clients submit requests -- (N = 2^log2_n, J, k host samples on I_r in
+ * ascending order) -- from any thread and later collect results.  The server:
+ *   * keeps the plans of recently seen supports resident on the device (a plan
+ *     cache keyed by (N, J), least recently used plans that no request holds
+ *     are destroyed once the cache exceeds cfg.plan_bytes);
+ *   * admits requests, in arrival order, into batches: a batch slot takes
+ *     requests while its device region (cfg.data_bytes / cfg.slots, half for
+ *     samples, half for coefficients) and cfg.max_batch allow;
+ *   * runs each batch as one grouped launch (see hidft_group_create) on the
+ *     slot's own stream, with upload and download through pinned staging
+ *     buffers, so up to cfg.slots batches are in flight at once and requests
+ *     that arrive while others are on the device fill the next free slot.
+ * A request's coefficients do not depend on which other requests share its
+ * batch (each instance runs the same per-signal code).
+ *
+ * hidft_server_submit: validates and plans the support synchronously (errors
+ * as hidft_plan_create; OUT_OF_MEMORY if k samples and k coefficients exceed a
+ * slot's region), then queues the request and returns its id.  host_samples
+ * (k complex64) must stay readable and host_coefs (k complex64) writable until
+ * the request's result has been polled.  Thread-safe.
+ * hidft_server_poll: moves up to `cap` finished results into `out`, waiting
+ * up to wait_us microseconds for the first one; *n receives the count.
+ * hidft_server_drain: waits until every submitted request has finished.
+ * hidft_server_destroy: finishes queued work, then frees everything (plans
+ * included).
+ */
+typedef struct hidft_server_s* hidft_server;
+
+typedef struct hidft_server_config {
+  size_t data_bytes;   /* device bytes for request samples and coefficients, all slots */
+  size_t plan_bytes;   /* device bytes of resident plans before LRU eviction */
+  uint32_t slots;      /* batches in flight, each with its own stream */
+  uint32_t max_batch;  /* requests per batch */
+} hidft_server_config;
+
+typedef struct hidft_server_result {
+  uint64_t id;
+  int32_t status;      /* hidft_status of the request */
+  uint32_t batch_size; /* requests in the batch that served it */
+  double latency_us;   /* from submit to the coefficients being in host_coefs */
+} hidft_server_result;
+
+typedef struct hidft_server_stats {
+  uint64_t submitted, completed, rejected, batches;
+  uint64_t plan_hits, plan_misses, plan_evictions;
+  uint64_t max_inflight_batches;
+  uint64_t plans_resident;
+  size_t plan_bytes_resident;
+  size_t slot_bytes;
+} hidft_server_stats;
+
+hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* out);
+hidft_status hidft_server_submit(hidft_server server, uint32_t log2_n, const uint64_t* J,
+                                 uint64_t k, const void* host_samples, void* host_coefs,
+                                 uint64_t* id);
+hidft_status hidft_server_poll(hidft_server server, hidft_server_result* out, uint32_t cap,
+                               uint32_t* n, int32_t wait_us);
+hidft_status hidft_server_drain(hidft_server server);
+hidft_status hidft_server_get_stats(hidft_server server, hidft_server_stats* stats);
+hidft_status hidft_server_destroy(hidft_server server);
+
 /* Human-readable name of a status code (static storage). */
 const char* hidft_status_string(hidft_status status);
 

@@ -18,7 +18,7 @@ LIB_NAME = "libhidft.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 ARCH = "gfx950"
 
-SOURCES = ["plan_core.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["plan_core.cpp", "capi.cpp", "server.cpp", "kernels.hip"]
 
 # Packed FP32 instructions are disabled for all device code; -O3 otherwise
 # emits them from ordinary float code.
@@ -50,7 +50,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB_PATH + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

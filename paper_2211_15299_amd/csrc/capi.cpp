@@ -9,22 +9,11 @@
 #include <new>
 #include <string>
 
-#include "hidft.h"
-#include "launch.h"
-#include "plan_core.h"
-
 #include <algorithm>
 #include <vector>
 
-struct hidft_plan_s {
-  hidft::PlanCore core;
-  bool host_only = true;
-  int device = -1;
-  float2* d_tw = nullptr;      // k-1 twiddles in a-order (at least one slot)
-  uint16_t* d_src = nullptr;   // k output gather positions
-  size_t device_bytes = 0;
-  float scale = 1.0f;          // N / k
-};
+#include "hidft.h"
+#include "internal.h"
 
 struct hidft_group_s {
   int device = -1;
@@ -158,6 +147,44 @@ hidft_status check_exec(hidft_plan plan, const void* d_in, int64_t ld_in, const 
 }
 
 }  // namespace
+
+namespace hidft {
+
+hidft_status set_error(hidft_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+hidft_status hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
+                    std::vector<GroupPack>* packs, std::vector<GroupSlot>* slots) {
+  std::vector<uint64_t> per_size(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
+  for (const auto& x : inst) per_size[x.first]++;
+  std::vector<uint64_t> next(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
+  uint64_t off = 0;
+  for (int s = HIDFT_MAX_LOG2_K_DEVICE; s >= 0; --s) {
+    next[s] = off;
+    off += per_size[s];
+  }
+  slots->resize(inst.size());
+  for (const auto& x : inst) (*slots)[next[x.first]++] = x.second;
+  packs->clear();
+  off = 0;
+  for (int s = HIDFT_MAX_LOG2_K_DEVICE; s >= 0; --s) {
+    const uint64_t per = (uint64_t)grouped_slots_per_pack((uint32_t)s);
+    for (uint64_t first = 0; first < per_size[s]; first += per) {
+      GroupPack pk;
+      pk.first_slot = (uint32_t)(off + first);
+      pk.log2_k = (uint16_t)s;
+      pk.n_slots = (uint16_t)std::min<uint64_t>(per, per_size[s] - first);
+      packs->push_back(pk);
+    }
+    off += per_size[s];
+  }
+}
+
+}  // namespace hidft
 
 extern "C" {
 
@@ -350,10 +377,9 @@ hidft_status hidft_group_create(const hidft_work* items, uint64_t n_items, void*
     return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_create: no work items");
   hidft_group g = nullptr;
   try {
-    // Validate every item and count instances per size.
+    // Validate every item and count instances.
     uint64_t n_inst = 0;
     int device = -1;
-    std::vector<uint64_t> per_size(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
     for (uint64_t i = 0; i < n_items; ++i) {
       const hidft_work& w = items[i];
       char fn[64];
@@ -362,45 +388,29 @@ hidft_status hidft_group_create(const hidft_work* items, uint64_t n_items, void*
       if (st != HIDFT_OK) return st;
       if (w.batch == 0) continue;
       device = w.plan->device;
-      per_size[w.plan->core.s] += w.batch;
       n_inst += w.batch;
     }
     if (n_inst == 0) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_create: no rows");
     if (n_inst > (1ULL << 31))
       return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_create: more than 2^31 instances");
-    // Slots ordered by size, largest first; packs of up to slots_per_pack(s).
-    std::vector<uint64_t> next(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
-    uint64_t off = 0;
-    for (int s = HIDFT_MAX_LOG2_K_DEVICE; s >= 0; --s) {
-      next[s] = off;
-      off += per_size[s];
-    }
-    std::vector<hidft::GroupSlot> slots(n_inst);
+    std::vector<std::pair<uint32_t, hidft::GroupSlot>> inst;
+    inst.reserve(n_inst);
     for (uint64_t i = 0; i < n_items; ++i) {
       const hidft_work& w = items[i];
       const hidft_plan p = w.plan;
       for (uint64_t b = 0; b < w.batch; ++b) {
-        hidft::GroupSlot& d = slots[next[p->core.s]++];
+        hidft::GroupSlot d;
         d.in = static_cast<const float2*>(w.d_samples) + b * (uint64_t)w.ld_in;
         d.out = static_cast<float2*>(w.d_coefs) + b * (uint64_t)w.ld_out;
         d.tw = p->d_tw;
         d.src = p->d_src;
         d.scale = p->scale;
+        inst.emplace_back(p->core.s, d);
       }
     }
     std::vector<hidft::GroupPack> packs;
-    off = 0;
-    for (int s = HIDFT_MAX_LOG2_K_DEVICE; s >= 0; --s) {
-      const uint64_t per = (uint64_t)hidft::grouped_slots_per_pack((uint32_t)s);
-      for (uint64_t first = 0; first < per_size[s]; first += per) {
-        hidft::GroupPack pk;
-        pk.first_slot = (uint32_t)(off + first);
-        pk.log2_k = (uint16_t)s;
-        pk.n_slots = (uint16_t)std::min<uint64_t>(per, per_size[s] - first);
-        packs.push_back(pk);
-      }
-      off += per_size[s];
-    }
+    std::vector<hidft::GroupSlot> slots;
+    hidft::pack_instances(inst, &packs, &slots);
     g = new hidft_group_s;
     g->device = device;
     g->n_instances = n_inst;

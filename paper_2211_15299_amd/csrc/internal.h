@@ -1,0 +1,37 @@
+// Library-internal types shared by the C ABI, the group API and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hidft.h"
+#include "launch.h"
+#include "plan_core.h"
+
+struct hidft_plan_s {
+  hidft::PlanCore core;
+  bool host_only = true;
+  int device = -1;
+  float2* d_tw = nullptr;      // k-1 twiddles in a-order (at least one slot)
+  uint16_t* d_src = nullptr;   // k output gather positions
+  size_t device_bytes = 0;
+  float scale = 1.0f;          // N / k
+};
+
+namespace hidft {
+
+// Records a failure message for hidft_last_error() and returns `st`.
+hidft_status set_error(hidft_status st, const std::string& msg);
+
+// HIP error -> status (OUT_OF_MEMORY or DEVICE) with a message.
+hidft_status hip_error(hipError_t e, const char* what);
+
+// Orders instances (size log2, descriptor) by size, largest first, and packs
+// instances of equal size into packs of at most grouped_slots_per_pack(s).
+void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
+                    std::vector<GroupPack>* packs, std::vector<GroupSlot>* slots);
+
+}  // namespace hidft

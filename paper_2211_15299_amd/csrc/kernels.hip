@@ -94,17 +94,18 @@ struct FusedShape {
   static constexpr int G1 = S == 0 ? 0 : S - (G - 1) * RHO;      // stages in group 1
   static constexpr int PADK = K + (K >> RHO);                    // LDS slots per signal
   static constexpr size_t LDS_BYTES = (size_t)SPB * PADK * sizeof(float2);
-  // Launch strategy.  PERSIST: a grid of (blocks resident per CU) x (CUs)
-  // walks over the batch, the twiddles of groups 2..G and the gather
-  // positions of a thread are loaded once per block and kept in registers,
-  // and the next signals' samples are loaded while the current ones are
-  // transformed.  Above 2^12 points a block needs 512 or 1024 threads
-  // (128 registers per thread at most) and at least 68 KB of LDS, the
-  // per-thread state would spill, and those sizes run one group of signals
-  // per block.
-  static constexpr bool PERSIST = S <= 12;
-  static constexpr bool PREFETCH = PERSIST;
-  static constexpr bool TW_REGS = PERSIST && (G - 1) * (R - 1) <= 30;
+  // Launch strategy.  Up to 2^12 points the grid is persistent (blocks
+  // resident per CU times the CU count) and walks over the batch: the
+  // twiddles of groups 2..G and the gather positions a thread needs are
+  // loaded once per block and kept in registers, and the next signals'
+  // samples are loaded while the current ones are transformed.  Above (BIG:
+  // 512 or 1024 threads and 68 or 136 KB of LDS per signal, at most 128
+  // registers per thread) the tables do not fit in registers; read per signal,
+  // their loads would queue behind a prefetch (vector memory counters retire
+  // in order), so BIG sizes run one signal per block with a grid of one block
+  // per signal.
+  static constexpr bool BIG = S >= 13;
+  static constexpr bool TW_REGS = !BIG && (G - 1) * (R - 1) <= 30;
   static constexpr int NTW = G > 1 ? (TW_REGS ? (G - 1) * (R - 1) : 1) : 1;
 };
 
@@ -140,16 +141,72 @@ __device__ __forceinline__ float2 make_uniform(float2 w) {
   return w;
 }
 
-// Transform the samples in v (this thread's R values of signal slot `slot`)
-// and store the coefficients of signal `sig` (skipped when sig >= batch).
-// HOISTED: twiddles and gather positions come from `ts`, else from memory.
-template <int S, bool HOISTED>
+// Access to one signal's tables and output row.  Every index is split into a
+// part that is the same for all lanes (compile-time constants here) and a
+// per-lane part.
+//   FlatMem: plain global pointers.
+//   BufMem:  buffer descriptors (base and size in scalar registers) with the
+//            lane part as the one vector offset and the uniform part as a
+//            scalar offset; it needs the signal to span whole wavefronts
+//            (T >= 64) so that its descriptors are uniform.
+struct FlatMem {
+  const float2* tw;
+  const uint16_t* src;
+  float2* out;
+  __device__ __forceinline__ float2 tw_at(int uni, int lane) const { return tw[uni + lane]; }
+  __device__ __forceinline__ int src_at(int uni, int lane) const { return src[uni + lane]; }
+  __device__ __forceinline__ void put(int uni, int lane, float2 x) const { out[uni + lane] = x; }
+};
+
+constexpr int BUFFER_DWORD3 = 0x00020000;  // raw buffer, 32-bit data format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                          BUFFER_DWORD3);
+}
+
+struct BufMem {
+  __amdgpu_buffer_rsrc_t tw, src, out;
+  __device__ __forceinline__ float2 tw_at(int uni, int lane) const {
+    return __builtin_bit_cast(float2,
+                              __builtin_amdgcn_raw_buffer_load_b64(tw, lane * 8, uni * 8, 0));
+  }
+  __device__ __forceinline__ int src_at(int uni, int lane) const {
+    return (int)__builtin_amdgcn_raw_buffer_load_b16(src, lane * 2, uni * 2, 0);
+  }
+  __device__ __forceinline__ void put(int uni, int lane, float2 x) const {
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, x), out, lane * 8,
+        uni * 8, 0);
+  }
+};
+
+// R samples of one signal row for thread tau: v[c] = row[c*T + tau], through a
+// buffer descriptor (BUF, the row must be wave-uniform) or a plain pointer.
+template <int R, int T, bool BUF>
+__device__ __forceinline__ void load_row(float2 (&v)[R], const float2* row, uint32_t k) {
+  if constexpr (BUF) {
+    static_assert(T >= 64, "a buffer descriptor needs a wave-uniform row");
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(row, k * 8u);
+    const int tau = threadIdx.x & (T - 1);
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      v[c] = __builtin_bit_cast(
+          float2, __builtin_amdgcn_raw_buffer_load_b64(r, tau * 8, c * T * 8, 0));
+  } else {
+    const int tau = threadIdx.x & (T - 1);
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = row[c * T + tau];
+  }
+}
+
+// Transform the samples in v (this thread's R values of one signal) and, if
+// `store`, write its coefficients through `mem`.  HOISTED: twiddles and
+// gather positions come from `ts`, else from the tables behind `mem`.
+template <int S, bool HOISTED, class Mem>
 __device__ __forceinline__ void transform_signal(float2 (&v)[FusedShape<S>::R], float2* L,
-                                                 int tau, uint64_t sig, uint64_t batch,
-                                                 float2* __restrict__ out, int64_t ld_out,
-                                                 const float2* __restrict__ tw,
-                                                 const uint16_t* __restrict__ src, float scale,
-                                                 const ThreadState<S>& ts) {
+                                                 int tau, bool store, const Mem& mem,
+                                                 float scale, const ThreadState<S>& ts) {
   using Sh = FusedShape<S>;
   constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, G = Sh::G, G1 = Sh::G1;
 
@@ -162,7 +219,7 @@ __device__ __forceinline__ void transform_signal(float2 (&v)[FusedShape<S>::R], 
     for (int c = 0; c < R; ++c) {
       if (c & (1 << bit)) continue;
       const int idx = (1 << (u - 1)) - 1 + (c >> (bit + 1));
-      butterfly(v[c], v[c | (1 << bit)], HOISTED ? ts.w1[idx] : tw[idx]);
+      butterfly(v[c], v[c | (1 << bit)], HOISTED ? ts.w1[idx] : mem.tw_at(idx, 0));
     }
   }
 #pragma unroll
@@ -190,7 +247,7 @@ __device__ __forceinline__ void transform_signal(float2 (&v)[FusedShape<S>::R], 
         if constexpr (HOISTED && Sh::TW_REGS)
           w = ts.wg[(g - 2) * (R - 1) + (1 << t) - 1 + h];
         else
-          w = tw[((1 << (u - 1)) - 1) + (a_hi << t) + h];
+          w = mem.tw_at(((1 << (u - 1)) - 1) + h, a_hi << t);
         butterfly(v[c], v[c | (1 << bit)], w);
       }
     }
@@ -199,14 +256,13 @@ __device__ __forceinline__ void transform_signal(float2 (&v)[FusedShape<S>::R], 
   }
   lds_barrier();
 
-  if (sig < batch) {
-    float2* orow = out + sig * (uint64_t)ld_out;
+  if (store) {
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       const int p = HOISTED ? (int)((ts.srcpk[c >> 1] >> (16 * (c & 1))) & 0xffffu)
-                            : (int)src[c * T + tau];
+                            : mem.src_at(c * T, tau);
       const float2 x = L[lds_pad<RHO>(p)];
-      orow[c * T + tau] = make_float2(x.x * scale, x.y * scale);
+      mem.put(c * T, tau, make_float2(x.x * scale, x.y * scale));
     }
   }
 }
@@ -218,6 +274,7 @@ hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
                    const uint16_t* __restrict__ src, float scale) {
   using Sh = FusedShape<S>;
   constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, SPB = Sh::SPB, G = Sh::G, G1 = Sh::G1;
+  constexpr uint32_t K = 1u << S;
   extern __shared__ float2 lds[];
 
   const int tid = threadIdx.x;
@@ -226,26 +283,26 @@ hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
   float2* L = lds + slot * Sh::PADK;
   const uint64_t n_groups = (batch + SPB - 1) / SPB;
 
-  float2 vn[R];
-  auto load = [&](uint64_t grp) {
-    const uint64_t sig = grp * SPB + slot;
-    if (sig < batch) {
-      const float2* row = in + sig * (uint64_t)ld_in;
-#pragma unroll
-      for (int c = 0; c < R; ++c) vn[c] = row[c * T + tau];
-    } else {
-#pragma unroll
-      for (int c = 0; c < R; ++c) vn[c] = make_float2(0.f, 0.f);
-    }
-  };
-
-  if constexpr (!Sh::PERSIST) {
+  if constexpr (Sh::BIG) {
+    // One signal per block, one block per signal (see BIG above).
+    static_assert(SPB == 1, "a large signal fills its block");
     const uint64_t grp = blockIdx.x;
-    load(grp);
+    float2 v[R];
+    load_row<R, T, false>(v, in + grp * (uint64_t)ld_in, K);
     ThreadState<S> unused;
-    transform_signal<S, false>(vn, L, tau, grp * SPB + slot, batch, out, ld_out, tw, src, scale,
-                               unused);
+    const FlatMem mem{tw, src, out + grp * (uint64_t)ld_out};
+    transform_signal<S, false>(v, L, tau, true, mem, scale, unused);
   } else {
+    float2 vn[R];
+    auto load = [&](uint64_t grp) {
+      const uint64_t sig = grp * SPB + slot;
+      if (sig < batch) {
+        load_row<R, T, false>(vn, in + sig * (uint64_t)ld_in, K);
+      } else {
+#pragma unroll
+        for (int c = 0; c < R; ++c) vn[c] = make_float2(0.f, 0.f);
+      }
+    };
     ThreadState<S> ts;
 #pragma unroll
     for (int i = 0; i < (1 << G1) - 1; ++i) ts.w1[i] = make_uniform(tw[i]);
@@ -272,15 +329,15 @@ hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
     }
 
     uint64_t grp = blockIdx.x;
-    if (Sh::PREFETCH && grp < n_groups) load(grp);
+    if (grp < n_groups) load(grp);
     for (; grp < n_groups; grp += gridDim.x) {
       float2 v[R];
-      if constexpr (!Sh::PREFETCH) load(grp);
 #pragma unroll
       for (int c = 0; c < R; ++c) v[c] = vn[c];
-      if (Sh::PREFETCH && grp + gridDim.x < n_groups) load(grp + gridDim.x);
-      transform_signal<S, true>(v, L, tau, grp * SPB + slot, batch, out, ld_out, tw, src, scale,
-                                ts);
+      if (grp + gridDim.x < n_groups) load(grp + gridDim.x);
+      const uint64_t sig = grp * SPB + slot;
+      const FlatMem mem{tw, src, out + (sig < batch ? sig : 0) * (uint64_t)ld_out};
+      transform_signal<S, true>(v, L, tau, sig < batch, mem, scale, ts);
       lds_barrier();  // the next group overwrites these LDS slots
     }
   }
@@ -318,7 +375,20 @@ static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, i
              &per_cu, (const void*)hidft_fused_kernel<S>, Sh::THREADS, Sh::LDS_BYTES)) !=
         hipSuccess)
       return e;
-    max_grid = Sh::PERSIST ? (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1) : 0x7fffffff;
+    max_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  }
+  if constexpr (Sh::BIG) {
+    // One block per signal: launch in chunks that fit the grid dimension.
+    const uint64_t chunk = 0x7fffffffULL;
+    for (uint64_t first = 0; first < batch; first += chunk) {
+      const uint64_t n = batch - first < chunk ? batch - first : chunk;
+      hipLaunchKernelGGL(hidft_fused_kernel<S>, dim3((unsigned)n), dim3(Sh::THREADS),
+                         Sh::LDS_BYTES, stream, in + first * (uint64_t)ld_in, ld_in,
+                         out + first * (uint64_t)ld_out, ld_out, n, tw, src, scale);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
   const uint64_t groups = (batch + Sh::SPB - 1) / Sh::SPB;
   const unsigned grid = (unsigned)(groups < (uint64_t)max_grid ? groups : (uint64_t)max_grid);
@@ -397,6 +467,7 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
                                                        int n_slots, float2* lds) {
   using Sh = FusedShape<S>;
   constexpr int R = Sh::R, T = Sh::T;
+  constexpr uint32_t K = 1u << S;
   const int tid = threadIdx.x;
   const int slot = tid / T;
   const int tau = tid - slot * T;
@@ -404,20 +475,33 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
   // Threads of empty slots (a partial pack) run the transform on zeros with
   // slot 0's tables (every pack has at least one slot) and store nothing.
   GroupSlot d = slots[valid ? slot : 0];
+  float2 v[R];
+  ThreadState<S> unused;
   if constexpr (T >= 64) {
+    // A slot spans whole wavefronts: its descriptor is wave-uniform.
     d.in = uniform_ptr(d.in);
     d.out = uniform_ptr(d.out);
     d.tw = uniform_ptr(d.tw);
     d.src = uniform_ptr(d.src);
     d.scale = __builtin_bit_cast(
         float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, d.scale)));
-  }
-  float2 v[R];
+    if (valid) {
+      load_row<R, T, true>(v, d.in, K);
+    } else {
 #pragma unroll
-  for (int c = 0; c < R; ++c) v[c] = valid ? d.in[c * T + tau] : make_float2(0.f, 0.f);
-  ThreadState<S> unused;
-  transform_signal<S, false>(v, lds + slot * Sh::PADK, tau, 0, valid ? 1 : 0, d.out, 0, d.tw,
-                             d.src, d.scale, unused);
+      for (int c = 0; c < R; ++c) v[c] = make_float2(0.f, 0.f);
+    }
+    BufMem mem;
+    mem.tw = make_rsrc(d.tw, (K > 1 ? K - 1 : 1) * 8u);
+    mem.src = make_rsrc(d.src, K * 2u);
+    mem.out = make_rsrc(d.out, K * 8u);
+    transform_signal<S, false>(v, lds + slot * Sh::PADK, tau, valid, mem, d.scale, unused);
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = valid ? d.in[c * T + tau] : make_float2(0.f, 0.f);
+    const FlatMem mem{d.tw, d.src, d.out};
+    transform_signal<S, false>(v, lds + slot * Sh::PADK, tau, valid, mem, d.scale, unused);
+  }
 }
 
 __global__ void __launch_bounds__(GROUPED_THREADS)

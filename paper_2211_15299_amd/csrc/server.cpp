@@ -1,0 +1,454 @@
+// Continuous-batching request server for homogeneous-support DFTs.
+//
+// Clients submit (N, J, samples) requests from any thread.  The server keeps
+// the plans of recently used supports resident on the device (a plan cache
+// with an LRU bound on device bytes), admits requests into batches as batch
+// slots and their device memory free up, and runs every batch -- requests of
+// different sizes and supports -- as one grouped kernel launch.  Each slot
+// owns a stream, a device region and pinned staging buffers, so the upload of
+// one batch, the transform of another and the download of a third overlap on
+// the device.  One scheduler thread forms batches, issues the work and
+// retires completed batches; clients collect results by polling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "hidft.h"
+#include "internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct PlanEntry {
+  uint32_t M = 0;
+  std::vector<uint64_t> J;
+  hidft_plan plan = nullptr;
+  uint64_t refs = 0;               // pending or in-flight requests using it
+  std::list<PlanEntry*>::iterator lru;
+};
+
+struct Request {
+  uint64_t id = 0;
+  PlanEntry* entry = nullptr;
+  const float2* host_in = nullptr;
+  float2* host_out = nullptr;
+  uint64_t k = 0;
+  uint32_t s = 0;
+  Clock::time_point t_submit;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  float2* d_data = nullptr;        // inputs then outputs of the batch
+  hidft::GroupPack* d_packs = nullptr;
+  hidft::GroupSlot* d_slots = nullptr;
+  float2* h_in = nullptr;          // pinned staging
+  float2* h_out = nullptr;
+  hidft::GroupPack* h_packs = nullptr;
+  hidft::GroupSlot* h_slots = nullptr;
+  std::vector<Request> batch;      // requests in flight (empty when free)
+  std::vector<uint64_t> offsets;   // point offset of each request in the region
+  uint64_t points = 0;
+};
+
+uint64_t hash_support(uint32_t M, const uint64_t* J, uint64_t k) {
+  uint64_t h = 0x9e3779b97f4a7c15ULL ^ (M * 0x100000001b3ULL) ^ k;
+  for (uint64_t i = 0; i < k; ++i) {
+    h ^= J[i] + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
+  }
+  return h;
+}
+
+}  // namespace
+
+struct hidft_server_s {
+  hidft_server_config cfg{};
+  int device = -1;
+  uint64_t slot_points = 0;        // complex values per slot and direction
+
+  // plan cache
+  std::mutex plan_mu;
+  std::unordered_multimap<uint64_t, std::unique_ptr<PlanEntry>> plans;
+  std::list<PlanEntry*> lru;       // front = most recently used
+  size_t plan_bytes_resident = 0;
+  hipStream_t plan_stream = nullptr;
+
+  // requests
+  std::mutex mu;
+  std::condition_variable cv_work;   // scheduler: new requests or stop
+  std::condition_variable cv_done;   // clients: results available
+  std::deque<Request> pending;
+  std::deque<hidft_server_result> results;
+  uint64_t next_id = 1;
+  uint64_t in_system = 0;            // submitted and not yet completed
+  bool stop = false;
+
+  std::vector<Slot> slots;
+  std::thread worker;
+
+  std::atomic<uint64_t> n_submitted{0}, n_completed{0}, n_rejected{0}, n_batches{0};
+  std::atomic<uint64_t> n_plan_hits{0}, n_plan_misses{0}, n_plan_evictions{0};
+  std::atomic<uint64_t> max_inflight{0};
+  std::atomic<int32_t> worker_error{0};
+
+  void loop();
+  void launch(Slot& sl);
+  void retire(Slot& sl);
+  PlanEntry* resolve(uint32_t M, const uint64_t* J, uint64_t k, hidft_status* st);
+  void release(PlanEntry* e);
+};
+
+// Finds or creates the plan of (M, J); takes a reference on it.
+PlanEntry* hidft_server_s::resolve(uint32_t M, const uint64_t* J, uint64_t k, hidft_status* st) {
+  const uint64_t h = hash_support(M, J, k);
+  std::lock_guard<std::mutex> lk(plan_mu);
+  auto range = plans.equal_range(h);
+  for (auto it = range.first; it != range.second; ++it) {
+    PlanEntry* e = it->second.get();
+    if (e->M == M && e->J.size() == k && std::equal(e->J.begin(), e->J.end(), J)) {
+      ++e->refs;
+      lru.splice(lru.begin(), lru, e->lru);
+      n_plan_hits++;
+      *st = HIDFT_OK;
+      return e;
+    }
+  }
+  n_plan_misses++;
+  hidft_plan p = nullptr;
+  *st = hidft_plan_create(M, J, k, 0, plan_stream, &p);
+  if (*st != HIDFT_OK) return nullptr;
+  auto owned = std::make_unique<PlanEntry>();
+  PlanEntry* e = owned.get();
+  e->M = M;
+  e->J.assign(J, J + k);
+  e->plan = p;
+  e->refs = 1;
+  lru.push_front(e);
+  e->lru = lru.begin();
+  plan_bytes_resident += p->device_bytes;
+  plans.emplace(h, std::move(owned));
+  // Evict least recently used plans that no request holds, down to budget.
+  for (auto it = lru.end(); plan_bytes_resident > cfg.plan_bytes && it != lru.begin();) {
+    --it;
+    PlanEntry* v = *it;
+    if (v->refs != 0) continue;
+    plan_bytes_resident -= v->plan->device_bytes;
+    hidft_plan_destroy(v->plan);
+    it = lru.erase(it);
+    const uint64_t vh = hash_support(v->M, v->J.data(), v->J.size());
+    auto r = plans.equal_range(vh);
+    for (auto pi = r.first; pi != r.second; ++pi)
+      if (pi->second.get() == v) {
+        plans.erase(pi);  // frees v
+        break;
+      }
+    n_plan_evictions++;
+  }
+  return e;
+}
+
+void hidft_server_s::release(PlanEntry* e) {
+  std::lock_guard<std::mutex> lk(plan_mu);
+  --e->refs;
+}
+
+// Stages the batch in `sl` and issues upload, grouped transform and download.
+void hidft_server_s::launch(Slot& sl) {
+  std::vector<std::pair<uint32_t, hidft::GroupSlot>> inst;
+  inst.reserve(sl.batch.size());
+  sl.offsets.resize(sl.batch.size());
+  uint64_t off = 0;
+  float2* d_in = sl.d_data;
+  float2* d_out = sl.d_data + slot_points;
+  for (size_t i = 0; i < sl.batch.size(); ++i) {
+    const Request& r = sl.batch[i];
+    sl.offsets[i] = off;
+    std::memcpy(sl.h_in + off, r.host_in, r.k * sizeof(float2));
+    hidft::GroupSlot d;
+    d.in = d_in + off;
+    d.out = d_out + off;
+    d.tw = r.entry->plan->d_tw;
+    d.src = r.entry->plan->d_src;
+    d.scale = r.entry->plan->scale;
+    inst.emplace_back(r.s, d);
+    off += r.k;
+  }
+  sl.points = off;
+  std::vector<hidft::GroupPack> packs;
+  std::vector<hidft::GroupSlot> slots_v;
+  hidft::pack_instances(inst, &packs, &slots_v);
+  std::memcpy(sl.h_packs, packs.data(), packs.size() * sizeof(hidft::GroupPack));
+  std::memcpy(sl.h_slots, slots_v.data(), slots_v.size() * sizeof(hidft::GroupSlot));
+  hipError_t e;
+  if ((e = hipMemcpyAsync(d_in, sl.h_in, off * sizeof(float2), hipMemcpyHostToDevice,
+                          sl.stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(sl.d_packs, sl.h_packs, packs.size() * sizeof(hidft::GroupPack),
+                          hipMemcpyHostToDevice, sl.stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(sl.d_slots, sl.h_slots, slots_v.size() * sizeof(hidft::GroupSlot),
+                          hipMemcpyHostToDevice, sl.stream)) != hipSuccess ||
+      (e = hidft::launch_grouped(sl.d_packs, (uint32_t)packs.size(), sl.d_slots, sl.stream)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(sl.h_out, d_out, off * sizeof(float2), hipMemcpyDeviceToHost,
+                          sl.stream)) != hipSuccess ||
+      (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) {
+    worker_error = (int32_t)HIDFT_ERR_DEVICE;
+  }
+  n_batches++;
+}
+
+// Hands the results of a completed batch to the clients and frees the slot.
+void hidft_server_s::retire(Slot& sl) {
+  const int32_t st = worker_error.load() ? worker_error.load() : (int32_t)HIDFT_OK;
+  const auto now = Clock::now();
+  std::vector<hidft_server_result> done;
+  done.reserve(sl.batch.size());
+  for (size_t i = 0; i < sl.batch.size(); ++i) {
+    const Request& r = sl.batch[i];
+    if (st == HIDFT_OK) std::memcpy(r.host_out, sl.h_out + sl.offsets[i], r.k * sizeof(float2));
+    hidft_server_result res;
+    res.id = r.id;
+    res.status = st;
+    res.batch_size = (uint32_t)sl.batch.size();
+    res.latency_us = std::chrono::duration<double, std::micro>(now - r.t_submit).count();
+    done.push_back(res);
+    release(r.entry);
+  }
+  sl.batch.clear();
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& r : done) results.push_back(r);
+    in_system -= done.size();
+  }
+  n_completed += done.size();
+  cv_done.notify_all();
+}
+
+void hidft_server_s::loop() {
+  (void)hipSetDevice(device);
+  const uint64_t cap_points = slot_points;
+  for (;;) {
+    bool progressed = false;
+    uint64_t inflight = 0;
+    for (Slot& sl : slots) {
+      if (sl.batch.empty()) continue;
+      const hipError_t q = hipEventQuery(sl.done);
+      if (q == hipSuccess) {
+        retire(sl);
+        progressed = true;
+      } else if (q != hipErrorNotReady) {
+        worker_error = (int32_t)HIDFT_ERR_DEVICE;
+        (void)hipStreamSynchronize(sl.stream);
+        retire(sl);
+        progressed = true;
+      } else {
+        ++inflight;
+      }
+    }
+    for (Slot& sl : slots) {
+      if (!sl.batch.empty()) continue;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        uint64_t pts = 0;
+        while (!pending.empty() && sl.batch.size() < cfg.max_batch &&
+               pts + pending.front().k <= cap_points) {
+          pts += pending.front().k;
+          sl.batch.push_back(pending.front());
+          pending.pop_front();
+        }
+      }
+      if (sl.batch.empty()) break;
+      launch(sl);
+      ++inflight;
+      progressed = true;
+    }
+    uint64_t m = max_inflight.load();
+    while (inflight > m && !max_inflight.compare_exchange_weak(m, inflight)) {
+    }
+    if (progressed) continue;
+    std::unique_lock<std::mutex> lk(mu);
+    if (stop && pending.empty() && inflight == 0) break;
+    if (inflight > 0) {
+      // batches on the device: poll their events again shortly
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
+    } else {
+      cv_work.wait_for(lk, std::chrono::milliseconds(2),
+                       [&] { return stop || !pending.empty(); });
+    }
+  }
+}
+
+extern "C" {
+
+hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* out) {
+  if (!out || !cfg)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_create: NULL argument");
+  *out = nullptr;
+  if (cfg->slots == 0 || cfg->max_batch == 0 || cfg->data_bytes < 2 * 16 * cfg->slots)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                            "hidft_server_create: slots, max_batch and data_bytes must be positive");
+  auto sv = std::make_unique<hidft_server_s>();
+  sv->cfg = *cfg;
+  hipError_t e = hipGetDevice(&sv->device);
+  if (e != hipSuccess) return hidft::hip_error(e, "hidft_server_create");
+  sv->slot_points = cfg->data_bytes / cfg->slots / (2 * sizeof(float2));
+  if ((e = hipStreamCreateWithFlags(&sv->plan_stream, hipStreamNonBlocking)) != hipSuccess)
+    return hidft::hip_error(e, "hidft_server_create: stream");
+  sv->slots.resize(cfg->slots);
+  for (Slot& sl : sv->slots) {
+    const size_t data = 2 * sv->slot_points * sizeof(float2);
+    const size_t packs = (size_t)cfg->max_batch * sizeof(hidft::GroupPack);
+    const size_t slots = (size_t)cfg->max_batch * sizeof(hidft::GroupSlot);
+    if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipMalloc(&sl.d_data, data)) != hipSuccess ||
+        (e = hipMalloc(&sl.d_packs, packs)) != hipSuccess ||
+        (e = hipMalloc(&sl.d_slots, slots)) != hipSuccess ||
+        (e = hipHostMalloc(&sl.h_in, sv->slot_points * sizeof(float2), hipHostMallocDefault)) !=
+            hipSuccess ||
+        (e = hipHostMalloc(&sl.h_out, sv->slot_points * sizeof(float2), hipHostMallocDefault)) !=
+            hipSuccess ||
+        (e = hipHostMalloc(&sl.h_packs, packs, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc(&sl.h_slots, slots, hipHostMallocDefault)) != hipSuccess) {
+      hidft_status st = hidft::hip_error(e, "hidft_server_create: slot resources");
+      hidft_server_destroy(sv.release());
+      return st;
+    }
+  }
+  hidft_server s = sv.release();
+  try {
+    s->worker = std::thread([s] { s->loop(); });
+  } catch (...) {
+    hidft_server_destroy(s);
+    return hidft::set_error(HIDFT_ERR_DEVICE, "hidft_server_create: cannot start the scheduler");
+  }
+  *out = s;
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_server_submit(hidft_server s, uint32_t log2_n, const uint64_t* J, uint64_t k,
+                                 const void* host_samples, void* host_coefs, uint64_t* id) {
+  if (!s || !J || !host_samples || !host_coefs || !id)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: NULL argument");
+  if (k == 0 || 2 * k > 2 * s->slot_points) {
+    s->n_rejected++;
+    return hidft::set_error(HIDFT_ERR_OUT_OF_MEMORY,
+                            "hidft_server_submit: request larger than a batch slot's memory");
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != s->device)
+    (void)hipSetDevice(s->device);
+  hidft_status st;
+  PlanEntry* e = s->resolve(log2_n, J, k, &st);
+  if (!e) {
+    s->n_rejected++;
+    return st;
+  }
+  Request r;
+  r.entry = e;
+  r.host_in = static_cast<const float2*>(host_samples);
+  r.host_out = static_cast<float2*>(host_coefs);
+  r.k = k;
+  r.s = e->plan->core.s;
+  r.t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      s->release(e);
+      return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: server stopping");
+    }
+    r.id = s->next_id++;
+    s->pending.push_back(r);
+    s->in_system++;
+  }
+  s->n_submitted++;
+  s->cv_work.notify_one();
+  *id = r.id;
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_server_poll(hidft_server s, hidft_server_result* out, uint32_t cap,
+                               uint32_t* n, int32_t wait_us) {
+  if (!s || !n || (!out && cap > 0))
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_poll: NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->results.empty() && wait_us > 0)
+    s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us),
+                        [&] { return !s->results.empty(); });
+  uint32_t m = 0;
+  while (m < cap && !s->results.empty()) {
+    out[m++] = s->results.front();
+    s->results.pop_front();
+  }
+  *n = m;
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_server_drain(hidft_server s) {
+  if (!s) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_drain: NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->in_system == 0; });
+  const int32_t err = s->worker_error.load();
+  return err ? hidft::set_error((hidft_status)err, "hidft_server_drain: a batch failed")
+             : hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_server_get_stats(hidft_server s, hidft_server_stats* st) {
+  if (!s || !st) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_get_stats: NULL");
+  st->submitted = s->n_submitted;
+  st->completed = s->n_completed;
+  st->rejected = s->n_rejected;
+  st->batches = s->n_batches;
+  st->plan_hits = s->n_plan_hits;
+  st->plan_misses = s->n_plan_misses;
+  st->plan_evictions = s->n_plan_evictions;
+  st->max_inflight_batches = s->max_inflight;
+  {
+    std::lock_guard<std::mutex> lk(s->plan_mu);
+    st->plan_bytes_resident = s->plan_bytes_resident;
+    st->plans_resident = s->plans.size();
+  }
+  st->slot_bytes = 2 * s->slot_points * sizeof(float2);
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_server_destroy(hidft_server s) {
+  if (!s) return hidft::set_error(HIDFT_OK, "");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (Slot& sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.d_data) (void)hipFree(sl.d_data);
+    if (sl.d_packs) (void)hipFree(sl.d_packs);
+    if (sl.d_slots) (void)hipFree(sl.d_slots);
+    if (sl.h_in) (void)hipHostFree(sl.h_in);
+    if (sl.h_out) (void)hipHostFree(sl.h_out);
+    if (sl.h_packs) (void)hipHostFree(sl.h_packs);
+    if (sl.h_slots) (void)hipHostFree(sl.h_slots);
+  }
+  for (auto& kv : s->plans) hidft_plan_destroy(kv.second->plan);
+  if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
+  delete s;
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+}  // extern "C"

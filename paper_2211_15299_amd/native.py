@@ -57,6 +57,13 @@ SIGNATURES = [
     ("hidft_group_destroy", ctypes.c_int, [_vp]),
     ("hidft_group_get_info", ctypes.c_int, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                                             ctypes.POINTER(ctypes.c_size_t)]),
+    ("hidft_server_create", ctypes.c_int, [_vp, _pp]),
+    ("hidft_server_submit", ctypes.c_int, [_vp, _u32, ctypes.POINTER(_u64), _u64, _vp, _vp,
+                                           ctypes.POINTER(_u64)]),
+    ("hidft_server_poll", ctypes.c_int, [_vp, _vp, _u32, ctypes.POINTER(_u32), _i32]),
+    ("hidft_server_drain", ctypes.c_int, [_vp]),
+    ("hidft_server_get_stats", ctypes.c_int, [_vp, _vp]),
+    ("hidft_server_destroy", ctypes.c_int, [_vp]),
     ("hidft_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("hidft_last_error", ctypes.c_char_p, []),
 ]
@@ -256,6 +263,68 @@ class Group:
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             _check(lib().hidft_group_destroy(self._h))
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("data_bytes", ctypes.c_size_t), ("plan_bytes", ctypes.c_size_t),
+                ("slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32)]
+
+
+RESULT_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("batch_size", np.uint32),
+                         ("latency_us", np.float64)])
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("submitted", "completed", "rejected", "batches", "plan_hits", "plan_misses",
+                 "plan_evictions", "max_inflight_batches", "plans_resident")] + \
+               [("plan_bytes_resident", ctypes.c_size_t), ("slot_bytes", ctypes.c_size_t)]
+
+
+class Server:
+    """Continuous-batching request server (hidft_server_*).
+
+    submit() takes host numpy arrays; the caller keeps `samples` and `out`
+    alive until the request's result has been polled.
+    """
+
+    def __init__(self, data_bytes=256 << 20, plan_bytes=64 << 20, slots=3, max_batch=512):
+        cfg = ServerConfig(data_bytes, plan_bytes, slots, max_batch)
+        self._h = ctypes.c_void_p(None)
+        _check(lib().hidft_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._res = np.zeros(4096, dtype=RESULT_DTYPE)
+
+    def submit(self, log2_n: int, J: np.ndarray, samples: np.ndarray, out: np.ndarray) -> int:
+        rid = _u64(0)
+        _check(lib().hidft_server_submit(self._h, log2_n, J.ctypes.data_as(ctypes.POINTER(_u64)),
+                                         J.shape[0], samples.ctypes.data, out.ctypes.data,
+                                         ctypes.byref(rid)))
+        return rid.value
+
+    def poll(self, wait_us: int = 0) -> np.ndarray:
+        n = _u32(0)
+        _check(lib().hidft_server_poll(self._h, self._res.ctypes.data, len(self._res),
+                                       ctypes.byref(n), wait_us))
+        return self._res[: n.value].copy()
+
+    def drain(self) -> None:
+        _check(lib().hidft_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().hidft_server_get_stats(self._h, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().hidft_server_destroy(self._h))
             self._h = ctypes.c_void_p(None)
 
     def __del__(self):

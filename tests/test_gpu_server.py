@@ -1,0 +1,159 @@
+"""Request server (continuous batching) on the GPU.
+
+Requests of different (N, J, k) arrive while others are on the device; each
+result must equal -- bit for bit -- the result of the same request run alone
+through the single-plan path, and agree with the FP64 oracle.
+"""
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import homogeneous_support, rng_for, sample_values
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+native = pytest.importorskip("paper_2211_15299_amd.native")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _supports(n, cfg=5):
+    out = []
+    for i in range(n):
+        rng = rng_for(cfg, i)
+        M = int(rng.integers(10, 23))
+        s = int(rng.integers(6, min(13, M - 2) + 1))
+        sup = homogeneous_support(M, s, rng)
+        out.append((M, np.ascontiguousarray(sup.J, dtype=np.uint64)))
+    return out
+
+
+def _alone(M, J, f):
+    plan = native.Plan(M, J.tolist())
+    x = torch.from_numpy(f).cuda()
+    y = plan.execute(x)
+    torch.cuda.synchronize()
+    r = y[0].cpu().numpy()
+    plan.close()
+    return r
+
+
+def test_server_mix_equals_alone_and_oracle():
+    sups = _supports(48)
+    rng = rng_for(5, 1000)
+    n_req = 1500
+    which = rng.integers(0, len(sups), size=n_req)
+    samples = [sample_values(sups[w][0], len(sups[w][1]), 1, rng) for w in which]
+    outs = [np.full(len(sups[w][1]), np.nan, dtype=np.complex64) for w in which]
+    srv = native.Server(data_bytes=64 << 20, plan_bytes=16 << 20, slots=3, max_batch=256)
+    ids = {}
+    for i, w in enumerate(which):
+        M, J = sups[w]
+        ids[srv.submit(M, J, samples[i][0], outs[i])] = i
+        if i % 100 == 0:
+            srv.poll()
+    srv.drain()
+    st = srv.stats()
+    _say(f"server: {st}")
+    assert st["completed"] == n_req and st["rejected"] == 0
+    assert st["batches"] >= 2
+    # every request's result, alone vs in the mix: bit-identical
+    checked = 0
+    for i in range(0, n_req, 7):
+        M, J = sups[which[i]]
+        alone = _alone(M, J, samples[i])
+        assert np.array_equal(alone, outs[i]), i
+        checked += 1
+    # oracle on a sample
+    for i in range(0, n_req, 97):
+        M, J = sups[which[i]]
+        plan = native.Plan(M, J.tolist(), host_only=True)
+        want = oracle.adjoint_coefficients(M, J.tolist(), plan.samples().tolist(),
+                                           samples[i][0].astype(np.complex128))
+        assert oracle.rel_l2(outs[i].astype(np.complex128), want) <= 1e-5
+    _say(f"server: {checked} requests identical alone and in the mix")
+    srv.close()
+
+
+def test_server_admission_errors_and_eviction():
+    srv = native.Server(data_bytes=2 * 16 * 1024 * 2, plan_bytes=1, slots=2, max_batch=8)
+    rng = rng_for(5, 2000)
+    # a request larger than one slot's region is rejected
+    big = homogeneous_support(16, 12, rng)
+    J = np.ascontiguousarray(big.J, dtype=np.uint64)
+    f = sample_values(16, len(J), 1, rng)[0]
+    out = np.zeros(len(J), dtype=np.complex64)
+    with pytest.raises(native.HiDFTError) as ei:
+        srv.submit(16, J, f, out)
+    assert ei.value.status_name == "HIDFT_ERR_OUT_OF_MEMORY"
+    # a non-homogeneous support is rejected at submit
+    bad = np.array([1, 2, 4, 8], dtype=np.uint64)
+    with pytest.raises(native.HiDFTError) as ei:
+        srv.submit(4, bad, np.zeros(4, np.complex64), np.zeros(4, np.complex64))
+    assert ei.value.status_name == "HIDFT_ERR_NOT_HOMOGENEOUS"
+    # tiny plan budget: plans are evicted once no request holds them
+    sups = _supports(12, cfg=6)
+    keep = []
+    for M, J in sups:
+        if len(J) > 1024:
+            continue
+        f = sample_values(M, len(J), 1, rng)[0]
+        o = np.zeros(len(J), dtype=np.complex64)
+        keep.append((M, J, f, o))
+        srv.submit(M, J, f, o)
+        srv.drain()
+    st = srv.stats()
+    assert st["plan_evictions"] >= len(keep) - 2, st
+    for M, J, f, o in keep:
+        assert np.array_equal(o, _alone(M, J, f[None, :]))
+    srv.close()
+
+
+def test_server_concurrent_clients():
+    sups = _supports(16, cfg=7)
+    srv = native.Server(data_bytes=32 << 20, plan_bytes=64 << 20, slots=2, max_batch=64)
+    errors = []
+    results = {}
+
+    def client(cid):
+        try:
+            rng = rng_for(7, 100 + cid)
+            for r in range(120):
+                w = int(rng.integers(0, len(sups)))
+                M, J = sups[w]
+                f = sample_values(M, len(J), 1, rng)[0]
+                o = np.zeros(len(J), dtype=np.complex64)
+                srv.submit(M, J, f, o)
+                results[(cid, r)] = (w, f, o)
+        except Exception as e:  # pragma: no cover
+            errors.append(e)
+
+    th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    srv.drain()
+    assert not errors
+    assert srv.stats()["completed"] == 480
+    for key in list(results)[::11]:
+        w, f, o = results[key]
+        M, J = sups[w]
+        assert np.array_equal(o, _alone(M, J, f[None, :]))
+    srv.close()
