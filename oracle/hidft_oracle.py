@@ -394,3 +394,62 @@ def op_count(k: int) -> int:
     """Theorem 1: 1.5 A log2 A + A arithmetic operations for A = k samples."""
     s = k.bit_length() - 1
     return int(1.5 * k * s + k) if k > 1 else 1
+
+
+# ---------------------------------------------------------------------------
+# Part-homogeneous supports, induced weights and Shift-and-Sample (Sec. VI,
+# Sec. VII-B, Sec. IX, Algorithm 2)
+# ---------------------------------------------------------------------------
+
+def level_nodes(M: int, J: Sequence[int], level: int) -> dict[int, list[int]]:
+    """Nodes of T(J) at `level`: positions t of J grouped by J[t] mod 2^level.
+
+    Keys are the residues, values the caller positions t in ascending order.
+    """
+    J = check_index_set(M, J)
+    nodes: dict[int, list[int]] = {}
+    for t, j in enumerate(J):
+        nodes.setdefault(j % (1 << level), []).append(t)
+    return nodes
+
+
+def is_part_homogeneous(M: int, J: Sequence[int], r: Sequence[int]) -> bool:
+    """Def. part-homogeneous: J has no pivot at a level <= r_max outside r."""
+    r = list(r)
+    if not r:
+        return True
+    return all(p in r for p in pivots(M, J) if p <= max(r))
+
+
+def induced_weights(M: int, J: Sequence[int], w: np.ndarray, level: int) -> dict[int, complex]:
+    """mu_J(v, w) = sum of w over the elements of each node v at `level`
+    (Sec. VI, induced weight), keyed by the node's residue mod 2^level."""
+    w = np.asarray(w, dtype=np.complex128)
+    return {res: complex(np.sum(w[ts])) for res, ts in level_nodes(M, J, level).items()}
+
+
+def sas_sample_set(M: int, r: Sequence[int], shifts: int) -> list[list[int]]:
+    """Rows j = 0..shifts-1 of the Shift-and-Sample pattern: I_r + j (mod N),
+    each row in ascending order of I_r (Algorithm 2, step 3)."""
+    N = 1 << M
+    base = sorted(sample_pattern_recursive(M, r))
+    return [[(i + j) % N for i in base] for j in range(shifts)]
+
+
+def sas_cost(M: int, J: Sequence[int], r: Sequence[int]) -> float:
+    """Lemma 4: c1 s 2^s mu* + c2 sum_v mu(v)^2 with c1 = 3/2, c2 = 6, the
+    nodes v taken at level r_max + 1 (level 0 when r is empty)."""
+    s = len(r)
+    level = (max(r) + 1) if s else 0
+    mus = [len(v) for v in level_nodes(M, J, level).values()]
+    return 1.5 * s * (1 << s) * max(mus) + 6.0 * sum(m * m for m in mus)
+
+
+def solve_on_samples(M: int, J: Sequence[int], S: Sequence[int], f_S: np.ndarray) -> np.ndarray:
+    """(Ff)_J from samples f(S), |S| >= |J|: the least-squares solution of
+    f_S = F^{-1}(S, J) (Ff)_J (Eq. submatrix-method with more rows than
+    unknowns; exact for f in B^J when F^{-1}(S, J) has full column rank)."""
+    A = idft_submatrix(M, S, J)
+    f_S = np.asarray(f_S, dtype=np.complex128)
+    sol, *_ = np.linalg.lstsq(A, f_S.T if f_S.ndim == 2 else f_S, rcond=None)
+    return sol.T if f_S.ndim == 2 else sol

@@ -32,3 +32,17 @@ def printed_matrix():
             i, j, re, im = [x.strip() for x in line.split("|")]
             rows.append((int(i), int(j), complex(float(re), float(im))))
     return rows
+
+
+def part_homogeneous_examples():
+    out = []
+    with open(os.path.join(HERE, "part_homogeneous_examples.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            M, J, r, level, nodes, cite = [x.strip() for x in line.split("|")]
+            groups = [sorted(int(x) for x in g.split(",")) for g in nodes.split(";")]
+            out.append(dict(M=int(M), J=_ints(J), r=_ints(r), level=int(level),
+                            nodes=sorted(groups), cite=cite))
+    return out
