@@ -297,6 +297,79 @@ hidft_status hidft_server_drain(hidft_server server);
 hidft_status hidft_server_get_stats(hidft_server server, hidft_server_stats* stats);
 hidft_status hidft_server_destroy(hidft_server server);
 
+/*
+ * hidft_execute_inverse -- the inverse map: coefficients on J to samples on I_r.
+ *
+ * For b < batch: d_samples[b*ld_out + p] = f_b(sample_idx[p]), the samples on
+ * I_r (ascending) of the signal f_b in B^J whose DFT on J is
+ * d_coefs[b*ld_in + t] (caller's order of J):
+ * f_I = F^{-1}(I_r, J) c (Sec. II, Sec. IV item 1; Eq. submatrix-method).
+ * Since F(J, I_r) F(J, I_r)^H = k Id (Lemma 1), this is (1/N) F(J, I_r)^H c,
+ * computed as the adjoint of the radix-2 stages of hidft_execute (reverse
+ * order, conjugated twiddles), O(k log k) per signal, one kernel launch.
+ * Same plans, layouts, alignment, overlap and error rules as hidft_execute,
+ * with the roles of the two buffers exchanged.
+ */
+hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t ld_in,
+                                   void* d_samples, int64_t ld_out, uint64_t batch,
+                                   void* stream);
+
+/*
+ * Shift-and-Sample (Sec. IX, Algorithm 2) and the Hi-DFT of part-homogeneous
+ * supports (Sec. VII-B, Def. Hi-DFT, Eq. aliasing-homogeneous-tree).
+ *
+ * J (any k distinct indices) is r-part-homogeneous when it has no pivot at a
+ * level <= r_max outside r (Sec. VI, Def. part-homogeneous).  The nodes of
+ * its congruence tree at level r_max + 1 (classes of J modulo 2^{r_max+1})
+ * then sit at distinct slots q = sum_u bit_{r_u}(node) 2^{u-1} of the
+ * 2^s-point Hi-DFT over I_r, s = |r|, and that Hi-DFT of f in B^J gives, at
+ * the slot of node v, (2^s/N) mu_J(v, Ff): the sum of the coefficients of the
+ * node (its induced weight).  Shift-and-Sample samples f on I_r + j for
+ * j < mu* (the largest node), computes the mu* Hi-DFTs (batched fused
+ * kernel) and solves one mu(v) x mu(v) dual Vandermonde system per node for
+ * its coefficients (Eq. alg1_system), in FP64 on the GPU.  Sample complexity
+ * mu* 2^s; cost per Lemma 4.
+ *
+ * hidft_sas_create: pivots == NULL chooses r: the first t pivots of J (J is
+ * part-homogeneous at any such prefix) minimising Lemma 4's cost
+ * 1.5 t 2^t mu* + 6 sum_v mu(v)^2 under 2^t <= 2^14 and mu* <= 32; else r is
+ * validated (ascending in [0, M); part-homogeneity: NOT_HOMOGENEOUS;
+ * 2^s <= 2^14: UNSUPPORTED); hidft_sas_execute refuses plans with mu* > 32
+ * (UNSUPPORTED, before any device work).  Device tables are built on the
+ * current device (synchronously on `stream`) unless HIDFT_PLAN_HOST_ONLY.
+ * hidft_sas_get_samples: mu* 2^s sample positions, row j = (I_r + j) mod N
+ * in ascending order of I_r: the layout of one signal's samples for execute.
+ * hidft_sas_get_nodes: node index of each J[t], and the slot of each node.
+ * hidft_sas_execute: d_samples rows (ld_in >= mu* 2^s) -> d_coefs rows
+ * (ld_out >= k, caller's order of J).  d_work: device workspace of
+ * hidft_sas_workspace_bytes(batch) bytes, 8-byte aligned, owned by the caller
+ * (no allocation happens in the call).  Inputs and outputs must not overlap.
+ * The leaf solves inherit the conditioning of the node's Vandermonde matrix
+ * (nodes e^{2 pi i l/N} on the unit circle), which the paper leaves open.
+ * hidft_sas_weights: d_samples rows of 2^s samples on I_r (ascending) ->
+ * 2^s induced weights mu_J(v, Ff) in slot order (0 at slots with no node, up
+ * to rounding); with r truncated to its first s-n pivots this is the Hi-DFT
+ * at height n.
+ */
+typedef struct hidft_sas_s* hidft_sas;
+#define HIDFT_SAS_MAX_MU 32u
+
+hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
+                              const uint32_t* pivots, uint32_t n_pivots, uint32_t flags,
+                              void* stream, hidft_sas* out);
+hidft_status hidft_sas_destroy(hidft_sas plan);
+hidft_status hidft_sas_get_info(hidft_sas plan, uint32_t* n_pivots, uint32_t* mu_max,
+                                uint64_t* n_nodes, uint64_t* samples_per_signal, double* cost);
+hidft_status hidft_sas_get_pivots(hidft_sas plan, uint32_t* pivots);
+hidft_status hidft_sas_get_samples(hidft_sas plan, uint64_t* sample_idx);
+hidft_status hidft_sas_get_nodes(hidft_sas plan, uint32_t* node_of_t, uint32_t* slot_of_node);
+hidft_status hidft_sas_workspace_bytes(hidft_sas plan, uint64_t batch, size_t* bytes);
+hidft_status hidft_sas_execute(hidft_sas plan, const void* d_samples, int64_t ld_in,
+                               void* d_coefs, int64_t ld_out, uint64_t batch, void* d_work,
+                               void* stream);
+hidft_status hidft_sas_weights(hidft_sas plan, const void* d_samples, int64_t ld_in,
+                               void* d_weights, int64_t ld_out, uint64_t batch, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* hidft_status_string(hidft_status status);
 

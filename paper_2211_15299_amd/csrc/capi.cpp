@@ -353,6 +353,20 @@ hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in
   return ok();
 }
 
+hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t ld_in,
+                                   void* d_samples, int64_t ld_out, uint64_t batch,
+                                   void* stream) {
+  hidft_status st =
+      check_exec(plan, d_coefs, ld_in, d_samples, ld_out, batch, "hidft_execute_inverse");
+  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
+  const float inv_n = std::ldexp(1.0f, -(int)plan->core.M);
+  hipError_t e = hidft::launch_inverse(plan->core.s, static_cast<const float2*>(d_coefs), ld_in,
+                                       static_cast<float2*>(d_samples), ld_out, batch, plan->d_tw,
+                                       plan->d_src, inv_n, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hidft_execute_inverse: kernel launch");
+  return ok();
+}
+
 hidft_status hidft_execute_plain(hidft_plan plan, const void* d_samples, int64_t ld_in,
                                  void* d_coefs, int64_t ld_out, uint64_t batch, void* stream) {
   hidft_status st =

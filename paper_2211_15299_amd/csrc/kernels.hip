@@ -353,6 +353,173 @@ __global__ void hidft_k1_kernel(const float2* __restrict__ in, int64_t ld_in,
   out[b * (uint64_t)ld_out] = make_float2(x.x * scale, x.y * scale);
 }
 
+// ---------------------------------------------------------------------------
+// Inverse transform: coefficients on J (caller's order) -> samples on I_r
+// (ascending), f_I = F^{-1}(I_r, J) c = (1/N) F(J, I_r)^H c.
+//
+// F(J, I_r) in the kernels' orders is the product of the S butterfly stages,
+// so its adjoint runs the stages in reverse with each butterfly transposed
+// and conjugated: (X, Y) -> (X + Y, conj(w) (X - Y)).  The coefficients are
+// scattered through the same gather table (its inverse permutation), the
+// radix-16 groups run from the lowest bits up, and the last group (the top
+// bits, group 1 of the forward kernel) stores straight to the output rows in
+// ascending sample order, scaled by 1/N.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void butterfly_adj(float2& X, float2& Y, const float2 w) {
+  const float dr = X.x - Y.x, di = X.y - Y.y;
+  X.x += Y.x;
+  X.y += Y.y;
+  Y.x = fmaf(w.x, dr, w.y * di);
+  Y.y = fmaf(w.x, di, -w.y * dr);
+}
+
+template <int S>
+__global__ void __launch_bounds__(FusedShape<S>::THREADS)
+hidft_inverse_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ out,
+                     int64_t ld_out, uint64_t batch, const float2* __restrict__ tw,
+                     const uint16_t* __restrict__ src, float scale) {
+  using Sh = FusedShape<S>;
+  constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, SPB = Sh::SPB, G = Sh::G, G1 = Sh::G1;
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int slot = tid / T;
+  const int tau = tid - slot * T;
+  float2* L = lds + slot * Sh::PADK;
+  const uint64_t n_groups = (batch + SPB - 1) / SPB;
+
+  // One group of signals; BIG sizes run one per block (see FusedShape), the
+  // others walk the batch with a grid stride.
+  auto body = [&](uint64_t grp) {
+    const uint64_t sig = grp * SPB + slot;
+    const bool valid = sig < batch;
+    float2 v[R];
+    {
+      const float2* row = in + (valid ? sig : 0) * (uint64_t)ld_in;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        const int t = c * T + tau;
+        L[lds_pad<RHO>((int)src[t])] = valid ? row[t] : make_float2(0.f, 0.f);
+      }
+    }
+    // Groups G..2 (lowest bits first), each stage reversed within the group.
+#pragma unroll
+    for (int g = G; g >= 2; --g) {
+      const int lo = S - G1 - (g - 1) * RHO;
+      const int a_lo = tau & ((1 << lo) - 1);
+      const int a_hi = tau >> lo;
+      const int base = a_lo + (a_hi << (lo + RHO));
+      lds_barrier();
+#pragma unroll
+      for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(base + (c << lo))];
+#pragma unroll
+      for (int t = RHO - 1; t >= 0; --t) {
+        const int u = S - lo - RHO + 1 + t;
+        const int bit = RHO - 1 - t;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+          if (c & (1 << bit)) continue;
+          const float2 w = tw[((1 << (u - 1)) - 1) + (a_hi << t) + (c >> (RHO - t))];
+          butterfly_adj(v[c], v[c | (1 << bit)], w);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < R; ++c) L[lds_pad<RHO>(base + (c << lo))] = v[c];
+    }
+    lds_barrier();
+    // Group 1 (the top G1 bits of a), then the coalesced store.
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(c * T + tau)];
+#pragma unroll
+    for (int u = G1; u >= 1; --u) {
+      const int bit = RHO - u;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (c & (1 << bit)) continue;
+        butterfly_adj(v[c], v[c | (1 << bit)], tw[(1 << (u - 1)) - 1 + (c >> (bit + 1))]);
+      }
+    }
+    if (valid) {
+      float2* orow = out + sig * (uint64_t)ld_out;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        orow[c * T + tau] = make_float2(v[c].x * scale, v[c].y * scale);
+    }
+  };
+  if constexpr (Sh::BIG) {
+    body(blockIdx.x);
+  } else {
+    for (uint64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+      body(grp);
+      lds_barrier();  // the next group of signals overwrites these LDS slots
+    }
+  }
+}
+
+template <int S>
+static hipError_t launch_inverse_s(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
+                                   uint64_t batch, const float2* tw, const uint16_t* src,
+                                   float scale, hipStream_t stream) {
+  using Sh = FusedShape<S>;
+  static int max_grid = 0;  // benign race: every thread computes the same value
+  if (max_grid == 0) {
+    hipError_t e = hipFuncSetAttribute((const void*)hidft_inverse_kernel<S>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)Sh::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+             &per_cu, (const void*)hidft_inverse_kernel<S>, Sh::THREADS, Sh::LDS_BYTES)) !=
+        hipSuccess)
+      return e;
+    max_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  }
+  if constexpr (Sh::BIG) {
+    const uint64_t chunk = 0x7fffffffULL;  // one block per signal
+    for (uint64_t first = 0; first < batch; first += chunk) {
+      const uint64_t n = batch - first < chunk ? batch - first : chunk;
+      hipLaunchKernelGGL(hidft_inverse_kernel<S>, dim3((unsigned)n), dim3(Sh::THREADS),
+                         Sh::LDS_BYTES, stream, in + first * (uint64_t)ld_in, ld_in,
+                         out + first * (uint64_t)ld_out, ld_out, n, tw, src, scale);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const uint64_t groups = (batch + Sh::SPB - 1) / Sh::SPB;
+  const unsigned grid = (unsigned)(groups < (uint64_t)max_grid ? groups : (uint64_t)max_grid);
+  hipLaunchKernelGGL(hidft_inverse_kernel<S>, dim3(grid), dim3(Sh::THREADS), Sh::LDS_BYTES,
+                     stream, in, ld_in, out, ld_out, batch, tw, src, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_inverse(uint32_t s, const float2* in, int64_t ld_in, float2* out,
+                          int64_t ld_out, uint64_t batch, const float2* tw, const uint16_t* src,
+                          float scale, hipStream_t stream) {
+  if (batch == 0) return hipSuccess;
+  switch (s) {
+    case 0: {
+      const uint64_t blocks = (batch + 255) / 256;
+      if (blocks > 0x7fffffffULL) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(hidft_k1_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, in,
+                         ld_in, out, ld_out, batch, scale);
+      return hipGetLastError();
+    }
+#define HIDFT_CASE(S) \
+  case S:             \
+    return launch_inverse_s<S>(in, ld_in, out, ld_out, batch, tw, src, scale, stream);
+    HIDFT_CASE(1) HIDFT_CASE(2) HIDFT_CASE(3) HIDFT_CASE(4) HIDFT_CASE(5) HIDFT_CASE(6)
+    HIDFT_CASE(7) HIDFT_CASE(8) HIDFT_CASE(9) HIDFT_CASE(10) HIDFT_CASE(11) HIDFT_CASE(12)
+    HIDFT_CASE(13) HIDFT_CASE(14)
+#undef HIDFT_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 template <int S>
 static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
                                  uint64_t batch, const float2* tw, const uint16_t* src,
@@ -555,6 +722,78 @@ hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const Grou
   const unsigned grid = n_packs < (uint32_t)max_grid ? n_packs : (unsigned)max_grid;
   hipLaunchKernelGGL(hidft_grouped_kernel, dim3(grid), dim3(GROUPED_THREADS), lds_bytes, stream,
                      d_packs, n_packs, d_slots);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Shift-and-Sample leaf solves (Algorithm 2, steps 5-7), FP64.
+//
+// y holds, per signal b and shift j < mu*, the Hi-DFT of the samples on
+// I_r + j scaled by N/2^s, in slot order: y_j(v) = sum_{l in v} c_l e^{2 pi i j l / N}
+// at the slot of node v.  For each node the mu(v) unknowns c_l solve the
+// dual Vandermonde system sum_t c_t z_t^j = y_j, j < mu(v), z_t = e^{2 pi i l_t / N}
+// (Eq. alg1_system), here by the Bjorck-Pereyra recurrences for that system
+// (O(mu^2) operations, O(mu) storage).  One thread per (signal, node).
+// ---------------------------------------------------------------------------
+struct cplx64 {
+  double x, y;
+};
+__device__ __forceinline__ cplx64 csub(cplx64 a, cplx64 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cplx64 cmul(cplx64 a, cplx64 b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ cplx64 cdiv(cplx64 a, cplx64 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+
+__global__ void __launch_bounds__(128)
+sas_leaf_kernel(const float2* __restrict__ y, uint32_t ks, uint32_t mu_star, uint64_t batch,
+                uint32_t n_nodes, const uint32_t* __restrict__ node_slot,
+                const uint32_t* __restrict__ node_first, const uint32_t* __restrict__ node_count,
+                const uint32_t* __restrict__ elem_t, const uint64_t* __restrict__ elem_val,
+                uint32_t log2_n, float2* __restrict__ out, int64_t ld_out) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= batch * (uint64_t)n_nodes) return;
+  const uint64_t b = idx / n_nodes;
+  const uint32_t v = (uint32_t)(idx - b * n_nodes);
+  const uint32_t mu = node_count[v];
+  const uint32_t first = node_first[v];
+  const uint32_t slot = node_slot[v];
+  cplx64 x[SAS_MAX_MU], z[SAS_MAX_MU];
+  for (uint32_t t = 0; t < mu; ++t) {
+    // z = exp(2 pi i l / N) = cospi(2l/N) + i sinpi(2l/N); 2l/N = l 2^{1-M} is exact
+    // for l < 2^53.
+    double sn, cs;
+    sincospi(ldexp((double)elem_val[first + t], 1 - (int)log2_n), &sn, &cs);
+    z[t] = {cs, sn};
+    const float2 yj = y[(b * mu_star + t) * ks + slot];
+    x[t] = {(double)yj.x, (double)yj.y};
+  }
+  const int n = (int)mu - 1;
+  for (int k = 0; k < n; ++k)
+    for (int i = n; i > k; --i) x[i] = csub(x[i], cmul(z[k], x[i - 1]));
+  for (int k = n - 1; k >= 0; --k) {
+    for (int i = k + 1; i <= n; ++i) x[i] = cdiv(x[i], csub(z[i], z[i - k - 1]));
+    for (int i = k; i < n; ++i) x[i] = csub(x[i], x[i + 1]);
+  }
+  float2* orow = out + b * (uint64_t)ld_out;
+  for (uint32_t t = 0; t < mu; ++t)
+    orow[elem_t[first + t]] = make_float2((float)x[t].x, (float)x[t].y);
+}
+
+hipError_t launch_sas_leaf(const float2* y, uint32_t ks, uint32_t mu_star, uint64_t batch,
+                           uint32_t n_nodes, const uint32_t* node_slot, const uint32_t* node_first,
+                           const uint32_t* node_count, const uint32_t* elem_t,
+                           const uint64_t* elem_val, uint32_t log2_n, float2* out, int64_t ld_out,
+                           hipStream_t stream) {
+  const uint64_t work = batch * (uint64_t)n_nodes;
+  if (work == 0) return hipSuccess;
+  const uint64_t blocks = (work + 127) / 128;
+  if (blocks > 0x7fffffffULL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sas_leaf_kernel, dim3((unsigned)blocks), dim3(128), 0, stream, y, ks,
+                     mu_star, batch, n_nodes, node_slot, node_first, node_count, elem_t, elem_val,
+                     log2_n, out, ld_out);
   return hipGetLastError();
 }
 

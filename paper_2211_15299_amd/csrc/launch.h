@@ -19,6 +19,11 @@ hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out
                         int64_t ld_out, uint64_t batch, const float2* tw, const uint16_t* src,
                         float scale, hipStream_t stream);
 
+// Inverse (adjoint) transform of size 2^s: coefficients -> samples, scaled.
+hipError_t launch_inverse(uint32_t s, const float2* in, int64_t ld_in, float2* out,
+                          int64_t ld_out, uint64_t batch, const float2* tw, const uint16_t* src,
+                          float scale, hipStream_t stream);
+
 // LDS bytes of one fused block for size 2^s.
 size_t fused_lds_bytes(uint32_t s);
 
@@ -45,6 +50,18 @@ int grouped_slots_per_pack(uint32_t s);
 // Grouped persistent launch over n_packs packs.
 hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,
                           hipStream_t stream);
+
+// Largest node (number of aliased coefficients) the leaf solves handle.
+constexpr int SAS_MAX_MU = 32;
+
+// Shift-and-Sample leaf solves: one FP64 dual Vandermonde solve per node and
+// signal, from the shifted Hi-DFT values y (slot order, mu* rows of ks per
+// signal), writing the coefficients to their positions t in the output rows.
+hipError_t launch_sas_leaf(const float2* y, uint32_t ks, uint32_t mu_star, uint64_t batch,
+                           uint32_t n_nodes, const uint32_t* node_slot, const uint32_t* node_first,
+                           const uint32_t* node_count, const uint32_t* elem_t,
+                           const uint64_t* elem_val, uint32_t log2_n, float2* out, int64_t ld_out,
+                           hipStream_t stream);
 
 // Plain method: one signal, one block, one radix-2 stage per barrier.
 hipError_t launch_plain(uint32_t s, const float2* in, float2* out, const float2* tw,

@@ -146,4 +146,157 @@ hidft_status build_plan_core(uint32_t M, const uint64_t* J, uint64_t k,
   return HIDFT_OK;
 }
 
+// Nodes of J at `level` (classes modulo 2^level): counts and mu*.
+static void node_sizes(const uint64_t* J, uint64_t k, uint32_t level, uint64_t* mu_max,
+                       double* sum_sq) {
+  const uint64_t mask = level >= 64 ? ~0ULL : ((1ULL << level) - 1);
+  std::vector<uint64_t> res(k);
+  for (uint64_t t = 0; t < k; ++t) res[t] = J[t] & mask;
+  std::sort(res.begin(), res.end());
+  *mu_max = 0;
+  *sum_sq = 0;
+  for (uint64_t a = 0; a < k;) {
+    uint64_t b = a;
+    while (b < k && res[b] == res[a]) ++b;
+    const uint64_t m = b - a;
+    *mu_max = std::max(*mu_max, m);
+    *sum_sq += (double)m * (double)m;
+    a = b;
+  }
+}
+
+hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const uint32_t* r,
+                             uint32_t nr, uint32_t max_s, uint32_t max_mu, PartPlan* pp,
+                             std::string* err) {
+  uint64_t mask = 0;
+  hidft_status st = analyze_core(M, J, k, &mask, err);
+  if (st != HIDFT_OK) return st;
+  std::vector<uint32_t> piv;
+  for (uint32_t e = 0; e < 64; ++e)
+    if ((mask >> e) & 1) piv.push_back(e);
+
+  std::vector<uint32_t> rv;
+  if (r != nullptr) {
+    for (uint32_t u = 0; u < nr; ++u) {
+      if (r[u] >= M || (u > 0 && r[u] <= r[u - 1])) {
+        set_err(err, "pivot vector must be strictly ascending in [0, M) (entry %llu)", u);
+        return HIDFT_ERR_INVALID_ARGUMENT;
+      }
+      rv.push_back(r[u]);
+    }
+    if (!rv.empty())
+      for (uint32_t p : piv)
+        if (p <= rv.back() && !std::binary_search(rv.begin(), rv.end(), p)) {
+          set_err(err, "J has pivot %llu below r_max = %llu that is not in r: "
+                       "not part-homogeneous at r", p, rv.back());
+          return HIDFT_ERR_NOT_HOMOGENEOUS;
+        }
+    if (rv.size() > max_s) {
+      set_err(err, "2^%llu samples per Hi-DFT exceed the supported 2^%llu", rv.size(), max_s);
+      return HIDFT_ERR_UNSUPPORTED;
+    }
+  } else {
+    double best = -1;
+    uint32_t best_t = 0;
+    bool found = false;
+    for (uint32_t t = 0; t <= piv.size() && t <= max_s; ++t) {
+      uint64_t mu = 0;
+      double sq = 0;
+      node_sizes(J, k, t ? piv[t - 1] + 1 : 0, &mu, &sq);
+      if (mu > max_mu) continue;
+      const double cost = 1.5 * t * (double)(1ULL << t) * (double)mu + 6.0 * sq;
+      if (!found || cost < best) {
+        best = cost;
+        best_t = t;
+        found = true;
+      }
+    }
+    if (!found) {
+      set_err(err, "no prefix of the pivots of J keeps mu* <= %llu with 2^s <= 2^%llu",
+              max_mu, max_s);
+      return HIDFT_ERR_UNSUPPORTED;
+    }
+    rv.assign(piv.begin(), piv.begin() + best_t);
+  }
+
+  const uint32_t s = (uint32_t)rv.size();
+  const uint32_t level = s ? rv.back() + 1 : 0;
+  const uint64_t lmask = level >= 64 ? ~0ULL : ((1ULL << level) - 1);
+  pp->M = M;
+  pp->s = s;
+  pp->level = level;
+  pp->k = k;
+  pp->J.assign(J, J + k);
+  pp->pivots = rv;
+
+  // Nodes: positions sorted by (slot, t).
+  auto slot_of = [&](uint64_t x) {
+    uint32_t q = 0;
+    for (uint32_t u = 0; u < s; ++u) q |= (uint32_t)((x >> rv[u]) & 1) << u;
+    return q;
+  };
+  std::vector<std::pair<uint64_t, uint32_t>> order(k);  // (slot << 32 | 0, t) via residue
+  std::vector<uint32_t> slot_t(k);
+  for (uint64_t t = 0; t < k; ++t) {
+    slot_t[t] = slot_of(J[t] & lmask);
+    order[t] = {((uint64_t)slot_t[t] << 32) | 0u, (uint32_t)t};
+  }
+  std::sort(order.begin(), order.end());
+  pp->node_slot.clear();
+  pp->node_residue.clear();
+  pp->node_first.clear();
+  pp->node_count.clear();
+  pp->elem_t.resize(k);
+  pp->mu_max = 0;
+  double sq = 0;
+  for (uint64_t a = 0; a < k;) {
+    uint64_t b = a;
+    while (b < k && (order[b].first >> 32) == (order[a].first >> 32)) ++b;
+    const uint64_t res = J[order[a].second] & lmask;
+    for (uint64_t i = a; i < b; ++i) {
+      if ((J[order[i].second] & lmask) != res) {
+        set_err(err, "internal: one slot holds two residues (not part-homogeneous)");
+        return HIDFT_ERR_NOT_HOMOGENEOUS;
+      }
+      pp->elem_t[i] = order[i].second;
+    }
+    pp->node_slot.push_back((uint32_t)(order[a].first >> 32));
+    pp->node_residue.push_back(res);
+    pp->node_first.push_back((uint32_t)a);
+    pp->node_count.push_back((uint32_t)(b - a));
+    pp->mu_max = std::max<uint32_t>(pp->mu_max, (uint32_t)(b - a));
+    sq += (double)(b - a) * (double)(b - a);
+    a = b;
+  }
+  pp->cost = 1.5 * s * (double)(1ULL << s) * pp->mu_max + 6.0 * sq;
+
+  // Sample set I_r ascending, as in build_plan_core.
+  const uint64_t ks = 1ULL << s;
+  pp->samples.assign(ks, 0);
+  for (uint64_t a = 0; a < ks; ++a) {
+    const uint64_t p = bit_reverse(a, s);
+    uint64_t i = 0;
+    for (uint32_t u = 0; u < s; ++u)
+      if ((p >> u) & 1) i |= 1ULL << (M - 1 - rv[u]);
+    pp->samples[a] = i;
+  }
+
+  // Twiddles of Lemma 3 from node representatives: all elements whose first
+  // u-1 pivot bits spell q_lo agree modulo 2^{r_u}; prefixes without any
+  // element get 0 (their outputs belong to no node).
+  const uint64_t ntw = ks - 1;
+  pp->tw_num.assign(ntw, 0);
+  pp->tw_log2den.assign(ntw, 0);
+  for (uint32_t u = 1; u <= s; ++u) {
+    const uint32_t ru = rv[u - 1];
+    const uint64_t off = (1ULL << (u - 1)) - 1;
+    for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) pp->tw_log2den[off + q_lo] = (uint8_t)ru;
+    for (size_t v = 0; v < pp->node_slot.size(); ++v) {
+      const uint64_t q_lo = pp->node_slot[v] & ((1ULL << (u - 1)) - 1);
+      pp->tw_num[off + q_lo] = pp->node_residue[v] & ((1ULL << ru) - 1);
+    }
+  }
+  return HIDFT_OK;
+}
+
 }  // namespace hidft

@@ -33,4 +33,35 @@ hidft_status analyze_core(uint32_t M, const uint64_t* J, uint64_t k,
 hidft_status build_plan_core(uint32_t M, const uint64_t* J, uint64_t k,
                              uint32_t max_log2_k, PlanCore* pc, std::string* err);
 
+// Plan of the Hi-DFT at a pivot vector r of an r-part-homogeneous J
+// (Sec. VI Def. part-homogeneous, Sec. VII-B, Algorithm 2): nodes of T(J) at
+// level r_max + 1 are indexed by the slot q = sum_u bit_{r_u}(residue) 2^{u-1},
+// which part-homogeneity makes injective on nodes.
+struct PartPlan {
+  uint32_t M = 0;
+  uint32_t s = 0;                   // |r|; the Hi-DFT has 2^s samples and slots
+  uint32_t level = 0;               // r_max + 1 (0 when r is empty)
+  uint32_t mu_max = 0;              // mu*: largest node
+  uint64_t k = 0;                   // |J|
+  std::vector<uint64_t> J;
+  std::vector<uint32_t> pivots;     // r, ascending
+  std::vector<uint64_t> samples;    // I_r ascending (2^s)
+  std::vector<uint64_t> tw_num;     // 2^s - 1 twiddles, schedule order (stage u, q_lo)
+  std::vector<uint8_t> tw_log2den;
+  std::vector<uint32_t> node_slot;  // per node, nodes in ascending slot order
+  std::vector<uint64_t> node_residue;
+  std::vector<uint32_t> node_first; // into elem_t
+  std::vector<uint32_t> node_count; // mu(v)
+  std::vector<uint32_t> elem_t;     // caller positions, grouped by node, ascending within
+  double cost = 0;                  // Lemma 4 with c1 = 3/2, c2 = 6
+};
+
+// Builds the plan.  If r == nullptr the pivot vector is chosen: the first t
+// pivots of J (J is part-homogeneous at any such prefix) for the t that
+// minimises Lemma 4's cost among those with mu* <= max_mu and t <= max_s.
+// A given r is only checked for part-homogeneity and |r| <= max_s.
+hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const uint32_t* r,
+                             uint32_t nr, uint32_t max_s, uint32_t max_mu, PartPlan* pp,
+                             std::string* err);
+
 }  // namespace hidft

@@ -1,0 +1,277 @@
+// Shift-and-Sample plans (Sec. IX, Algorithm 2) and the Hi-DFT of
+// part-homogeneous supports (Sec. VII-B): C ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hidft.h"
+#include "internal.h"
+
+struct hidft_sas_s {
+  hidft::PartPlan core;
+  int device = -1;
+  float scale = 1.0f;              // N / 2^s
+  float2* d_tw = nullptr;          // 2^s - 1 twiddles, a-order
+  uint16_t* d_src = nullptr;       // slot order: src[t] = bitrev_s(t)
+  uint32_t* d_node_slot = nullptr;
+  uint32_t* d_node_first = nullptr;
+  uint32_t* d_node_count = nullptr;
+  uint32_t* d_elem_t = nullptr;
+  uint64_t* d_elem_val = nullptr;
+  size_t device_bytes = 0;
+};
+
+namespace {
+
+void release(hidft_sas p) {
+  void* ptrs[] = {p->d_tw, p->d_src, p->d_node_slot, p->d_node_first,
+                  p->d_node_count, p->d_elem_t, p->d_elem_val};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  p->d_tw = nullptr;
+  p->d_src = nullptr;
+  p->d_node_slot = p->d_node_first = p->d_node_count = p->d_elem_t = nullptr;
+  p->d_elem_val = nullptr;
+}
+
+template <typename T>
+hipError_t upload_vec(T** dst, const std::vector<T>& v, hipStream_t st, size_t* total) {
+  const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e != hipSuccess) return e;
+  *total += bytes;
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+hidft_status upload(hidft_sas p, hipStream_t st) {
+  const hidft::PartPlan& c = p->core;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_create");
+  const uint64_t ks = 1ULL << c.s;
+  const uint64_t ntw = ks - 1;
+  std::vector<uint64_t> num(ntw ? ntw : 1, 0);
+  std::vector<uint8_t> den(ntw ? ntw : 1, 0);
+  for (uint32_t u = 1; u <= c.s; ++u) {
+    const uint64_t off = (1ULL << (u - 1)) - 1;
+    for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
+      const uint64_t h = hidft::bit_reverse(q_lo, u - 1);
+      num[off + h] = c.tw_num[off + q_lo];
+      den[off + h] = c.tw_log2den[off + q_lo];
+    }
+  }
+  std::vector<uint16_t> src(ks);
+  for (uint64_t t = 0; t < ks; ++t) src[t] = (uint16_t)hidft::bit_reverse(t, c.s);
+  std::vector<uint64_t> elem_val(c.k);
+  for (uint64_t i = 0; i < c.k; ++i) elem_val[i] = c.J[c.elem_t[i]];
+  uint64_t* d_num = nullptr;
+  uint8_t* d_den = nullptr;
+  size_t total = 0, tmp = 0;
+  hidft_status status = HIDFT_OK;
+  if ((e = hipMalloc(&p->d_tw, (ntw ? ntw : 1) * sizeof(float2))) != hipSuccess ||
+      (e = upload_vec(&d_num, num, st, &tmp)) != hipSuccess ||
+      (e = upload_vec(&d_den, den, st, &tmp)) != hipSuccess ||
+      (e = upload_vec(&p->d_src, src, st, &total)) != hipSuccess ||
+      (e = upload_vec(&p->d_node_slot, c.node_slot, st, &total)) != hipSuccess ||
+      (e = upload_vec(&p->d_node_first, c.node_first, st, &total)) != hipSuccess ||
+      (e = upload_vec(&p->d_node_count, c.node_count, st, &total)) != hipSuccess ||
+      (e = upload_vec(&p->d_elem_t, c.elem_t, st, &total)) != hipSuccess ||
+      (e = upload_vec(&p->d_elem_val, elem_val, st, &total)) != hipSuccess ||
+      (e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    status = hidft::hip_error(e, "hidft_sas_create: table upload");
+  }
+  if (d_num) (void)hipFree(d_num);
+  if (d_den) (void)hipFree(d_den);
+  if (status != HIDFT_OK) {
+    release(p);
+    return status;
+  }
+  p->device_bytes = total + (ntw ? ntw : 1) * sizeof(float2);
+  return HIDFT_OK;
+}
+
+hidft_status check_rows(hidft_sas p, const void* in, int64_t ld_in, uint64_t in_len,
+                        const void* out, int64_t ld_out, uint64_t out_len, uint64_t batch,
+                        const char* fn) {
+  if (!p) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, std::string(fn) + ": plan is NULL");
+  if (batch == 0) return HIDFT_OK;
+  if (!in || !out)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, std::string(fn) + ": NULL buffer");
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 7u)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                            std::string(fn) + ": buffers must be 8-byte aligned");
+  if (ld_in < 0 || ld_out < 0 || (uint64_t)ld_in < in_len || (uint64_t)ld_out < out_len)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                            std::string(fn) + ": leading dimension smaller than a row");
+  if (batch > (1ULL << 31))
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, std::string(fn) + ": batch too large");
+  const uint64_t a0 = reinterpret_cast<uintptr_t>(in);
+  const uint64_t a1 = a0 + ((batch - 1) * (uint64_t)ld_in + in_len) * 8;
+  const uint64_t b0 = reinterpret_cast<uintptr_t>(out);
+  const uint64_t b1 = b0 + ((batch - 1) * (uint64_t)ld_out + out_len) * 8;
+  if (a0 < b1 && b0 < a1)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                            std::string(fn) + ": input and output overlap");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hidft::hip_error(e, fn);
+  if (dev != p->device)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                            std::string(fn) + ": current device differs from the plan's");
+  return HIDFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
+                              const uint32_t* pivots, uint32_t n_pivots, uint32_t flags,
+                              void* stream, hidft_sas* out) {
+  if (!out) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_create: out is NULL");
+  *out = nullptr;
+  if (flags & ~HIDFT_PLAN_HOST_ONLY)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_create: unknown flags");
+  hidft_sas p = nullptr;
+  try {
+    p = new hidft_sas_s;
+    std::string err;
+    hidft_status st = hidft::build_part_plan(log2_n, J, k, pivots, n_pivots,
+                                             HIDFT_MAX_LOG2_K_DEVICE, HIDFT_SAS_MAX_MU,
+                                             &p->core, &err);
+    if (st != HIDFT_OK) {
+      delete p;
+      return hidft::set_error(st, "hidft_sas_create: " + err);
+    }
+    p->scale = std::ldexp(1.0f, (int)p->core.M - (int)p->core.s);
+    if (!(flags & HIDFT_PLAN_HOST_ONLY)) {
+      st = upload(p, static_cast<hipStream_t>(stream));
+      if (st != HIDFT_OK) {
+        delete p;
+        return st;
+      }
+    }
+    *out = p;
+    return hidft::set_error(HIDFT_OK, "");
+  } catch (const std::bad_alloc&) {
+    if (p) {
+      release(p);
+      delete p;
+    }
+    return hidft::set_error(HIDFT_ERR_OUT_OF_MEMORY, "hidft_sas_create: host allocation failed");
+  }
+}
+
+hidft_status hidft_sas_destroy(hidft_sas p) {
+  if (!p) return hidft::set_error(HIDFT_OK, "");
+  release(p);
+  delete p;
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_sas_get_info(hidft_sas p, uint32_t* n_pivots, uint32_t* mu_max,
+                                uint64_t* n_nodes, uint64_t* samples_per_signal, double* cost) {
+  if (!p) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_get_info: plan is NULL");
+  if (n_pivots) *n_pivots = p->core.s;
+  if (mu_max) *mu_max = p->core.mu_max;
+  if (n_nodes) *n_nodes = p->core.node_slot.size();
+  if (samples_per_signal) *samples_per_signal = (uint64_t)p->core.mu_max << p->core.s;
+  if (cost) *cost = p->core.cost;
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_sas_get_pivots(hidft_sas p, uint32_t* pivots) {
+  if (!p || !pivots)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_get_pivots: NULL argument");
+  std::memcpy(pivots, p->core.pivots.data(), p->core.s * sizeof(uint32_t));
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_sas_get_samples(hidft_sas p, uint64_t* idx) {
+  if (!p || !idx)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_get_samples: NULL argument");
+  const uint64_t ks = 1ULL << p->core.s;
+  const uint64_t mask = p->core.M >= 64 ? ~0ULL : ((1ULL << p->core.M) - 1);
+  for (uint32_t j = 0; j < p->core.mu_max; ++j)
+    for (uint64_t a = 0; a < ks; ++a) idx[j * ks + a] = (p->core.samples[a] + j) & mask;
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_sas_get_nodes(hidft_sas p, uint32_t* node_of_t, uint32_t* slot_of_node) {
+  if (!p) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_get_nodes: plan is NULL");
+  const hidft::PartPlan& c = p->core;
+  if (node_of_t)
+    for (size_t v = 0; v < c.node_slot.size(); ++v)
+      for (uint32_t i = 0; i < c.node_count[v]; ++i) node_of_t[c.elem_t[c.node_first[v] + i]] = (uint32_t)v;
+  if (slot_of_node) std::memcpy(slot_of_node, c.node_slot.data(), c.node_slot.size() * 4);
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_sas_workspace_bytes(hidft_sas p, uint64_t batch, size_t* bytes) {
+  if (!p || !bytes)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_workspace_bytes: NULL");
+  *bytes = (size_t)batch * p->core.mu_max * (1ULL << p->core.s) * sizeof(float2);
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_sas_weights(hidft_sas p, const void* d_samples, int64_t ld_in, void* d_weights,
+                               int64_t ld_out, uint64_t batch, void* stream) {
+  const uint64_t ks = p ? (1ULL << p->core.s) : 0;
+  hidft_status st = check_rows(p, d_samples, ld_in, ks, d_weights, ld_out, ks, batch,
+                               "hidft_sas_weights");
+  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? hidft::set_error(HIDFT_OK, "") : st;
+  if (!p->d_tw)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_weights: HOST_ONLY plan");
+  hipError_t e = hidft::launch_fused(p->core.s, static_cast<const float2*>(d_samples), ld_in,
+                                     static_cast<float2*>(d_weights), ld_out, batch, p->d_tw,
+                                     p->d_src, p->scale, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_weights: kernel launch");
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in, void* d_coefs,
+                               int64_t ld_out, uint64_t batch, void* d_work, void* stream) {
+  const uint64_t ks = p ? (1ULL << p->core.s) : 0;
+  const uint64_t mu = p ? p->core.mu_max : 0;
+  if (p && mu > HIDFT_SAS_MAX_MU)
+    return hidft::set_error(HIDFT_ERR_UNSUPPORTED,
+                            "hidft_sas_execute: mu* = " + std::to_string(mu) +
+                                " exceeds the leaf solver's " + std::to_string(HIDFT_SAS_MAX_MU));
+  hidft_status st = check_rows(p, d_samples, ld_in, mu * ks, d_coefs, ld_out, p ? p->core.k : 0,
+                               batch, "hidft_sas_execute");
+  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? hidft::set_error(HIDFT_OK, "") : st;
+  if (!p->d_tw)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_execute: HOST_ONLY plan");
+  if (!d_work || (reinterpret_cast<uintptr_t>(d_work) & 7u))
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                            "hidft_sas_execute: workspace missing or misaligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float2* in = static_cast<const float2*>(d_samples);
+  float2* work = static_cast<float2*>(d_work);
+  hipError_t e = hipSuccess;
+  // Steps 2-4: the mu* shifted Hi-DFTs, as one batched launch when the rows
+  // are packed, else one launch per shift.
+  if ((uint64_t)ld_in == mu * ks) {
+    e = hidft::launch_fused(p->core.s, in, (int64_t)ks, work, (int64_t)ks, batch * mu, p->d_tw,
+                            p->d_src, p->scale, s);
+  } else {
+    for (uint64_t j = 0; j < mu && e == hipSuccess; ++j)
+      e = hidft::launch_fused(p->core.s, in + j * ks, ld_in, work + j * ks, (int64_t)(mu * ks),
+                              batch, p->d_tw, p->d_src, p->scale, s);
+  }
+  // Steps 5-7: one dual Vandermonde solve per node.
+  if (e == hipSuccess)
+    e = hidft::launch_sas_leaf(work, (uint32_t)ks, (uint32_t)mu, batch,
+                               (uint32_t)p->core.node_slot.size(), p->d_node_slot,
+                               p->d_node_first, p->d_node_count, p->d_elem_t, p->d_elem_val,
+                               p->core.M, static_cast<float2*>(d_coefs), ld_out, s);
+  if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+}  // extern "C"

@@ -52,6 +52,7 @@ SIGNATURES = [
     ("hidft_plan_device_bytes", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("hidft_execute", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
     ("hidft_execute_plain", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
+    ("hidft_execute_inverse", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
     ("hidft_group_create", ctypes.c_int, [_vp, _u64, _vp, _pp]),
     ("hidft_group_execute", ctypes.c_int, [_vp, _vp]),
     ("hidft_group_destroy", ctypes.c_int, [_vp]),
@@ -64,6 +65,18 @@ SIGNATURES = [
     ("hidft_server_drain", ctypes.c_int, [_vp]),
     ("hidft_server_get_stats", ctypes.c_int, [_vp, _vp]),
     ("hidft_server_destroy", ctypes.c_int, [_vp]),
+    ("hidft_sas_create", ctypes.c_int, [_u32, ctypes.POINTER(_u64), _u64, ctypes.POINTER(_u32),
+                                        _u32, _u32, _vp, _pp]),
+    ("hidft_sas_destroy", ctypes.c_int, [_vp]),
+    ("hidft_sas_get_info", ctypes.c_int, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32),
+                                          ctypes.POINTER(_u64), ctypes.POINTER(_u64),
+                                          ctypes.POINTER(ctypes.c_double)]),
+    ("hidft_sas_get_pivots", ctypes.c_int, [_vp, ctypes.POINTER(_u32)]),
+    ("hidft_sas_get_samples", ctypes.c_int, [_vp, ctypes.POINTER(_u64)]),
+    ("hidft_sas_get_nodes", ctypes.c_int, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
+    ("hidft_sas_workspace_bytes", ctypes.c_int, [_vp, _u64, ctypes.POINTER(ctypes.c_size_t)]),
+    ("hidft_sas_execute", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp, _vp]),
+    ("hidft_sas_weights", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
     ("hidft_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("hidft_last_error", ctypes.c_char_p, []),
 ]
@@ -208,6 +221,11 @@ class Plan:
         fn = lib().hidft_execute_plain if plain else lib().hidft_execute
         _check(fn(self.handle, d_in, ld_in, d_out, ld_out, batch, _stream_handle(stream)))
 
+    def inverse_ptr(self, d_coefs: int, ld_in: int, d_samples: int, ld_out: int, batch: int,
+                    stream=None) -> None:
+        _check(lib().hidft_execute_inverse(self.handle, d_coefs, ld_in, d_samples, ld_out, batch,
+                                           _stream_handle(stream)))
+
     # -- execution on torch tensors
     def execute(self, samples, out=None, stream=None, plain: bool = False):
         """Coefficients (batch, k) complex64 of samples (batch, k) or (k,) on the device."""
@@ -325,6 +343,76 @@ class Server:
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             _check(lib().hidft_server_destroy(self._h))
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SASPlan:
+    """Shift-and-Sample plan of a part-homogeneous support (hidft_sas_*).
+
+    pivots=None lets the planner choose r (Lemma 4's cost).
+    """
+
+    def __init__(self, log2_n: int, J: Sequence[int], pivots=None, host_only: bool = False,
+                 stream=None):
+        arr = _u64_array(J)
+        self._h = ctypes.c_void_p(None)
+        if pivots is None:
+            rp, nr = None, 0
+        else:  # an explicit vector, possibly empty: always a non-NULL pointer
+            self._r = np.zeros(max(len(pivots), 1), dtype=np.uint32)
+            self._r[: len(pivots)] = pivots
+            rp, nr = _ptr(self._r, _u32), len(pivots)
+        flags = HIDFT_PLAN_HOST_ONLY if host_only else 0
+        _check(lib().hidft_sas_create(log2_n, _ptr(arr, _u64), len(arr), rp, nr, flags,
+                                      None if host_only else _stream_handle(stream),
+                                      ctypes.byref(self._h)))
+        s, mu, nn, sp = _u32(0), _u32(0), _u64(0), _u64(0)
+        cost = ctypes.c_double(0)
+        _check(lib().hidft_sas_get_info(self._h, ctypes.byref(s), ctypes.byref(mu),
+                                        ctypes.byref(nn), ctypes.byref(sp), ctypes.byref(cost)))
+        self.log2_n, self.k = log2_n, len(arr)
+        self.s, self.mu_max, self.n_nodes = s.value, mu.value, nn.value
+        self.samples_per_signal, self.cost = sp.value, cost.value
+
+    def pivots(self):
+        out = np.zeros(max(self.s, 1), dtype=np.uint32)
+        _check(lib().hidft_sas_get_pivots(self._h, _ptr(out, _u32)))
+        return [int(x) for x in out[: self.s]]
+
+    def samples(self) -> np.ndarray:
+        out = np.zeros(self.samples_per_signal, dtype=np.uint64)
+        _check(lib().hidft_sas_get_samples(self._h, _ptr(out, _u64)))
+        return out
+
+    def nodes(self):
+        """(node index of each J[t], slot of each node)."""
+        nt = np.zeros(self.k, dtype=np.uint32)
+        sl = np.zeros(max(self.n_nodes, 1), dtype=np.uint32)
+        _check(lib().hidft_sas_get_nodes(self._h, _ptr(nt, _u32), _ptr(sl, _u32)))
+        return nt, sl[: self.n_nodes]
+
+    def workspace_bytes(self, batch: int) -> int:
+        b = ctypes.c_size_t(0)
+        _check(lib().hidft_sas_workspace_bytes(self._h, batch, ctypes.byref(b)))
+        return b.value
+
+    def execute_ptr(self, d_in, ld_in, d_out, ld_out, batch, d_work, stream=None):
+        _check(lib().hidft_sas_execute(self._h, d_in, ld_in, d_out, ld_out, batch, d_work,
+                                       _stream_handle(stream)))
+
+    def weights_ptr(self, d_in, ld_in, d_out, ld_out, batch, stream=None):
+        _check(lib().hidft_sas_weights(self._h, d_in, ld_in, d_out, ld_out, batch,
+                                       _stream_handle(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().hidft_sas_destroy(self._h))
             self._h = ctypes.c_void_p(None)
 
     def __del__(self):
