@@ -236,8 +236,17 @@ def main():
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(M, J, f_host, y, args.cpu_sample)
-    print(json.dumps(result), flush=True)
     plan.close()
+    del xs, ys, x, y, yp
+    torch.cuda.empty_cache()
+    # The other configurations, reported beside the headline (not the metric):
+    # the uneven batch in one grouped launch, and Poisson-arrival serving.
+    gsteps = args.steps
+    args.steps, args.warmup = 20, 3
+    result["config3_grouped"] = grouped_bench(args, native, torch, stream)
+    args.steps = gsteps
+    result["config5_serving"] = serve_bench(args, native, seconds=min(args.serve_seconds, 5.0))
+    print(json.dumps(result), flush=True)
 
 
 def grouped_instances(n):
