@@ -21,6 +21,11 @@ Prints one JSON line.  Modes for profiling runs:
   --mode serve     the serving configuration: Poisson arrivals (20k/s) of
                    requests over 256 supports reused Zipf(1.1), through the
                    continuous-batching server
+  --mode precision the precision configuration (N = 2^22, k = 2^14, 1024
+                   signals, |c| log-uniform on [1e-3, 1e3]): FP32 butterflies
+                   against the FP16 / BF16 split-precision matrix-core group
+The full run also reports the autotuned variant of the headline workload
+(hidft_autotune, then hidft_execute_config with the tuned variant).
 """
 from __future__ import annotations
 
@@ -50,7 +55,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", choices=["full", "execute", "copy", "grouped", "serve"],
+    ap.add_argument("--mode", choices=["full", "execute", "copy", "grouped", "serve", "precision"],
                     default="full")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="duration of the Poisson arrival process (serving)")
@@ -135,6 +140,10 @@ def main():
         del xs, ys, x, y
         print(json.dumps(serve_bench(args, native)), flush=True)
         return
+    if args.mode == "precision":
+        del xs, ys, x, y
+        print(json.dumps(precision_bench(args, native, torch, stream)), flush=True)
+        return
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -199,7 +208,7 @@ def main():
         "wall_s_timed": wall_s,
         "roofline": {
             "bound": "hbm",
-            "kernel": "hidft_fused_kernel<12>",
+            "kernel": "hidft_fused_kernel<12, SHORT_FIRST, radix 16, FP32>",
             "achieved": achieved_gbps,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
@@ -236,6 +245,32 @@ def main():
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(M, J, f_host, y, args.cpu_sample)
+
+    # The autotuner on the same workload: search, then the tuned variant timed
+    # like the headline loop.
+    tuned = native.ExecConfig(native.PREC_FP32, native.SCHED_TUNED, 0, 0)
+    t0 = time.perf_counter()
+    best, best_us = plan.autotune_ptr(xs[-1].data_ptr(), k, ys[-1].data_ptr(), k, batch,
+                                      reps=10, stream=stream)
+    search_s = time.perf_counter() - t0
+    for i in range(args.warmup):
+        j = i % args.sets
+        plan.execute_ptr(xs[j].data_ptr(), k, ys[j].data_ptr(), k, batch, stream, config=tuned)
+    torch.cuda.synchronize()
+    g0.record(stream)
+    for i in range(args.steps):
+        j = i % args.sets
+        plan.execute_ptr(xs[j].data_ptr(), k, ys[j].data_ptr(), k, batch, stream, config=tuned)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    tuned_ms = g0.elapsed_time(g1) / args.steps
+    result["autotuned"] = {
+        "config": {"precision": best.precision, "schedule": best.schedule, "radix": best.radix,
+                   "blocks_per_cu": best.blocks_per_cu},
+        "search_us_per_launch": best_us, "search_s": search_s,
+        "ms_per_step": tuned_ms, "transforms_per_s": batch / (tuned_ms * 1e-3),
+        "hbm_GBps": bytes_per_launch / (tuned_ms * 1e-3) / 1e9,
+    }
     plan.close()
     del xs, ys, x, y, yp
     torch.cuda.empty_cache()
@@ -246,6 +281,9 @@ def main():
     result["config3_grouped"] = grouped_bench(args, native, torch, stream)
     args.steps = gsteps
     result["config5_serving"] = serve_bench(args, native, seconds=min(args.serve_seconds, 5.0))
+    result["config4_precision"] = precision_bench(args, native, torch, stream, steps=20)
+    if not args.no_cpu:
+        result["cpu_baseline"]["precision_vs_oracle"] = precision_vs_oracle(native, torch, stream)
     print(json.dumps(result), flush=True)
 
 
@@ -388,6 +426,101 @@ def serve_bench(args, native, seconds=None):
             "plans_resident": int(st["plans_resident"]),
             "plan_warmup_s": plan_warm_s, "max_submit_lag_us": late * 1e6,
             "supports": 256, "zipf": 1.1}
+
+
+PRECISION_WORKLOAD = dict(workload="precision: N=2^22, k=2^14, 1024 signals, |c| log-uniform "
+                                   "on [1e-3, 1e3] with random phase", log2_n=22, log2_k=14,
+                          batch=1024)
+
+
+def _precision_setup(native, stream):
+    from workloads import homogeneous_support, rng_for
+    rng = rng_for(4, 0)
+    M, s = PRECISION_WORKLOAD["log2_n"], PRECISION_WORKLOAD["log2_k"]
+    sup = homogeneous_support(M, s, rng)
+    J = sup.J.tolist()
+    return M, J, native.Plan(M, J, stream=stream), rng
+
+
+def precision_bench(args, native, torch, stream, steps=None):
+    """Launch time of each precision of group 1 on the precision workload.
+
+    Samples of the workload's magnitude: per signal, CN(0, 1) scaled by
+    10^U(-3, 3) sqrt(k) / N (the size of samples of coefficients with that
+    spread).  Reports the FP32 path and the two split-precision matrix-core
+    paths, and how far each result is from the FP32 one.
+    """
+    from workloads import complex_normal
+    M, J, plan, rng = _precision_setup(native, stream)
+    k, batch, N = plan.k, PRECISION_WORKLOAD["batch"], float(1 << M)
+    f = complex_normal((batch, k), rng) * (10.0 ** rng.uniform(-3, 3, (batch, 1))) * np.sqrt(k) / N
+    sets = max(args.sets, 1)
+    xs = [torch.from_numpy(f.astype(np.complex64)).cuda()]
+    xs += [xs[0].clone() for _ in range(sets - 1)]
+    ys = [torch.empty_like(xs[0]) for _ in range(sets)]
+    steps = steps or args.steps
+    out = {"config": PRECISION_WORKLOAD, "sets": sets, "steps": steps}
+    ref = None
+    for name, prec in (("fp32", native.PREC_FP32), ("f16x2", native.PREC_F16X2),
+                       ("bf16x3", native.PREC_BF16X3)):
+        cfg = native.ExecConfig(prec, native.SCHED_DEFAULT, 0, 0)
+        for i in range(3):
+            plan.execute_ptr(xs[i % sets].data_ptr(), k, ys[i % sets].data_ptr(), k, batch,
+                             stream, config=cfg)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            plan.execute_ptr(xs[i % sets].data_ptr(), k, ys[i % sets].data_ptr(), k, batch,
+                             stream, config=cfg)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        plan.execute_ptr(xs[0].data_ptr(), k, ys[0].data_ptr(), k, batch, stream, config=cfg)
+        torch.cuda.synchronize()
+        y = ys[0].cpu().numpy().astype(np.complex128)
+        entry = {"ms_per_launch": ms, "transforms_per_s": batch / (ms * 1e-3),
+                 "GBps": batch * k * 16 / (ms * 1e-3) / 1e9}
+        if ref is None:
+            ref = y
+        else:
+            d = np.linalg.norm(y - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            entry["rel_l2_vs_fp32"] = {"max": float(d.max()), "median": float(np.median(d))}
+        out[name] = entry
+    plan.close()
+    del xs, ys
+    torch.cuda.empty_cache()
+    return out
+
+
+def precision_vs_oracle(native, torch, stream, n_exact=8):
+    """Per-instance error of each precision against the FP64 oracle on the
+    precision workload: n_exact signals synthesised by the oracle from seeded
+    coefficients (log-uniform magnitudes, random phase)."""
+    import oracle
+    from workloads import log_uniform_coefficients
+    M, J, plan, rng = _precision_setup(native, stream)
+    k = plan.k
+    c = log_uniform_coefficients((n_exact, k), rng)
+    t0 = time.perf_counter()
+    f = oracle.synthesize_samples_fft(M, J, c, plan.samples().tolist())
+    synth_s = time.perf_counter() - t0
+    x = torch.from_numpy(f.astype(np.complex64)).cuda()
+    out = {"instances": n_exact, "synthesis": "oracle.synthesize_samples_fft (FP64)",
+           "synthesis_s": synth_s}
+    for name, prec in (("fp32", native.PREC_FP32), ("f16x2", native.PREC_F16X2),
+                       ("bf16x3", native.PREC_BF16X3)):
+        y = plan.execute(x, config=native.ExecConfig(prec, native.SCHED_DEFAULT, 0, 0),
+                         stream=stream)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy().astype(np.complex128)
+        err = oracle.rel_l2(got, c)
+        mabs = oracle.max_abs(got, c)
+        out[name] = {"rel_l2": [float(e) for e in err], "rel_l2_max": float(err.max()),
+                     "max_abs": [float(a) for a in mabs], "max_abs_rel_to_max_coef":
+                     float(np.max(mabs / np.max(np.abs(c), axis=1)))}
+    plan.close()
+    return out
 
 
 def cpu_baseline(M, J, f_host, y_dev, n_sample):

@@ -182,6 +182,117 @@ hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in
                            void* stream);
 
 /*
+ * Execution variants of the fused transform (hidft_execute_config).
+ *
+ * precision -- arithmetic of the first radix-16 group of stages (stages
+ *   1..4 of Lemma 3, the recursion levels of the four lowest pivots, which
+ *   form one fixed 16 x 16 matrix per plan); every other stage is FP32:
+ *   HIDFT_PREC_FP32   FP32 butterflies (the default).
+ *   HIDFT_PREC_F16X2  matrix cores: samples and matrix split into two FP16
+ *                     terms (samples scaled per column by a power of two),
+ *                     three products summed in FP32.
+ *   HIDFT_PREC_BF16X3 matrix cores: three-term BF16 split, six products
+ *                     summed in FP32.
+ *   The matrix is computed in FP64 on the device at plan creation and split
+ *   there.  The matrix-core precisions need k >= 16.
+ * schedule -- where the short group of stages goes when 4 does not divide
+ *   s = log2 k (the transform runs in groups of four stages):
+ *   HIDFT_SCHED_DEFAULT      SHORT_FIRST for FP32, SHORT_LAST otherwise.
+ *   HIDFT_SCHED_SHORT_FIRST  the first group is short.
+ *   HIDFT_SCHED_SHORT_LAST   the first group is a full four stages and the
+ *                            last one is short (required by the matrix-core
+ *                            precisions when 4 does not divide s).
+ *   HIDFT_SCHED_TUNED        the whole variant (schedule, radix, blocks per
+ *                            CU) that hidft_autotune recorded for this
+ *                            device, size, precision and batch class; DEFAULT
+ *                            with the given radix and blocks_per_cu if none.
+ *   The schedules compute the same stages in a different grouping; results
+ *   agree to rounding.
+ * radix -- stages per group (and points per thread): 0 = default (16),
+ *   16, or 32 (FP32 and k >= 2^13 only: 13 = 3 + 5 + 5 stages, 14 = 4 + 5 + 5
+ *   with SHORT_FIRST).  Like the schedule, changes the grouping only.
+ * blocks_per_cu -- for k <= 2^12 (persistent launches): at most this many
+ *   resident workgroups per compute unit, 0 = as many as fit.  Ignored for
+ *   larger k (one workgroup per signal).  Does not change results.
+ */
+#define HIDFT_PREC_FP32 0u
+#define HIDFT_PREC_F16X2 1u
+#define HIDFT_PREC_BF16X3 2u
+
+#define HIDFT_SCHED_DEFAULT 0u
+#define HIDFT_SCHED_SHORT_FIRST 1u
+#define HIDFT_SCHED_SHORT_LAST 2u
+#define HIDFT_SCHED_TUNED 3u
+
+typedef struct hidft_exec_config {
+  uint32_t precision;
+  uint32_t schedule;
+  uint32_t radix;
+  uint32_t blocks_per_cu;
+} hidft_exec_config;
+
+/*
+ * hidft_execute_config -- hidft_execute with an explicit execution variant.
+ *
+ * Same contract as hidft_execute (Lemma 3, Sec. VII-B); `config` (host,
+ * read during the call only) selects precision, schedule and launch shape.
+ * hidft_execute is this call with {FP32, DEFAULT, 0, 0}.
+ * Errors: as hidft_execute, plus INVALID_ARGUMENT for a NULL config or an
+ * unknown precision, schedule or radix, and UNSUPPORTED for a matrix-core
+ * precision with k < 16, or with SHORT_FIRST when 4 does not divide s, and
+ * for radix 32 outside FP32 with k >= 2^13.
+ */
+hidft_status hidft_execute_config(hidft_plan plan, const hidft_exec_config* config,
+                                  const void* d_samples, int64_t ld_in, void* d_coefs,
+                                  int64_t ld_out, uint64_t batch, void* stream);
+
+/*
+ * hidft_autotune -- pick the fastest execution variant by measurement.
+ *
+ * Runs every variant of `precision` for this plan (both schedules where they
+ * differ, radix 16 and 32 where both exist, 0..3 blocks per CU for
+ * persistent sizes) on the caller's buffers, as hidft_execute_config would:
+ * two warm-up launches, then `reps` timed launches between two HIP events on
+ * `stream`, in two interleaved rounds (the better round counts).  Blocks until
+ * the measurements are done.  The winner goes to *best (and its mean launch
+ * time in microseconds to *best_us, which may be NULL) and into the
+ * process-wide tuning table under (device architecture and CU count,
+ * s = log2 k, precision, batch class floor(log2 batch)), replacing an older
+ * entry; HIDFT_SCHED_TUNED reads it back.
+ *
+ *   d_samples, ld_in, d_coefs, ld_out, batch  as for hidft_execute; the
+ *       samples are read and the coefficient rows are overwritten (they
+ *       hold the transform of the samples on return).  The buffers must be
+ *       distinct.
+ *   reps   timed launches per variant and round, > 0.
+ * Errors: as hidft_execute_config, plus INVALID_ARGUMENT for batch == 0,
+ * reps == 0, equal buffers or a NULL `best`; DEVICE for event failures.
+ */
+hidft_status hidft_autotune(hidft_plan plan, uint32_t precision, const void* d_samples,
+                            int64_t ld_in, void* d_coefs, int64_t ld_out, uint64_t batch,
+                            uint32_t reps, void* stream, hidft_exec_config* best,
+                            double* best_us);
+
+/* The tuning table entry for (plan's device, plan's s, precision, class of
+ * batch): *found = 1 and *config set, or *found = 0.  Host only. */
+hidft_status hidft_tune_lookup(hidft_plan plan, uint32_t precision, uint64_t batch,
+                               hidft_exec_config* config, int* found);
+
+/* Empties the process-wide tuning table. */
+hidft_status hidft_tune_clear(void);
+
+/*
+ * Saves the tuning table to a text file (header line "hidft-tune 1", then one
+ * entry per line: device tag, s, precision, batch class, schedule, radix,
+ * blocks per CU, measured microseconds), or merges such a file into the table
+ * (entries of the file replace equal keys).  INVALID_ARGUMENT if the file
+ * cannot be opened or written, lacks the header or has a malformed entry (the
+ * table is then unchanged).
+ */
+hidft_status hidft_tune_save(const char* path);
+hidft_status hidft_tune_load(const char* path);
+
+/*
  * hidft_execute_plain -- the plain per-signal GPU method (baseline).
  *
  * Same contract and results as hidft_execute, computed the textbook way:

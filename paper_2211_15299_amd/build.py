@@ -18,7 +18,7 @@ LIB_NAME = "libhidft.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 ARCH = "gfx950"
 
-SOURCES = ["plan_core.cpp", "capi.cpp", "server.cpp", "sas.cpp", "kernels.hip"]
+SOURCES = ["plan_core.cpp", "capi.cpp", "server.cpp", "sas.cpp", "tune.cpp", "kernels.hip"]
 
 # Packed FP32 instructions are disabled for all device code; -O3 otherwise
 # emits them from ordinary float code.

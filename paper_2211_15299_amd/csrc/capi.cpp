@@ -52,8 +52,10 @@ hidft_status hip_fail(hipError_t e, const char* what) {
 void release_device(hidft_plan p) {
   if (p->d_tw) (void)hipFree(p->d_tw);
   if (p->d_src) (void)hipFree(p->d_src);
+  if (p->d_amat) (void)hipFree(p->d_amat);
   p->d_tw = nullptr;
   p->d_src = nullptr;
+  p->d_amat = nullptr;
 }
 
 // Uploads the device tables and generates the twiddles on `stream`.
@@ -81,11 +83,14 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
     src[t] = static_cast<uint16_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
 
   const size_t ntw_alloc = ntw ? ntw : 1;
+  // The matrix-core group 1 (radix 16) needs its split matrix operands.
+  const bool with_amat = c.s >= 4;
   uint64_t* d_num = nullptr;
   uint8_t* d_den = nullptr;
   hidft_status st = HIDFT_OK;
   if ((e = hipMalloc(&p->d_tw, ntw_alloc * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&p->d_src, k * sizeof(uint16_t))) != hipSuccess ||
+      (with_amat && (e = hipMalloc(&p->d_amat, hidft::AMAT_BYTES)) != hipSuccess) ||
       (e = hipMalloc(&d_num, ntw_alloc * sizeof(uint64_t))) != hipSuccess ||
       (e = hipMalloc(&d_den, ntw_alloc)) != hipSuccess) {
     st = hip_fail(e, "hipMalloc of plan tables");
@@ -99,6 +104,9 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
   } else if ((e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, stream)) !=
              hipSuccess) {
     st = hip_fail(e, "twiddle generation launch");
+  } else if (with_amat &&
+             (e = hidft::launch_stage_matrix(d_num, d_den, p->d_amat, stream)) != hipSuccess) {
+    st = hip_fail(e, "stage matrix launch");
   } else if ((e = hipStreamSynchronize(stream)) != hipSuccess) {
     st = hip_fail(e, "hipStreamSynchronize after plan upload");
   }
@@ -108,7 +116,8 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
     release_device(p);
     return st;
   }
-  p->device_bytes = ntw_alloc * sizeof(float2) + k * sizeof(uint16_t);
+  p->device_bytes =
+      ntw_alloc * sizeof(float2) + k * sizeof(uint16_t) + (with_amat ? hidft::AMAT_BYTES : 0);
   return HIDFT_OK;
 }
 
@@ -182,6 +191,42 @@ void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
     }
     off += per_size[s];
   }
+}
+
+}  // namespace hidft
+
+namespace hidft {
+
+hidft_status resolve_config(const hidft_plan plan, const hidft_exec_config* cfg, ExecConfig* out,
+                            const char* fn) {
+  const uint32_t s = plan->core.s;
+  if (cfg->precision > HIDFT_PREC_BF16X3)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: unknown precision %u", fn, cfg->precision);
+  if (cfg->schedule > HIDFT_SCHED_SHORT_LAST)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: unknown schedule %u", fn, cfg->schedule);
+  if (cfg->radix != 0 && cfg->radix != 16 && cfg->radix != 32)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: radix %u is not 0, 16 or 32", fn, cfg->radix);
+  ExecConfig c;
+  c.prec = (int)cfg->precision;  // HIDFT_PREC_* values equal Prec
+  if (cfg->schedule == HIDFT_SCHED_DEFAULT)
+    c.sched = c.prec == PREC_FP32 ? SCHED_SHORT_FIRST : SCHED_SHORT_LAST;
+  else
+    c.sched = cfg->schedule == HIDFT_SCHED_SHORT_LAST ? SCHED_SHORT_LAST : SCHED_SHORT_FIRST;
+  c.rho = cfg->radix == 32 ? 5 : 4;
+  c.blocks_per_cu = cfg->blocks_per_cu > 1024 ? 1024 : (int)cfg->blocks_per_cu;
+  if (c.prec != PREC_FP32 && s < 4)
+    return fail(HIDFT_ERR_UNSUPPORTED,
+                "%s: the matrix-core precisions need k >= 16 (a radix-16 first group), k = %llu",
+                fn, (unsigned long long)plan->core.k);
+  if (c.rho == 5 && (c.prec != PREC_FP32 || s < 13))
+    return fail(HIDFT_ERR_UNSUPPORTED, "%s: radix 32 needs FP32 and k >= 2^13 (s = %u)", fn, s);
+  if (!fused_variant_exists(s, c.sched, c.prec, c.rho))
+    return fail(HIDFT_ERR_UNSUPPORTED,
+                "%s: the matrix-core precisions need the full radix-16 group first "
+                "(schedule SHORT_LAST or DEFAULT) when 4 does not divide s = %u",
+                fn, s);
+  *out = c;
+  return HIDFT_OK;
 }
 
 }  // namespace hidft
@@ -348,8 +393,36 @@ hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in
   if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
   hipError_t e = hidft::launch_fused(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
                                      static_cast<float2*>(d_coefs), ld_out, batch, plan->d_tw,
-                                     plan->d_src, plan->scale, static_cast<hipStream_t>(stream));
+                                     plan->d_src, plan->d_amat, plan->scale, hidft::ExecConfig{},
+                                     static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hidft_execute: kernel launch");
+  return ok();
+}
+
+
+hidft_status hidft_execute_config(hidft_plan plan, const hidft_exec_config* config,
+                                  const void* d_samples, int64_t ld_in, void* d_coefs,
+                                  int64_t ld_out, uint64_t batch, void* stream) {
+  const char* fn = "hidft_execute_config";
+  if (!config) return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: config is NULL", fn);
+  hidft_status st = check_exec(plan, d_samples, ld_in, d_coefs, ld_out, batch, fn);
+  if (st != HIDFT_OK) return st;
+  hidft_exec_config eff = *config;
+  if (eff.schedule == HIDFT_SCHED_TUNED) {
+    hidft_exec_config tuned;
+    if (hidft::tune_lookup(plan, eff.precision, batch, &tuned))
+      eff = tuned;
+    else
+      eff.schedule = HIDFT_SCHED_DEFAULT;
+  }
+  hidft::ExecConfig c;
+  if ((st = hidft::resolve_config(plan, &eff, &c, fn)) != HIDFT_OK) return st;
+  if (batch == 0) return ok();
+  hipError_t e = hidft::launch_fused(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
+                                     static_cast<float2*>(d_coefs), ld_out, batch, plan->d_tw,
+                                     plan->d_src, plan->d_amat, plan->scale, c,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hidft_execute_config: kernel launch");
   return ok();
 }
 

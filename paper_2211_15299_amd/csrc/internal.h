@@ -17,6 +17,7 @@ struct hidft_plan_s {
   int device = -1;
   float2* d_tw = nullptr;      // k-1 twiddles in a-order (at least one slot)
   uint16_t* d_src = nullptr;   // k output gather positions
+  void* d_amat = nullptr;      // split operands of the group-1 matrix (k >= 16)
   size_t device_bytes = 0;
   float scale = 1.0f;          // N / k
 };
@@ -28,6 +29,16 @@ hidft_status set_error(hidft_status st, const std::string& msg);
 
 // HIP error -> status (OUT_OF_MEMORY or DEVICE) with a message.
 hidft_status hip_error(hipError_t e, const char* what);
+
+// Public execution variant -> launch variant for this plan (records the
+// error message and returns INVALID_ARGUMENT / UNSUPPORTED when it has none).
+hidft_status resolve_config(const hidft_plan plan, const hidft_exec_config* cfg,
+                            ExecConfig* out, const char* fn);
+
+// The tuned variant recorded by hidft_autotune for this plan's device and
+// size, the precision and the class of `batch`; false if there is none.
+bool tune_lookup(const hidft_plan plan, uint32_t precision, uint64_t batch,
+                 hidft_exec_config* cfg);
 
 // Orders instances (size log2, descriptor) by size, largest first, and packs
 // instances of equal size into packs of at most grouped_slots_per_pack(s).

@@ -82,16 +82,28 @@ __device__ __forceinline__ void lds_barrier() {
 template <int RHO>
 __device__ __forceinline__ int lds_pad(int a) { return a + (a >> RHO); }
 
-template <int S>
+template <int S, int SCHED = SCHED_SHORT_FIRST, int RH = 4>
 struct FusedShape {
-  static constexpr int RHO = S < 4 ? S : 4;                      // log2 points per thread
+  static constexpr int RHO = S < RH ? S : RH;                    // log2 points per thread
   static constexpr int R = 1 << RHO;
   static constexpr int K = 1 << S;
   static constexpr int T = K / R;                                // threads per signal
   static constexpr int SPB = T >= 256 ? 1 : 256 / T;             // signals per block
   static constexpr int THREADS = T * SPB;
   static constexpr int G = S == 0 ? 0 : (S + RHO - 1) / RHO;     // radix groups
-  static constexpr int G1 = S == 0 ? 0 : S - (G - 1) * RHO;      // stages in group 1
+  // Stages of group 1.  When RHO does not divide S one group is short:
+  // SHORT_FIRST makes it group 1 (run straight from the global load),
+  // SHORT_LAST makes group 1 a full radix-2^RHO group and the last one short.
+  static constexpr int G1 = S == 0 ? 0
+                            : (SCHED == SCHED_SHORT_LAST && S >= RHO) ? RHO
+                                                                      : S - (G - 1) * RHO;
+  // Group g >= 2 runs the stages of bits [lo(g), hi(g)) of a.  Its threads
+  // always hold the RHO bits [lo(g), lo(g) + RHO): a short last group also
+  // carries bits of the previous group, on which it runs no stage, and starts
+  // at stage t0(g) of the window.
+  static constexpr int hi(int g) { return S - G1 - (g - 2) * RHO; }
+  static constexpr int lo(int g) { return hi(g) > RHO ? hi(g) - RHO : 0; }
+  static constexpr int t0(int g) { return RHO - (hi(g) - lo(g)); }
   static constexpr int PADK = K + (K >> RHO);                    // LDS slots per signal
   static constexpr size_t LDS_BYTES = (size_t)SPB * PADK * sizeof(float2);
   // Launch strategy.  Up to 2^12 points the grid is persistent (blocks
@@ -109,26 +121,239 @@ struct FusedShape {
   static constexpr int NTW = G > 1 ? (TW_REGS ? (G - 1) * (R - 1) : 1) : 1;
 };
 
+// One thread's values of a signal.
+template <int S, int RH>
+using SigVec = float2[FusedShape<S, SCHED_SHORT_FIRST, RH>::R];
+
+// ---------------------------------------------------------------------------
+// Group 1 on the matrix cores (PREC_F16X2, PREC_BF16X3).
+//
+// The four stages of a full group 1 multiply every column of 16 values
+// (a = col + c T, c < 16, col < T = 2^{S-4}) by the same 16 x 16 complex
+// matrix W, the product of the four butterfly stages; its entries have unit
+// modulus.  As a real product, Re(Wx) = [Re W, -Im W] [Re x; Im x] and
+// Im(Wx) = [Im W, Re W] [Re x; Im x]: two 16 x 32 by 32 x 16 MFMA products
+// (v_mfma_f32_16x16x32_{f16,bf16}) per tile of 16 columns, FP32 accumulation.
+//
+// Operand layout: lane l holds row or column l & 15 and the 8 consecutive
+// k-entries 8 (l >> 4) .. + 7, here the interleaved (re, im) pairs of
+// c = 4 (l >> 4) .. + 3; the result holds rows 4 (l >> 4) .. + 3 of column
+// l & 15.  So lane l of wave w keeps, for tile j < 4, the values c = 4 (l >> 4)
+// + i (i < 4) of block column 64 w + 16 j + (l & 15) before and after the
+// product.
+//
+// Split precision: x = x1 + x2 (+ x3) and W = W1 + W2 (+ W3) in FP16 (two
+// terms) or BF16 (three terms); the products of the leading terms are summed
+// in FP32, smallest first.
+//   F16X2:  x W ~ W1 x1 + W1 x2 + W2 x1.  FP16 has a narrow exponent range, so
+//           each column is first scaled by a power of two that brings its
+//           largest component into [2^14, 2^15) (exact; undone after).
+//   BF16X3: x W ~ W1 x1 + W1 x2 + W2 x1 + W1 x3 + W2 x2 + W3 x1, no scaling.
+// The split operands of W are computed in FP64 on the device at plan creation
+// (stage_matrix_kernel).
+// ---------------------------------------------------------------------------
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// Offsets (in 16-byte operands) of the split operands in a plan's table.
+constexpr int AMAT_F16_OPS = 4;   // Re-row hi, lo; Im-row hi, lo
+constexpr int AMAT_BF16_OPS = 6;  // Re-row terms 1..3; Im-row terms 1..3
+constexpr int AMAT_BF16_BASE = AMAT_F16_OPS * 64;
+
+template <int PREC>
+struct MfmaOps {};
+template <>
+struct MfmaOps<PREC_F16X2> {
+  half8_t rh, rl, ih, il;
+};
+template <>
+struct MfmaOps<PREC_BF16X3> {
+  bf16x8_t r1, r2, r3, i1, i2, i3;
+};
+
+template <int PREC>
+__device__ __forceinline__ MfmaOps<PREC> load_mfma_ops(const uint4* __restrict__ amat) {
+  MfmaOps<PREC> op;
+  const int l = threadIdx.x & 63;
+  if constexpr (PREC == PREC_F16X2) {
+    op.rh = __builtin_bit_cast(half8_t, amat[0 * 64 + l]);
+    op.rl = __builtin_bit_cast(half8_t, amat[1 * 64 + l]);
+    op.ih = __builtin_bit_cast(half8_t, amat[2 * 64 + l]);
+    op.il = __builtin_bit_cast(half8_t, amat[3 * 64 + l]);
+  } else if constexpr (PREC == PREC_BF16X3) {
+    const uint4* b = amat + AMAT_BF16_BASE;
+    op.r1 = __builtin_bit_cast(bf16x8_t, b[0 * 64 + l]);
+    op.r2 = __builtin_bit_cast(bf16x8_t, b[1 * 64 + l]);
+    op.r3 = __builtin_bit_cast(bf16x8_t, b[2 * 64 + l]);
+    op.i1 = __builtin_bit_cast(bf16x8_t, b[3 * 64 + l]);
+    op.i2 = __builtin_bit_cast(bf16x8_t, b[4 * 64 + l]);
+    op.i3 = __builtin_bit_cast(bf16x8_t, b[5 * 64 + l]);
+  }
+  return op;
+}
+
+// Group 1 of the 64 block columns of this wave (v in the MFMA layout).
+template <int PREC>
+__device__ __forceinline__ void group1_mfma(float2 (&v)[16], const MfmaOps<PREC>& op) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float4_t dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (PREC == PREC_F16X2) {
+      float mx = 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        mx = fmaxf(mx, fmaxf(fabsf(v[4 * j + i].x), fabsf(v[4 * j + i].y)));
+      // The column's 16 values sit in lanes l, l ^ 16, l ^ 32, l ^ 48.
+      mx = fmaxf(mx, __shfl_xor(mx, 16));
+      mx = fmaxf(mx, __shfl_xor(mx, 32));
+      int e = (int)((__builtin_bit_cast(uint32_t, mx) >> 23) & 0xffu);
+      e = e < 15 ? 15 : (e > 254 ? 254 : e);
+      const float sc = __builtin_bit_cast(float, (uint32_t)(268 - e) << 23);   // 2^(141-e)
+      const float inv = __builtin_bit_cast(float, (uint32_t)(e - 14) << 23);   // 2^(e-141)
+      half8_t x1, x2;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const float xr = v[4 * j + p].x * sc, xi = v[4 * j + p].y * sc;
+        const _Float16 hr = (_Float16)xr, hi = (_Float16)xi;
+        x1[2 * p] = hr;
+        x1[2 * p + 1] = hi;
+        x2[2 * p] = (_Float16)(xr - (float)hr);
+        x2[2 * p + 1] = (_Float16)(xi - (float)hi);
+      }
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.rl, x1, dr, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.rh, x2, dr, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.rh, x1, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.il, x1, di, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.ih, x2, di, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.ih, x1, di, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[4 * j + i] = make_float2(dr[i] * inv, di[i] * inv);
+    } else {
+      bf16x8_t x1, x2, x3;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const float x = q ? v[4 * j + p].y : v[4 * j + p].x;
+          const __bf16 b1 = (__bf16)x;
+          const float r1 = x - (float)b1;
+          const __bf16 b2 = (__bf16)r1;
+          const float r2 = r1 - (float)b2;
+          x1[2 * p + q] = b1;
+          x2[2 * p + q] = b2;
+          x3[2 * p + q] = (__bf16)r2;
+        }
+      }
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r1, x3, dr, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r2, x2, dr, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r3, x1, dr, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r1, x2, dr, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r2, x1, dr, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r1, x1, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i1, x3, di, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i2, x2, di, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i3, x1, di, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i1, x2, di, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i2, x1, di, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i1, x1, di, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[4 * j + i] = make_float2(dr[i], di[i]);
+    }
+  }
+}
+
+// Split operands of W from the FP64 twiddles of stages 1..4 (a-order entries
+// 0..14), one wavefront.  Lane l = 16 g + m builds W[m][c] for c = 4g .. 4g+3
+// by running the four stages on the unit vector e_c in FP64.
+__global__ void __launch_bounds__(64)
+stage_matrix_kernel(const uint64_t* __restrict__ num, const uint8_t* __restrict__ log2den,
+                    uint4* __restrict__ amat) {
+  const int l = threadIdx.x;
+  const int g = l >> 4, m = l & 15;
+  double wr[15], wi[15];
+  for (int e = 0; e < 15; ++e) {
+    double sn, cs;
+    sincospi(ldexp((double)num[e], -(int)log2den[e]), &sn, &cs);
+    wr[e] = cs;
+    wi[e] = -sn;
+  }
+  double Wr[4], Wi[4];
+  for (int p = 0; p < 4; ++p) {
+    double xr[16], xi[16];
+    for (int c = 0; c < 16; ++c) xr[c] = xi[c] = 0.0;
+    xr[4 * g + p] = 1.0;
+    for (int u = 1; u <= 4; ++u) {
+      const int bit = 4 - u;
+      for (int c = 0; c < 16; ++c) {
+        if (c & (1 << bit)) continue;
+        const int e = (1 << (u - 1)) - 1 + (c >> (bit + 1));
+        const int d = c | (1 << bit);
+        const double qr = wr[e] * xr[d] - wi[e] * xi[d];
+        const double qi = wr[e] * xi[d] + wi[e] * xr[d];
+        xr[d] = xr[c] - qr;
+        xi[d] = xi[c] - qi;
+        xr[c] += qr;
+        xi[c] += qi;
+      }
+    }
+    Wr[p] = xr[m];
+    Wi[p] = xi[m];
+  }
+  // Row operands: element e pairs with (re, im)[e & 1] of c = 4g + e/2.
+  half8_t f16[4];
+  bf16x8_t b16[6];
+  for (int e = 0; e < 8; ++e) {
+    const int p = e >> 1;
+    const double ar = (e & 1) ? -Wi[p] : Wr[p];  // Re row: [Re W, -Im W]
+    const double ai = (e & 1) ? Wr[p] : Wi[p];   // Im row: [Im W,  Re W]
+    const double a[2] = {ar, ai};
+    for (int q = 0; q < 2; ++q) {
+      const _Float16 h = (_Float16)(float)a[q];
+      f16[2 * q][e] = h;
+      f16[2 * q + 1][e] = (_Float16)(float)(a[q] - (double)(float)h);
+      const __bf16 b1 = (__bf16)(float)a[q];
+      const double r1 = a[q] - (double)(float)b1;
+      const __bf16 b2 = (__bf16)(float)r1;
+      const double r2 = r1 - (double)(float)b2;
+      b16[3 * q][e] = b1;
+      b16[3 * q + 1][e] = b2;
+      b16[3 * q + 2][e] = (__bf16)(float)r2;
+    }
+  }
+  for (int o = 0; o < AMAT_F16_OPS; ++o) amat[o * 64 + l] = __builtin_bit_cast(uint4, f16[o]);
+  for (int o = 0; o < AMAT_BF16_OPS; ++o)
+    amat[AMAT_BF16_BASE + o * 64 + l] = __builtin_bit_cast(uint4, b16[o]);
+}
+
+hipError_t launch_stage_matrix(const uint64_t* d_num, const uint8_t* d_den, void* d_amat,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(stage_matrix_kernel, dim3(1), dim3(64), 0, stream, d_num, d_den,
+                     static_cast<uint4*>(d_amat));
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Fused batched transform.  Each block owns SPB signal slots of T threads.
 // Per signal:
 //   * group 1 (stages 1..G1, the top G1 bits of a) runs straight from the
 //     global load: thread tau holds a = tau + c*T for c < R, so each load
-//     instruction of a wavefront reads 64 consecutive samples;
-//   * every later group takes RHO = 4 stages (radix 16) on the next lower four
-//     bits of a, through LDS; each thread reads and writes back its own 16
-//     slots, so one barrier per group suffices;
+//     instruction of a wavefront reads 64 consecutive samples (with MFMA,
+//     16-sample runs, see above);
+//   * every later group takes up to RHO = 4 stages (radix 16) on the next
+//     lower bits of a, through LDS; each thread reads and writes back its own
+//     16 slots, so one barrier per group suffices;
 //   * the block gathers the outputs in the caller's order of J (src table),
 //     scales by N/k and stores them coalesced.
 // Up to 2^12 points the grid is persistent (blocks resident per CU times the
 // CU count) and walks over the batch; the twiddles and gather positions a
 // thread needs are then loaded once per block and kept in registers, and
-// (PREFETCH) the next signals' samples are loaded while the current ones are
-// transformed.  Larger sizes run one group of signals per block.
+// the next signals' samples are loaded while the current ones are
+// transformed.  Larger sizes run one signal per block.
 // ---------------------------------------------------------------------------
-template <int S>
+template <int S, int SCHED, int RH>
 struct ThreadState {  // per-thread constants of the persistent form
-  using Sh = FusedShape<S>;
+  using Sh = FusedShape<S, SCHED, RH>;
   float2 w1[(1 << Sh::G1) > 1 ? (1 << Sh::G1) - 1 : 1];  // block-uniform (scalar registers)
   float2 wg[Sh::NTW];
   uint32_t srcpk[(Sh::R + 1) / 2];  // two 16-bit gather positions per register
@@ -200,43 +425,119 @@ __device__ __forceinline__ void load_row(float2 (&v)[R], const float2* row, uint
   }
 }
 
-// Transform the samples in v (this thread's R values of one signal) and, if
-// `store`, write its coefficients through `mem`.  HOISTED: twiddles and
-// gather positions come from `ts`, else from the tables behind `mem`.
-template <int S, bool HOISTED, class Mem>
-__device__ __forceinline__ void transform_signal(float2 (&v)[FusedShape<S>::R], float2* L,
-                                                 int tau, bool store, const Mem& mem,
-                                                 float scale, const ThreadState<S>& ts) {
-  using Sh = FusedShape<S>;
-  constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, G = Sh::G, G1 = Sh::G1;
+// Position of value i of tile j of this thread in the MFMA layout: the
+// block's signal slot and the position a within that signal.
+template <int S>
+__device__ __forceinline__ void mfma_pos(int tid, int j, int i, int& slot, int& a) {
+  constexpr int T = FusedShape<S>::T;  // columns per signal, 2^{S-4}
+  const int col = (tid & ~63) + 16 * j + (tid & 15);
+  slot = col >> (S - 4);
+  a = (col & (T - 1)) + (4 * ((tid >> 4) & 3) + i) * T;
+}
 
-  // Group 1: stage u pairs bit RHO-u of c; the twiddle index is the top u-1
-  // bits of c, the same for every thread.
+// Loads the samples of the signals first_sig + slot (slot < SPB) that this
+// thread holds for group 1: standard layout for FP32, MFMA layout otherwise.
+// Signals at or beyond `batch` read as zeros.
+template <int S, int SCHED, int RH, int PREC>
+__device__ __forceinline__ void load_group1(SigVec<S, RH>& v, const float2* __restrict__ in,
+                                            int64_t ld_in, uint64_t first_sig, uint64_t batch) {
+  using Sh = FusedShape<S, SCHED, RH>;
+  constexpr int R = Sh::R, T = Sh::T;
+  const int tid = threadIdx.x;
+  if constexpr (PREC == PREC_FP32) {
+    const int slot = tid / T;
+    const uint64_t sig = first_sig + slot;
+    if (sig < batch) {
+      load_row<R, T, false>(v, in + sig * (uint64_t)ld_in, 1u << S);
+    } else {
 #pragma unroll
-  for (int u = 1; u <= G1; ++u) {
-    const int bit = RHO - u;
+      for (int c = 0; c < R; ++c) v[c] = make_float2(0.f, 0.f);
+    }
+  } else {
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-      if (c & (1 << bit)) continue;
-      const int idx = (1 << (u - 1)) - 1 + (c >> (bit + 1));
-      butterfly(v[c], v[c | (1 << bit)], HOISTED ? ts.w1[idx] : mem.tw_at(idx, 0));
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int slot, a;
+        mfma_pos<S>(tid, j, i, slot, a);
+        const uint64_t sig = first_sig + slot;
+        v[4 * j + i] = sig < batch ? in[sig * (uint64_t)ld_in + a] : make_float2(0.f, 0.f);
+      }
     }
   }
-#pragma unroll
-  for (int c = 0; c < R; ++c) L[lds_pad<RHO>(c * T + tau)] = v[c];
+}
 
-  // Groups 2..G on bits [lo, lo + RHO), lo = S - G1 - (g-1)*RHO.
+// Transform the samples in v (this thread's R values of group 1, in the
+// layout of load_group1) and, if `store`, write the coefficients of this
+// thread's signal slot through `mem`.  Lb is the block's LDS.  HOISTED:
+// twiddles and gather positions come from `ts`, else from the tables behind
+// `mem`.
+template <int S, int SCHED, int RH, int PREC, bool HOISTED, class Mem>
+__device__ __forceinline__ void transform_signal(SigVec<S, RH>& v, float2* Lb, int slot, int tau,
+                                                 bool store, const Mem& mem, float scale,
+                                                 const ThreadState<S, SCHED, RH>& ts,
+                                                 const MfmaOps<PREC>& op) {
+  using Sh = FusedShape<S, SCHED, RH>;
+  constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, G = Sh::G, G1 = Sh::G1;
+  float2* L = Lb + slot * Sh::PADK;
+
+  if constexpr (PREC == PREC_FP32) {
+    // Group 1: stage u pairs bit RHO-u of c; the twiddle index is the top
+    // u-1 bits of c, the same for every thread.
+#pragma unroll
+    for (int u = 1; u <= G1; ++u) {
+      const int bit = RHO - u;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (c & (1 << bit)) continue;
+        const int idx = (1 << (u - 1)) - 1 + (c >> (bit + 1));
+        butterfly(v[c], v[c | (1 << bit)], HOISTED ? ts.w1[idx] : mem.tw_at(idx, 0));
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) L[lds_pad<RHO>(c * T + tau)] = v[c];
+  } else {
+    static_assert(S >= 4 && RHO == 4 && G1 == 4,
+                  "the matrix-core group 1 is a full radix-16 group");
+    group1_mfma<PREC>(v, op);
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int sl, a;
+        mfma_pos<S>(tid, j, i, sl, a);
+        Lb[sl * Sh::PADK + lds_pad<RHO>(a)] = v[4 * j + i];
+      }
+    }
+  }
+
+  // Groups 2..G on the window [lo, lo + RHO), stages t0..RHO-1 of it.
 #pragma unroll
   for (int g = 2; g <= G; ++g) {
-    const int lo = S - G1 - (g - 1) * RHO;
+    const int lo = Sh::lo(g), t0 = Sh::t0(g);
     const int a_lo = tau & ((1 << lo) - 1);
     const int a_hi = tau >> lo;
     const int base = a_lo + (a_hi << (lo + RHO));
+    // Without hoisted tables, the group's twiddles are requested before the
+    // barrier, so that their latency overlaps the wait for the other waves.
+    float2 wq[R > 1 ? R - 1 : 1];
+    if constexpr (!(HOISTED && Sh::TW_REGS)) {
+#pragma unroll
+      for (int t = 0; t < RHO; ++t) {
+        if (t < t0) continue;
+        const int u = S - lo - RHO + 1 + t;
+#pragma unroll
+        for (int h = 0; h < (1 << t); ++h)
+          wq[(1 << t) - 1 + h] = mem.tw_at(((1 << (u - 1)) - 1) + h, a_hi << t);
+      }
+    }
     lds_barrier();
 #pragma unroll
     for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(base + (c << lo))];
 #pragma unroll
     for (int t = 0; t < RHO; ++t) {
+      if (t < t0) continue;
       const int u = S - lo - RHO + 1 + t;
       const int bit = RHO - 1 - t;
 #pragma unroll
@@ -247,97 +548,113 @@ __device__ __forceinline__ void transform_signal(float2 (&v)[FusedShape<S>::R], 
         if constexpr (HOISTED && Sh::TW_REGS)
           w = ts.wg[(g - 2) * (R - 1) + (1 << t) - 1 + h];
         else
-          w = mem.tw_at(((1 << (u - 1)) - 1) + h, a_hi << t);
+          w = wq[(1 << t) - 1 + h];
+        (void)u;
         butterfly(v[c], v[c | (1 << bit)], w);
       }
     }
 #pragma unroll
     for (int c = 0; c < R; ++c) L[lds_pad<RHO>(base + (c << lo))] = v[c];
   }
+  // Gather positions of the output, requested before the last barrier.
+  int pq[R];
+  if constexpr (!HOISTED) {
+    if (store) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) pq[c] = mem.src_at(c * T, tau);
+    }
+  }
   lds_barrier();
 
   if (store) {
 #pragma unroll
     for (int c = 0; c < R; ++c) {
-      const int p = HOISTED ? (int)((ts.srcpk[c >> 1] >> (16 * (c & 1))) & 0xffffu)
-                            : mem.src_at(c * T, tau);
+      const int p = HOISTED ? (int)((ts.srcpk[c >> 1] >> (16 * (c & 1))) & 0xffffu) : pq[c];
       const float2 x = L[lds_pad<RHO>(p)];
       mem.put(c * T, tau, make_float2(x.x * scale, x.y * scale));
     }
   }
 }
 
-template <int S>
-__global__ void __launch_bounds__(FusedShape<S>::THREADS)
+// Loads the per-thread constants: group-1 twiddles (uniform), the twiddles
+// of groups 2..G this thread uses, and its gather positions.
+template <int S, int SCHED, int RH, int PREC>
+__device__ __forceinline__ void load_thread_state(ThreadState<S, SCHED, RH>& ts,
+                                                  const float2* __restrict__ tw,
+                                                  const uint16_t* __restrict__ src, int tau) {
+  using Sh = FusedShape<S, SCHED, RH>;
+  constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, G = Sh::G, G1 = Sh::G1;
+  if constexpr (PREC == PREC_FP32) {
+#pragma unroll
+    for (int i = 0; i < (1 << G1) - 1; ++i) ts.w1[i] = make_uniform(tw[i]);
+  }
+  if constexpr (Sh::TW_REGS) {
+#pragma unroll
+    for (int g = 2; g <= G; ++g) {
+      const int lo = Sh::lo(g);
+      const int a_hi = tau >> lo;
+#pragma unroll
+      for (int t = 0; t < RHO; ++t) {
+        // (a loop from 0 unrolls completely, keeping ts.wg in registers)
+        if (t < Sh::t0(g)) continue;
+        const int u = S - lo - RHO + 1 + t;
+#pragma unroll
+        for (int h = 0; h < (1 << t); ++h)
+          ts.wg[(g - 2) * (R - 1) + (1 << t) - 1 + h] =
+              tw[((1 << (u - 1)) - 1) + (a_hi << t) + h];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < R; c += 2) {
+    const uint32_t lo16 = src[c * T + tau];
+    const uint32_t hi16 = c + 1 < R ? src[(c + 1) * T + tau] : 0u;
+    ts.srcpk[c >> 1] = lo16 | (hi16 << 16);
+  }
+}
+
+template <int S, int SCHED, int RH, int PREC>
+__global__ void __launch_bounds__((FusedShape<S, SCHED, RH>::THREADS))
 hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ out,
                    int64_t ld_out, uint64_t batch, const float2* __restrict__ tw,
-                   const uint16_t* __restrict__ src, float scale) {
-  using Sh = FusedShape<S>;
-  constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, SPB = Sh::SPB, G = Sh::G, G1 = Sh::G1;
-  constexpr uint32_t K = 1u << S;
+                   const uint16_t* __restrict__ src, const uint4* __restrict__ amat,
+                   float scale) {
+  using Sh = FusedShape<S, SCHED, RH>;
+  constexpr int R = Sh::R, T = Sh::T, SPB = Sh::SPB;
   extern __shared__ float2 lds[];
 
   const int tid = threadIdx.x;
   const int slot = tid / T;
   const int tau = tid - slot * T;
-  float2* L = lds + slot * Sh::PADK;
   const uint64_t n_groups = (batch + SPB - 1) / SPB;
+  MfmaOps<PREC> op;
+  if constexpr (PREC != PREC_FP32) op = load_mfma_ops<PREC>(amat);
 
   if constexpr (Sh::BIG) {
     // One signal per block, one block per signal (see BIG above).
     static_assert(SPB == 1, "a large signal fills its block");
     const uint64_t grp = blockIdx.x;
     float2 v[R];
-    load_row<R, T, false>(v, in + grp * (uint64_t)ld_in, K);
-    ThreadState<S> unused;
+    load_group1<S, SCHED, RH, PREC>(v, in, ld_in, grp, batch);
     const FlatMem mem{tw, src, out + grp * (uint64_t)ld_out};
-    transform_signal<S, false>(v, L, tau, true, mem, scale, unused);
+    ThreadState<S, SCHED, RH> unused;
+    transform_signal<S, SCHED, RH, PREC, false>(v, lds, 0, tau, true, mem, scale, unused, op);
   } else {
+    ThreadState<S, SCHED, RH> ts;
+    load_thread_state<S, SCHED, RH, PREC>(ts, tw, src, tau);
     float2 vn[R];
-    auto load = [&](uint64_t grp) {
-      const uint64_t sig = grp * SPB + slot;
-      if (sig < batch) {
-        load_row<R, T, false>(vn, in + sig * (uint64_t)ld_in, K);
-      } else {
-#pragma unroll
-        for (int c = 0; c < R; ++c) vn[c] = make_float2(0.f, 0.f);
-      }
-    };
-    ThreadState<S> ts;
-#pragma unroll
-    for (int i = 0; i < (1 << G1) - 1; ++i) ts.w1[i] = make_uniform(tw[i]);
-    if constexpr (Sh::TW_REGS) {
-#pragma unroll
-      for (int g = 2; g <= G; ++g) {
-        const int lo = S - G1 - (g - 1) * RHO;
-        const int a_hi = tau >> lo;
-#pragma unroll
-        for (int t = 0; t < RHO; ++t) {
-          const int u = S - lo - RHO + 1 + t;
-#pragma unroll
-          for (int h = 0; h < (1 << t); ++h)
-            ts.wg[(g - 2) * (R - 1) + (1 << t) - 1 + h] =
-                tw[((1 << (u - 1)) - 1) + (a_hi << t) + h];
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < R; c += 2) {
-      const uint32_t lo16 = src[c * T + tau];
-      const uint32_t hi16 = c + 1 < R ? src[(c + 1) * T + tau] : 0u;
-      ts.srcpk[c >> 1] = lo16 | (hi16 << 16);
-    }
-
     uint64_t grp = blockIdx.x;
-    if (grp < n_groups) load(grp);
+    if (grp < n_groups) load_group1<S, SCHED, RH, PREC>(vn, in, ld_in, grp * SPB, batch);
     for (; grp < n_groups; grp += gridDim.x) {
       float2 v[R];
 #pragma unroll
       for (int c = 0; c < R; ++c) v[c] = vn[c];
-      if (grp + gridDim.x < n_groups) load(grp + gridDim.x);
+      if (grp + gridDim.x < n_groups)
+        load_group1<S, SCHED, RH, PREC>(vn, in, ld_in, (grp + gridDim.x) * SPB, batch);
       const uint64_t sig = grp * SPB + slot;
       const FlatMem mem{tw, src, out + (sig < batch ? sig : 0) * (uint64_t)ld_out};
-      transform_signal<S, true>(v, L, tau, sig < batch, mem, scale, ts);
+      transform_signal<S, SCHED, RH, PREC, true>(v, lds, slot, tau, sig < batch, mem, scale,
+                                                  ts, op);
       lds_barrier();  // the next group overwrites these LDS slots
     }
   }
@@ -520,54 +837,129 @@ hipError_t launch_inverse(uint32_t s, const float2* in, int64_t ld_in, float2* o
   }
 }
 
-template <int S>
+// Occupancy of a kernel: blocks resident per CU and the CU count, queried
+// once per kernel (the first call also raises its dynamic LDS limit).
+struct Occupancy {
+  int per_cu = 0;
+  int cus = 0;
+};
+
+static hipError_t query_occupancy(const void* kernel, int threads, size_t lds_bytes,
+                                  Occupancy* occ) {
+  hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds_bytes)) !=
+      hipSuccess)
+    return e;
+  occ->per_cu = per_cu > 0 ? per_cu : 1;
+  occ->cus = cus > 0 ? cus : 1;
+  return hipSuccess;
+}
+
+template <int S, int SCHED, int RH, int PREC>
 static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
                                  uint64_t batch, const float2* tw, const uint16_t* src,
-                                 float scale, hipStream_t stream) {
-  using Sh = FusedShape<S>;
-  // Per-kernel launch shape, computed once: blocks that fit on a CU at the
-  // same time (registers and LDS) times the CU count.
-  static int max_grid = 0;  // benign race: every thread computes the same value
-  if (max_grid == 0) {
-    hipError_t e = hipFuncSetAttribute((const void*)hidft_fused_kernel<S>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)Sh::LDS_BYTES);
+                                 const uint4* amat, float scale, int blocks_per_cu,
+                                 hipStream_t stream) {
+  using Sh = FusedShape<S, SCHED, RH>;
+  const void* kernel = (const void*)hidft_fused_kernel<S, SCHED, RH, PREC>;
+  static Occupancy occ;  // benign race: every thread computes the same value
+  if (occ.cus == 0) {
+    Occupancy o;
+    hipError_t e = query_occupancy(kernel, Sh::THREADS, Sh::LDS_BYTES, &o);
     if (e != hipSuccess) return e;
-    int dev = 0, cus = 0, per_cu = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
-        hipSuccess)
-      return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-             &per_cu, (const void*)hidft_fused_kernel<S>, Sh::THREADS, Sh::LDS_BYTES)) !=
-        hipSuccess)
-      return e;
-    max_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    occ = o;
   }
   if constexpr (Sh::BIG) {
     // One block per signal: launch in chunks that fit the grid dimension.
     const uint64_t chunk = 0x7fffffffULL;
     for (uint64_t first = 0; first < batch; first += chunk) {
       const uint64_t n = batch - first < chunk ? batch - first : chunk;
-      hipLaunchKernelGGL(hidft_fused_kernel<S>, dim3((unsigned)n), dim3(Sh::THREADS),
-                         Sh::LDS_BYTES, stream, in + first * (uint64_t)ld_in, ld_in,
-                         out + first * (uint64_t)ld_out, ld_out, n, tw, src, scale);
+      hipLaunchKernelGGL((hidft_fused_kernel<S, SCHED, RH, PREC>), dim3((unsigned)n),
+                         dim3(Sh::THREADS), Sh::LDS_BYTES, stream, in + first * (uint64_t)ld_in,
+                         ld_in, out + first * (uint64_t)ld_out, ld_out, n, tw, src, amat, scale);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }
+  const int per_cu =
+      blocks_per_cu > 0 && blocks_per_cu < occ.per_cu ? blocks_per_cu : occ.per_cu;
+  const uint64_t max_grid = (uint64_t)per_cu * (uint64_t)occ.cus;
   const uint64_t groups = (batch + Sh::SPB - 1) / Sh::SPB;
-  const unsigned grid = (unsigned)(groups < (uint64_t)max_grid ? groups : (uint64_t)max_grid);
-  hipLaunchKernelGGL(hidft_fused_kernel<S>, dim3(grid), dim3(Sh::THREADS), Sh::LDS_BYTES,
-                     stream, in, ld_in, out, ld_out, batch, tw, src, scale);
+  const unsigned grid = (unsigned)(groups < max_grid ? groups : max_grid);
+  hipLaunchKernelGGL((hidft_fused_kernel<S, SCHED, RH, PREC>), dim3(grid), dim3(Sh::THREADS),
+                     Sh::LDS_BYTES, stream, in, ld_in, out, ld_out, batch, tw, src, amat, scale);
   return hipGetLastError();
+}
+
+bool fused_variant_exists(uint32_t s, int sched, int prec, int rho) {
+  if (s > HIDFT_MAX_LOG2_K_DEVICE) return false;
+  if (sched != SCHED_SHORT_FIRST && sched != SCHED_SHORT_LAST) return false;
+  if (rho != 4 && rho != 5) return false;
+  // Radix-32 tiles exist for the one-signal-per-block sizes, in FP32.
+  if (rho == 5) return prec == PREC_FP32 && s >= 13;
+  if (prec == PREC_FP32) return true;
+  if (prec != PREC_F16X2 && prec != PREC_BF16X3) return false;
+  // Matrix-core group 1 is a full radix-16 group.
+  return s >= 4 && (sched == SCHED_SHORT_LAST || s % 4 == 0);
+}
+
+template <int S>
+static hipError_t dispatch_fused(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
+                                 uint64_t batch, const float2* tw, const uint16_t* src,
+                                 const uint4* amat, float scale, const ExecConfig& cfg,
+                                 hipStream_t stream) {
+  const int bpc = cfg.blocks_per_cu;
+  const bool last = cfg.sched == SCHED_SHORT_LAST;
+  if constexpr (S >= 13) {
+    if (cfg.rho == 5) {
+      // Radix 32: 13 = 3 + 5 + 5 or 5 + 5 + 3, 14 = 4 + 5 + 5 or 5 + 5 + 4.
+      if (last)
+        return launch_fused_s<S, SCHED_SHORT_LAST, 5, PREC_FP32>(in, ld_in, out, ld_out, batch,
+                                                                 tw, src, amat, scale, bpc,
+                                                                 stream);
+      return launch_fused_s<S, SCHED_SHORT_FIRST, 5, PREC_FP32>(in, ld_in, out, ld_out, batch,
+                                                                tw, src, amat, scale, bpc, stream);
+    }
+  }
+  // When 4 divides S (or S < 4) the two schedules are the same kernel.
+  constexpr bool TWO_SCHEDS = S > 4 && S % 4 != 0;
+  if (cfg.prec == PREC_FP32) {
+    if constexpr (TWO_SCHEDS) {
+      if (last)
+        return launch_fused_s<S, SCHED_SHORT_LAST, 4, PREC_FP32>(in, ld_in, out, ld_out, batch,
+                                                                 tw, src, amat, scale, bpc,
+                                                                 stream);
+    }
+    return launch_fused_s<S, SCHED_SHORT_FIRST, 4, PREC_FP32>(in, ld_in, out, ld_out, batch, tw,
+                                                              src, amat, scale, bpc, stream);
+  }
+  if constexpr (S >= 4) {
+    constexpr int SC = TWO_SCHEDS ? SCHED_SHORT_LAST : SCHED_SHORT_FIRST;
+    if (cfg.prec == PREC_F16X2)
+      return launch_fused_s<S, SC, 4, PREC_F16X2>(in, ld_in, out, ld_out, batch, tw, src, amat,
+                                                  scale, bpc, stream);
+    if (cfg.prec == PREC_BF16X3)
+      return launch_fused_s<S, SC, 4, PREC_BF16X3>(in, ld_in, out, ld_out, batch, tw, src, amat,
+                                                   scale, bpc, stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out,
                         int64_t ld_out, uint64_t batch, const float2* tw, const uint16_t* src,
-                        float scale, hipStream_t stream) {
+                        const void* amat, float scale, ExecConfig cfg, hipStream_t stream) {
+  if (!fused_variant_exists(s, cfg.sched, cfg.prec, cfg.rho)) return hipErrorInvalidValue;
+  if (cfg.prec != PREC_FP32 && amat == nullptr) return hipErrorInvalidValue;
   if (batch == 0) return hipSuccess;
+  const uint4* am = static_cast<const uint4*>(amat);
   switch (s) {
     case 0: {
       const uint64_t blocks = (batch + 255) / 256;
@@ -578,7 +970,7 @@ hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out
     }
 #define HIDFT_CASE(S) \
   case S:             \
-    return launch_fused_s<S>(in, ld_in, out, ld_out, batch, tw, src, scale, stream);
+    return dispatch_fused<S>(in, ld_in, out, ld_out, batch, tw, src, am, scale, cfg, stream);
     HIDFT_CASE(1) HIDFT_CASE(2) HIDFT_CASE(3) HIDFT_CASE(4) HIDFT_CASE(5) HIDFT_CASE(6)
     HIDFT_CASE(7) HIDFT_CASE(8) HIDFT_CASE(9) HIDFT_CASE(10) HIDFT_CASE(11) HIDFT_CASE(12)
     HIDFT_CASE(13) HIDFT_CASE(14)
@@ -643,7 +1035,8 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
   // slot 0's tables (every pack has at least one slot) and store nothing.
   GroupSlot d = slots[valid ? slot : 0];
   float2 v[R];
-  ThreadState<S> unused;
+  ThreadState<S, SCHED_SHORT_FIRST, 4> unused;
+  const MfmaOps<PREC_FP32> no_mfma;
   if constexpr (T >= 64) {
     // A slot spans whole wavefronts: its descriptor is wave-uniform.
     d.in = uniform_ptr(d.in);
@@ -662,12 +1055,14 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
     mem.tw = make_rsrc(d.tw, (K > 1 ? K - 1 : 1) * 8u);
     mem.src = make_rsrc(d.src, K * 2u);
     mem.out = make_rsrc(d.out, K * 8u);
-    transform_signal<S, false>(v, lds + slot * Sh::PADK, tau, valid, mem, d.scale, unused);
+    transform_signal<S, SCHED_SHORT_FIRST, 4, PREC_FP32, false>(v, lds, slot, tau, valid, mem,
+                                                             d.scale, unused, no_mfma);
   } else {
 #pragma unroll
     for (int c = 0; c < R; ++c) v[c] = valid ? d.in[c * T + tau] : make_float2(0.f, 0.f);
     const FlatMem mem{d.tw, d.src, d.out};
-    transform_signal<S, false>(v, lds + slot * Sh::PADK, tau, valid, mem, d.scale, unused);
+    transform_signal<S, SCHED_SHORT_FIRST, 4, PREC_FP32, false>(v, lds, slot, tau, valid, mem,
+                                                             d.scale, unused, no_mfma);
   }
 }
 

@@ -14,10 +14,37 @@ namespace hidft {
 hipError_t launch_twiddle_gen(const uint64_t* d_num, const uint8_t* d_den, float2* d_tw,
                               uint64_t n, hipStream_t stream);
 
+// Where the short radix group goes when 4 does not divide s.
+enum Sched : int { SCHED_SHORT_FIRST = 0, SCHED_SHORT_LAST = 1 };
+// Arithmetic of group 1 (values equal the public HIDFT_PREC_*).
+enum Prec : int { PREC_FP32 = 0, PREC_F16X2 = 1, PREC_BF16X3 = 2 };
+
+// Launch variant of the fused kernel.  blocks_per_cu caps the persistent grid
+// (sizes up to 2^12) at that many blocks per CU; 0 = as many as fit.
+struct ExecConfig {
+  int sched = SCHED_SHORT_FIRST;
+  int prec = PREC_FP32;
+  int rho = 4;  // log2 points per thread and stages per group: 4 (radix 16) or 5 (radix 32)
+  int blocks_per_cu = 0;
+};
+
+// Bytes of a plan's split operands of the group-1 matrix (s >= 4).
+constexpr size_t AMAT_BYTES = 10 * 64 * 16;
+
+// Split operands of the group-1 matrix in FP64 from the exponents of stages
+// 1..4 (a-order entries 0..14), into d_amat (AMAT_BYTES).
+hipError_t launch_stage_matrix(const uint64_t* d_num, const uint8_t* d_den, void* d_amat,
+                               hipStream_t stream);
+
 // Fused batched transform of size 2^s (s <= HIDFT_MAX_LOG2_K_DEVICE).
+// amat may be NULL for PREC_FP32.  hipErrorInvalidValue for a variant that
+// does not exist (matrix cores with s < 4, or with the short group first).
 hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out,
                         int64_t ld_out, uint64_t batch, const float2* tw, const uint16_t* src,
-                        float scale, hipStream_t stream);
+                        const void* amat, float scale, ExecConfig cfg, hipStream_t stream);
+
+// Whether launch_fused has the variant (s, sched, prec, rho).
+bool fused_variant_exists(uint32_t s, int sched, int prec, int rho);
 
 // Inverse (adjoint) transform of size 2^s: coefficients -> samples, scaled.
 hipError_t launch_inverse(uint32_t s, const float2* in, int64_t ld_in, float2* out,

@@ -229,7 +229,8 @@ hidft_status hidft_sas_weights(hidft_sas p, const void* d_samples, int64_t ld_in
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_weights: HOST_ONLY plan");
   hipError_t e = hidft::launch_fused(p->core.s, static_cast<const float2*>(d_samples), ld_in,
                                      static_cast<float2*>(d_weights), ld_out, batch, p->d_tw,
-                                     p->d_src, p->scale, static_cast<hipStream_t>(stream));
+                                     p->d_src, nullptr, p->scale, hidft::ExecConfig{},
+                                     static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_weights: kernel launch");
   return hidft::set_error(HIDFT_OK, "");
 }
@@ -258,11 +259,12 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
   // are packed, else one launch per shift.
   if ((uint64_t)ld_in == mu * ks) {
     e = hidft::launch_fused(p->core.s, in, (int64_t)ks, work, (int64_t)ks, batch * mu, p->d_tw,
-                            p->d_src, p->scale, s);
+                            p->d_src, nullptr, p->scale, hidft::ExecConfig{}, s);
   } else {
     for (uint64_t j = 0; j < mu && e == hipSuccess; ++j)
       e = hidft::launch_fused(p->core.s, in + j * ks, ld_in, work + j * ks, (int64_t)(mu * ks),
-                              batch, p->d_tw, p->d_src, p->scale, s);
+                              batch, p->d_tw, p->d_src, nullptr, p->scale, hidft::ExecConfig{},
+                              s);
   }
   // Steps 5-7: one dual Vandermonde solve per node.
   if (e == hipSuccess)

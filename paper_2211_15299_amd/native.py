@@ -27,6 +27,11 @@ LIB_PATH = os.path.join(HERE, "libhidft.so")
 HIDFT_PLAN_HOST_ONLY = 0x1
 MAX_LOG2_K_DEVICE = 14
 
+# Execution variants (hidft_exec_config)
+PREC_FP32, PREC_F16X2, PREC_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp32": PREC_FP32, "f16x2": PREC_F16X2, "bf16x3": PREC_BF16X3}
+SCHED_DEFAULT, SCHED_SHORT_FIRST, SCHED_SHORT_LAST, SCHED_TUNED = 0, 1, 2, 3
+
 STATUS_NAMES = {
     0: "HIDFT_OK", 1: "HIDFT_ERR_INVALID_ARGUMENT", 2: "HIDFT_ERR_INDEX_OUT_OF_RANGE",
     3: "HIDFT_ERR_DUPLICATE_INDEX", 4: "HIDFT_ERR_SIZE_NOT_POW2",
@@ -51,6 +56,13 @@ SIGNATURES = [
     ("hidft_plan_get_twiddles", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float)]),
     ("hidft_plan_device_bytes", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("hidft_execute", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
+    ("hidft_execute_config", ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _u64, _vp]),
+    ("hidft_autotune", ctypes.c_int, [_vp, _u32, _vp, _i64, _vp, _i64, _u64, _u32, _vp, _vp,
+                                      ctypes.POINTER(ctypes.c_double)]),
+    ("hidft_tune_lookup", ctypes.c_int, [_vp, _u32, _u64, _vp, ctypes.POINTER(_i32)]),
+    ("hidft_tune_clear", ctypes.c_int, []),
+    ("hidft_tune_save", ctypes.c_int, [ctypes.c_char_p]),
+    ("hidft_tune_load", ctypes.c_int, [ctypes.c_char_p]),
     ("hidft_execute_plain", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
     ("hidft_execute_inverse", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
     ("hidft_group_create", ctypes.c_int, [_vp, _u64, _vp, _pp]),
@@ -144,6 +156,19 @@ def _stream_handle(stream) -> Optional[int]:
     return stream.cuda_stream
 
 
+class ExecConfig(ctypes.Structure):
+    """hidft_exec_config: precision, schedule and launch shape of a transform."""
+    _fields_ = [("precision", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
+                ("radix", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32)]
+
+    def __repr__(self):
+        return (f"ExecConfig(precision={self.precision}, schedule={self.schedule}, "
+                f"radix={self.radix}, blocks_per_cu={self.blocks_per_cu})")
+
+    def as_tuple(self):
+        return (self.precision, self.schedule, self.radix, self.blocks_per_cu)
+
+
 class Plan:
     """Owning wrapper of a hidft_plan (hidft_plan_create / hidft_plan_destroy)."""
 
@@ -217,9 +242,33 @@ class Plan:
 
     # -- execution on raw device pointers
     def execute_ptr(self, d_in: int, ld_in: int, d_out: int, ld_out: int, batch: int,
-                    stream=None, plain: bool = False) -> None:
+                    stream=None, plain: bool = False,
+                    config: Optional[ExecConfig] = None) -> None:
+        if config is not None:
+            if plain:
+                raise HiDFTError(1, "the plain method has no execution variants")
+            _check(lib().hidft_execute_config(self.handle, ctypes.byref(config), d_in, ld_in,
+                                              d_out, ld_out, batch, _stream_handle(stream)))
+            return
         fn = lib().hidft_execute_plain if plain else lib().hidft_execute
         _check(fn(self.handle, d_in, ld_in, d_out, ld_out, batch, _stream_handle(stream)))
+
+    def autotune_ptr(self, d_in: int, ld_in: int, d_out: int, ld_out: int, batch: int,
+                     precision: int = PREC_FP32, reps: int = 10, stream=None):
+        """hidft_autotune: (best ExecConfig, its mean launch time in us)."""
+        best = ExecConfig()
+        us = ctypes.c_double(0.0)
+        _check(lib().hidft_autotune(self.handle, precision, d_in, ld_in, d_out, ld_out, batch,
+                                    reps, _stream_handle(stream), ctypes.byref(best),
+                                    ctypes.byref(us)))
+        return best, us.value
+
+    def tune_lookup(self, batch: int, precision: int = PREC_FP32) -> Optional[ExecConfig]:
+        cfg = ExecConfig()
+        found = _i32(0)
+        _check(lib().hidft_tune_lookup(self.handle, precision, batch, ctypes.byref(cfg),
+                                       ctypes.byref(found)))
+        return cfg if found.value else None
 
     def inverse_ptr(self, d_coefs: int, ld_in: int, d_samples: int, ld_out: int, batch: int,
                     stream=None) -> None:
@@ -227,7 +276,8 @@ class Plan:
                                            _stream_handle(stream)))
 
     # -- execution on torch tensors
-    def execute(self, samples, out=None, stream=None, plain: bool = False):
+    def execute(self, samples, out=None, stream=None, plain: bool = False,
+                config: Optional[ExecConfig] = None):
         """Coefficients (batch, k) complex64 of samples (batch, k) or (k,) on the device."""
         if torch is None:
             raise RuntimeError("torch is required for tensor execution")
@@ -244,8 +294,20 @@ class Plan:
             raise HiDFTError(1, "out must match samples' shape, complex64, unit inner stride")
         self.execute_ptr(x.data_ptr(), x.stride(0) if x.shape[0] > 1 else self.k,
                          y.data_ptr(), y.stride(0) if y.shape[0] > 1 else self.k,
-                         x.shape[0], stream, plain)
+                         x.shape[0], stream, plain, config)
         return out
+
+
+def tune_clear() -> None:
+    _check(lib().hidft_tune_clear())
+
+
+def tune_save(path: str) -> None:
+    _check(lib().hidft_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str) -> None:
+    _check(lib().hidft_tune_load(os.fsencode(path)))
 
 
 class Work(ctypes.Structure):

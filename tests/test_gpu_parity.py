@@ -174,10 +174,10 @@ def test_config4_precision_fp32():
     k = len(J)
     plan = native.Plan(M, J)
     I = plan.samples().tolist()
-    n_exact = 3
+    n_exact = 8
     c = log_uniform_coefficients((n_exact, k), rng)
     _say("C4: synthesising 3 signals with the oracle")
-    f_exact = oracle.synthesize_samples(M, J, c, I)
+    f_exact = oracle.synthesize_samples_fft(M, J, c, I)
     f = np.empty((batch, k), dtype=np.complex128)
     f[:n_exact] = f_exact
     scale = np.sqrt(np.mean(np.abs(f_exact) ** 2))

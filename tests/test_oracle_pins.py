@@ -226,6 +226,30 @@ def test_recovery_against_full_fft_and_brute_force(seed):
         assert oracle.rel_l2(bf, c) < 1e-12
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_fft_synthesis_equals_the_direct_sum(seed):
+    """synthesize_samples_fft (one inverse FFT per signal) against the direct
+    O(k |I|) sum and, on tiny N, a brute-force inverse DFT written out."""
+    rng = rng_for(905, seed)
+    M = int(rng.integers(3, 13))
+    s = int(rng.integers(1, min(M, 8) + 1))
+    sup = homogeneous_support(M, s, rng)
+    J = sup.J.tolist()
+    N = 1 << M
+    c = complex_normal((3, len(J)), rng)
+    I = oracle.sample_set(M, J)
+    fast = oracle.synthesize_samples_fft(M, J, c, I)
+    assert fast.shape == (3, len(I))
+    assert np.max(np.abs(fast - oracle.synthesize_samples(M, J, c, I))) < 1e-13
+    assert np.allclose(oracle.synthesize_samples_fft(M, J, c[0], I), fast[0], atol=0)
+    if N <= 64:
+        brute = [[sum(c[b, t] * cmath.exp(2j * math.pi * ((J[t] * i) % N) / N)
+                      for t in range(len(J))) / N for i in I] for b in range(3)]
+        assert np.max(np.abs(fast - np.array(brute))) < 1e-13
+    with pytest.raises(ValueError):
+        oracle.synthesize_samples_fft(M, [0, 0], c[0, :2], I)
+
+
 def test_full_support_is_the_fft():
     """Sec. VIII: J = Z_N reduces the Hi-DFT to the DFT (I_r = Z_N)."""
     rng = rng_for(905, 0)
