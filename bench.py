@@ -54,7 +54,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--mode", choices=["full", "execute", "copy", "grouped", "serve", "precision"],
                     default="full")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -208,7 +208,7 @@ def main():
         "wall_s_timed": wall_s,
         "roofline": {
             "bound": "hbm",
-            "kernel": "hidft_fused_kernel<12, SHORT_FIRST, radix 16, FP32>",
+            "kernel": "hidft_fused_kernel<12, 0, 4, 0>",
             "achieved": achieved_gbps,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",

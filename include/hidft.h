@@ -197,7 +197,7 @@ hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in
  *   there.  The matrix-core precisions need k >= 16.
  * schedule -- where the short group of stages goes when 4 does not divide
  *   s = log2 k (the transform runs in groups of four stages):
- *   HIDFT_SCHED_DEFAULT      SHORT_FIRST for FP32, SHORT_LAST otherwise.
+ *   HIDFT_SCHED_DEFAULT      SHORT_LAST (measured the faster grouping).
  *   HIDFT_SCHED_SHORT_FIRST  the first group is short.
  *   HIDFT_SCHED_SHORT_LAST   the first group is a full four stages and the
  *                            last one is short (required by the matrix-core

@@ -208,10 +208,7 @@ hidft_status resolve_config(const hidft_plan plan, const hidft_exec_config* cfg,
     return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: radix %u is not 0, 16 or 32", fn, cfg->radix);
   ExecConfig c;
   c.prec = (int)cfg->precision;  // HIDFT_PREC_* values equal Prec
-  if (cfg->schedule == HIDFT_SCHED_DEFAULT)
-    c.sched = c.prec == PREC_FP32 ? SCHED_SHORT_FIRST : SCHED_SHORT_LAST;
-  else
-    c.sched = cfg->schedule == HIDFT_SCHED_SHORT_LAST ? SCHED_SHORT_LAST : SCHED_SHORT_FIRST;
+  c.sched = cfg->schedule == HIDFT_SCHED_SHORT_FIRST ? SCHED_SHORT_FIRST : SCHED_SHORT_LAST;
   c.rho = cfg->radix == 32 ? 5 : 4;
   c.blocks_per_cu = cfg->blocks_per_cu > 1024 ? 1024 : (int)cfg->blocks_per_cu;
   if (c.prec != PREC_FP32 && s < 4)

@@ -22,7 +22,7 @@ enum Prec : int { PREC_FP32 = 0, PREC_F16X2 = 1, PREC_BF16X3 = 2 };
 // Launch variant of the fused kernel.  blocks_per_cu caps the persistent grid
 // (sizes up to 2^12) at that many blocks per CU; 0 = as many as fit.
 struct ExecConfig {
-  int sched = SCHED_SHORT_FIRST;
+  int sched = SCHED_SHORT_LAST;
   int prec = PREC_FP32;
   int rho = 4;  // log2 points per thread and stages per group: 4 (radix 16) or 5 (radix 32)
   int blocks_per_cu = 0;

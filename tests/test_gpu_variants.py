@@ -110,7 +110,7 @@ def test_default_config_is_hidft_execute():
     x = torch.from_numpy(f.astype(np.complex64)).cuda()
     a = plan.execute(x)
     b = plan.execute(x, config=native.ExecConfig(FP32, DEFAULT, 0, 0))
-    c = plan.execute(x, config=native.ExecConfig(FP32, FIRST, 0, 0))
+    c = plan.execute(x, config=native.ExecConfig(FP32, LAST, 0, 0))
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(a, c)
 
