@@ -282,6 +282,7 @@ def main():
     args.steps = gsteps
     result["config5_serving"] = serve_bench(args, native, seconds=min(args.serve_seconds, 5.0))
     result["config4_precision"] = precision_bench(args, native, torch, stream, steps=20)
+    result["gap_supports"] = gap_bench(native, torch, stream)
     if not args.no_cpu:
         result["cpu_baseline"]["precision_vs_oracle"] = precision_vs_oracle(native, torch, stream)
     print(json.dumps(result), flush=True)
@@ -520,6 +521,49 @@ def precision_vs_oracle(native, torch, stream, n_exact=8):
                      "max_abs": [float(a) for a in mabs], "max_abs_rel_to_max_coef":
                      float(np.max(mabs / np.max(np.abs(c), axis=1)))}
     plan.close()
+    return out
+
+
+def gap_bench(native, torch, stream, batch=8192, steps=20):
+    """Supports with additive structure: a proper 2-dimensional GAP (16 x 16
+    terms) and an arithmetic progression (1000 terms, difference 2^5 odd) in
+    Z_{2^20}, through Shift-and-Sample with r = all pivots (Lemma 5: 2^n
+    samples, mu* = 1) and with Lemma 4's choice of r."""
+    from workloads import arithmetic_progression, gap_support, rng_for, sample_values
+    out = {"batch": batch, "steps": steps}
+    cases = {"gap_16x16": gap_support(20, [16, 16], rng_for(940, 0)),
+             "ap_1000_alpha5": arithmetic_progression(20, 1000, rng_for(940, 1), 5)}
+    for name, sup in cases.items():
+        J = sup.J.tolist()
+        P, _ = native.analyze(20, J)
+        for label, piv in (("all_pivots", P), ("lemma4_r", None)):
+            plan = native.SASPlan(20, J, pivots=piv, stream=stream)
+            n_in = plan.samples_per_signal
+            x = torch.from_numpy(sample_values(20, n_in, batch, rng_for(940, 2)).astype(
+                np.complex64)).cuda()
+            y = torch.empty((batch, plan.k), dtype=torch.complex64, device="cuda")
+            work = torch.empty(max(plan.workspace_bytes(batch) // 8, 1), dtype=torch.complex64,
+                               device="cuda")
+            run = lambda: plan.execute_ptr(x.data_ptr(), n_in, y.data_ptr(), plan.k, batch,
+                                           work.data_ptr(), stream)
+            for _ in range(3):
+                run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            out[f"{name}/{label}"] = {
+                "k": plan.k, "pivots_of_J": len(P), "r": plan.pivots(), "mu_star": plan.mu_max,
+                "samples_per_transform": n_in, "ms_per_launch": ms,
+                "transforms_per_s": batch / (ms * 1e-3),
+                "GBps": batch * (n_in + plan.k) * 8 / (ms * 1e-3) / 1e9}
+            plan.close()
+            del x, y, work
+    torch.cuda.empty_cache()
     return out
 
 

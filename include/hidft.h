@@ -457,6 +457,11 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  * (no allocation happens in the call).  Inputs and outputs must not overlap.
  * The leaf solves inherit the conditioning of the node's Vandermonde matrix
  * (nodes e^{2 pi i l/N} on the unit circle), which the paper leaves open.
+ * Supports with additive structure (Sec. IX-B, Lemma 5): passing every pivot
+ * of J (from hidft_analyze) as r gives mu* = 1 -- each node at level
+ * r_max + 1 holds one element -- so the call is the Hi-DFT on all pivots,
+ * 2^n samples for n pivots, with trivial leaf solves.  For a proper GAP of
+ * dimension d, 2^n <= n^d 2^d k (the bound in the proof of Lemma 5).
  * hidft_sas_weights: d_samples rows of 2^s samples on I_r (ascending) ->
  * 2^s induced weights mu_J(v, Ff) in slot order (0 at slots with no node, up
  * to rounding); with r truncated to its first s-n pivots this is the Hi-DFT

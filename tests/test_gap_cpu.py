@@ -1,0 +1,106 @@
+"""Supports with additive structure (Sec. IX-A arithmetic progressions, Sec.
+IX-B generalized arithmetic progressions): pins of the oracle's pivot
+computation on them, and the planner against it.
+
+Pins:
+  * Corollary (arithmetic progressions): for J = {a + i s}, s = 2^alpha odd,
+    the differences are (i - i') s, whose 2-adic valuations are alpha + nu2(d)
+    for d = 1..k-1, so the pivot set is exactly {alpha, ..., alpha +
+    floor(log2(k - 1))} -- the closed form of the containment the paper states.
+  * Lemma 5 (proof, Eq. gap-pivot-bound): a proper GAP of dimension d with n
+    pivots satisfies 2^n <= n^d 2^d |J|.
+  * The step of that proof: representatives alpha_i 2^{r_i} of the n pivots
+    (differences of elements of J) have 2^n distinct subset sums mod N.
+  * With r = all pivots, every node at level r_max + 1 holds one element
+    (part-homogeneous with mu* = 1), so the Hi-DFT on all pivots (2^n
+    samples) yields every coefficient: the algorithm of Lemma 5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import arithmetic_progression, gap_support, rng_for
+
+native = pytest.importorskip("paper_2211_15299_amd.native")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_arithmetic_progression_pivots_closed_form(seed):
+    rng = rng_for(920, seed)
+    M = int(rng.integers(4, 25))
+    alpha = int(rng.integers(0, M))
+    k = int(rng.integers(2, min(1 << (M - alpha), 700) + 1))
+    ap = arithmetic_progression(M, k, rng, alpha)
+    J = ap.J.tolist()
+    want = list(range(alpha, alpha + int(math.floor(math.log2(k - 1))) + 1))
+    assert oracle.pivots(M, J) == want
+    if k <= 64:
+        assert oracle.pivots_by_tree(M, J) == want
+    got, hom = native.analyze(M, J)
+    assert got == want
+    assert hom == (len(want) == math.log2(k))
+
+
+def _representatives(M, J, P):
+    """One difference of elements of J with valuation r, for each pivot r."""
+    N = 1 << M
+    reps = {}
+    Js = np.asarray(J, dtype=np.int64)
+    for j in J[:64]:
+        d = (Js - j) % N
+        for x in d[d != 0].tolist():
+            r = oracle.nu2(x)
+            reps.setdefault(r, x)
+    # pivots realised only by pairs not involving the first 64 elements
+    if len(reps) < len(P):
+        for a in range(len(J)):
+            for b in range(a + 1, len(J)):
+                x = (J[a] - J[b]) % N
+                reps.setdefault(oracle.nu2(x), x)
+    return [reps[r] for r in P]
+
+
+@pytest.mark.parametrize("sizes", [[64], [16, 16], [8, 8, 4], [32, 8], [4, 4, 4, 4],
+                                   [128], [8, 16, 2]])
+def test_gap_pivot_bound_and_subset_sums(sizes):
+    rng = rng_for(921, len(sizes) * 1000 + sizes[0])
+    for inst in range(3):
+        M = int(rng.integers(14, 25))
+        g = gap_support(M, sizes, rng)
+        J = g.J.tolist()
+        k, d = len(J), len(sizes)
+        P = oracle.pivots(M, J)
+        n = len(P)
+        assert 2 ** n <= (n ** d) * (2 ** d) * k, (sizes, n)
+        assert n >= math.ceil(math.log2(k))              # Prop. 1: never fewer
+        reps = _representatives(M, J, P)
+        assert [oracle.nu2(x) for x in reps] == P
+        N = 1 << M
+        sums = set()
+        for mask in range(1 << n):
+            sums.add(sum(reps[i] for i in range(n) if mask >> i & 1) % N)
+        assert len(sums) == 1 << n
+        # all pivots: one element per node at level r_max + 1
+        assert oracle.is_part_homogeneous(M, J, P)
+        nodes = oracle.level_nodes(M, J, max(P) + 1)
+        assert all(len(v) == 1 for v in nodes.values())
+        # the planner agrees, and plans the Hi-DFT on all pivots with mu* = 1
+        got, hom = native.analyze(M, J)
+        assert got == P
+        if n <= native.MAX_LOG2_K_DEVICE:
+            plan = native.SASPlan(M, J, pivots=P, host_only=True)
+            assert plan.mu_max == 1 and plan.samples_per_signal == 1 << n
+            assert plan.samples().tolist() == oracle.sas_sample_set(M, P, 1)[0]
+            plan.close()
+
+
+def test_gap_generator_is_proper_and_seeded():
+    a = gap_support(16, [8, 4], rng_for(922, 0))
+    b = gap_support(16, [8, 4], rng_for(922, 0))
+    assert a.J.tolist() == b.J.tolist() and len(set(a.J.tolist())) == 32
+    with pytest.raises(ValueError):
+        gap_support(4, [8, 4], rng_for(922, 1))
+    with pytest.raises(ValueError):
+        arithmetic_progression(10, 9, rng_for(922, 2), alpha=7)

@@ -122,6 +122,52 @@ def composite_support(M: int, blocks: list, rng: np.random.Generator) -> Support
     return Support(M, J, tuple(sorted(levels)))
 
 
+def gap_support(M: int, sizes, rng: np.random.Generator, *, max_tries: int = 1000,
+                shuffle: bool = True) -> Support:
+    """A proper generalized arithmetic progression of dimension d = len(sizes)
+    (Sec. IX-B, Def. GAP): {a + n_1 s_1 + ... + n_d s_d mod N : 0 <= n_i < N_i},
+    with the offset a and the common differences s_i drawn uniformly from Z_N
+    (odd or even), redrawn until all prod(N_i) sums are distinct (proper).
+
+    GAPs are not built from split levels: ``levels`` is empty.
+    """
+    sizes = [int(n) for n in sizes]
+    N = 1 << M
+    k = int(np.prod(sizes)) if sizes else 1
+    if k > N:
+        raise ValueError("a proper GAP has at most N elements")
+    grids = np.meshgrid(*[np.arange(n, dtype=np.int64) for n in sizes], indexing="ij")
+    for _ in range(max_tries):
+        a = int(rng.integers(0, N))
+        steps = [int(x) for x in rng.integers(1, N, size=len(sizes))]
+        J = np.full(grids[0].shape if sizes else (), a, dtype=np.int64)
+        for g, st in zip(grids, steps):
+            J = J + g * st
+        J = (J.reshape(-1) % N).astype(np.uint64)
+        if len(np.unique(J)) == k:
+            if shuffle:
+                J = J[rng.permutation(k)]
+            return Support(M, J, ())
+    raise RuntimeError("no proper GAP found; use smaller sizes or a larger N")
+
+
+def arithmetic_progression(M: int, k: int, rng: np.random.Generator, alpha: int,
+                           shuffle: bool = True) -> Support:
+    """{a + i s mod N : i < k} with common difference s = 2^alpha * (odd), a
+    and the odd factor drawn uniformly (Sec. IX-A, arithmetic progressions of
+    arbitrary common difference).  Needs k <= 2^(M - alpha) (distinct terms)."""
+    N = 1 << M
+    if alpha < 0 or alpha >= M or k > (N >> alpha):
+        raise ValueError("need 0 <= alpha < M and k <= 2^(M - alpha)")
+    a = int(rng.integers(0, N))
+    odd = int(rng.integers(0, max(N >> (alpha + 1), 1))) * 2 + 1
+    s = (odd << alpha) % N
+    J = ((a + np.arange(k, dtype=np.int64) * s) % N).astype(np.uint64)
+    if shuffle:
+        J = J[rng.permutation(k)]
+    return Support(M, J, ())
+
+
 def complex_normal(shape, rng: np.random.Generator, scale: float = 1.0) -> np.ndarray:
     """Circular standard complex normal CN(0, scale^2): Re, Im ~ N(0, scale^2/2)."""
     re = rng.standard_normal(shape)
