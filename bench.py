@@ -283,6 +283,8 @@ def main():
     result["config5_serving"] = serve_bench(args, native, seconds=min(args.serve_seconds, 5.0))
     result["config4_precision"] = precision_bench(args, native, torch, stream, steps=20)
     result["gap_supports"] = gap_bench(native, torch, stream)
+    result["inverse"] = inverse_bench(args, native, torch, stream)
+    result["shift_and_sample"] = sas_bench(native, torch, stream)
     if not args.no_cpu:
         result["cpu_baseline"]["precision_vs_oracle"] = precision_vs_oracle(native, torch, stream)
     print(json.dumps(result), flush=True)
@@ -521,6 +523,79 @@ def precision_vs_oracle(native, torch, stream, n_exact=8):
                      "max_abs": [float(a) for a in mabs], "max_abs_rel_to_max_coef":
                      float(np.max(mabs / np.max(np.abs(c), axis=1)))}
     plan.close()
+    return out
+
+
+def inverse_bench(args, native, torch, stream, steps=50):
+    """The inverse map (coefficients on J -> samples on I_r) on the headline
+    workload's shape: N = 2^20, k = 2^12, 4096 signals, rotating buffers."""
+    from workloads import complex_normal, homogeneous_support, rng_for
+    M, k, batch = WORKLOAD["log2_n"], WORKLOAD["k"], WORKLOAD["batch"]
+    rng = rng_for(2, 0)
+    J = homogeneous_support(M, k.bit_length() - 1, rng).J.tolist()
+    plan = native.Plan(M, J, stream=stream)
+    sets = max(args.sets, 1)
+    cs = [torch.from_numpy(complex_normal((batch, k), rng).astype(np.complex64)).cuda()]
+    cs += [cs[0].clone() for _ in range(sets - 1)]
+    fs = [torch.empty_like(cs[0]) for _ in range(sets)]
+    for i in range(5):
+        plan.inverse_ptr(cs[i % sets].data_ptr(), k, fs[i % sets].data_ptr(), k, batch, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        plan.inverse_ptr(cs[i % sets].data_ptr(), k, fs[i % sets].data_ptr(), k, batch, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # round trip on one set: forward(inverse(c)) = c
+    back = torch.empty_like(cs[0])
+    plan.inverse_ptr(cs[0].data_ptr(), k, fs[0].data_ptr(), k, batch, stream)
+    plan.execute_ptr(fs[0].data_ptr(), k, back.data_ptr(), k, batch, stream)
+    torch.cuda.synchronize()
+    rt = ((back - cs[0]).abs().pow(2).sum(1).sqrt() / cs[0].abs().pow(2).sum(1).sqrt()).max().item()
+    plan.close()
+    del cs, fs, back
+    torch.cuda.empty_cache()
+    return {"workload": "N=2^20, k=2^12, 4096 signals", "ms_per_launch": ms,
+            "transforms_per_s": batch / (ms * 1e-3), "GBps": batch * k * 16 / (ms * 1e-3) / 1e9,
+            "round_trip_rel_l2_max": rt, "steps": steps, "sets": sets}
+
+
+def sas_bench(native, torch, stream, batch=4096, steps=20):
+    """Shift-and-Sample on a random half of a homogeneous set (N = 2^20, 2^12
+    candidate positions, 2048 elements kept), r chosen by Lemma 4's cost: mu*
+    shifted Hi-DFTs in one launch, then the FP64 leaf solves."""
+    from workloads import homogeneous_support, rng_for, sample_values
+    rng = rng_for(941, 0)
+    K = homogeneous_support(20, 12, rng)
+    keep = rng.random(len(K.J)) < 0.5
+    J = [int(j) for j, kp in zip(K.J, keep) if kp]
+    plan = native.SASPlan(20, J, stream=stream)
+    n_in = plan.samples_per_signal
+    x = torch.from_numpy(sample_values(20, n_in, batch, rng).astype(np.complex64)).cuda()
+    y = torch.empty((batch, plan.k), dtype=torch.complex64, device="cuda")
+    work = torch.empty(max(plan.workspace_bytes(batch) // 8, 1), dtype=torch.complex64,
+                       device="cuda")
+    run = lambda: plan.execute_ptr(x.data_ptr(), n_in, y.data_ptr(), plan.k, batch,
+                                   work.data_ptr(), stream)
+    for _ in range(3):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out = {"k": plan.k, "r": plan.pivots(), "mu_star": plan.mu_max, "nodes": plan.n_nodes,
+           "samples_per_transform": n_in, "lemma4_cost": plan.cost, "batch": batch,
+           "ms_per_launch": ms, "transforms_per_s": batch / (ms * 1e-3),
+           "GBps": batch * (n_in + plan.k) * 8 / (ms * 1e-3) / 1e9}
+    plan.close()
+    del x, y, work
+    torch.cuda.empty_cache()
     return out
 
 

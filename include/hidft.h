@@ -453,10 +453,16 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  * hidft_sas_get_nodes: node index of each J[t], and the slot of each node.
  * hidft_sas_execute: d_samples rows (ld_in >= mu* 2^s) -> d_coefs rows
  * (ld_out >= k, caller's order of J).  d_work: device workspace of
- * hidft_sas_workspace_bytes(batch) bytes, 8-byte aligned, owned by the caller
- * (no allocation happens in the call).  Inputs and outputs must not overlap.
- * The leaf solves inherit the conditioning of the node's Vandermonde matrix
- * (nodes e^{2 pi i l/N} on the unit circle), which the paper leaves open.
+ * hidft_sas_workspace_bytes(batch) bytes (mu* n_nodes complex64 values per
+ * signal), 8-byte aligned, owned by the caller (no allocation happens in the
+ * call); when that size is 0 (mu* = 1: the Hi-DFT output is the answer)
+ * d_work may be NULL.  Inputs and outputs must not overlap.
+ * The leaf solves: each node's dual Vandermonde matrix is inverted once, in
+ * FP64 on the device, at plan creation (the plan holds sum_v mu(v)^2
+ * complex128 values); per signal each coefficient is one row of that inverse
+ * times the node's mu(v) values, accumulated in FP64.  They inherit the
+ * conditioning of the node's Vandermonde matrix (nodes e^{2 pi i l/N} on the
+ * unit circle), which the paper leaves open.
  * Supports with additive structure (Sec. IX-B, Lemma 5): passing every pivot
  * of J (from hidft_analyze) as r gives mu* = 1 -- each node at level
  * r_max + 1 holds one element -- so the call is the Hi-DFT on all pivots,

@@ -392,10 +392,11 @@ struct FlatMem {
   const float2* tw;
   const uint16_t* src;
   float2* out;
+  uint32_t n_out;  // outputs stored per signal (a prefix of the gather order)
   __device__ __forceinline__ float2 tw_at(int uni, int lane) const { return tw[uni + lane]; }
   __device__ __forceinline__ int src_at(int uni, int lane) const { return src[uni + lane]; }
   __device__ __forceinline__ void put(int uni, int lane, float2 x) const {
-    store_stream(out + uni + lane, x);
+    if ((uint32_t)(uni + lane) < n_out) store_stream(out + uni + lane, x);
   }
 };
 
@@ -635,7 +636,7 @@ __global__ void __launch_bounds__((FusedShape<S, SCHED, RH>::THREADS))
 hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ out,
                    int64_t ld_out, uint64_t batch, const float2* __restrict__ tw,
                    const uint16_t* __restrict__ src, const uint4* __restrict__ amat,
-                   float scale) {
+                   float scale, uint32_t n_out) {
   using Sh = FusedShape<S, SCHED, RH>;
   constexpr int R = Sh::R, T = Sh::T, SPB = Sh::SPB;
   extern __shared__ float2 lds[];
@@ -653,7 +654,7 @@ hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
     const uint64_t grp = blockIdx.x;
     float2 v[R];
     load_group1<S, SCHED, RH, PREC>(v, in, ld_in, grp, batch);
-    const FlatMem mem{tw, src, out + grp * (uint64_t)ld_out};
+    const FlatMem mem{tw, src, out + grp * (uint64_t)ld_out, n_out};
     ThreadState<S, SCHED, RH> unused;
     transform_signal<S, SCHED, RH, PREC, false>(v, lds, 0, tau, true, mem, scale, unused, op);
   } else {
@@ -669,7 +670,7 @@ hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
       if (grp + gridDim.x < n_groups)
         load_group1<S, SCHED, RH, PREC>(vn, in, ld_in, (grp + gridDim.x) * SPB, batch);
       const uint64_t sig = grp * SPB + slot;
-      const FlatMem mem{tw, src, out + (sig < batch ? sig : 0) * (uint64_t)ld_out};
+      const FlatMem mem{tw, src, out + (sig < batch ? sig : 0) * (uint64_t)ld_out, n_out};
       transform_signal<S, SCHED, RH, PREC, true>(v, lds, slot, tau, sig < batch, mem, scale,
                                                   ts, op);
       lds_barrier();  // the next group overwrites these LDS slots
@@ -882,8 +883,8 @@ static hipError_t query_occupancy(const void* kernel, int threads, size_t lds_by
 template <int S, int SCHED, int RH, int PREC>
 static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
                                  uint64_t batch, const float2* tw, const uint16_t* src,
-                                 const uint4* amat, float scale, int blocks_per_cu,
-                                 hipStream_t stream) {
+                                 const uint4* amat, float scale, uint32_t n_out,
+                                 int blocks_per_cu, hipStream_t stream) {
   using Sh = FusedShape<S, SCHED, RH>;
   const void* kernel = (const void*)hidft_fused_kernel<S, SCHED, RH, PREC>;
   static Occupancy occ;  // benign race: every thread computes the same value
@@ -900,7 +901,8 @@ static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, i
       const uint64_t n = batch - first < chunk ? batch - first : chunk;
       hipLaunchKernelGGL((hidft_fused_kernel<S, SCHED, RH, PREC>), dim3((unsigned)n),
                          dim3(Sh::THREADS), Sh::LDS_BYTES, stream, in + first * (uint64_t)ld_in,
-                         ld_in, out + first * (uint64_t)ld_out, ld_out, n, tw, src, amat, scale);
+                         ld_in, out + first * (uint64_t)ld_out, ld_out, n, tw, src, amat, scale,
+                         n_out);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -912,7 +914,8 @@ static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, i
   const uint64_t groups = (batch + Sh::SPB - 1) / Sh::SPB;
   const unsigned grid = (unsigned)(groups < max_grid ? groups : max_grid);
   hipLaunchKernelGGL((hidft_fused_kernel<S, SCHED, RH, PREC>), dim3(grid), dim3(Sh::THREADS),
-                     Sh::LDS_BYTES, stream, in, ld_in, out, ld_out, batch, tw, src, amat, scale);
+                     Sh::LDS_BYTES, stream, in, ld_in, out, ld_out, batch, tw, src, amat, scale,
+                     n_out);
   return hipGetLastError();
 }
 
@@ -931,8 +934,8 @@ bool fused_variant_exists(uint32_t s, int sched, int prec, int rho) {
 template <int S>
 static hipError_t dispatch_fused(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
                                  uint64_t batch, const float2* tw, const uint16_t* src,
-                                 const uint4* amat, float scale, const ExecConfig& cfg,
-                                 hipStream_t stream) {
+                                 const uint4* amat, float scale, uint32_t n_out,
+                                 const ExecConfig& cfg, hipStream_t stream) {
   const int bpc = cfg.blocks_per_cu;
   const bool last = cfg.sched == SCHED_SHORT_LAST;
   if constexpr (S >= 13) {
@@ -940,10 +943,10 @@ static hipError_t dispatch_fused(const float2* in, int64_t ld_in, float2* out, i
       // Radix 32: 13 = 3 + 5 + 5 or 5 + 5 + 3, 14 = 4 + 5 + 5 or 5 + 5 + 4.
       if (last)
         return launch_fused_s<S, SCHED_SHORT_LAST, 5, PREC_FP32>(in, ld_in, out, ld_out, batch,
-                                                                 tw, src, amat, scale, bpc,
+                                                                 tw, src, amat, scale, n_out, bpc,
                                                                  stream);
       return launch_fused_s<S, SCHED_SHORT_FIRST, 5, PREC_FP32>(in, ld_in, out, ld_out, batch,
-                                                                tw, src, amat, scale, bpc, stream);
+                                                                tw, src, amat, scale, n_out, bpc, stream);
     }
   }
   // When 4 divides S (or S < 4) the two schedules are the same kernel.
@@ -952,30 +955,33 @@ static hipError_t dispatch_fused(const float2* in, int64_t ld_in, float2* out, i
     if constexpr (TWO_SCHEDS) {
       if (last)
         return launch_fused_s<S, SCHED_SHORT_LAST, 4, PREC_FP32>(in, ld_in, out, ld_out, batch,
-                                                                 tw, src, amat, scale, bpc,
+                                                                 tw, src, amat, scale, n_out, bpc,
                                                                  stream);
     }
     return launch_fused_s<S, SCHED_SHORT_FIRST, 4, PREC_FP32>(in, ld_in, out, ld_out, batch, tw,
-                                                              src, amat, scale, bpc, stream);
+                                                              src, amat, scale, n_out, bpc, stream);
   }
   if constexpr (S >= 4) {
     constexpr int SC = TWO_SCHEDS ? SCHED_SHORT_LAST : SCHED_SHORT_FIRST;
     if (cfg.prec == PREC_F16X2)
       return launch_fused_s<S, SC, 4, PREC_F16X2>(in, ld_in, out, ld_out, batch, tw, src, amat,
-                                                  scale, bpc, stream);
+                                                  scale, n_out, bpc, stream);
     if (cfg.prec == PREC_BF16X3)
       return launch_fused_s<S, SC, 4, PREC_BF16X3>(in, ld_in, out, ld_out, batch, tw, src, amat,
-                                                   scale, bpc, stream);
+                                                   scale, n_out, bpc, stream);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out,
                         int64_t ld_out, uint64_t batch, const float2* tw, const uint16_t* src,
-                        const void* amat, float scale, ExecConfig cfg, hipStream_t stream) {
+                        const void* amat, float scale, ExecConfig cfg, hipStream_t stream,
+                        uint32_t n_out) {
   if (!fused_variant_exists(s, cfg.sched, cfg.prec, cfg.rho)) return hipErrorInvalidValue;
   if (cfg.prec != PREC_FP32 && amat == nullptr) return hipErrorInvalidValue;
   if (batch == 0) return hipSuccess;
+  const uint32_t k = 1u << s;
+  if (n_out == 0 || n_out > k) n_out = k;
   const uint4* am = static_cast<const uint4*>(amat);
   switch (s) {
     case 0: {
@@ -987,7 +993,8 @@ hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out
     }
 #define HIDFT_CASE(S) \
   case S:             \
-    return dispatch_fused<S>(in, ld_in, out, ld_out, batch, tw, src, am, scale, cfg, stream);
+    return dispatch_fused<S>(in, ld_in, out, ld_out, batch, tw, src, am, scale, n_out, cfg, \
+                             stream);
     HIDFT_CASE(1) HIDFT_CASE(2) HIDFT_CASE(3) HIDFT_CASE(4) HIDFT_CASE(5) HIDFT_CASE(6)
     HIDFT_CASE(7) HIDFT_CASE(8) HIDFT_CASE(9) HIDFT_CASE(10) HIDFT_CASE(11) HIDFT_CASE(12)
     HIDFT_CASE(13) HIDFT_CASE(14)
@@ -1078,7 +1085,7 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
 #pragma unroll
     for (int c = 0; c < R; ++c)
       v[c] = valid ? load_stream(d.in + c * T + tau) : make_float2(0.f, 0.f);
-    const FlatMem mem{d.tw, d.src, d.out};
+    const FlatMem mem{d.tw, d.src, d.out, K};
     transform_signal<S, SCHED_SHORT_LAST, 4, PREC_FP32, false>(v, lds, slot, tau, valid, mem,
                                                              d.scale, unused, no_mfma);
   }
@@ -1141,12 +1148,15 @@ hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const Grou
 // ---------------------------------------------------------------------------
 // Shift-and-Sample leaf solves (Algorithm 2, steps 5-7), FP64.
 //
-// y holds, per signal b and shift j < mu*, the Hi-DFT of the samples on
-// I_r + j scaled by N/2^s, in slot order: y_j(v) = sum_{l in v} c_l e^{2 pi i j l / N}
-// at the slot of node v.  For each node the mu(v) unknowns c_l solve the
-// dual Vandermonde system sum_t c_t z_t^j = y_j, j < mu(v), z_t = e^{2 pi i l_t / N}
-// (Eq. alg1_system), here by the Bjorck-Pereyra recurrences for that system
-// (O(mu^2) operations, O(mu) storage).  One thread per (signal, node).
+// For each node v at level r_max + 1 with elements l_0..l_{mu-1}, the shifted
+// Hi-DFTs give y_j(v) = sum_t c_t z_t^j for j < mu* (scaled by N/2^s),
+// z_t = e^{2 pi i l_t / N}: the dual Vandermonde system V c = y of
+// Eq. alg1_system, V[j][t] = z_t^j, in its first mu(v) rows.  The matrix
+// depends on the plan only, so its inverse is formed once, in FP64, at plan
+// creation (sas_inverse_kernel: column j is the Bjorck-Pereyra solution for
+// the unit vector e_j, O(mu^2) per column), and each signal's solve is one
+// row of that inverse times the node's mu values, accumulated in FP64
+// (sas_apply_kernel).
 // ---------------------------------------------------------------------------
 struct cplx64 {
   double x, y;
@@ -1160,19 +1170,16 @@ __device__ __forceinline__ cplx64 cdiv(cplx64 a, cplx64 b) {
   return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
 }
 
-__global__ void __launch_bounds__(128)
-sas_leaf_kernel(const float2* __restrict__ y, uint32_t ks, uint32_t mu_star, uint64_t batch,
-                uint32_t n_nodes, const uint32_t* __restrict__ node_slot,
-                const uint32_t* __restrict__ node_first, const uint32_t* __restrict__ node_count,
-                const uint32_t* __restrict__ elem_t, const uint64_t* __restrict__ elem_val,
-                uint32_t log2_n, float2* __restrict__ out, int64_t ld_out) {
-  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= batch * (uint64_t)n_nodes) return;
-  const uint64_t b = idx / n_nodes;
-  const uint32_t v = (uint32_t)(idx - b * n_nodes);
+// Plan time, one thread per node: inv[off(v) + i*mu + j] = (V_v^{-1})[i][j].
+__global__ void __launch_bounds__(64)
+sas_inverse_kernel(uint32_t n_nodes, const uint32_t* __restrict__ node_first,
+                   const uint32_t* __restrict__ node_count, const uint32_t* __restrict__ inv_off,
+                   const uint64_t* __restrict__ elem_val, uint32_t log2_n,
+                   cplx64* __restrict__ inv) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_nodes) return;
   const uint32_t mu = node_count[v];
   const uint32_t first = node_first[v];
-  const uint32_t slot = node_slot[v];
   cplx64 x[SAS_MAX_MU], z[SAS_MAX_MU];
   for (uint32_t t = 0; t < mu; ++t) {
     // z = exp(2 pi i l / N) = cospi(2l/N) + i sinpi(2l/N); 2l/N = l 2^{1-M} is exact
@@ -1180,33 +1187,139 @@ sas_leaf_kernel(const float2* __restrict__ y, uint32_t ks, uint32_t mu_star, uin
     double sn, cs;
     sincospi(ldexp((double)elem_val[first + t], 1 - (int)log2_n), &sn, &cs);
     z[t] = {cs, sn};
-    const float2 yj = y[(b * mu_star + t) * ks + slot];
-    x[t] = {(double)yj.x, (double)yj.y};
   }
   const int n = (int)mu - 1;
-  for (int k = 0; k < n; ++k)
-    for (int i = n; i > k; --i) x[i] = csub(x[i], cmul(z[k], x[i - 1]));
-  for (int k = n - 1; k >= 0; --k) {
-    for (int i = k + 1; i <= n; ++i) x[i] = cdiv(x[i], csub(z[i], z[i - k - 1]));
-    for (int i = k; i < n; ++i) x[i] = csub(x[i], x[i + 1]);
+  for (uint32_t col = 0; col < mu; ++col) {
+    for (uint32_t t = 0; t < mu; ++t) x[t] = {t == col ? 1.0 : 0.0, 0.0};
+    for (int k = 0; k < n; ++k)
+      for (int i = n; i > k; --i) x[i] = csub(x[i], cmul(z[k], x[i - 1]));
+    for (int k = n - 1; k >= 0; --k) {
+      for (int i = k + 1; i <= n; ++i) x[i] = cdiv(x[i], csub(z[i], z[i - k - 1]));
+      for (int i = k; i < n; ++i) x[i] = csub(x[i], x[i + 1]);
+    }
+    for (uint32_t i = 0; i < mu; ++i) inv[inv_off[v] + i * mu + col] = x[i];
   }
-  float2* orow = out + b * (uint64_t)ld_out;
-  for (uint32_t t = 0; t < mu; ++t)
-    orow[elem_t[first + t]] = make_float2((float)x[t].x, (float)x[t].y);
 }
 
-hipError_t launch_sas_leaf(const float2* y, uint32_t ks, uint32_t mu_star, uint64_t batch,
-                           uint32_t n_nodes, const uint32_t* node_slot, const uint32_t* node_first,
-                           const uint32_t* node_count, const uint32_t* elem_t,
-                           const uint64_t* elem_val, uint32_t log2_n, float2* out, int64_t ld_out,
-                           hipStream_t stream) {
-  const uint64_t work = batch * (uint64_t)n_nodes;
-  if (work == 0) return hipSuccess;
-  const uint64_t blocks = (work + 127) / 128;
-  if (blocks > 0x7fffffffULL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sas_leaf_kernel, dim3((unsigned)blocks), dim3(128), 0, stream, y, ks,
-                     mu_star, batch, n_nodes, node_slot, node_first, node_count, elem_t, elem_val,
-                     log2_n, out, ld_out);
+hipError_t launch_sas_inverse(uint32_t n_nodes, const uint32_t* node_first,
+                              const uint32_t* node_count, const uint32_t* inv_off,
+                              const uint64_t* elem_val, uint32_t log2_n, void* inv,
+                              hipStream_t stream) {
+  if (n_nodes == 0) return hipSuccess;
+  hipLaunchKernelGGL(sas_inverse_kernel, dim3((n_nodes + 63) / 64), dim3(64), 0, stream,
+                     n_nodes, node_first, node_count, inv_off, elem_val, log2_n,
+                     static_cast<cplx64*>(inv));
+  return hipGetLastError();
+}
+
+// Per signal, one thread per element e (elements in node order): the element
+// is row i = e - first(v) of node v = elem_node[e]; y is [signal][shift][node].
+constexpr int SAS_APPLY_THREADS = 256;
+
+__global__ void __launch_bounds__(SAS_APPLY_THREADS)
+sas_apply_kernel(const float2* __restrict__ y, uint32_t n_nodes, uint32_t mu_star,
+                 uint64_t batch, uint32_t k, const uint32_t* __restrict__ elem_node,
+                 const uint32_t* __restrict__ node_first, const uint32_t* __restrict__ node_count,
+                 const uint32_t* __restrict__ inv_off, const cplx64* __restrict__ inv,
+                 const uint32_t* __restrict__ elem_t, float2* __restrict__ out, int64_t ld_out) {
+  const uint32_t e = blockIdx.x * SAS_APPLY_THREADS + threadIdx.x;
+  if (e >= k) return;
+  const uint32_t v = elem_node[e];
+  const uint32_t mu = node_count[v];
+  const cplx64* row = inv + inv_off[v] + (e - node_first[v]) * mu;
+  const uint32_t dst = elem_t[e];
+  for (uint64_t b = blockIdx.y; b < batch; b += gridDim.y) {
+    const float2* yv = y + b * mu_star * (uint64_t)n_nodes + v;
+    double ar = 0.0, ai = 0.0;
+    for (uint32_t j = 0; j < mu; ++j) {
+      const float2 q = yv[(uint64_t)j * n_nodes];
+      const cplx64 m = row[j];
+      ar = fma(m.x, (double)q.x, fma(-m.y, (double)q.y, ar));
+      ai = fma(m.x, (double)q.y, fma(m.y, (double)q.x, ai));
+    }
+    store_stream(out + b * (uint64_t)ld_out + dst, make_float2((float)ar, (float)ai));
+  }
+}
+
+// The same solves with one block per signal (grid-stride over the batch):
+// the signal's mu* rows of node values are loaded into LDS with coalesced
+// reads, each element's coefficient is written to its caller position in
+// LDS, and the output row leaves with coalesced stores.  For plans whose
+// (mu* n_nodes + k) values fit in SAS_LDS_VALUES.
+constexpr int SAS_LDS_VALUES = 8192;  // 64 KB of complex64
+
+__global__ void __launch_bounds__(SAS_APPLY_THREADS)
+sas_apply_lds_kernel(const float2* __restrict__ y, uint32_t n_nodes, uint32_t mu_star,
+                     uint64_t batch, uint32_t k, const uint32_t* __restrict__ elem_node,
+                     const uint32_t* __restrict__ node_first,
+                     const uint32_t* __restrict__ node_count,
+                     const uint32_t* __restrict__ inv_off, const cplx64* __restrict__ inv,
+                     const uint32_t* __restrict__ elem_t, float2* __restrict__ out,
+                     int64_t ld_out) {
+  extern __shared__ float2 sm[];
+  const uint32_t ny = mu_star * n_nodes;
+  float2* res = sm + ny;
+  for (uint64_t b = blockIdx.x; b < batch; b += gridDim.x) {
+    const float2* yb = y + b * (uint64_t)ny;
+    for (uint32_t i = threadIdx.x; i < ny; i += SAS_APPLY_THREADS) sm[i] = load_stream(yb + i);
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < k; e += SAS_APPLY_THREADS) {
+      const uint32_t v = elem_node[e];
+      const uint32_t mu = node_count[v];
+      const cplx64* row = inv + inv_off[v] + (e - node_first[v]) * mu;
+      double ar = 0.0, ai = 0.0;
+      for (uint32_t j = 0; j < mu; ++j) {
+        const float2 q = sm[j * n_nodes + v];
+        const cplx64 m = row[j];
+        ar = fma(m.x, (double)q.x, fma(-m.y, (double)q.y, ar));
+        ai = fma(m.x, (double)q.y, fma(m.y, (double)q.x, ai));
+      }
+      res[elem_t[e]] = make_float2((float)ar, (float)ai);
+    }
+    __syncthreads();
+    float2* ob = out + b * (uint64_t)ld_out;
+    for (uint32_t t = threadIdx.x; t < k; t += SAS_APPLY_THREADS) store_stream(ob + t, res[t]);
+    __syncthreads();  // the next signal overwrites the LDS
+  }
+}
+
+hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star, uint64_t batch,
+                            uint32_t k, const uint32_t* elem_node, const uint32_t* node_first,
+                            const uint32_t* node_count, const uint32_t* inv_off, const void* inv,
+                            const uint32_t* elem_t, float2* out, int64_t ld_out,
+                            hipStream_t stream) {
+  if (batch == 0 || k == 0) return hipSuccess;
+  const uint64_t lds_values = (uint64_t)mu_star * n_nodes + k;
+  if (lds_values <= (uint64_t)SAS_LDS_VALUES) {
+    const size_t lds = lds_values * sizeof(float2);
+    static Occupancy occ;  // benign race: every thread computes the same value
+    if (occ.cus == 0) {
+      Occupancy o;
+      hipError_t e = query_occupancy((const void*)sas_apply_lds_kernel, SAS_APPLY_THREADS,
+                                     SAS_LDS_VALUES * sizeof(float2), &o);
+      if (e != hipSuccess) return e;
+      occ = o;
+    }
+    // Blocks that fit per CU at this plan's LDS size (the occupancy above is
+    // for the largest size), times the CUs.
+    const uint64_t per_cu_lds = (160u * 1024u) / (lds ? lds : 1);
+    const uint64_t per_cu = per_cu_lds < 8 ? (per_cu_lds > 0 ? per_cu_lds : 1) : 8;
+    uint64_t grid = per_cu * (uint64_t)occ.cus;
+    if (grid > batch) grid = batch;
+    hipLaunchKernelGGL(sas_apply_lds_kernel, dim3((unsigned)grid), dim3(SAS_APPLY_THREADS), lds,
+                       stream, y, n_nodes, mu_star, batch, k, elem_node, node_first, node_count,
+                       inv_off, static_cast<const cplx64*>(inv), elem_t, out, ld_out);
+    return hipGetLastError();
+  }
+  const unsigned gx = (k + SAS_APPLY_THREADS - 1) / SAS_APPLY_THREADS;
+  // Enough blocks along the batch to fill the device, each striding over signals.
+  uint64_t gy = (4096 + gx - 1) / gx;
+  if (gy > batch) gy = batch;
+  if (gy > 65535) gy = 65535;
+  if (gy == 0) gy = 1;
+  hipLaunchKernelGGL(sas_apply_kernel, dim3(gx, (unsigned)gy), dim3(SAS_APPLY_THREADS), 0,
+                     stream, y, n_nodes, mu_star, batch, k, elem_node, node_first, node_count,
+                     inv_off, static_cast<const cplx64*>(inv), elem_t, out, ld_out);
   return hipGetLastError();
 }
 

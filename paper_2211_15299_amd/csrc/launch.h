@@ -39,9 +39,12 @@ hipError_t launch_stage_matrix(const uint64_t* d_num, const uint8_t* d_den, void
 // Fused batched transform of size 2^s (s <= HIDFT_MAX_LOG2_K_DEVICE).
 // amat may be NULL for PREC_FP32.  hipErrorInvalidValue for a variant that
 // does not exist (matrix cores with s < 4, or with the short group first).
+// n_out: outputs stored per signal, the first n_out of the gather order
+// (0 = all 2^s); the gather table still has 2^s entries.
 hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out,
                         int64_t ld_out, uint64_t batch, const float2* tw, const uint16_t* src,
-                        const void* amat, float scale, ExecConfig cfg, hipStream_t stream);
+                        const void* amat, float scale, ExecConfig cfg, hipStream_t stream,
+                        uint32_t n_out = 0);
 
 // Whether launch_fused has the variant (s, sched, prec, rho).
 bool fused_variant_exists(uint32_t s, int sched, int prec, int rho);
@@ -81,14 +84,21 @@ hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const Grou
 // Largest node (number of aliased coefficients) the leaf solves handle.
 constexpr int SAS_MAX_MU = 32;
 
-// Shift-and-Sample leaf solves: one FP64 dual Vandermonde solve per node and
-// signal, from the shifted Hi-DFT values y (slot order, mu* rows of ks per
-// signal), writing the coefficients to their positions t in the output rows.
-hipError_t launch_sas_leaf(const float2* y, uint32_t ks, uint32_t mu_star, uint64_t batch,
-                           uint32_t n_nodes, const uint32_t* node_slot, const uint32_t* node_first,
-                           const uint32_t* node_count, const uint32_t* elem_t,
-                           const uint64_t* elem_val, uint32_t log2_n, float2* out, int64_t ld_out,
-                           hipStream_t stream);
+// Shift-and-Sample leaf solves, plan time: each node's inverse dual
+// Vandermonde matrix in FP64, row-major at inv + inv_off[v] (complex128).
+hipError_t launch_sas_inverse(uint32_t n_nodes, const uint32_t* node_first,
+                              const uint32_t* node_count, const uint32_t* inv_off,
+                              const uint64_t* elem_val, uint32_t log2_n, void* inv,
+                              hipStream_t stream);
+
+// Per signal: the coefficients c = V_v^{-1} y(v) of every node, from the
+// shifted Hi-DFT values y ([signal][shift][node], n_nodes per row), written
+// to the caller's positions elem_t of each output row.
+hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star, uint64_t batch,
+                            uint32_t k, const uint32_t* elem_node, const uint32_t* node_first,
+                            const uint32_t* node_count, const uint32_t* inv_off, const void* inv,
+                            const uint32_t* elem_t, float2* out, int64_t ld_out,
+                            hipStream_t stream);
 
 // Plain method: one signal, one block, one radix-2 stage per barrier.
 hipError_t launch_plain(uint32_t s, const float2* in, float2* out, const float2* tw,

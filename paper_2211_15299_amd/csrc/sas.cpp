@@ -16,26 +16,29 @@ struct hidft_sas_s {
   int device = -1;
   float scale = 1.0f;              // N / 2^s
   float2* d_tw = nullptr;          // 2^s - 1 twiddles, a-order
-  uint16_t* d_src = nullptr;       // slot order: src[t] = bitrev_s(t)
-  uint32_t* d_node_slot = nullptr;
+  uint16_t* d_src = nullptr;       // slot order: src[t] = bitrev_s(t) (induced weights)
+  uint16_t* d_src_node = nullptr;  // node order: bitrev_s(slot of node v), padded to 2^s
+  uint16_t* d_src_elem = nullptr;  // mu* = 1: caller order, bitrev_s(slot of J[t]'s node)
   uint32_t* d_node_first = nullptr;
   uint32_t* d_node_count = nullptr;
   uint32_t* d_elem_t = nullptr;
-  uint64_t* d_elem_val = nullptr;
+  uint32_t* d_elem_node = nullptr;  // node of each element, elements in node order
+  uint32_t* d_inv_off = nullptr;    // offset of each node's inverse (complex128 units)
+  void* d_inv = nullptr;            // inverse dual Vandermonde matrices, FP64
   size_t device_bytes = 0;
 };
 
 namespace {
 
 void release(hidft_sas p) {
-  void* ptrs[] = {p->d_tw, p->d_src, p->d_node_slot, p->d_node_first,
-                  p->d_node_count, p->d_elem_t, p->d_elem_val};
+  void* ptrs[] = {p->d_tw,         p->d_src,      p->d_src_node,  p->d_src_elem, p->d_node_first,
+                  p->d_node_count, p->d_elem_t,   p->d_elem_node, p->d_inv_off,  p->d_inv};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   p->d_tw = nullptr;
-  p->d_src = nullptr;
-  p->d_node_slot = p->d_node_first = p->d_node_count = p->d_elem_t = nullptr;
-  p->d_elem_val = nullptr;
+  p->d_src = p->d_src_node = p->d_src_elem = nullptr;
+  p->d_node_first = p->d_node_count = p->d_elem_t = p->d_elem_node = p->d_inv_off = nullptr;
+  p->d_inv = nullptr;
 }
 
 template <typename T>
@@ -64,29 +67,55 @@ hidft_status upload(hidft_sas p, hipStream_t st) {
       den[off + h] = c.tw_log2den[off + q_lo];
     }
   }
-  std::vector<uint16_t> src(ks);
+  const uint32_t n_nodes = (uint32_t)c.node_slot.size();
+  std::vector<uint16_t> src(ks), src_node(ks, 0), src_elem;
   for (uint64_t t = 0; t < ks; ++t) src[t] = (uint16_t)hidft::bit_reverse(t, c.s);
+  for (uint32_t v = 0; v < n_nodes; ++v)
+    src_node[v] = (uint16_t)hidft::bit_reverse(c.node_slot[v], c.s);
   std::vector<uint64_t> elem_val(c.k);
-  for (uint64_t i = 0; i < c.k; ++i) elem_val[i] = c.J[c.elem_t[i]];
+  std::vector<uint32_t> elem_node(c.k), inv_off(n_nodes);
+  uint64_t inv_entries = 0;
+  for (uint32_t v = 0; v < n_nodes; ++v) {
+    inv_off[v] = (uint32_t)inv_entries;
+    inv_entries += (uint64_t)c.node_count[v] * c.node_count[v];
+    for (uint32_t i = 0; i < c.node_count[v]; ++i) {
+      elem_node[c.node_first[v] + i] = v;
+      elem_val[c.node_first[v] + i] = c.J[c.elem_t[c.node_first[v] + i]];
+    }
+  }
+  if (c.mu_max == 1) {  // one element per node: the Hi-DFT output is the answer
+    src_elem.assign(ks, 0);
+    for (uint32_t v = 0; v < n_nodes; ++v) src_elem[c.elem_t[c.node_first[v]]] = src_node[v];
+  }
   uint64_t* d_num = nullptr;
   uint8_t* d_den = nullptr;
+  uint64_t* d_elem_val = nullptr;
   size_t total = 0, tmp = 0;
+  const size_t inv_bytes = (size_t)std::max<uint64_t>(inv_entries, 1) * 16;
   hidft_status status = HIDFT_OK;
   if ((e = hipMalloc(&p->d_tw, (ntw ? ntw : 1) * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&p->d_inv, inv_bytes)) != hipSuccess ||
       (e = upload_vec(&d_num, num, st, &tmp)) != hipSuccess ||
       (e = upload_vec(&d_den, den, st, &tmp)) != hipSuccess ||
+      (e = upload_vec(&d_elem_val, elem_val, st, &tmp)) != hipSuccess ||
       (e = upload_vec(&p->d_src, src, st, &total)) != hipSuccess ||
-      (e = upload_vec(&p->d_node_slot, c.node_slot, st, &total)) != hipSuccess ||
+      (e = upload_vec(&p->d_src_node, src_node, st, &total)) != hipSuccess ||
+      (!src_elem.empty() && (e = upload_vec(&p->d_src_elem, src_elem, st, &total)) != hipSuccess) ||
       (e = upload_vec(&p->d_node_first, c.node_first, st, &total)) != hipSuccess ||
       (e = upload_vec(&p->d_node_count, c.node_count, st, &total)) != hipSuccess ||
       (e = upload_vec(&p->d_elem_t, c.elem_t, st, &total)) != hipSuccess ||
-      (e = upload_vec(&p->d_elem_val, elem_val, st, &total)) != hipSuccess ||
+      (e = upload_vec(&p->d_elem_node, elem_node, st, &total)) != hipSuccess ||
+      (e = upload_vec(&p->d_inv_off, inv_off, st, &total)) != hipSuccess ||
       (e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, st)) != hipSuccess ||
+      (e = hidft::launch_sas_inverse(n_nodes, p->d_node_first, p->d_node_count, p->d_inv_off,
+                                     d_elem_val, c.M, p->d_inv, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess) {
     status = hidft::hip_error(e, "hidft_sas_create: table upload");
   }
+  total += inv_bytes;
   if (d_num) (void)hipFree(d_num);
   if (d_den) (void)hipFree(d_den);
+  if (d_elem_val) (void)hipFree(d_elem_val);
   if (status != HIDFT_OK) {
     release(p);
     return status;
@@ -215,7 +244,10 @@ hidft_status hidft_sas_get_nodes(hidft_sas p, uint32_t* node_of_t, uint32_t* slo
 hidft_status hidft_sas_workspace_bytes(hidft_sas p, uint64_t batch, size_t* bytes) {
   if (!p || !bytes)
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_workspace_bytes: NULL");
-  *bytes = (size_t)batch * p->core.mu_max * (1ULL << p->core.s) * sizeof(float2);
+  // [signal][shift][node]; none when every node holds one element (mu* = 1).
+  *bytes = p->core.mu_max == 1
+               ? 0
+               : (size_t)batch * p->core.mu_max * p->core.node_slot.size() * sizeof(float2);
   return hidft::set_error(HIDFT_OK, "");
 }
 
@@ -248,30 +280,41 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
   if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? hidft::set_error(HIDFT_OK, "") : st;
   if (!p->d_tw)
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_execute: HOST_ONLY plan");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float2* in = static_cast<const float2*>(d_samples);
+  float2* coefs = static_cast<float2*>(d_coefs);
+  hipError_t e = hipSuccess;
+  if (mu == 1) {
+    // One element per node: the Hi-DFT, gathered straight into the caller's
+    // order of J, is the answer (no workspace, no solve).
+    e = hidft::launch_fused(p->core.s, in, ld_in, coefs, ld_out, batch, p->d_tw, p->d_src_elem,
+                            nullptr, p->scale, hidft::ExecConfig{}, s, (uint32_t)p->core.k);
+    if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
+    return hidft::set_error(HIDFT_OK, "");
+  }
   if (!d_work || (reinterpret_cast<uintptr_t>(d_work) & 7u))
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
                             "hidft_sas_execute: workspace missing or misaligned");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const float2* in = static_cast<const float2*>(d_samples);
+  const uint64_t nn = p->core.node_slot.size();
   float2* work = static_cast<float2*>(d_work);
-  hipError_t e = hipSuccess;
-  // Steps 2-4: the mu* shifted Hi-DFTs, as one batched launch when the rows
-  // are packed, else one launch per shift.
+  // Steps 2-4: the mu* shifted Hi-DFTs, each gathered in node order (the
+  // first nn outputs), as one batched launch when the rows are packed, else
+  // one launch per shift.
   if ((uint64_t)ld_in == mu * ks) {
-    e = hidft::launch_fused(p->core.s, in, (int64_t)ks, work, (int64_t)ks, batch * mu, p->d_tw,
-                            p->d_src, nullptr, p->scale, hidft::ExecConfig{}, s);
+    e = hidft::launch_fused(p->core.s, in, (int64_t)ks, work, (int64_t)nn, batch * mu, p->d_tw,
+                            p->d_src_node, nullptr, p->scale, hidft::ExecConfig{}, s,
+                            (uint32_t)nn);
   } else {
     for (uint64_t j = 0; j < mu && e == hipSuccess; ++j)
-      e = hidft::launch_fused(p->core.s, in + j * ks, ld_in, work + j * ks, (int64_t)(mu * ks),
-                              batch, p->d_tw, p->d_src, nullptr, p->scale, hidft::ExecConfig{},
-                              s);
+      e = hidft::launch_fused(p->core.s, in + j * ks, ld_in, work + j * nn, (int64_t)(mu * nn),
+                              batch, p->d_tw, p->d_src_node, nullptr, p->scale,
+                              hidft::ExecConfig{}, s, (uint32_t)nn);
   }
-  // Steps 5-7: one dual Vandermonde solve per node.
+  // Steps 5-7: every node's solve, one row of its inverse per element.
   if (e == hipSuccess)
-    e = hidft::launch_sas_leaf(work, (uint32_t)ks, (uint32_t)mu, batch,
-                               (uint32_t)p->core.node_slot.size(), p->d_node_slot,
-                               p->d_node_first, p->d_node_count, p->d_elem_t, p->d_elem_val,
-                               p->core.M, static_cast<float2*>(d_coefs), ld_out, s);
+    e = hidft::launch_sas_apply(work, (uint32_t)nn, (uint32_t)mu, batch, (uint32_t)p->core.k,
+                                p->d_elem_node, p->d_node_first, p->d_node_count, p->d_inv_off,
+                                p->d_inv, p->d_elem_t, coefs, ld_out, s);
   if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
   return hidft::set_error(HIDFT_OK, "");
 }

@@ -127,7 +127,10 @@ def test_sas_strided_rows_and_errors():
     rng = rng_for(814, 0)
     M = 14
     K, J = _subset(rng, M, 8, 0.5)
-    plan = native.SASPlan(M, J)
+    P, _ = native.analyze(M, J)
+    plan = native.SASPlan(M, J, pivots=P[:5])     # a prefix: nodes of several elements
+    assert plan.mu_max > 1
+    assert plan.workspace_bytes(3) == 3 * plan.mu_max * plan.n_nodes * 8
     n = plan.samples_per_signal
     S = plan.samples().tolist()
     c = complex_normal((3, len(J)), rng)
@@ -144,4 +147,25 @@ def test_sas_strided_rows_and_errors():
         plan.execute_ptr(x.data_ptr(), n - 1, y.data_ptr(), plan.k, 1, work.data_ptr())
     with pytest.raises(native.HiDFTError):
         plan.execute_ptr(x.data_ptr(), n + 5, y.data_ptr(), plan.k, 1, 0)
+    plan.close()
+
+
+def test_sas_single_element_nodes_need_no_workspace():
+    """mu* = 1 (r = every pivot): the Hi-DFT gathered in the caller's order is
+    the answer; no workspace is needed and none is read."""
+    rng = rng_for(815, 0)
+    M = 16
+    K, J = _subset(rng, M, 9, 0.4)
+    P, _ = native.analyze(M, J)
+    plan = native.SASPlan(M, J, pivots=P)
+    assert plan.mu_max == 1 and plan.workspace_bytes(5) == 0
+    S = plan.samples().tolist()
+    c = complex_normal((5, len(J)), rng)
+    f = oracle.synthesize_samples(M, J, c, S)
+    x = torch.from_numpy(f.astype(np.complex64)).cuda()
+    y = torch.full((5, plan.k), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda")
+    plan.execute_ptr(x.data_ptr(), plan.samples_per_signal, y.data_ptr(), plan.k, 5, 0)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.complex128)
+    assert np.max(oracle.rel_l2(got, c)) <= 1e-5
     plan.close()
