@@ -77,6 +77,31 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Occupancy of a kernel: blocks resident per CU and the CU count, queried
+// once per kernel (the first call also raises its dynamic LDS limit).
+struct Occupancy {
+  int per_cu = 0;
+  int cus = 0;
+};
+
+static hipError_t query_occupancy(const void* kernel, int threads, size_t lds_bytes,
+                                  Occupancy* occ) {
+  hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds_bytes)) !=
+      hipSuccess)
+    return e;
+  occ->per_cu = per_cu > 0 ? per_cu : 1;
+  occ->cus = cus > 0 ? cus : 1;
+  return hipSuccess;
+}
+
 // Samples and coefficients are read or written exactly once: their loads and
 // stores carry the non-temporal cache policy (measured: about 7% less time
 // than cached stores at 2^12 points), while the plan tables, which every
@@ -708,72 +733,94 @@ __device__ __forceinline__ void butterfly_adj(float2& X, float2& Y, const float2
   Y.y = fmaf(w.x, di, -w.y * dr);
 }
 
-template <int S>
-__global__ void __launch_bounds__(FusedShape<S>::THREADS)
+// Adjoint of transform_signal for one signal: v holds this thread's
+// coefficients t = c*T + tau (the caller's order of J).  They are scattered to
+// their positions src[t] (the inverse of the forward gather), the groups run
+// from the last to the first, each stage reversed within its group, and group
+// 1 leaves the samples in registers (positions a = tau + c*T, ascending I_r).
+template <int S, int SCHED, bool HOISTED, class Mem>
+__device__ __forceinline__ void inverse_signal(SigVec<S, 4>& v, float2* L, int tau,
+                                               const Mem& mem,
+                                               const ThreadState<S, SCHED, 4>& ts) {
+  using Sh = FusedShape<S, SCHED, 4>;
+  constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, G = Sh::G, G1 = Sh::G1;
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const int p = HOISTED ? (int)((ts.srcpk[c >> 1] >> (16 * (c & 1))) & 0xffffu)
+                          : mem.src_at(c * T, tau);
+    L[lds_pad<RHO>(p)] = v[c];
+  }
+#pragma unroll
+  for (int g = G; g >= 2; --g) {
+    const int lo = Sh::lo(g), t0 = Sh::t0(g);
+    const int a_lo = tau & ((1 << lo) - 1);
+    const int a_hi = tau >> lo;
+    const int base = a_lo + (a_hi << (lo + RHO));
+    float2 wq[R > 1 ? R - 1 : 1];
+    if constexpr (!(HOISTED && Sh::TW_REGS)) {
+#pragma unroll
+      for (int t = 0; t < RHO; ++t) {
+        if (t < t0) continue;
+        const int u = S - lo - RHO + 1 + t;
+#pragma unroll
+        for (int h = 0; h < (1 << t); ++h)
+          wq[(1 << t) - 1 + h] = mem.tw_at(((1 << (u - 1)) - 1) + h, a_hi << t);
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(base + (c << lo))];
+#pragma unroll
+    for (int t = RHO - 1; t >= 0; --t) {
+      if (t < t0) continue;
+      const int bit = RHO - 1 - t;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (c & (1 << bit)) continue;
+        const int h = c >> (RHO - t);
+        float2 w;
+        if constexpr (HOISTED && Sh::TW_REGS)
+          w = ts.wg[(g - 2) * (R - 1) + (1 << t) - 1 + h];
+        else
+          w = wq[(1 << t) - 1 + h];
+        butterfly_adj(v[c], v[c | (1 << bit)], w);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) L[lds_pad<RHO>(base + (c << lo))] = v[c];
+  }
+  lds_barrier();
+#pragma unroll
+  for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(c * T + tau)];
+#pragma unroll
+  for (int u = G1; u >= 1; --u) {
+    const int bit = RHO - u;
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      if (c & (1 << bit)) continue;
+      const int idx = (1 << (u - 1)) - 1 + (c >> (bit + 1));
+      butterfly_adj(v[c], v[c | (1 << bit)], HOISTED ? ts.w1[idx] : mem.tw_at(idx, 0));
+    }
+  }
+}
+
+// Inverse transform with the forward kernel's shapes: persistent with the
+// next signal prefetched and the tables in registers up to 2^13 points, one
+// signal per block at 2^14.
+template <int S, int SCHED>
+__global__ void __launch_bounds__((FusedShape<S, SCHED, 4>::THREADS))
 hidft_inverse_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ out,
                      int64_t ld_out, uint64_t batch, const float2* __restrict__ tw,
                      const uint16_t* __restrict__ src, float scale) {
-  using Sh = FusedShape<S>;
-  constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, SPB = Sh::SPB, G = Sh::G, G1 = Sh::G1;
+  using Sh = FusedShape<S, SCHED, 4>;
+  constexpr int R = Sh::R, T = Sh::T, SPB = Sh::SPB;
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int slot = tid / T;
   const int tau = tid - slot * T;
   float2* L = lds + slot * Sh::PADK;
-  const uint64_t n_groups = (batch + SPB - 1) / SPB;
-
-  // One group of signals; BIG sizes run one per block (see FusedShape), the
-  // others walk the batch with a grid stride.
-  auto body = [&](uint64_t grp) {
-    const uint64_t sig = grp * SPB + slot;
-    const bool valid = sig < batch;
-    float2 v[R];
-    {
-      const float2* row = in + (valid ? sig : 0) * (uint64_t)ld_in;
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        const int t = c * T + tau;
-        L[lds_pad<RHO>((int)src[t])] = valid ? load_stream(row + t) : make_float2(0.f, 0.f);
-      }
-    }
-    // Groups G..2 (lowest bits first), each stage reversed within the group.
-#pragma unroll
-    for (int g = G; g >= 2; --g) {
-      const int lo = S - G1 - (g - 1) * RHO;
-      const int a_lo = tau & ((1 << lo) - 1);
-      const int a_hi = tau >> lo;
-      const int base = a_lo + (a_hi << (lo + RHO));
-      lds_barrier();
-#pragma unroll
-      for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(base + (c << lo))];
-#pragma unroll
-      for (int t = RHO - 1; t >= 0; --t) {
-        const int u = S - lo - RHO + 1 + t;
-        const int bit = RHO - 1 - t;
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-          if (c & (1 << bit)) continue;
-          const float2 w = tw[((1 << (u - 1)) - 1) + (a_hi << t) + (c >> (RHO - t))];
-          butterfly_adj(v[c], v[c | (1 << bit)], w);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < R; ++c) L[lds_pad<RHO>(base + (c << lo))] = v[c];
-    }
-    lds_barrier();
-    // Group 1 (the top G1 bits of a), then the coalesced store.
-#pragma unroll
-    for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(c * T + tau)];
-#pragma unroll
-    for (int u = G1; u >= 1; --u) {
-      const int bit = RHO - u;
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        if (c & (1 << bit)) continue;
-        butterfly_adj(v[c], v[c | (1 << bit)], tw[(1 << (u - 1)) - 1 + (c >> (bit + 1))]);
-      }
-    }
-    if (valid) {
+  auto store = [&](const float2 (&v)[R], uint64_t sig) {
+    if (sig < batch) {
       float2* orow = out + sig * (uint64_t)ld_out;
 #pragma unroll
       for (int c = 0; c < R; ++c)
@@ -781,10 +828,29 @@ hidft_inverse_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __res
     }
   };
   if constexpr (Sh::BIG) {
-    body(blockIdx.x);
+    const uint64_t sig = blockIdx.x;
+    float2 v[R];
+    load_group1<S, SCHED, 4, PREC_FP32>(v, in, ld_in, sig, batch);
+    ThreadState<S, SCHED, 4> unused;
+    const FlatMem mem{tw, src, nullptr, 0};
+    inverse_signal<S, SCHED, false>(v, L, tau, mem, unused);
+    store(v, sig);
   } else {
-    for (uint64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
-      body(grp);
+    const uint64_t n_groups = (batch + SPB - 1) / SPB;
+    ThreadState<S, SCHED, 4> ts;
+    load_thread_state<S, SCHED, 4, PREC_FP32>(ts, tw, src, tau);
+    const FlatMem mem{tw, src, nullptr, 0};
+    float2 vn[R];
+    uint64_t grp = blockIdx.x;
+    if (grp < n_groups) load_group1<S, SCHED, 4, PREC_FP32>(vn, in, ld_in, grp * SPB, batch);
+    for (; grp < n_groups; grp += gridDim.x) {
+      float2 v[R];
+#pragma unroll
+      for (int c = 0; c < R; ++c) v[c] = vn[c];
+      if (grp + gridDim.x < n_groups)
+        load_group1<S, SCHED, 4, PREC_FP32>(vn, in, ld_in, (grp + gridDim.x) * SPB, batch);
+      inverse_signal<S, SCHED, true>(v, L, tau, mem, ts);
+      store(v, grp * SPB + slot);
       lds_barrier();  // the next group of signals overwrites these LDS slots
     }
   }
@@ -794,29 +860,22 @@ template <int S>
 static hipError_t launch_inverse_s(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
                                    uint64_t batch, const float2* tw, const uint16_t* src,
                                    float scale, hipStream_t stream) {
-  using Sh = FusedShape<S>;
-  static int max_grid = 0;  // benign race: every thread computes the same value
-  if (max_grid == 0) {
-    hipError_t e = hipFuncSetAttribute((const void*)hidft_inverse_kernel<S>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)Sh::LDS_BYTES);
+  // The adjoint of hidft_execute's default grouping (short group last).
+  constexpr int SC = S > 4 && S % 4 != 0 ? SCHED_SHORT_LAST : SCHED_SHORT_FIRST;
+  using Sh = FusedShape<S, SC, 4>;
+  static Occupancy occ;  // benign race: every thread computes the same value
+  if (occ.cus == 0) {
+    Occupancy o;
+    hipError_t e = query_occupancy((const void*)hidft_inverse_kernel<S, SC>, Sh::THREADS,
+                                   Sh::LDS_BYTES, &o);
     if (e != hipSuccess) return e;
-    int dev = 0, cus = 0, per_cu = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
-        hipSuccess)
-      return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-             &per_cu, (const void*)hidft_inverse_kernel<S>, Sh::THREADS, Sh::LDS_BYTES)) !=
-        hipSuccess)
-      return e;
-    max_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    occ = o;
   }
   if constexpr (Sh::BIG) {
     const uint64_t chunk = 0x7fffffffULL;  // one block per signal
     for (uint64_t first = 0; first < batch; first += chunk) {
       const uint64_t n = batch - first < chunk ? batch - first : chunk;
-      hipLaunchKernelGGL(hidft_inverse_kernel<S>, dim3((unsigned)n), dim3(Sh::THREADS),
+      hipLaunchKernelGGL((hidft_inverse_kernel<S, SC>), dim3((unsigned)n), dim3(Sh::THREADS),
                          Sh::LDS_BYTES, stream, in + first * (uint64_t)ld_in, ld_in,
                          out + first * (uint64_t)ld_out, ld_out, n, tw, src, scale);
       hipError_t e = hipGetLastError();
@@ -824,9 +883,10 @@ static hipError_t launch_inverse_s(const float2* in, int64_t ld_in, float2* out,
     }
     return hipSuccess;
   }
+  const uint64_t max_grid = (uint64_t)occ.per_cu * (uint64_t)occ.cus;
   const uint64_t groups = (batch + Sh::SPB - 1) / Sh::SPB;
-  const unsigned grid = (unsigned)(groups < (uint64_t)max_grid ? groups : (uint64_t)max_grid);
-  hipLaunchKernelGGL(hidft_inverse_kernel<S>, dim3(grid), dim3(Sh::THREADS), Sh::LDS_BYTES,
+  const unsigned grid = (unsigned)(groups < max_grid ? groups : max_grid);
+  hipLaunchKernelGGL((hidft_inverse_kernel<S, SC>), dim3(grid), dim3(Sh::THREADS), Sh::LDS_BYTES,
                      stream, in, ld_in, out, ld_out, batch, tw, src, scale);
   return hipGetLastError();
 }
@@ -853,31 +913,6 @@ hipError_t launch_inverse(uint32_t s, const float2* in, int64_t ld_in, float2* o
     default:
       return hipErrorInvalidValue;
   }
-}
-
-// Occupancy of a kernel: blocks resident per CU and the CU count, queried
-// once per kernel (the first call also raises its dynamic LDS limit).
-struct Occupancy {
-  int per_cu = 0;
-  int cus = 0;
-};
-
-static hipError_t query_occupancy(const void* kernel, int threads, size_t lds_bytes,
-                                  Occupancy* occ) {
-  hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds_bytes);
-  if (e != hipSuccess) return e;
-  int dev = 0, cus = 0, per_cu = 0;
-  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
-      hipSuccess)
-    return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds_bytes)) !=
-      hipSuccess)
-    return e;
-  occ->per_cu = per_cu > 0 ? per_cu : 1;
-  occ->cus = cus > 0 ? cus : 1;
-  return hipSuccess;
 }
 
 template <int S, int SCHED, int RH, int PREC>
