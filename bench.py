@@ -208,7 +208,7 @@ def main():
         "wall_s_timed": wall_s,
         "roofline": {
             "bound": "hbm",
-            "kernel": "hidft_fused_kernel<12, 0, 4, 0>",
+            "kernel": "hidft_fused_kernel<12, 0, 4, 0, false>",
             "achieved": achieved_gbps,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",

@@ -413,17 +413,26 @@ __device__ __forceinline__ float2 make_uniform(float2 w) {
 //            lane part as the one vector offset and the uniform part as a
 //            scalar offset; it needs the signal to span whole wavefronts
 //            (T >= 64) so that its descriptors are uniform.
-struct FlatMem {
+// PARTIAL: only the first n_out outputs of the gather order are stored (the
+// Shift-and-Sample workspace and direct paths); otherwise all of them, with
+// no per-store predicate.
+template <bool PARTIAL>
+struct FlatMemT {
   const float2* tw;
   const uint16_t* src;
   float2* out;
-  uint32_t n_out;  // outputs stored per signal (a prefix of the gather order)
+  uint32_t n_out;
   __device__ __forceinline__ float2 tw_at(int uni, int lane) const { return tw[uni + lane]; }
   __device__ __forceinline__ int src_at(int uni, int lane) const { return src[uni + lane]; }
   __device__ __forceinline__ void put(int uni, int lane, float2 x) const {
-    if ((uint32_t)(uni + lane) < n_out) store_stream(out + uni + lane, x);
+    if constexpr (PARTIAL) {
+      if ((uint32_t)(uni + lane) < n_out) store_stream(out + uni + lane, x);
+    } else {
+      store_stream(out + uni + lane, x);
+    }
   }
 };
+using FlatMem = FlatMemT<false>;
 
 constexpr int BUFFER_DWORD3 = 0x00020000;  // raw buffer, 32-bit data format
 
@@ -656,7 +665,7 @@ __device__ __forceinline__ void load_thread_state(ThreadState<S, SCHED, RH>& ts,
   }
 }
 
-template <int S, int SCHED, int RH, int PREC>
+template <int S, int SCHED, int RH, int PREC, bool PARTIAL = false>
 __global__ void __launch_bounds__((FusedShape<S, SCHED, RH>::THREADS))
 hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ out,
                    int64_t ld_out, uint64_t batch, const float2* __restrict__ tw,
@@ -679,7 +688,7 @@ hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
     const uint64_t grp = blockIdx.x;
     float2 v[R];
     load_group1<S, SCHED, RH, PREC>(v, in, ld_in, grp, batch);
-    const FlatMem mem{tw, src, out + grp * (uint64_t)ld_out, n_out};
+    const FlatMemT<PARTIAL> mem{tw, src, out + grp * (uint64_t)ld_out, n_out};
     ThreadState<S, SCHED, RH> unused;
     transform_signal<S, SCHED, RH, PREC, false>(v, lds, 0, tau, true, mem, scale, unused, op);
   } else {
@@ -695,7 +704,8 @@ hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
       if (grp + gridDim.x < n_groups)
         load_group1<S, SCHED, RH, PREC>(vn, in, ld_in, (grp + gridDim.x) * SPB, batch);
       const uint64_t sig = grp * SPB + slot;
-      const FlatMem mem{tw, src, out + (sig < batch ? sig : 0) * (uint64_t)ld_out, n_out};
+      const FlatMemT<PARTIAL> mem{tw, src, out + (sig < batch ? sig : 0) * (uint64_t)ld_out,
+                                  n_out};
       transform_signal<S, SCHED, RH, PREC, true>(v, lds, slot, tau, sig < batch, mem, scale,
                                                   ts, op);
       lds_barrier();  // the next group overwrites these LDS slots
@@ -915,13 +925,13 @@ hipError_t launch_inverse(uint32_t s, const float2* in, int64_t ld_in, float2* o
   }
 }
 
-template <int S, int SCHED, int RH, int PREC>
+template <int S, int SCHED, int RH, int PREC, bool PARTIAL = false>
 static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
                                  uint64_t batch, const float2* tw, const uint16_t* src,
                                  const uint4* amat, float scale, uint32_t n_out,
                                  int blocks_per_cu, hipStream_t stream) {
   using Sh = FusedShape<S, SCHED, RH>;
-  const void* kernel = (const void*)hidft_fused_kernel<S, SCHED, RH, PREC>;
+  const void* kernel = (const void*)hidft_fused_kernel<S, SCHED, RH, PREC, PARTIAL>;
   static Occupancy occ;  // benign race: every thread computes the same value
   if (occ.cus == 0) {
     Occupancy o;
@@ -934,7 +944,7 @@ static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, i
     const uint64_t chunk = 0x7fffffffULL;
     for (uint64_t first = 0; first < batch; first += chunk) {
       const uint64_t n = batch - first < chunk ? batch - first : chunk;
-      hipLaunchKernelGGL((hidft_fused_kernel<S, SCHED, RH, PREC>), dim3((unsigned)n),
+      hipLaunchKernelGGL((hidft_fused_kernel<S, SCHED, RH, PREC, PARTIAL>), dim3((unsigned)n),
                          dim3(Sh::THREADS), Sh::LDS_BYTES, stream, in + first * (uint64_t)ld_in,
                          ld_in, out + first * (uint64_t)ld_out, ld_out, n, tw, src, amat, scale,
                          n_out);
@@ -948,7 +958,8 @@ static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, i
   const uint64_t max_grid = (uint64_t)per_cu * (uint64_t)occ.cus;
   const uint64_t groups = (batch + Sh::SPB - 1) / Sh::SPB;
   const unsigned grid = (unsigned)(groups < max_grid ? groups : max_grid);
-  hipLaunchKernelGGL((hidft_fused_kernel<S, SCHED, RH, PREC>), dim3(grid), dim3(Sh::THREADS),
+  hipLaunchKernelGGL((hidft_fused_kernel<S, SCHED, RH, PREC, PARTIAL>), dim3(grid),
+                     dim3(Sh::THREADS),
                      Sh::LDS_BYTES, stream, in, ld_in, out, ld_out, batch, tw, src, amat, scale,
                      n_out);
   return hipGetLastError();
@@ -973,6 +984,15 @@ static hipError_t dispatch_fused(const float2* in, int64_t ld_in, float2* out, i
                                  const ExecConfig& cfg, hipStream_t stream) {
   const int bpc = cfg.blocks_per_cu;
   const bool last = cfg.sched == SCHED_SHORT_LAST;
+  // When 4 divides S (or S < 4) the two schedules are the same kernel.
+  constexpr bool TWO_SCHEDS = S > 4 && S % 4 != 0;
+  if (n_out < (1u << S)) {
+    // Partial output exists for the default variant (FP32, short group last).
+    if (cfg.prec != PREC_FP32 || cfg.rho != 4 || !last) return hipErrorInvalidValue;
+    constexpr int SC = TWO_SCHEDS ? SCHED_SHORT_LAST : SCHED_SHORT_FIRST;
+    return launch_fused_s<S, SC, 4, PREC_FP32, true>(in, ld_in, out, ld_out, batch, tw, src,
+                                                     amat, scale, n_out, bpc, stream);
+  }
   if constexpr (S >= 13) {
     if (cfg.rho == 5) {
       // Radix 32: 13 = 3 + 5 + 5 or 5 + 5 + 3, 14 = 4 + 5 + 5 or 5 + 5 + 4.
@@ -984,8 +1004,6 @@ static hipError_t dispatch_fused(const float2* in, int64_t ld_in, float2* out, i
                                                                 tw, src, amat, scale, n_out, bpc, stream);
     }
   }
-  // When 4 divides S (or S < 4) the two schedules are the same kernel.
-  constexpr bool TWO_SCHEDS = S > 4 && S % 4 != 0;
   if (cfg.prec == PREC_FP32) {
     if constexpr (TWO_SCHEDS) {
       if (last)
