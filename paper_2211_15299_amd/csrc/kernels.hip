@@ -121,6 +121,25 @@ __device__ __forceinline__ void store_stream(float2* p, float2 x) {
 template <int RHO>
 __device__ __forceinline__ int lds_pad(int a) { return a + (a >> RHO); }
 
+// The padded slot of base + (c << lo) for a group window [lo, lo + RHO):
+// with base = a_lo + (a_hi << (lo + RHO)), a_lo < 2^lo, and c < 2^RHO the low
+// lo + RHO bits never carry, so
+//   lds_pad(base + (c << lo)) = lds_pad(base) + (c << lo) + (c >> (RHO - lo))
+// for lo < RHO, and + (c << (lo - RHO)) for lo >= RHO.  The per-c part is a
+// compile-time constant (an LDS instruction offset), the rest one add per
+// thread and group.
+template <int RHO>
+__device__ __forceinline__ constexpr int lds_window_off(int c, int lo) {
+  return (c << lo) + (lo >= RHO ? (c << (lo - RHO)) : (c >> (RHO - lo)));
+}
+
+// The padded slot of c * T + tau for T a multiple of 2^RHO: lds_pad(tau) plus
+// a per-c constant.
+template <int RHO>
+__device__ __forceinline__ constexpr int lds_column_off(int c, int T) {
+  return c * T + ((c * T) >> RHO);
+}
+
 template <int S, int SCHED = SCHED_SHORT_FIRST, int RH = 4>
 struct FusedShape {
   static constexpr int RHO = S < RH ? S : RH;                    // log2 points per thread
@@ -546,8 +565,14 @@ __device__ __forceinline__ void transform_signal(SigVec<S, RH>& v, float2* Lb, i
         butterfly(v[c], v[c | (1 << bit)], HOISTED ? ts.w1[idx] : mem.tw_at(idx, 0));
       }
     }
+    if constexpr (T % R == 0) {
+      const int pt = lds_pad<RHO>(tau);
 #pragma unroll
-    for (int c = 0; c < R; ++c) L[lds_pad<RHO>(c * T + tau)] = v[c];
+      for (int c = 0; c < R; ++c) L[pt + lds_column_off<RHO>(c, T)] = v[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < R; ++c) L[lds_pad<RHO>(c * T + tau)] = v[c];
+    }
   } else {
     static_assert(S >= 4 && RHO == 4 && G1 == 4,
                   "the matrix-core group 1 is a full radix-16 group");
@@ -585,8 +610,9 @@ __device__ __forceinline__ void transform_signal(SigVec<S, RH>& v, float2* Lb, i
       }
     }
     lds_barrier();
+    const int pb = lds_pad<RHO>(base);
 #pragma unroll
-    for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(base + (c << lo))];
+    for (int c = 0; c < R; ++c) v[c] = L[pb + lds_window_off<RHO>(c, lo)];
 #pragma unroll
     for (int t = 0; t < RHO; ++t) {
       if (t < t0) continue;
@@ -606,7 +632,7 @@ __device__ __forceinline__ void transform_signal(SigVec<S, RH>& v, float2* Lb, i
       }
     }
 #pragma unroll
-    for (int c = 0; c < R; ++c) L[lds_pad<RHO>(base + (c << lo))] = v[c];
+    for (int c = 0; c < R; ++c) L[pb + lds_window_off<RHO>(c, lo)] = v[c];
   }
   // Gather positions of the output, requested before the last barrier.
   int pq[R];
@@ -778,8 +804,9 @@ __device__ __forceinline__ void inverse_signal(SigVec<S, 4>& v, float2* L, int t
       }
     }
     lds_barrier();
+    const int pb = lds_pad<RHO>(base);
 #pragma unroll
-    for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(base + (c << lo))];
+    for (int c = 0; c < R; ++c) v[c] = L[pb + lds_window_off<RHO>(c, lo)];
 #pragma unroll
     for (int t = RHO - 1; t >= 0; --t) {
       if (t < t0) continue;
@@ -797,11 +824,17 @@ __device__ __forceinline__ void inverse_signal(SigVec<S, 4>& v, float2* L, int t
       }
     }
 #pragma unroll
-    for (int c = 0; c < R; ++c) L[lds_pad<RHO>(base + (c << lo))] = v[c];
+    for (int c = 0; c < R; ++c) L[pb + lds_window_off<RHO>(c, lo)] = v[c];
   }
   lds_barrier();
+  if constexpr (T % R == 0) {
+    const int pt = lds_pad<RHO>(tau);
 #pragma unroll
-  for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(c * T + tau)];
+    for (int c = 0; c < R; ++c) v[c] = L[pt + lds_column_off<RHO>(c, T)];
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = L[lds_pad<RHO>(c * T + tau)];
+  }
 #pragma unroll
   for (int u = G1; u >= 1; --u) {
     const int bit = RHO - u;
