@@ -58,6 +58,26 @@ def test_planner_matches_oracle_bit_exactly():
         assert piv == r and hom
 
 
+def test_planner_bit_exact_over_ten_thousand_generator_sets():
+    """10^4 seeded homogeneous supports (N <= 2^16, k <= 64): pivots, sample
+    set I_r, frequency positions and twiddle exponents equal the oracle's."""
+    for seed in range(10_000):
+        rng = rng_for(1010, seed)
+        M = int(rng.integers(0, 17))
+        s = int(rng.integers(0, min(M, 6) + 1))
+        sup = homogeneous_support(M, s, rng)
+        J = sup.J.tolist()
+        plan = native.Plan(M, J, host_only=True)
+        r = oracle.pivots(M, J)
+        assert plan.pivots() == r == list(sup.levels), (seed, M, J)
+        assert plan.samples().tolist() == oracle.sample_set(M, J), (seed, M, J)
+        fp, num, den = plan.schedule()
+        assert fp.tolist() == oracle.frequency_positions(M, J), (seed, M, J)
+        tw = oracle.twiddle_exponents(M, J)
+        assert num.tolist() == [m for (_, _, m, _) in tw], (seed, M, J)
+        assert den.tolist() == [ru for (_, _, _, ru) in tw], (seed, M, J)
+
+
 def test_planner_at_large_k_and_N():
     for M, s in [(63, 10), (40, 14), (24, 16), (20, 12)]:
         sup = homogeneous_support(M, s, rng_for(1002, M))
@@ -109,6 +129,31 @@ def test_pivots_invariant_under_odd_dilation_and_translation():
         t = int(rng.integers(0, 1 << M))
         J2 = [((int(j) * d + t) % (1 << M)) for j in J]
         assert native.analyze(M, J.tolist())[0] == native.analyze(M, J2)[0]
+
+
+hypothesis = pytest.importorskip("hypothesis")
+st = hypothesis.strategies
+
+
+@hypothesis.settings(max_examples=300, deadline=None, derandomize=True)
+@hypothesis.given(data=st.data(), M=st.integers(1, 40))
+def test_affine_invariance_property(data, M):
+    """Pivots, the homogeneity verdict and the sample set are unchanged by an
+    odd dilation and a translation of J, for arbitrary sets drawn by
+    hypothesis: two leaves first meet at the level given by the 2-adic
+    valuation of their difference (Sec. VI), which both maps preserve."""
+    N = 1 << M
+    J = data.draw(st.lists(st.integers(0, N - 1), min_size=1, max_size=48, unique=True))
+    d = data.draw(st.integers(0, (N >> 1) - 1 if M > 1 else 0)) * 2 + 1
+    t = data.draw(st.integers(0, N - 1))
+    J2 = [(j * d + t) % N for j in J]
+    piv, hom = native.analyze(M, J)
+    piv2, hom2 = native.analyze(M, J2)
+    assert piv == piv2 == oracle.pivots(M, J2)
+    assert hom == hom2 == oracle.is_homogeneous(M, J)
+    if hom and len(J) > 1:
+        assert (native.Plan(M, J, host_only=True).samples().tolist()
+                == native.Plan(M, J2, host_only=True).samples().tolist())
 
 
 def test_special_families_and_composites():
