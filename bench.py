@@ -333,9 +333,15 @@ def grouped_bench(args, native, torch, stream):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     byts = total * 16
+    # Per-instance plans: the minimum plan input is J as uint32 (4 B per
+    # point); the tables the kernel actually reads are the twiddles and the
+    # gather positions (8 (k - 1) + 2 k B per instance).
+    table_bytes = int(sum(8 * (kk - 1) + 2 * kk for kk in ks.tolist()))
     return {"mode": "grouped", "instances": len(plans), "points": total, "packs": groups[0].n_packs,
             "k_min": int(ks.min()), "k_max": int(ks.max()), "ms_per_launch": ms,
             "transforms_per_s": len(plans) / (ms * 1e-3), "GBps": byts / (ms * 1e-3) / 1e9,
+            "GBps_data_plus_plan": (byts + 4 * total) / (ms * 1e-3) / 1e9,
+            "table_bytes_per_launch": table_bytes,
             "frac_of_8TBps": byts / (ms * 1e-3) / 8e12, "sets": sets}
 
 
@@ -420,6 +426,7 @@ def serve_bench(args, native, seconds=None):
             "rejected": int(st["rejected"] - st0["rejected"]),
             "transforms_per_s": n / wall, "wall_s": wall,
             "data_GBps": float(ks.sum()) * 16 / wall / 1e9,
+            "data_plus_plan_GBps": float(ks.sum()) * 20 / wall / 1e9,
             "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "max": float(lat.max())},
             "batch_size_mean": float(np.mean(bsz)), "batches": int(st["batches"] - st0["batches"]),
@@ -661,14 +668,40 @@ def cpu_baseline(M, J, f_host, y_dev, n_sample):
     dt = time.perf_counter() - t0
     got = y_dev[:n_sample].cpu().numpy().astype(np.complex128)
     err = oracle.rel_l2(got, c)
+    # The oracle's other route on the same sample: c = (N/k) F(J, I_r) f_I.
+    t0 = time.perf_counter()
+    ca = oracle.coefficients(M, J, f, method="adjoint")
+    dta = time.perf_counter() - t0
     return {
         "value": n_sample / dt, "unit": "transforms/s", "cores": int(threads), "kind": "oracle",
         "sample": f"first {n_sample} of the 4096 signals; oracle.coefficients (LU route, "
                   f"factorisation included), {dt:.1f} s",
         "seconds": dt,
+        "adjoint_route": {"value": n_sample / dta, "unit": "transforms/s", "seconds": dta,
+                          "rel_l2_vs_lu_max": float(np.max(oracle.rel_l2(ca, c)))},
+        "config1_single_thread": oracle_config1_single_thread(oracle),
         "gpu_rel_l2_vs_oracle": {"max": float(np.max(err)), "mean": float(np.mean(err))},
         "gpu_max_abs_vs_oracle": float(np.max(np.abs(got - c))),
     }
+
+
+def oracle_config1_single_thread(oracle, seconds=1.0):
+    """The oracle on the single-signal configuration (N = 2^10, k = 64, an
+    odd dilation and translation of {0..63}), one signal per call, one BLAS
+    thread: transforms/s."""
+    from workloads import elementary_support, rng_for, sample_values
+    rng = rng_for(1, 0)
+    J = elementary_support(10, 6, rng).J.tolist()
+    f = sample_values(10, len(J), 64, rng).astype(np.complex128)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            oracle.coefficients(10, J, f[n % 64:n % 64 + 1])
+            n += 1
+        dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "transforms/s", "threads": 1, "calls": n,
+            "route": "LU (factorisation per call)"}
 
 
 if __name__ == "__main__":
