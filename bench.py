@@ -24,6 +24,11 @@ Prints one JSON line.  Modes for profiling runs:
   --mode precision the precision configuration (N = 2^22, k = 2^14, 1024
                    signals, |c| log-uniform on [1e-3, 1e3]): FP32 butterflies
                    against the FP16 / BF16 split-precision matrix-core group
+  --mode inverse   the inverse map (coefficients -> samples) on the headline
+                   workload's shape
+  --mode sas       Shift-and-Sample on a random half of a homogeneous set
+  --mode gap       GAP and arithmetic-progression supports through
+                   Shift-and-Sample
 The full run also reports the autotuned variant of the headline workload
 (hidft_autotune, then hidft_execute_config with the tuned variant).
 """
@@ -55,7 +60,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=400)
-    ap.add_argument("--mode", choices=["full", "execute", "copy", "grouped", "serve", "precision"],
+    ap.add_argument("--mode", choices=["full", "execute", "copy", "grouped", "serve", "precision",
+                                       "inverse", "sas", "gap"],
                     default="full")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="duration of the Poisson arrival process (serving)")
@@ -143,6 +149,16 @@ def main():
     if args.mode == "precision":
         del xs, ys, x, y
         print(json.dumps(precision_bench(args, native, torch, stream)), flush=True)
+        return
+    if args.mode in ("inverse", "sas", "gap"):
+        del xs, ys, x, y
+        if args.mode == "inverse":
+            r = inverse_bench(args, native, torch, stream, steps=args.steps)
+        elif args.mode == "sas":
+            r = sas_bench(native, torch, stream, steps=args.steps)
+        else:
+            r = gap_bench(native, torch, stream, steps=args.steps)
+        print(json.dumps(r), flush=True)
         return
 
     torch.cuda.synchronize()
@@ -569,50 +585,82 @@ def inverse_bench(args, native, torch, stream, steps=50):
             "round_trip_rel_l2_max": rt, "steps": steps, "sets": sets}
 
 
-def sas_bench(native, torch, stream, batch=4096, steps=20):
+ROTATE_SETS = 4               # input/output buffer sets cycled through by a leg
+ROTATE_INPUT_BYTES = 128 << 20  # input bytes per set: 4 sets exceed the 256 MB cache
+
+
+def _rotating_sas_run(native, torch, stream, plan, batch, rng, steps):
+    """Times plan.execute over ROTATE_SETS (input, output) pairs; the
+    workspace is shared.  Returns ms per launch and the buffers of set 0."""
+    from workloads import sample_values
+    n_in = plan.samples_per_signal
+    x0 = torch.from_numpy(sample_values(20, n_in, batch, rng).astype(np.complex64)).cuda()
+    xs = [x0] + [x0.clone() for _ in range(ROTATE_SETS - 1)]
+    ys = [torch.empty((batch, plan.k), dtype=torch.complex64, device="cuda")
+          for _ in range(ROTATE_SETS)]
+    work = torch.empty(max(plan.workspace_bytes(batch) // 8, 1), dtype=torch.complex64,
+                       device="cuda")
+
+    def run(i):
+        j = i % ROTATE_SETS
+        plan.execute_ptr(xs[j].data_ptr(), n_in, ys[j].data_ptr(), plan.k, batch,
+                         work.data_ptr(), stream)
+
+    for i in range(2 * ROTATE_SETS):
+        run(i)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        run(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del xs, ys, work
+    torch.cuda.empty_cache()
+    return ms
+
+
+def _sas_rates(plan, batch, ms):
+    """Rates of a Shift-and-Sample launch: data (samples in, coefficients out)
+    and data plus the workspace (the mu* shifted Hi-DFT outputs, written by
+    the fused kernel and read by the leaf solves)."""
+    n_in = plan.samples_per_signal
+    data = batch * (n_in + plan.k) * 8
+    work = 2 * plan.workspace_bytes(batch)
+    return {"ms_per_launch": ms, "transforms_per_s": batch / (ms * 1e-3),
+            "GBps": data / (ms * 1e-3) / 1e9,
+            "GBps_with_workspace": (data + work) / (ms * 1e-3) / 1e9}
+
+
+def sas_bench(native, torch, stream, steps=20):
     """Shift-and-Sample on a random half of a homogeneous set (N = 2^20, 2^12
     candidate positions, 2048 elements kept), r chosen by Lemma 4's cost: mu*
-    shifted Hi-DFTs in one launch, then the FP64 leaf solves."""
-    from workloads import homogeneous_support, rng_for, sample_values
+    shifted Hi-DFTs in one launch, then the FP64 leaf solves.  4096 signals
+    per launch, 4 rotating buffer sets."""
+    from workloads import homogeneous_support, rng_for
     rng = rng_for(941, 0)
     K = homogeneous_support(20, 12, rng)
     keep = rng.random(len(K.J)) < 0.5
     J = [int(j) for j, kp in zip(K.J, keep) if kp]
     plan = native.SASPlan(20, J, stream=stream)
-    n_in = plan.samples_per_signal
-    x = torch.from_numpy(sample_values(20, n_in, batch, rng).astype(np.complex64)).cuda()
-    y = torch.empty((batch, plan.k), dtype=torch.complex64, device="cuda")
-    work = torch.empty(max(plan.workspace_bytes(batch) // 8, 1), dtype=torch.complex64,
-                       device="cuda")
-    run = lambda: plan.execute_ptr(x.data_ptr(), n_in, y.data_ptr(), plan.k, batch,
-                                   work.data_ptr(), stream)
-    for _ in range(3):
-        run()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        run()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    batch = 4096
+    ms = _rotating_sas_run(native, torch, stream, plan, batch, rng, steps)
     out = {"k": plan.k, "r": plan.pivots(), "mu_star": plan.mu_max, "nodes": plan.n_nodes,
-           "samples_per_transform": n_in, "lemma4_cost": plan.cost, "batch": batch,
-           "ms_per_launch": ms, "transforms_per_s": batch / (ms * 1e-3),
-           "GBps": batch * (n_in + plan.k) * 8 / (ms * 1e-3) / 1e9}
+           "samples_per_transform": plan.samples_per_signal, "lemma4_cost": plan.cost,
+           "batch": batch, "sets": ROTATE_SETS, **_sas_rates(plan, batch, ms)}
     plan.close()
-    del x, y, work
-    torch.cuda.empty_cache()
     return out
 
 
-def gap_bench(native, torch, stream, batch=8192, steps=20):
+def gap_bench(native, torch, stream, steps=20):
     """Supports with additive structure: a proper 2-dimensional GAP (16 x 16
     terms) and an arithmetic progression (1000 terms, difference 2^5 odd) in
     Z_{2^20}, through Shift-and-Sample with r = all pivots (Lemma 5: 2^n
-    samples, mu* = 1) and with Lemma 4's choice of r."""
-    from workloads import arithmetic_progression, gap_support, rng_for, sample_values
-    out = {"batch": batch, "steps": steps}
+    samples, mu* = 1) and with Lemma 4's choice of r.  The batch holds 128 MiB
+    of samples, 4 rotating buffer sets."""
+    from workloads import arithmetic_progression, gap_support, rng_for
+    out = {"steps": steps, "sets": ROTATE_SETS}
     cases = {"gap_16x16": gap_support(20, [16, 16], rng_for(940, 0)),
              "ap_1000_alpha5": arithmetic_progression(20, 1000, rng_for(940, 1), 5)}
     for name, sup in cases.items():
@@ -621,31 +669,12 @@ def gap_bench(native, torch, stream, batch=8192, steps=20):
         for label, piv in (("all_pivots", P), ("lemma4_r", None)):
             plan = native.SASPlan(20, J, pivots=piv, stream=stream)
             n_in = plan.samples_per_signal
-            x = torch.from_numpy(sample_values(20, n_in, batch, rng_for(940, 2)).astype(
-                np.complex64)).cuda()
-            y = torch.empty((batch, plan.k), dtype=torch.complex64, device="cuda")
-            work = torch.empty(max(plan.workspace_bytes(batch) // 8, 1), dtype=torch.complex64,
-                               device="cuda")
-            run = lambda: plan.execute_ptr(x.data_ptr(), n_in, y.data_ptr(), plan.k, batch,
-                                           work.data_ptr(), stream)
-            for _ in range(3):
-                run()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(steps):
-                run()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / steps
+            batch = max(1, ROTATE_INPUT_BYTES // (8 * n_in))
+            ms = _rotating_sas_run(native, torch, stream, plan, batch, rng_for(940, 2), steps)
             out[f"{name}/{label}"] = {
                 "k": plan.k, "pivots_of_J": len(P), "r": plan.pivots(), "mu_star": plan.mu_max,
-                "samples_per_transform": n_in, "ms_per_launch": ms,
-                "transforms_per_s": batch / (ms * 1e-3),
-                "GBps": batch * (n_in + plan.k) * 8 / (ms * 1e-3) / 1e9}
+                "samples_per_transform": n_in, "batch": batch, **_sas_rates(plan, batch, ms)}
             plan.close()
-            del x, y, work
-    torch.cuda.empty_cache()
     return out
 
 

@@ -1327,75 +1327,155 @@ sas_apply_kernel(const float2* __restrict__ y, uint32_t n_nodes, uint32_t mu_sta
   }
 }
 
-// The same solves with one block per signal (grid-stride over the batch):
-// the signal's mu* rows of node values are loaded into LDS with coalesced
-// reads, each element's coefficient is written to its caller position in
-// LDS, and the output row leaves with coalesced stores.  For plans whose
-// (mu* n_nodes + k) values fit in SAS_LDS_VALUES.
-constexpr int SAS_LDS_VALUES = 8192;  // 64 KB of complex64
+// The same solves with one block per signal (grid-stride over the batch),
+// for plans whose (mu* n_nodes + k) values fit in SAS_LDS_VALUES:
+//   * the signal's mu* rows of node values are loaded into LDS with
+//     coalesced reads;
+//   * thread x serves the elements x + i * SAS_LDS_THREADS (i < EPT).  Each
+//     element's record {node | caller position << 16, offset of its inverse
+//     row, mu(v)} is read once per block, so a signal needs only the
+//     inverse-row reads (L2-resident), all issued together;
+//   * each coefficient is written to its caller position in LDS, and the
+//     output row leaves with coalesced stores.
+// MU: the row loop unrolled for mu* = 2..4 (elements of smaller nodes skip
+// the missing terms), 0 for a loop over mu(v).  The barriers order LDS only.
+constexpr int SAS_LDS_THREADS = 512;
 
-__global__ void __launch_bounds__(SAS_APPLY_THREADS)
+template <int EPT, int MU>
+__global__ void __launch_bounds__(SAS_LDS_THREADS)
 sas_apply_lds_kernel(const float2* __restrict__ y, uint32_t n_nodes, uint32_t mu_star,
-                     uint64_t batch, uint32_t k, const uint32_t* __restrict__ elem_node,
-                     const uint32_t* __restrict__ node_first,
-                     const uint32_t* __restrict__ node_count,
-                     const uint32_t* __restrict__ inv_off, const cplx64* __restrict__ inv,
-                     const uint32_t* __restrict__ elem_t, float2* __restrict__ out,
+                     uint64_t batch, uint32_t k, const uint4* __restrict__ rec,
+                     const cplx64* __restrict__ inv, float2* __restrict__ out,
                      int64_t ld_out) {
   extern __shared__ float2 sm[];
   const uint32_t ny = mu_star * n_nodes;
   float2* res = sm + ny;
+  uint32_t pos[EPT], row[EPT], cnt[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const uint32_t e = threadIdx.x + i * SAS_LDS_THREADS;
+    const uint4 r = e < k ? rec[e] : make_uint4(0u, 0u, 0u, 0u);
+    pos[i] = r.x;
+    row[i] = r.y;
+    cnt[i] = r.z;  // 0: no element
+  }
+  constexpr int UNROLL = 4;
   for (uint64_t b = blockIdx.x; b < batch; b += gridDim.x) {
     const float2* yb = y + b * (uint64_t)ny;
-    for (uint32_t i = threadIdx.x; i < ny; i += SAS_APPLY_THREADS) sm[i] = load_stream(yb + i);
-    __syncthreads();
-    for (uint32_t e = threadIdx.x; e < k; e += SAS_APPLY_THREADS) {
-      const uint32_t v = elem_node[e];
-      const uint32_t mu = node_count[v];
-      const cplx64* row = inv + inv_off[v] + (e - node_first[v]) * mu;
-      double ar = 0.0, ai = 0.0;
-      for (uint32_t j = 0; j < mu; ++j) {
-        const float2 q = sm[j * n_nodes + v];
-        const cplx64 m = row[j];
-        ar = fma(m.x, (double)q.x, fma(-m.y, (double)q.y, ar));
-        ai = fma(m.x, (double)q.y, fma(m.y, (double)q.x, ai));
+    for (uint32_t i0 = threadIdx.x; i0 < ny; i0 += UNROLL * SAS_LDS_THREADS) {
+      float2 a[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const uint32_t i = i0 + u * SAS_LDS_THREADS;
+        a[u] = i < ny ? load_stream(yb + i) : make_float2(0.f, 0.f);
       }
-      res[elem_t[e]] = make_float2((float)ar, (float)ai);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const uint32_t i = i0 + u * SAS_LDS_THREADS;
+        if (i < ny) sm[i] = a[u];
+      }
     }
-    __syncthreads();
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const uint32_t v = pos[i] & 0xffffu;
+      const cplx64* m = inv + row[i];
+      double ar = 0.0, ai = 0.0;
+      if constexpr (MU > 0) {
+#pragma unroll
+        for (int j = 0; j < MU; ++j) {
+          if ((uint32_t)j < cnt[i]) {
+            const float2 q = sm[j * n_nodes + v];
+            const cplx64 w = m[j];
+            ar = fma(w.x, (double)q.x, fma(-w.y, (double)q.y, ar));
+            ai = fma(w.x, (double)q.y, fma(w.y, (double)q.x, ai));
+          }
+        }
+      } else {
+        for (uint32_t j = 0; j < cnt[i]; ++j) {
+          const float2 q = sm[j * n_nodes + v];
+          const cplx64 w = m[j];
+          ar = fma(w.x, (double)q.x, fma(-w.y, (double)q.y, ar));
+          ai = fma(w.x, (double)q.y, fma(w.y, (double)q.x, ai));
+        }
+      }
+      if (cnt[i] != 0) res[pos[i] >> 16] = make_float2((float)ar, (float)ai);
+    }
+    lds_barrier();
     float2* ob = out + b * (uint64_t)ld_out;
-    for (uint32_t t = threadIdx.x; t < k; t += SAS_APPLY_THREADS) store_stream(ob + t, res[t]);
-    __syncthreads();  // the next signal overwrites the LDS
+    for (uint32_t t = threadIdx.x; t < k; t += SAS_LDS_THREADS) store_stream(ob + t, res[t]);
+    lds_barrier();  // the next signal overwrites the LDS
+  }
+}
+
+template <int EPT, int MU>
+static hipError_t launch_sas_apply_lds(const float2* y, uint32_t n_nodes, uint32_t mu_star,
+                                       uint64_t batch, uint32_t k, const uint4* rec,
+                                       const cplx64* inv, float2* out, int64_t ld_out,
+                                       hipStream_t stream) {
+  static int cus = 0;  // benign race: every thread computes the same value
+  if (cus == 0) {
+    int dev = 0, c = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    cus = c > 0 ? c : 1;
+  }
+  const size_t lds = ((size_t)mu_star * n_nodes + k) * sizeof(float2);
+  // Blocks that fit per CU: by LDS (160 KB) and by threads (2048).
+  uint64_t per_cu = (160u * 1024u) / (lds ? lds : 1);
+  if (per_cu > 2048 / SAS_LDS_THREADS) per_cu = 2048 / SAS_LDS_THREADS;
+  if (per_cu == 0) per_cu = 1;
+  uint64_t grid = per_cu * (uint64_t)cus;
+  if (grid > batch) grid = batch;
+  hipLaunchKernelGGL((sas_apply_lds_kernel<EPT, MU>), dim3((unsigned)grid),
+                     dim3(SAS_LDS_THREADS), lds, stream, y, n_nodes, mu_star, batch, k, rec, inv,
+                     out, ld_out);
+  return hipGetLastError();
+}
+
+template <int EPT>
+static hipError_t launch_sas_apply_lds_mu(const float2* y, uint32_t n_nodes, uint32_t mu_star,
+                                          uint64_t batch, uint32_t k, const uint4* rec,
+                                          const cplx64* inv, float2* out, int64_t ld_out,
+                                          hipStream_t stream) {
+  switch (mu_star) {
+#define HIDFT_MU(MU)                                                                          \
+  case MU:                                                                                    \
+    return launch_sas_apply_lds<EPT, MU>(y, n_nodes, mu_star, batch, k, rec, inv, out, ld_out, \
+                                         stream);
+    HIDFT_MU(2) HIDFT_MU(3) HIDFT_MU(4)  // (mu* = 1 plans take the direct path)
+#undef HIDFT_MU
+    default:
+      return launch_sas_apply_lds<EPT, 0>(y, n_nodes, mu_star, batch, k, rec, inv, out, ld_out,
+                                          stream);
   }
 }
 
 hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star, uint64_t batch,
                             uint32_t k, const uint32_t* elem_node, const uint32_t* node_first,
                             const uint32_t* node_count, const uint32_t* inv_off, const void* inv,
-                            const uint32_t* elem_t, float2* out, int64_t ld_out,
-                            hipStream_t stream) {
+                            const uint32_t* elem_t, const void* elem_rec, float2* out,
+                            int64_t ld_out, hipStream_t stream) {
   if (batch == 0 || k == 0) return hipSuccess;
-  const uint64_t lds_values = (uint64_t)mu_star * n_nodes + k;
-  if (lds_values <= (uint64_t)SAS_LDS_VALUES) {
-    const size_t lds = lds_values * sizeof(float2);
-    static Occupancy occ;  // benign race: every thread computes the same value
-    if (occ.cus == 0) {
-      Occupancy o;
-      hipError_t e = query_occupancy((const void*)sas_apply_lds_kernel, SAS_APPLY_THREADS,
-                                     SAS_LDS_VALUES * sizeof(float2), &o);
-      if (e != hipSuccess) return e;
-      occ = o;
-    }
-    // Blocks that fit per CU at this plan's LDS size (the occupancy above is
-    // for the largest size), times the CUs.
-    const uint64_t per_cu_lds = (160u * 1024u) / (lds ? lds : 1);
-    const uint64_t per_cu = per_cu_lds < 8 ? (per_cu_lds > 0 ? per_cu_lds : 1) : 8;
-    uint64_t grid = per_cu * (uint64_t)occ.cus;
-    if (grid > batch) grid = batch;
-    hipLaunchKernelGGL(sas_apply_lds_kernel, dim3((unsigned)grid), dim3(SAS_APPLY_THREADS), lds,
-                       stream, y, n_nodes, mu_star, batch, k, elem_node, node_first, node_count,
-                       inv_off, static_cast<const cplx64*>(inv), elem_t, out, ld_out);
-    return hipGetLastError();
+  const cplx64* m = static_cast<const cplx64*>(inv);
+  if ((uint64_t)mu_star * n_nodes + k <= (uint64_t)SAS_LDS_VALUES) {
+    if (elem_rec == nullptr) return hipErrorInvalidValue;
+    const uint4* rec = static_cast<const uint4*>(elem_rec);
+    // Elements per thread: k / SAS_LDS_THREADS rounded up to a power of two.
+    // The nodes' element counts sum to k <= mu* n_nodes, so k is at most half
+    // of SAS_LDS_VALUES: at most 8 elements per thread.
+    static_assert(SAS_LDS_VALUES / 2 <= 8 * SAS_LDS_THREADS, "at most 8 elements per thread");
+    const uint32_t per = (k + SAS_LDS_THREADS - 1) / SAS_LDS_THREADS;
+    if (per <= 1)
+      return launch_sas_apply_lds_mu<1>(y, n_nodes, mu_star, batch, k, rec, m, out, ld_out, stream);
+    if (per <= 2)
+      return launch_sas_apply_lds_mu<2>(y, n_nodes, mu_star, batch, k, rec, m, out, ld_out, stream);
+    if (per <= 4)
+      return launch_sas_apply_lds_mu<4>(y, n_nodes, mu_star, batch, k, rec, m, out, ld_out, stream);
+    if (per <= 8)
+      return launch_sas_apply_lds_mu<8>(y, n_nodes, mu_star, batch, k, rec, m, out, ld_out, stream);
+    return hipErrorInvalidValue;
   }
   const unsigned gx = (k + SAS_APPLY_THREADS - 1) / SAS_APPLY_THREADS;
   // Enough blocks along the batch to fill the device, each striding over signals.
@@ -1405,7 +1485,7 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
   if (gy == 0) gy = 1;
   hipLaunchKernelGGL(sas_apply_kernel, dim3(gx, (unsigned)gy), dim3(SAS_APPLY_THREADS), 0,
                      stream, y, n_nodes, mu_star, batch, k, elem_node, node_first, node_count,
-                     inv_off, static_cast<const cplx64*>(inv), elem_t, out, ld_out);
+                     inv_off, m, elem_t, out, ld_out);
   return hipGetLastError();
 }
 

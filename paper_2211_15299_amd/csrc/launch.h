@@ -94,11 +94,15 @@ hipError_t launch_sas_inverse(uint32_t n_nodes, const uint32_t* node_first,
 // Per signal: the coefficients c = V_v^{-1} y(v) of every node, from the
 // shifted Hi-DFT values y ([signal][shift][node], n_nodes per row), written
 // to the caller's positions elem_t of each output row.
+// elem_rec: per element (node order), {node | caller position << 16, offset
+// of its inverse row, mu(v), 0} as uint4; required when the plan's
+// mu* n_nodes + k values fit in SAS_LDS_VALUES (one block per signal).
+constexpr uint32_t SAS_LDS_VALUES = 8192;  // 64 KB of complex64
 hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star, uint64_t batch,
                             uint32_t k, const uint32_t* elem_node, const uint32_t* node_first,
                             const uint32_t* node_count, const uint32_t* inv_off, const void* inv,
-                            const uint32_t* elem_t, float2* out, int64_t ld_out,
-                            hipStream_t stream);
+                            const uint32_t* elem_t, const void* elem_rec, float2* out,
+                            int64_t ld_out, hipStream_t stream);
 
 // Plain method: one signal, one block, one radix-2 stage per barrier.
 hipError_t launch_plain(uint32_t s, const float2* in, float2* out, const float2* tw,

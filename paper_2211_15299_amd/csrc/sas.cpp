@@ -25,6 +25,7 @@ struct hidft_sas_s {
   uint32_t* d_elem_node = nullptr;  // node of each element, elements in node order
   uint32_t* d_inv_off = nullptr;    // offset of each node's inverse (complex128 units)
   void* d_inv = nullptr;            // inverse dual Vandermonde matrices, FP64
+  uint4* d_elem_rec = nullptr;      // per element: {v | t << 16, row offset, mu(v), 0}
   size_t device_bytes = 0;
 };
 
@@ -32,13 +33,15 @@ namespace {
 
 void release(hidft_sas p) {
   void* ptrs[] = {p->d_tw,         p->d_src,      p->d_src_node,  p->d_src_elem, p->d_node_first,
-                  p->d_node_count, p->d_elem_t,   p->d_elem_node, p->d_inv_off,  p->d_inv};
+                  p->d_node_count, p->d_elem_t,   p->d_elem_node, p->d_inv_off,  p->d_inv,
+                  p->d_elem_rec};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   p->d_tw = nullptr;
   p->d_src = p->d_src_node = p->d_src_elem = nullptr;
   p->d_node_first = p->d_node_count = p->d_elem_t = p->d_elem_node = p->d_inv_off = nullptr;
   p->d_inv = nullptr;
+  p->d_elem_rec = nullptr;
 }
 
 template <typename T>
@@ -83,6 +86,19 @@ hidft_status upload(hidft_sas p, hipStream_t st) {
       elem_val[c.node_first[v] + i] = c.J[c.elem_t[c.node_first[v] + i]];
     }
   }
+  // Element records of the one-block-per-signal solve (node and caller
+  // position fit in 16 bits there: both are below SAS_LDS_VALUES).
+  std::vector<uint4> elem_rec;
+  if (c.mu_max > 1 && (uint64_t)c.mu_max * n_nodes + c.k <= hidft::SAS_LDS_VALUES) {
+    elem_rec.resize(c.k);
+    for (uint32_t v = 0; v < n_nodes; ++v) {
+      const uint32_t mu = c.node_count[v];
+      for (uint32_t i = 0; i < mu; ++i) {
+        const uint32_t e = c.node_first[v] + i;
+        elem_rec[e] = make_uint4(v | (c.elem_t[e] << 16), inv_off[v] + i * mu, mu, 0u);
+      }
+    }
+  }
   if (c.mu_max == 1) {  // one element per node: the Hi-DFT output is the answer
     src_elem.assign(ks, 0);
     for (uint32_t v = 0; v < n_nodes; ++v) src_elem[c.elem_t[c.node_first[v]]] = src_node[v];
@@ -106,6 +122,7 @@ hidft_status upload(hidft_sas p, hipStream_t st) {
       (e = upload_vec(&p->d_elem_t, c.elem_t, st, &total)) != hipSuccess ||
       (e = upload_vec(&p->d_elem_node, elem_node, st, &total)) != hipSuccess ||
       (e = upload_vec(&p->d_inv_off, inv_off, st, &total)) != hipSuccess ||
+      (!elem_rec.empty() && (e = upload_vec(&p->d_elem_rec, elem_rec, st, &total)) != hipSuccess) ||
       (e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, st)) != hipSuccess ||
       (e = hidft::launch_sas_inverse(n_nodes, p->d_node_first, p->d_node_count, p->d_inv_off,
                                      d_elem_val, c.M, p->d_inv, st)) != hipSuccess ||
@@ -314,7 +331,7 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
   if (e == hipSuccess)
     e = hidft::launch_sas_apply(work, (uint32_t)nn, (uint32_t)mu, batch, (uint32_t)p->core.k,
                                 p->d_elem_node, p->d_node_first, p->d_node_count, p->d_inv_off,
-                                p->d_inv, p->d_elem_t, coefs, ld_out, s);
+                                p->d_inv, p->d_elem_t, p->d_elem_rec, coefs, ld_out, s);
   if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
   return hidft::set_error(HIDFT_OK, "");
 }

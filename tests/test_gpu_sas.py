@@ -123,6 +123,74 @@ def test_induced_weights_and_height_n():
             plan.close()
 
 
+# Cases of each leaf-solve kernel form, chosen on the CPU from the node
+# structure: (rng config, seed, M, s, kept fraction or explicit split levels,
+# pivot prefix length).
+#   lds_mu4_ept1 / lds_mu4_ept4 / lds_mu2_ept8: one block per signal with the
+#       row loop unrolled (mu* <= 4), 1, 4 and 8 elements per thread;
+#   lds_generic_mu: one block per signal, mu* = 32 (a loop over mu(v)).  Its
+#       support splits at bits 0-3 and 9-13, so with r = (0, 1, 2, 3) every
+#       node is a full coset of the top five bits: equispaced points on the
+#       circle, a leaf system with condition number 1.  (A random subset
+#       with mu* = 26 has leaf condition numbers near 6e6, which turns the
+#       FP32 Hi-DFT's rounding into errors of order 1e-2: a property of the
+#       problem, which the paper leaves open, not of the kernel.)
+#   per_element: mu* n_nodes + k > 8192 values, one thread per element.
+APPLY_CASES = {
+    "lds_mu4_ept1": (816, 0, 12, 8, 0.6, 6),
+    "lds_mu4_ept4": (817, 0, 14, 11, 0.9, 9),
+    "lds_mu2_ept8": (817, 0, 15, 12, 0.9, 11),
+    "lds_generic_mu": (816, 0, 14, 9, (0, 1, 2, 3, 9, 10, 11, 12, 13), 4),
+    "per_element": (816, 0, 16, 13, 0.7, 11),
+}
+APPLY_EPT = {"lds_mu4_ept1": (0, 1), "lds_mu4_ept4": (2, 4), "lds_mu2_ept8": (4, 8)}
+
+
+def _leaf_condition(M, J, r):
+    """Largest condition number over the nodes' dual Vandermonde systems
+    (rows z_t^j, j < mu(v), z_t = exp(2 pi i l_t / N))."""
+    worst = 1.0
+    for ts in oracle.level_nodes(M, J, max(r) + 1).values():
+        z = np.exp(2j * np.pi * np.array([J[t] for t in ts], dtype=np.float64) / (1 << M))
+        V = z[None, :] ** np.arange(len(ts))[:, None]
+        worst = max(worst, float(np.linalg.cond(V)))
+    return worst
+
+
+@pytest.mark.parametrize("name", sorted(APPLY_CASES))
+def test_sas_leaf_solve_kernel_forms(name):
+    """Each form of the leaf-solve kernel recovers seeded coefficients from
+    samples the oracle synthesised on the plan's sample set (well-conditioned
+    leaf systems, checked here)."""
+    cfg, seed, M, s, sel, npiv = APPLY_CASES[name]
+    rng = rng_for(cfg, seed)
+    if isinstance(sel, tuple):
+        J = homogeneous_support(M, s, rng, levels=sel).J.tolist()
+    else:
+        K, J = _subset(rng, M, s, sel)
+    P, _ = native.analyze(M, J)
+    r = P[:npiv]
+    assert _leaf_condition(M, J, r) < 100
+    plan = native.SASPlan(M, J, pivots=r)
+    mu, nn, k = plan.mu_max, plan.n_nodes, plan.k
+    fits_lds = mu * nn + k <= 8192
+    per_thread = -(-k // 512)
+    if name == "per_element":
+        assert not fits_lds, (mu, nn, k)
+    elif name == "lds_generic_mu":
+        assert fits_lds and mu > 4, (mu, nn, k)
+    else:
+        lo, hi = APPLY_EPT[name]
+        assert fits_lds and 2 <= mu <= 4 and lo < per_thread <= hi, (mu, nn, k)
+    S = plan.samples().tolist()
+    c = complex_normal((2, k), rng)
+    f = oracle.synthesize_samples_fft(M, J, c, S)
+    got = _sas_run(plan, f)
+    err = oracle.rel_l2(got, c)
+    assert np.max(err) <= 1e-4, (name, mu, nn, k, np.max(err))
+    plan.close()
+
+
 def test_sas_strided_rows_and_errors():
     rng = rng_for(814, 0)
     M = 14
