@@ -633,23 +633,29 @@ def _sas_rates(plan, batch, ms):
             "GBps_with_workspace": (data + work) / (ms * 1e-3) / 1e9}
 
 
-def sas_bench(native, torch, stream, steps=20):
+def sas_bench(native, torch, stream, steps=20, two_pass=False):
     """Shift-and-Sample on a random half of a homogeneous set (N = 2^20, 2^12
-    candidate positions, 2048 elements kept), r chosen by Lemma 4's cost: mu*
-    shifted Hi-DFTs in one launch, then the FP64 leaf solves.  4096 signals
-    per launch, 4 rotating buffer sets."""
+    candidate positions, 2048 elements kept), r chosen by Lemma 4's cost: the
+    mu* shifted Hi-DFTs and the FP64 leaf solves (one kernel for this plan;
+    two launches through a workspace with two_pass).  4096 signals per
+    launch, 4 rotating buffer sets."""
     from workloads import homogeneous_support, rng_for
     rng = rng_for(941, 0)
     K = homogeneous_support(20, 12, rng)
     keep = rng.random(len(K.J)) < 0.5
     J = [int(j) for j, kp in zip(K.J, keep) if kp]
-    plan = native.SASPlan(20, J, stream=stream)
+    plan = native.SASPlan(20, J, stream=stream, two_pass=two_pass)
     batch = 4096
     ms = _rotating_sas_run(native, torch, stream, plan, batch, rng, steps)
     out = {"k": plan.k, "r": plan.pivots(), "mu_star": plan.mu_max, "nodes": plan.n_nodes,
            "samples_per_transform": plan.samples_per_signal, "lemma4_cost": plan.cost,
+           "one_kernel": plan.workspace_bytes(batch) == 0,
            "batch": batch, "sets": ROTATE_SETS, **_sas_rates(plan, batch, ms)}
     plan.close()
+    if not two_pass:
+        out["two_pass"] = {k: v for k, v in sas_bench(native, torch, stream, steps, True).items()
+                           if k in ("ms_per_launch", "transforms_per_s", "GBps",
+                                    "GBps_with_workspace")}
     return out
 
 

@@ -448,6 +448,7 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  * 2^s <= 2^14: UNSUPPORTED); hidft_sas_execute refuses plans with mu* > 32
  * (UNSUPPORTED, before any device work).  Device tables are built on the
  * current device (synchronously on `stream`) unless HIDFT_PLAN_HOST_ONLY.
+ * flags: 0, HIDFT_PLAN_HOST_ONLY and/or HIDFT_SAS_TWO_PASS.
  * hidft_sas_get_samples: mu* 2^s sample positions, row j = (I_r + j) mod N
  * in ascending order of I_r: the layout of one signal's samples for execute.
  * hidft_sas_get_nodes: node index of each J[t], and the slot of each node.
@@ -455,8 +456,13 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  * (ld_out >= k, caller's order of J).  d_work: device workspace of
  * hidft_sas_workspace_bytes(batch) bytes (mu* n_nodes complex64 values per
  * signal), 8-byte aligned, owned by the caller (no allocation happens in the
- * call); when that size is 0 (mu* = 1: the Hi-DFT output is the answer)
- * d_work may be NULL.  Inputs and outputs must not overlap.
+ * call); when that size is 0 d_work may be NULL.  It is 0 when mu* = 1 (the
+ * Hi-DFT output is the answer) and when the plan runs as one kernel: for
+ * 2^s <= 2^13, mu* = 2..4 and node values that fit in LDS beside the
+ * transform, the shifted Hi-DFTs gather their node values into LDS and the
+ * leaf solves read them there (bit-identical results, no workspace
+ * traffic), unless the plan was created with HIDFT_SAS_TWO_PASS.  Inputs and
+ * outputs must not overlap.
  * The leaf solves: each node's dual Vandermonde matrix is inverted once, in
  * FP64 on the device, at plan creation (the plan holds sum_v mu(v)^2
  * complex128 values); per signal each coefficient is one row of that inverse
@@ -475,6 +481,9 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  */
 typedef struct hidft_sas_s* hidft_sas;
 #define HIDFT_SAS_MAX_MU 32u
+#define HIDFT_SAS_TWO_PASS 0x2u  /* hidft_sas_create flag: always run the
+                                    shifted Hi-DFTs and the leaf solves as two
+                                    launches through the caller's workspace */
 
 hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
                               const uint32_t* pivots, uint32_t n_pivots, uint32_t flags,

@@ -1452,6 +1452,197 @@ static hipError_t launch_sas_apply_lds_mu(const float2* y, uint32_t n_nodes, uin
   }
 }
 
+// ---------------------------------------------------------------------------
+// Shift-and-Sample in one kernel (Algorithm 2, steps 2-7) for plans with
+// mu* = 2..4 whose node values fit in LDS beside the transform area.
+//
+// Per signal, the block runs the mu* shifted Hi-DFTs SPB at a time (one per
+// signal slot of the fused kernel's shape, with its per-thread tables held
+// in registers across the whole batch); each gathers its first n_nodes
+// outputs (node order, scaled by N/2^s) into an LDS row of node values
+// instead of global memory.  The leaf solves then read those values from
+// LDS: thread x serves the elements x + i * THREADS, i < SAS_FUSED_EPT,
+// whose records {node | caller position << 16, inverse-row offset, mu(v)}
+// it loaded once; each coefficient is written to its caller position in an
+// LDS row (over the transform area, or after the node values when k does
+// not fit there), which leaves with coalesced stores.  The transforms and
+// solves are the two-launch path's, operation for operation, so the results
+// are bit-identical to it; what goes away is the workspace round trip
+// through HBM (mu* n_nodes values written and read back per signal).
+// ---------------------------------------------------------------------------
+constexpr int SAS_FUSED_EPT = 8;
+constexpr size_t SAS_FUSED_MAX_LDS = 80 * 1024;
+
+template <int S>
+struct SasFused {
+  static constexpr int SC = (S > 4 && S % 4 != 0) ? SCHED_SHORT_LAST : SCHED_SHORT_FIRST;
+  using Sh = FusedShape<S, SC, 4>;
+  static constexpr uint32_t TRANSFORM_SLOTS = (uint32_t)(Sh::SPB * Sh::PADK);
+  static size_t lds_bytes(uint32_t mu_star, uint32_t n_nodes, uint32_t k) {
+    const uint64_t extra = k <= TRANSFORM_SLOTS ? 0 : k;
+    return ((uint64_t)TRANSFORM_SLOTS + (uint64_t)mu_star * n_nodes + extra) * sizeof(float2);
+  }
+};
+
+// Output of a shifted Hi-DFT into LDS: the first n_out outputs of the gather
+// order (the nodes) go to y[0 .. n_out).
+struct LdsOut {
+  const float2* tw;
+  const uint16_t* src;
+  float2* y;
+  uint32_t n_out;
+  __device__ __forceinline__ float2 tw_at(int uni, int lane) const { return tw[uni + lane]; }
+  __device__ __forceinline__ int src_at(int uni, int lane) const { return src[uni + lane]; }
+  __device__ __forceinline__ void put(int uni, int lane, float2 x) const {
+    if ((uint32_t)(uni + lane) < n_out) y[uni + lane] = x;
+  }
+};
+
+template <int S>
+__global__ void __launch_bounds__(SasFused<S>::Sh::THREADS)
+sas_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ out,
+                 int64_t ld_out, uint64_t batch, uint32_t mu_star, uint32_t n_nodes, uint32_t k,
+                 const float2* __restrict__ tw, const uint16_t* __restrict__ src_node,
+                 float scale, const uint4* __restrict__ rec, const cplx64* __restrict__ inv) {
+  constexpr int SC = SasFused<S>::SC;
+  using Sh = typename SasFused<S>::Sh;
+  constexpr int R = Sh::R, T = Sh::T, SPB = Sh::SPB, THREADS = Sh::THREADS;
+  constexpr uint32_t K = 1u << S;
+  static_assert(!Sh::BIG && Sh::TW_REGS, "the persistent shape holds its tables in registers");
+  extern __shared__ float2 lds[];
+  float2* yv = lds + SasFused<S>::TRANSFORM_SLOTS;
+  float2* res = k <= SasFused<S>::TRANSFORM_SLOTS ? lds : yv + mu_star * n_nodes;
+  const int tid = threadIdx.x;
+  const int slot = tid / T;
+  const int tau = tid - slot * T;
+  ThreadState<S, SC, 4> ts;
+  load_thread_state<S, SC, 4, PREC_FP32>(ts, tw, src_node, tau);
+  uint32_t pos[SAS_FUSED_EPT], row[SAS_FUSED_EPT], cnt[SAS_FUSED_EPT];
+#pragma unroll
+  for (int i = 0; i < SAS_FUSED_EPT; ++i) {
+    const uint32_t e = tid + i * THREADS;
+    const uint4 r = e < k ? rec[e] : make_uint4(0u, 0u, 0u, 0u);
+    pos[i] = r.x;
+    row[i] = r.y;
+    cnt[i] = r.z;  // 0: no element
+  }
+  const MfmaOps<PREC_FP32> no_mfma;
+  for (uint64_t b = blockIdx.x; b < batch; b += gridDim.x) {
+    const float2* sig = in + b * (uint64_t)ld_in;
+    for (uint32_t j0 = 0; j0 < mu_star; j0 += SPB) {
+      const uint32_t j = j0 + slot;
+      const bool live = j < mu_star;
+      float2 v[R];
+      if (live) {
+        const float2* x = sig + (uint64_t)j * K;
+#pragma unroll
+        for (int c = 0; c < R; ++c) v[c] = load_stream(x + c * T + tau);
+      } else {
+#pragma unroll
+        for (int c = 0; c < R; ++c) v[c] = make_float2(0.f, 0.f);
+      }
+      const LdsOut mem{tw, src_node, yv + (live ? j : 0) * n_nodes, n_nodes};
+      transform_signal<S, SC, 4, PREC_FP32, true>(v, lds, slot, tau, live, mem, scale, ts,
+                                                   no_mfma);
+      lds_barrier();  // node values complete; the transform area is free
+    }
+#pragma unroll
+    for (int i = 0; i < SAS_FUSED_EPT; ++i) {
+      const uint32_t v = pos[i] & 0xffffu;
+      const cplx64* m = inv + row[i];
+      double ar = 0.0, ai = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        if ((uint32_t)jj < cnt[i]) {
+          const float2 q = yv[jj * n_nodes + v];
+          const cplx64 w = m[jj];
+          ar = fma(w.x, (double)q.x, fma(-w.y, (double)q.y, ar));
+          ai = fma(w.x, (double)q.y, fma(w.y, (double)q.x, ai));
+        }
+      }
+      if (cnt[i] != 0) res[pos[i] >> 16] = make_float2((float)ar, (float)ai);
+    }
+    lds_barrier();
+    float2* ob = out + b * (uint64_t)ld_out;
+    for (uint32_t t = tid; t < k; t += THREADS) store_stream(ob + t, res[t]);
+    lds_barrier();  // the next signal overwrites the LDS
+  }
+}
+
+template <int S>
+static bool sas_fused_fits_s(uint32_t mu_star, uint32_t n_nodes, uint32_t k) {
+  return k <= (uint32_t)(SAS_FUSED_EPT * SasFused<S>::Sh::THREADS) &&
+         SasFused<S>::lds_bytes(mu_star, n_nodes, k) <= SAS_FUSED_MAX_LDS;
+}
+
+template <int S>
+static hipError_t launch_sas_fused_s(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
+                                     uint64_t batch, uint32_t mu_star, uint32_t n_nodes,
+                                     uint32_t k, const float2* tw, const uint16_t* src_node,
+                                     float scale, const uint4* rec, const cplx64* inv,
+                                     hipStream_t stream) {
+  using Sh = typename SasFused<S>::Sh;
+  const size_t lds = SasFused<S>::lds_bytes(mu_star, n_nodes, k);
+  static Occupancy occ;  // benign race: every thread computes the same value
+  if (occ.cus == 0) {
+    Occupancy o;
+    hipError_t e = query_occupancy((const void*)sas_fused_kernel<S>, Sh::THREADS,
+                                   SAS_FUSED_MAX_LDS, &o);
+    if (e != hipSuccess) return e;
+    occ = o;
+  }
+  // Blocks per CU: by this plan's LDS size, and by registers (the occupancy
+  // query above, at the largest LDS size, bounds it from below).
+  int per_cu_regs = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu_regs, (const void*)sas_fused_kernel<S>, Sh::THREADS, lds);
+  if (e != hipSuccess) return e;
+  uint64_t per_cu = per_cu_regs > 0 ? (uint64_t)per_cu_regs : (uint64_t)occ.per_cu;
+  uint64_t grid = per_cu * (uint64_t)occ.cus;
+  if (grid > batch) grid = batch;
+  hipLaunchKernelGGL(sas_fused_kernel<S>, dim3((unsigned)grid), dim3(Sh::THREADS), lds, stream,
+                     in, ld_in, out, ld_out, batch, mu_star, n_nodes, k, tw, src_node, scale,
+                     rec, inv);
+  return hipGetLastError();
+}
+
+bool sas_fused_fits(uint32_t s, uint32_t mu_star, uint32_t n_nodes, uint32_t k) {
+  if (mu_star < 2 || mu_star > 4 || n_nodes == 0 || k == 0) return false;
+  switch (s) {
+#define HIDFT_CASE(S) \
+  case S:             \
+    return sas_fused_fits_s<S>(mu_star, n_nodes, k);
+    HIDFT_CASE(1) HIDFT_CASE(2) HIDFT_CASE(3) HIDFT_CASE(4) HIDFT_CASE(5) HIDFT_CASE(6)
+    HIDFT_CASE(7) HIDFT_CASE(8) HIDFT_CASE(9) HIDFT_CASE(10) HIDFT_CASE(11) HIDFT_CASE(12)
+    HIDFT_CASE(13)
+#undef HIDFT_CASE
+    default:
+      return false;
+  }
+}
+
+hipError_t launch_sas_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out,
+                            int64_t ld_out, uint64_t batch, uint32_t mu_star, uint32_t n_nodes,
+                            uint32_t k, const float2* tw, const uint16_t* src_node, float scale,
+                            const void* elem_rec, const void* inv, hipStream_t stream) {
+  if (!sas_fused_fits(s, mu_star, n_nodes, k) || elem_rec == nullptr) return hipErrorInvalidValue;
+  if (batch == 0) return hipSuccess;
+  const uint4* rec = static_cast<const uint4*>(elem_rec);
+  const cplx64* m = static_cast<const cplx64*>(inv);
+  switch (s) {
+#define HIDFT_CASE(S) \
+  case S:             \
+    return launch_sas_fused_s<S>(in, ld_in, out, ld_out, batch, mu_star, n_nodes, k, tw, \
+                                 src_node, scale, rec, m, stream);
+    HIDFT_CASE(1) HIDFT_CASE(2) HIDFT_CASE(3) HIDFT_CASE(4) HIDFT_CASE(5) HIDFT_CASE(6)
+    HIDFT_CASE(7) HIDFT_CASE(8) HIDFT_CASE(9) HIDFT_CASE(10) HIDFT_CASE(11) HIDFT_CASE(12)
+    HIDFT_CASE(13)
+#undef HIDFT_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star, uint64_t batch,
                             uint32_t k, const uint32_t* elem_node, const uint32_t* node_first,
                             const uint32_t* node_count, const uint32_t* inv_off, const void* inv,

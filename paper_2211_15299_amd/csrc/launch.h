@@ -104,6 +104,17 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
                             const uint32_t* elem_t, const void* elem_rec, float2* out,
                             int64_t ld_out, hipStream_t stream);
 
+// Shift-and-Sample in one kernel: the mu* shifted Hi-DFTs of a signal
+// (sample rows j * 2^s of its input row, ld_in >= mu* 2^s) gathered into LDS
+// and solved there, with no workspace.  sas_fused_fits tells whether a plan
+// qualifies (2^s <= 2^13, mu* = 2..4, k and the LDS within the kernel's
+// bounds); elem_rec as for launch_sas_apply.
+bool sas_fused_fits(uint32_t s, uint32_t mu_star, uint32_t n_nodes, uint32_t k);
+hipError_t launch_sas_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out,
+                            int64_t ld_out, uint64_t batch, uint32_t mu_star, uint32_t n_nodes,
+                            uint32_t k, const float2* tw, const uint16_t* src_node, float scale,
+                            const void* elem_rec, const void* inv, hipStream_t stream);
+
 // Plain method: one signal, one block, one radix-2 stage per barrier.
 hipError_t launch_plain(uint32_t s, const float2* in, float2* out, const float2* tw,
                         const uint16_t* src, float scale, hipStream_t stream);

@@ -26,6 +26,7 @@ struct hidft_sas_s {
   uint32_t* d_inv_off = nullptr;    // offset of each node's inverse (complex128 units)
   void* d_inv = nullptr;            // inverse dual Vandermonde matrices, FP64
   uint4* d_elem_rec = nullptr;      // per element: {v | t << 16, row offset, mu(v), 0}
+  bool fused = false;               // one kernel per launch, no workspace
   size_t device_bytes = 0;
 };
 
@@ -89,7 +90,7 @@ hidft_status upload(hidft_sas p, hipStream_t st) {
   // Element records of the one-block-per-signal solve (node and caller
   // position fit in 16 bits there: both are below SAS_LDS_VALUES).
   std::vector<uint4> elem_rec;
-  if (c.mu_max > 1 && (uint64_t)c.mu_max * n_nodes + c.k <= hidft::SAS_LDS_VALUES) {
+  if (c.mu_max > 1 && (p->fused || (uint64_t)c.mu_max * n_nodes + c.k <= hidft::SAS_LDS_VALUES)) {
     elem_rec.resize(c.k);
     for (uint32_t v = 0; v < n_nodes; ++v) {
       const uint32_t mu = c.node_count[v];
@@ -181,7 +182,7 @@ hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
                               void* stream, hidft_sas* out) {
   if (!out) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_create: out is NULL");
   *out = nullptr;
-  if (flags & ~HIDFT_PLAN_HOST_ONLY)
+  if (flags & ~(HIDFT_PLAN_HOST_ONLY | HIDFT_SAS_TWO_PASS))
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_create: unknown flags");
   hidft_sas p = nullptr;
   try {
@@ -195,6 +196,9 @@ hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
       return hidft::set_error(st, "hidft_sas_create: " + err);
     }
     p->scale = std::ldexp(1.0f, (int)p->core.M - (int)p->core.s);
+    p->fused = !(flags & HIDFT_SAS_TWO_PASS) &&
+               hidft::sas_fused_fits(p->core.s, p->core.mu_max,
+                                     (uint32_t)p->core.node_slot.size(), (uint32_t)p->core.k);
     if (!(flags & HIDFT_PLAN_HOST_ONLY)) {
       st = upload(p, static_cast<hipStream_t>(stream));
       if (st != HIDFT_OK) {
@@ -261,8 +265,9 @@ hidft_status hidft_sas_get_nodes(hidft_sas p, uint32_t* node_of_t, uint32_t* slo
 hidft_status hidft_sas_workspace_bytes(hidft_sas p, uint64_t batch, size_t* bytes) {
   if (!p || !bytes)
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_workspace_bytes: NULL");
-  // [signal][shift][node]; none when every node holds one element (mu* = 1).
-  *bytes = p->core.mu_max == 1
+  // [signal][shift][node]; none when every node holds one element (mu* = 1)
+  // or when the plan runs as one kernel.
+  *bytes = p->core.mu_max == 1 || p->fused
                ? 0
                : (size_t)batch * p->core.mu_max * p->core.node_slot.size() * sizeof(float2);
   return hidft::set_error(HIDFT_OK, "");
@@ -309,10 +314,18 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
     if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
     return hidft::set_error(HIDFT_OK, "");
   }
+  const uint64_t nn = p->core.node_slot.size();
+  if (p->fused) {
+    // Shifted Hi-DFTs and leaf solves in one kernel, node values in LDS.
+    e = hidft::launch_sas_fused(p->core.s, in, ld_in, coefs, ld_out, batch, (uint32_t)mu,
+                                (uint32_t)nn, (uint32_t)p->core.k, p->d_tw, p->d_src_node,
+                                p->scale, p->d_elem_rec, p->d_inv, s);
+    if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
+    return hidft::set_error(HIDFT_OK, "");
+  }
   if (!d_work || (reinterpret_cast<uintptr_t>(d_work) & 7u))
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
                             "hidft_sas_execute: workspace missing or misaligned");
-  const uint64_t nn = p->core.node_slot.size();
   float2* work = static_cast<float2*>(d_work);
   // Steps 2-4: the mu* shifted Hi-DFTs, each gathered in node order (the
   // first nn outputs), as one batched launch when the rows are packed, else

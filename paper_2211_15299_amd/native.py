@@ -25,6 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhidft.so")
 
 HIDFT_PLAN_HOST_ONLY = 0x1
+HIDFT_SAS_TWO_PASS = 0x2
 MAX_LOG2_K_DEVICE = 14
 
 # Execution variants (hidft_exec_config)
@@ -417,11 +418,13 @@ class Server:
 class SASPlan:
     """Shift-and-Sample plan of a part-homogeneous support (hidft_sas_*).
 
-    pivots=None lets the planner choose r (Lemma 4's cost).
+    pivots=None lets the planner choose r (Lemma 4's cost).  two_pass=True
+    keeps the shifted Hi-DFTs and the leaf solves in two launches through a
+    workspace even where the plan could run as one kernel.
     """
 
     def __init__(self, log2_n: int, J: Sequence[int], pivots=None, host_only: bool = False,
-                 stream=None):
+                 stream=None, two_pass: bool = False):
         arr = _u64_array(J)
         self._h = ctypes.c_void_p(None)
         if pivots is None:
@@ -430,7 +433,7 @@ class SASPlan:
             self._r = np.zeros(max(len(pivots), 1), dtype=np.uint32)
             self._r[: len(pivots)] = pivots
             rp, nr = _ptr(self._r, _u32), len(pivots)
-        flags = HIDFT_PLAN_HOST_ONLY if host_only else 0
+        flags = (HIDFT_PLAN_HOST_ONLY if host_only else 0) | (HIDFT_SAS_TWO_PASS if two_pass else 0)
         _check(lib().hidft_sas_create(log2_n, _ptr(arr, _u64), len(arr), rp, nr, flags,
                                       None if host_only else _stream_handle(stream),
                                       ctypes.byref(self._h)))

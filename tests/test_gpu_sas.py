@@ -171,7 +171,7 @@ def test_sas_leaf_solve_kernel_forms(name):
     P, _ = native.analyze(M, J)
     r = P[:npiv]
     assert _leaf_condition(M, J, r) < 100
-    plan = native.SASPlan(M, J, pivots=r)
+    plan = native.SASPlan(M, J, pivots=r, two_pass=True)
     mu, nn, k = plan.mu_max, plan.n_nodes, plan.k
     fits_lds = mu * nn + k <= 8192
     per_thread = -(-k // 512)
@@ -191,12 +191,69 @@ def test_sas_leaf_solve_kernel_forms(name):
     plan.close()
 
 
+def _one_kernel_case(case):
+    """(M, J, r) of a one-kernel test case: six random subsets with a pivot
+    prefix (2^4..2^8 points), the benchmark's random half of a homogeneous
+    set with Lemma 4's r (2^11 points, k = 1965), and a 2 % subset of a
+    2^15-point homogeneous set at 13 pivots (2^13 points, one 512-thread
+    block per CU's worth of LDS)."""
+    if case == "bench":
+        rng = rng_for(941, 0)
+        K = homogeneous_support(20, 12, rng)
+        keep = rng.random(len(K.J)) < 0.5
+        return 20, [int(j) for j, kp in zip(K.J, keep) if kp], None, rng
+    if case == "s13":
+        rng = rng_for(819, 0)
+        K, J = _subset(rng, 20, 15, 0.02)
+        return 20, J, native.analyze(20, J)[0][:13], rng
+    rng = rng_for(818, case)
+    M = int(rng.integers(10, 21))
+    s = int(rng.integers(6, min(M - 1, 12) + 1))
+    K, J = _subset(rng, M, s, rng.uniform(0.4, 0.8))
+    P, _ = native.analyze(M, J)
+    return M, J, P[: max(1, len(P) - int(rng.integers(1, 3)))], rng
+
+
+@pytest.mark.parametrize("case", list(range(6)) + ["bench", "s13"])
+def test_sas_one_kernel_form_matches_two_launches(case):
+    """Plans that run as one kernel (shifted Hi-DFTs and leaf solves, node
+    values in LDS) need no workspace and give bit-identical results to the
+    two-launch form through a workspace, on seeded samples."""
+    M, J, r, rng = _one_kernel_case(case)
+    one = native.SASPlan(M, J, pivots=r)
+    r = one.pivots()
+    two = native.SASPlan(M, J, pivots=r, two_pass=True)
+    assert one.pivots() == two.pivots() and one.mu_max == two.mu_max
+    if not (2 <= one.mu_max <= 4):
+        pytest.skip(f"mu* = {one.mu_max}: not a one-kernel plan")
+    assert one.workspace_bytes(7) == 0, (one.mu_max, one.n_nodes, one.k)
+    assert two.workspace_bytes(7) == 7 * two.mu_max * two.n_nodes * 8
+    n = one.samples_per_signal
+    x = torch.from_numpy(complex_normal((7, n), rng).astype(np.complex64)).cuda()
+    y1 = torch.full((7, one.k), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda")
+    y2 = torch.full_like(y1, complex(np.nan, np.nan))
+    work = torch.empty(two.workspace_bytes(7) // 8, dtype=torch.complex64, device="cuda")
+    one.execute_ptr(x.data_ptr(), n, y1.data_ptr(), one.k, 7, 0)
+    two.execute_ptr(x.data_ptr(), n, y2.data_ptr(), two.k, 7, work.data_ptr())
+    torch.cuda.synchronize()
+    assert torch.equal(y1.view(torch.float32), y2.view(torch.float32))
+    # and both recover seeded coefficients from synthesised samples
+    S = one.samples().tolist()
+    c = complex_normal((2, one.k), rng)
+    f = oracle.synthesize_samples_fft(M, J, c, S)
+    got = _sas_run(one, f)
+    if _leaf_condition(M, J, r) < 100:
+        assert np.max(oracle.rel_l2(got, c)) <= 1e-4
+    one.close()
+    two.close()
+
+
 def test_sas_strided_rows_and_errors():
     rng = rng_for(814, 0)
     M = 14
     K, J = _subset(rng, M, 8, 0.5)
     P, _ = native.analyze(M, J)
-    plan = native.SASPlan(M, J, pivots=P[:5])     # a prefix: nodes of several elements
+    plan = native.SASPlan(M, J, pivots=P[:5], two_pass=True)  # nodes of several elements
     assert plan.mu_max > 1
     assert plan.workspace_bytes(3) == 3 * plan.mu_max * plan.n_nodes * 8
     n = plan.samples_per_signal
