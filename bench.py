@@ -296,7 +296,7 @@ def main():
     args.steps, args.warmup = 20, 3
     result["config3_grouped"] = grouped_bench(args, native, torch, stream)
     args.steps = gsteps
-    result["config5_serving"] = serve_bench(args, native, seconds=min(args.serve_seconds, 5.0))
+    result["config5_serving"] = serve_bench(args, native)
     result["config4_precision"] = precision_bench(args, native, torch, stream, steps=20)
     result["gap_supports"] = gap_bench(native, torch, stream)
     result["inverse"] = inverse_bench(args, native, torch, stream)
