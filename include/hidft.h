@@ -461,8 +461,8 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  * 2^s <= 2^13, mu* = 2..4 and node values that fit in LDS beside the
  * transform, the shifted Hi-DFTs gather their node values into LDS and the
  * leaf solves read them there (bit-identical results, no workspace
- * traffic), unless the plan was created with HIDFT_SAS_TWO_PASS.  Inputs and
- * outputs must not overlap.
+ * traffic), unless the plan was created with HIDFT_SAS_TWO_PASS.  Inputs,
+ * outputs and the workspace must not overlap (INVALID_ARGUMENT).
  * The leaf solves: each node's dual Vandermonde matrix is inverted once, in
  * FP64 on the device, at plan creation (the plan holds sum_v mu(v)^2
  * complex128 values); per signal each coefficient is one row of that inverse

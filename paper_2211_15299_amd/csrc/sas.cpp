@@ -326,6 +326,19 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
   if (!d_work || (reinterpret_cast<uintptr_t>(d_work) & 7u))
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
                             "hidft_sas_execute: workspace missing or misaligned");
+  {
+    // The workspace is written while the samples are read and read while the
+    // coefficients are written: it must overlap neither.
+    const uint64_t w0 = reinterpret_cast<uintptr_t>(d_work);
+    const uint64_t w1 = w0 + batch * mu * nn * sizeof(float2);
+    const uint64_t a0 = reinterpret_cast<uintptr_t>(d_samples);
+    const uint64_t a1 = a0 + ((batch - 1) * (uint64_t)ld_in + mu * ks) * sizeof(float2);
+    const uint64_t b0 = reinterpret_cast<uintptr_t>(d_coefs);
+    const uint64_t b1 = b0 + ((batch - 1) * (uint64_t)ld_out + p->core.k) * sizeof(float2);
+    if ((w0 < a1 && a0 < w1) || (w0 < b1 && b0 < w1))
+      return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                              "hidft_sas_execute: workspace overlaps the samples or coefficients");
+  }
   float2* work = static_cast<float2*>(d_work);
   // Steps 2-4: the mu* shifted Hi-DFTs, each gathered in node order (the
   // first nn outputs), as one batched launch when the rows are packed, else

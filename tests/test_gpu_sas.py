@@ -272,6 +272,10 @@ def test_sas_strided_rows_and_errors():
         plan.execute_ptr(x.data_ptr(), n - 1, y.data_ptr(), plan.k, 1, work.data_ptr())
     with pytest.raises(native.HiDFTError):
         plan.execute_ptr(x.data_ptr(), n + 5, y.data_ptr(), plan.k, 1, 0)
+    with pytest.raises(native.HiDFTError):   # workspace overlapping the samples
+        plan.execute_ptr(x.data_ptr(), n + 5, y.data_ptr(), plan.k, 1, x.data_ptr())
+    with pytest.raises(native.HiDFTError):   # workspace overlapping the coefficients
+        plan.execute_ptr(x.data_ptr(), n + 5, y.data_ptr(), plan.k, 1, y.data_ptr())
     plan.close()
 
 
