@@ -248,6 +248,43 @@ def test_sas_one_kernel_form_matches_two_launches(case):
     two.close()
 
 
+@pytest.mark.parametrize("s", range(1, 14))
+def test_sas_one_kernel_form_at_every_size(s):
+    """The one-kernel form at every Hi-DFT size 2^1..2^13: a homogeneous set
+    whose top split level is bit M-1, with r = its other s levels, so each
+    node holds two elements half a circle apart (mu* = 2, leaf condition
+    number 1); above 2^10 points a subset keeps k and the LDS within the
+    kernel's bounds.  Bit-identical to the two-launch form, and recovers
+    seeded coefficients."""
+    rng = rng_for(820, s)
+    M = max(s + 4, 12)
+    levels = sorted(rng.choice(M - 1, size=s, replace=False).tolist()) + [M - 1]
+    J = homogeneous_support(M, s + 1, rng, levels=levels).J.tolist()
+    cap = {11: 1500, 12: 1500, 13: 600}.get(s)
+    if cap is not None and len(J) > cap:
+        keep = rng.choice(len(J), size=cap, replace=False)
+        J = [J[i] for i in sorted(keep)]
+    r = levels[:s]
+    one = native.SASPlan(M, J, pivots=r)
+    two = native.SASPlan(M, J, pivots=r, two_pass=True)
+    assert one.mu_max == 2 and one.workspace_bytes(5) == 0, (one.mu_max, one.n_nodes, one.k)
+    n, k = one.samples_per_signal, one.k
+    c = complex_normal((5, k), rng)
+    f = oracle.synthesize_samples_fft(M, J, c, one.samples().tolist())
+    x = torch.from_numpy(f.astype(np.complex64)).cuda()
+    y1 = torch.full((5, k), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda")
+    y2 = torch.full_like(y1, complex(np.nan, np.nan))
+    work = torch.empty(two.workspace_bytes(5) // 8, dtype=torch.complex64, device="cuda")
+    one.execute_ptr(x.data_ptr(), n, y1.data_ptr(), k, 5, 0)
+    two.execute_ptr(x.data_ptr(), n, y2.data_ptr(), k, 5, work.data_ptr())
+    torch.cuda.synchronize()
+    assert torch.equal(y1.view(torch.float32), y2.view(torch.float32))
+    err = oracle.rel_l2(y1.cpu().numpy().astype(np.complex128), c)
+    assert np.max(err) <= 1e-5, (s, np.max(err))
+    one.close()
+    two.close()
+
+
 def test_sas_strided_rows_and_errors():
     rng = rng_for(814, 0)
     M = 14
