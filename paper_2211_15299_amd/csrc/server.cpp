@@ -10,6 +10,7 @@
 // the device.  One scheduler thread forms batches, issues the work and
 // retires completed batches; clients collect results by polling.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <atomic>
@@ -31,6 +32,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
 struct PlanEntry {
   uint32_t M = 0;
   std::vector<uint64_t> J;
@@ -49,16 +52,17 @@ struct Request {
   Clock::time_point t_submit;
 };
 
+// Upload region of a slot, on the device and as pinned host staging, with
+// the same layout: the batch's samples, then (from the next 256-byte
+// boundary) its pack descriptors, then its instance descriptors.  One copy
+// moves all three.
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  float2* d_data = nullptr;        // inputs then outputs of the batch
-  hidft::GroupPack* d_packs = nullptr;
-  hidft::GroupSlot* d_slots = nullptr;
-  float2* h_in = nullptr;          // pinned staging
+  char* d_up = nullptr;            // samples | packs | instance descriptors
+  float2* d_out = nullptr;         // coefficients of the batch
+  char* h_up = nullptr;            // pinned staging, same layout as d_up
   float2* h_out = nullptr;
-  hidft::GroupPack* h_packs = nullptr;
-  hidft::GroupSlot* h_slots = nullptr;
   std::vector<Request> batch;      // requests in flight (empty when free)
   std::vector<uint64_t> offsets;   // point offset of each request in the region
   uint64_t points = 0;
@@ -171,12 +175,13 @@ void hidft_server_s::launch(Slot& sl) {
   inst.reserve(sl.batch.size());
   sl.offsets.resize(sl.batch.size());
   uint64_t off = 0;
-  float2* d_in = sl.d_data;
-  float2* d_out = sl.d_data + slot_points;
+  float2* d_in = reinterpret_cast<float2*>(sl.d_up);
+  float2* d_out = sl.d_out;
+  float2* h_in = reinterpret_cast<float2*>(sl.h_up);
   for (size_t i = 0; i < sl.batch.size(); ++i) {
     const Request& r = sl.batch[i];
     sl.offsets[i] = off;
-    std::memcpy(sl.h_in + off, r.host_in, r.k * sizeof(float2));
+    std::memcpy(h_in + off, r.host_in, r.k * sizeof(float2));
     hidft::GroupSlot d;
     d.in = d_in + off;
     d.out = d_out + off;
@@ -190,17 +195,18 @@ void hidft_server_s::launch(Slot& sl) {
   std::vector<hidft::GroupPack> packs;
   std::vector<hidft::GroupSlot> slots_v;
   hidft::pack_instances(inst, &packs, &slots_v);
-  std::memcpy(sl.h_packs, packs.data(), packs.size() * sizeof(hidft::GroupPack));
-  std::memcpy(sl.h_slots, slots_v.data(), slots_v.size() * sizeof(hidft::GroupSlot));
+  const size_t packs_at = align_up(off * sizeof(float2), 256);
+  const size_t slots_at = align_up(packs_at + packs.size() * sizeof(hidft::GroupPack), 64);
+  const size_t up_bytes = slots_at + slots_v.size() * sizeof(hidft::GroupSlot);
+  std::memcpy(sl.h_up + packs_at, packs.data(), packs.size() * sizeof(hidft::GroupPack));
+  std::memcpy(sl.h_up + slots_at, slots_v.data(), slots_v.size() * sizeof(hidft::GroupSlot));
   hipError_t e;
-  if ((e = hipMemcpyAsync(d_in, sl.h_in, off * sizeof(float2), hipMemcpyHostToDevice,
-                          sl.stream)) != hipSuccess ||
-      (e = hipMemcpyAsync(sl.d_packs, sl.h_packs, packs.size() * sizeof(hidft::GroupPack),
-                          hipMemcpyHostToDevice, sl.stream)) != hipSuccess ||
-      (e = hipMemcpyAsync(sl.d_slots, sl.h_slots, slots_v.size() * sizeof(hidft::GroupSlot),
-                          hipMemcpyHostToDevice, sl.stream)) != hipSuccess ||
-      (e = hidft::launch_grouped(sl.d_packs, (uint32_t)packs.size(), sl.d_slots, sl.stream)) !=
+  if ((e = hipMemcpyAsync(sl.d_up, sl.h_up, up_bytes, hipMemcpyHostToDevice, sl.stream)) !=
           hipSuccess ||
+      (e = hidft::launch_grouped(reinterpret_cast<const hidft::GroupPack*>(sl.d_up + packs_at),
+                                 (uint32_t)packs.size(),
+                                 reinterpret_cast<const hidft::GroupSlot*>(sl.d_up + slots_at),
+                                 sl.stream)) != hipSuccess ||
       (e = hipMemcpyAsync(sl.h_out, d_out, off * sizeof(float2), hipMemcpyDeviceToHost,
                           sl.stream)) != hipSuccess ||
       (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) {
@@ -238,6 +244,9 @@ void hidft_server_s::retire(Slot& sl) {
 
 void hidft_server_s::loop() {
   (void)hipSetDevice(device);
+  // The loop polls in-flight batches with short sleeps; the default timer
+  // slack (50 us) would stretch each of them, and with it every latency.
+  (void)prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
   const uint64_t cap_points = slot_points;
   for (;;) {
     bool progressed = false;
@@ -309,20 +318,18 @@ hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* o
     return hidft::hip_error(e, "hidft_server_create: stream");
   sv->slots.resize(cfg->slots);
   for (Slot& sl : sv->slots) {
-    const size_t data = 2 * sv->slot_points * sizeof(float2);
-    const size_t packs = (size_t)cfg->max_batch * sizeof(hidft::GroupPack);
-    const size_t slots = (size_t)cfg->max_batch * sizeof(hidft::GroupSlot);
+    const size_t data = sv->slot_points * sizeof(float2);
+    // samples, then packs and instance descriptors (one pack per instance at
+    // most) after their alignment padding
+    const size_t up = align_up(data, 256) +
+                      align_up((size_t)cfg->max_batch * sizeof(hidft::GroupPack), 64) +
+                      (size_t)cfg->max_batch * sizeof(hidft::GroupSlot);
     if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipMalloc(&sl.d_data, data)) != hipSuccess ||
-        (e = hipMalloc(&sl.d_packs, packs)) != hipSuccess ||
-        (e = hipMalloc(&sl.d_slots, slots)) != hipSuccess ||
-        (e = hipHostMalloc(&sl.h_in, sv->slot_points * sizeof(float2), hipHostMallocDefault)) !=
-            hipSuccess ||
-        (e = hipHostMalloc(&sl.h_out, sv->slot_points * sizeof(float2), hipHostMallocDefault)) !=
-            hipSuccess ||
-        (e = hipHostMalloc(&sl.h_packs, packs, hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc(&sl.h_slots, slots, hipHostMallocDefault)) != hipSuccess) {
+        (e = hipMalloc(&sl.d_up, up)) != hipSuccess ||
+        (e = hipMalloc(&sl.d_out, data)) != hipSuccess ||
+        (e = hipHostMalloc(&sl.h_up, up, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc(&sl.h_out, data, hipHostMallocDefault)) != hipSuccess) {
       hidft_status st = hidft::hip_error(e, "hidft_server_create: slot resources");
       hidft_server_destroy(sv.release());
       return st;
@@ -437,13 +444,10 @@ hidft_status hidft_server_destroy(hidft_server s) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
-    if (sl.d_data) (void)hipFree(sl.d_data);
-    if (sl.d_packs) (void)hipFree(sl.d_packs);
-    if (sl.d_slots) (void)hipFree(sl.d_slots);
-    if (sl.h_in) (void)hipHostFree(sl.h_in);
+    if (sl.d_up) (void)hipFree(sl.d_up);
+    if (sl.d_out) (void)hipFree(sl.d_out);
+    if (sl.h_up) (void)hipHostFree(sl.h_up);
     if (sl.h_out) (void)hipHostFree(sl.h_out);
-    if (sl.h_packs) (void)hipHostFree(sl.h_packs);
-    if (sl.h_slots) (void)hipHostFree(sl.h_slots);
   }
   for (auto& kv : s->plans) hidft_plan_destroy(kv.second->plan);
   if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
