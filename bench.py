@@ -353,12 +353,33 @@ def grouped_bench(args, native, torch, stream):
     # point); the tables the kernel actually reads are the twiddles and the
     # gather positions (8 (k - 1) + 2 k B per instance).
     table_bytes = int(sum(8 * (kk - 1) + 2 * kk for kk in ks.tolist()))
-    return {"mode": "grouped", "instances": len(plans), "points": total, "packs": groups[0].n_packs,
-            "k_min": int(ks.min()), "k_max": int(ks.max()), "ms_per_launch": ms,
-            "transforms_per_s": len(plans) / (ms * 1e-3), "GBps": byts / (ms * 1e-3) / 1e9,
-            "GBps_data_plus_plan": (byts + 4 * total) / (ms * 1e-3) / 1e9,
-            "table_bytes_per_launch": table_bytes,
-            "frac_of_8TBps": byts / (ms * 1e-3) / 8e12, "sets": sets}
+    out = {"mode": "grouped", "instances": len(plans), "points": total, "packs": groups[0].n_packs,
+           "k_min": int(ks.min()), "k_max": int(ks.max()), "ms_per_launch": ms,
+           "transforms_per_s": len(plans) / (ms * 1e-3), "GBps": byts / (ms * 1e-3) / 1e9,
+           "GBps_data_plus_plan": (byts + 4 * total) / (ms * 1e-3) / 1e9,
+           "table_bytes_per_launch": table_bytes,
+           "frac_of_8TBps": byts / (ms * 1e-3) / 8e12, "sets": sets}
+    # The group autotuner (schedule and pack order), then the tuned launch
+    # timed like the default one.
+    t0 = time.perf_counter()
+    cfg, tune_us = groups[0].autotune(reps=10, stream=stream)
+    search_s = time.perf_counter() - t0
+    for g in groups[1:]:
+        g.set_config(cfg.schedule, cfg.order, stream)
+    for i in range(args.warmup):
+        groups[i % sets].execute(stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(args.steps):
+        groups[i % sets].execute(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    tms = e0.elapsed_time(e1) / args.steps
+    out["autotuned"] = {"schedule": cfg.schedule, "order": cfg.order, "search_s": search_s,
+                        "search_us_per_launch": tune_us, "ms_per_launch": tms,
+                        "transforms_per_s": len(plans) / (tms * 1e-3),
+                        "GBps": byts / (tms * 1e-3) / 1e9}
+    return out
 
 
 def serve_bench(args, native, seconds=None):

@@ -345,6 +345,41 @@ hidft_status hidft_group_get_info(hidft_group group, uint64_t* n_instances,
                                   uint64_t* n_packs, size_t* device_bytes);
 
 /*
+ * Launch configuration of a group (the schedule and pack layout of the one
+ * grouped launch; the arithmetic of each stage is the same in all of them).
+ *   schedule  HIDFT_SCHED_DEFAULT or _SHORT_LAST: for sizes 2^s with s > 4
+ *             and 4 not dividing s, the short radix group runs last;
+ *             _SHORT_FIRST: first.  The results of an instance equal
+ *             hidft_execute_config's with the same schedule, bit for bit.
+ *   order     HIDFT_GROUP_ORDER_LARGEST_FIRST: packs by size, largest first,
+ *             so the persistent blocks take them in that order;
+ *             _ALTERNATE: the blocks take, in alternate rounds, the largest
+ *             and the smallest packs left (a block whose first pack is long
+ *             gets a short second one).  The order changes no result.
+ * hidft_group_set_config re-packs the group's instances and uploads the new
+ * descriptor list on `stream` (waiting for it); it must not overlap an
+ * execution of the group.  hidft_group_autotune times every configuration
+ * (two warm-up and `reps` timed launches each, in two interleaved rounds,
+ * the better round counting), leaves the group in the fastest one and
+ * returns it with its mean launch time.  The group's samples are
+ * transformed by the timed launches (its outputs are overwritten).
+ * Errors: INVALID_ARGUMENT (NULL, unknown schedule or order, reps == 0,
+ * another current device), DEVICE for upload or timing failures.
+ */
+#define HIDFT_GROUP_ORDER_LARGEST_FIRST 0u
+#define HIDFT_GROUP_ORDER_ALTERNATE 1u
+typedef struct hidft_group_config {
+  uint32_t schedule;  /* HIDFT_SCHED_DEFAULT, _SHORT_FIRST or _SHORT_LAST */
+  uint32_t order;     /* HIDFT_GROUP_ORDER_* */
+} hidft_group_config;
+
+hidft_status hidft_group_set_config(hidft_group group, const hidft_group_config* config,
+                                    void* stream);
+hidft_status hidft_group_get_config(hidft_group group, hidft_group_config* config);
+hidft_status hidft_group_autotune(hidft_group group, uint32_t reps, void* stream,
+                                  hidft_group_config* best, double* best_us);
+
+/*
  * Request server (continuous batching).
  *
  * Clients submit requests -- (N = 2^log2_n, J, k host samples on I_r in

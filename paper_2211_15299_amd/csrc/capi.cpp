@@ -22,6 +22,8 @@ struct hidft_group_s {
   hidft::GroupPack* d_packs = nullptr;
   hidft::GroupSlot* d_slots = nullptr;
   size_t device_bytes = 0;
+  std::vector<std::pair<uint32_t, hidft::GroupSlot>> inst;  // for re-packing
+  hidft_group_config cfg{HIDFT_SCHED_DEFAULT, HIDFT_GROUP_ORDER_LARGEST_FIRST};
 };
 
 namespace {
@@ -167,7 +169,8 @@ hidft_status set_error(hidft_status st, const std::string& msg) {
 hidft_status hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
 
 void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
-                    std::vector<GroupPack>* packs, std::vector<GroupSlot>* slots) {
+                    std::vector<GroupPack>* packs, std::vector<GroupSlot>* slots,
+                    bool short_first, uint32_t snake_rounds) {
   std::vector<uint64_t> per_size(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
   for (const auto& x : inst) per_size[x.first]++;
   std::vector<uint64_t> next(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
@@ -185,11 +188,31 @@ void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
     for (uint64_t first = 0; first < per_size[s]; first += per) {
       GroupPack pk;
       pk.first_slot = (uint32_t)(off + first);
-      pk.log2_k = (uint16_t)s;
+      pk.log2_k = (uint16_t)(s | (short_first ? GROUP_SHORT_FIRST : 0));
       pk.n_slots = (uint16_t)std::min<uint64_t>(per, per_size[s] - first);
       packs->push_back(pk);
     }
     off += per_size[s];
+  }
+  if (snake_rounds > 0 && packs->size() > snake_rounds) {
+    // Round r of the grid takes packs [r G, (r + 1) G) of the new list;
+    // rounds alternate between the largest and the smallest packs left.
+    std::vector<GroupPack> out;
+    out.reserve(packs->size());
+    size_t lo = 0, hi = packs->size();
+    for (uint32_t r = 0; lo < hi; ++r) {
+      const size_t n = std::min<size_t>(snake_rounds, hi - lo);
+      if (r % 2 == 0) {
+        for (size_t i = 0; i < n; ++i) out.push_back((*packs)[lo + i]);
+        lo += n;
+      } else {
+        // smallest first, so that block b (whose first pack was among the
+        // largest) gets one of the smallest
+        for (size_t i = 0; i < n; ++i) out.push_back((*packs)[hi - 1 - i]);
+        hi -= n;
+      }
+    }
+    packs->swap(out);
   }
 }
 
@@ -499,6 +522,7 @@ hidft_status hidft_group_create(const hidft_work* items, uint64_t n_items, void*
     g->device = device;
     g->n_instances = n_inst;
     g->n_packs = (uint32_t)packs.size();
+    g->inst = std::move(inst);
     const size_t pack_bytes = packs.size() * sizeof(hidft::GroupPack);
     const size_t slot_bytes = slots.size() * sizeof(hidft::GroupSlot);
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -537,6 +561,106 @@ hidft_status hidft_group_execute(hidft_group g, void* stream) {
                 g->device);
   e = hidft::launch_grouped(g->d_packs, g->n_packs, g->d_slots, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hidft_group_execute: kernel launch");
+  return ok();
+}
+
+hidft_status hidft_group_set_config(hidft_group g, const hidft_group_config* cfg,
+                                    void* stream) {
+  if (!g || !cfg) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_set_config: NULL argument");
+  if (cfg->schedule > HIDFT_SCHED_SHORT_LAST)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_set_config: unknown schedule %u",
+                cfg->schedule);
+  if (cfg->order > HIDFT_GROUP_ORDER_ALTERNATE)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_set_config: unknown order %u", cfg->order);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hidft_group_set_config");
+  if (dev != g->device)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_set_config: group lives on device %d",
+                g->device);
+  uint32_t rounds = 0;
+  if (cfg->order == HIDFT_GROUP_ORDER_ALTERNATE &&
+      (e = hidft::grouped_grid(&rounds)) != hipSuccess)
+    return hip_fail(e, "hidft_group_set_config: grid");
+  try {
+    std::vector<hidft::GroupPack> packs;
+    std::vector<hidft::GroupSlot> slots;
+    hidft::pack_instances(g->inst, &packs, &slots, cfg->schedule == HIDFT_SCHED_SHORT_FIRST,
+                          rounds);
+    // The same packs and slots as at creation, in another order or with the
+    // schedule flag: the device arrays keep their sizes.
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((e = hipMemcpyAsync(g->d_packs, packs.data(), packs.size() * sizeof(hidft::GroupPack),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(g->d_slots, slots.data(), slots.size() * sizeof(hidft::GroupSlot),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return hip_fail(e, "hidft_group_set_config: descriptor upload");
+  } catch (const std::bad_alloc&) {
+    return fail(HIDFT_ERR_OUT_OF_MEMORY, "hidft_group_set_config: host allocation failed");
+  }
+  g->cfg = *cfg;
+  return ok();
+}
+
+hidft_status hidft_group_get_config(hidft_group g, hidft_group_config* cfg) {
+  if (!g || !cfg) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_get_config: NULL argument");
+  *cfg = g->cfg;
+  return ok();
+}
+
+hidft_status hidft_group_autotune(hidft_group g, uint32_t reps, void* stream,
+                                  hidft_group_config* best, double* best_us) {
+  if (!g || !best) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_autotune: NULL argument");
+  if (reps == 0) return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_autotune: reps must be positive");
+  const hidft_group_config cands[] = {
+      {HIDFT_SCHED_SHORT_LAST, HIDFT_GROUP_ORDER_LARGEST_FIRST},
+      {HIDFT_SCHED_SHORT_FIRST, HIDFT_GROUP_ORDER_LARGEST_FIRST},
+      {HIDFT_SCHED_SHORT_LAST, HIDFT_GROUP_ORDER_ALTERNATE},
+      {HIDFT_SCHED_SHORT_FIRST, HIDFT_GROUP_ORDER_ALTERNATE}};
+  constexpr int NC = (int)(sizeof cands / sizeof cands[0]);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e, "hidft_group_autotune: hipEventCreate");
+  }
+  double us[NC];
+  for (double& x : us) x = 1e300;
+  hidft_status rs = HIDFT_OK;
+  // Two interleaved rounds; each candidate keeps its better one.
+  for (int round = 0; round < 2 && rs == HIDFT_OK; ++round) {
+    for (int i = 0; i < NC && rs == HIDFT_OK; ++i) {
+      if ((rs = hidft_group_set_config(g, &cands[i], stream)) != HIDFT_OK) break;
+      for (int w = 0; w < 2 && rs == HIDFT_OK; ++w) rs = hidft_group_execute(g, stream);
+      if (rs != HIDFT_OK) break;
+      float ms = 0.f;
+      if ((e = hipEventRecord(e0, st)) != hipSuccess) {
+        rs = hip_fail(e, "hidft_group_autotune: hipEventRecord");
+        break;
+      }
+      for (uint32_t r = 0; r < reps && rs == HIDFT_OK; ++r) rs = hidft_group_execute(g, stream);
+      if (rs != HIDFT_OK) break;
+      if ((e = hipEventRecord(e1, st)) != hipSuccess ||
+          (e = hipEventSynchronize(e1)) != hipSuccess ||
+          (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+        rs = hip_fail(e, "hidft_group_autotune: timing");
+        break;
+      }
+      us[i] = std::min(us[i], 1e3 * (double)ms / reps);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rs != HIDFT_OK) return rs;
+  int ib = 0;
+  for (int i = 1; i < NC; ++i)
+    if (us[i] < us[ib]) ib = i;
+  if ((rs = hidft_group_set_config(g, &cands[ib], stream)) != HIDFT_OK) return rs;
+  *best = cands[ib];
+  if (best_us) *best_us = us[ib];
   return ok();
 }
 

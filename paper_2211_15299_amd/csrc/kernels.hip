@@ -1129,12 +1129,13 @@ __device__ __forceinline__ P* uniform_ptr(P* p) {
   return reinterpret_cast<P*>(((uint64_t)hi << 32) | lo);
 }
 
-// One pack of 2^S-point instances.  Not inlined: each size gets a register
-// allocation of its own instead of one shared by the whole switch.
-template <int S>
+// One pack of 2^S-point instances, short group first or last (SC).  Not
+// inlined: each size gets a register allocation of its own instead of one
+// shared by the whole switch.
+template <int S, int SC>
 __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restrict__ slots,
                                                        int n_slots, float2* lds) {
-  using Sh = FusedShape<S>;
+  using Sh = FusedShape<S, SC, 4>;
   constexpr int R = Sh::R, T = Sh::T;
   constexpr uint32_t K = 1u << S;
   const int tid = threadIdx.x;
@@ -1145,7 +1146,7 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
   // slot 0's tables (every pack has at least one slot) and store nothing.
   GroupSlot d = slots[valid ? slot : 0];
   float2 v[R];
-  ThreadState<S, SCHED_SHORT_LAST, 4> unused;
+  ThreadState<S, SC, 4> unused;
   const MfmaOps<PREC_FP32> no_mfma;
   if constexpr (T >= 64) {
     // A slot spans whole wavefronts: its descriptor is wave-uniform.
@@ -1165,15 +1166,15 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
     mem.tw = make_rsrc(d.tw, (K > 1 ? K - 1 : 1) * 8u);
     mem.src = make_rsrc(d.src, K * 2u);
     mem.out = make_rsrc(d.out, K * 8u);
-    transform_signal<S, SCHED_SHORT_LAST, 4, PREC_FP32, false>(v, lds, slot, tau, valid, mem,
-                                                             d.scale, unused, no_mfma);
+    transform_signal<S, SC, 4, PREC_FP32, false>(v, lds, slot, tau, valid, mem, d.scale, unused,
+                                               no_mfma);
   } else {
 #pragma unroll
     for (int c = 0; c < R; ++c)
       v[c] = valid ? load_stream(d.in + c * T + tau) : make_float2(0.f, 0.f);
     const FlatMem mem{d.tw, d.src, d.out, K};
-    transform_signal<S, SCHED_SHORT_LAST, 4, PREC_FP32, false>(v, lds, slot, tau, valid, mem,
-                                                             d.scale, unused, no_mfma);
+    transform_signal<S, SC, 4, PREC_FP32, false>(v, lds, slot, tau, valid, mem, d.scale, unused,
+                                               no_mfma);
   }
 }
 
@@ -1184,15 +1185,26 @@ hidft_grouped_kernel(const GroupPack* __restrict__ packs, uint32_t n_packs,
   for (uint32_t p = blockIdx.x; p < n_packs; p += gridDim.x) {
     const GroupPack pk = packs[p];
     const GroupSlot* sl = slots + pk.first_slot;
+    // Sizes with two schedules (S > 4, 4 does not divide S) have a body for
+    // each; the others ignore the flag.
     switch (pk.log2_k) {
-#define HIDFT_CASE(S) \
-  case S:             \
-    grouped_pack<S>(sl, (int)pk.n_slots, lds); \
+#define HIDFT_ONE(S)                                          \
+  case S:                                                     \
+  case S | GROUP_SHORT_FIRST:                                 \
+    grouped_pack<S, SCHED_SHORT_FIRST>(sl, (int)pk.n_slots, lds); \
     break;
-      HIDFT_CASE(0) HIDFT_CASE(1) HIDFT_CASE(2) HIDFT_CASE(3) HIDFT_CASE(4) HIDFT_CASE(5)
-      HIDFT_CASE(6) HIDFT_CASE(7) HIDFT_CASE(8) HIDFT_CASE(9) HIDFT_CASE(10) HIDFT_CASE(11)
-      HIDFT_CASE(12) HIDFT_CASE(13) HIDFT_CASE(14)
-#undef HIDFT_CASE
+#define HIDFT_TWO(S)                                          \
+  case S:                                                     \
+    grouped_pack<S, SCHED_SHORT_LAST>(sl, (int)pk.n_slots, lds); \
+    break;                                                    \
+  case S | GROUP_SHORT_FIRST:                                 \
+    grouped_pack<S, SCHED_SHORT_FIRST>(sl, (int)pk.n_slots, lds); \
+    break;
+      HIDFT_ONE(0) HIDFT_ONE(1) HIDFT_ONE(2) HIDFT_ONE(3) HIDFT_ONE(4) HIDFT_TWO(5)
+      HIDFT_TWO(6) HIDFT_TWO(7) HIDFT_ONE(8) HIDFT_TWO(9) HIDFT_TWO(10) HIDFT_TWO(11)
+      HIDFT_ONE(12) HIDFT_TWO(13) HIDFT_TWO(14)
+#undef HIDFT_ONE
+#undef HIDFT_TWO
       default:
         break;
     }
@@ -1204,9 +1216,7 @@ int grouped_slots_per_pack(uint32_t s) {
   return GROUPED_THREADS >> (s > 4 ? s - 4 : 0);
 }
 
-hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,
-                          hipStream_t stream) {
-  if (n_packs == 0) return hipSuccess;
+hipError_t grouped_grid(uint32_t* blocks) {
   static int max_grid = 0;  // benign race: every thread computes the same value
   const size_t lds_bytes = (size_t)GROUPED_LDS_SLOTS * sizeof(float2);
   if (max_grid == 0) {
@@ -1225,7 +1235,18 @@ hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const Grou
       return e;
     max_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
   }
-  const unsigned grid = n_packs < (uint32_t)max_grid ? n_packs : (unsigned)max_grid;
+  *blocks = (uint32_t)max_grid;
+  return hipSuccess;
+}
+
+hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,
+                          hipStream_t stream) {
+  if (n_packs == 0) return hipSuccess;
+  uint32_t max_grid = 0;
+  hipError_t e = grouped_grid(&max_grid);
+  if (e != hipSuccess) return e;
+  const size_t lds_bytes = (size_t)GROUPED_LDS_SLOTS * sizeof(float2);
+  const unsigned grid = n_packs < max_grid ? n_packs : max_grid;
   hipLaunchKernelGGL(hidft_grouped_kernel, dim3(grid), dim3(GROUPED_THREADS), lds_bytes, stream,
                      d_packs, n_packs, d_slots);
   return hipGetLastError();

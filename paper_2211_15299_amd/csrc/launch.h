@@ -74,8 +74,15 @@ struct GroupPack {
   uint16_t n_slots;
 };
 
+// GroupPack::log2_k flag: run the pack with the short group first (sizes
+// with two schedules); without it, the short group is last.
+constexpr uint16_t GROUP_SHORT_FIRST = 0x100;
+
 // Instances of size 2^s that one pack holds (the block's 1024 threads).
 int grouped_slots_per_pack(uint32_t s);
+
+// Blocks of the persistent grouped launch on the current device.
+hipError_t grouped_grid(uint32_t* blocks);
 
 // Grouped persistent launch over n_packs packs.
 hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,

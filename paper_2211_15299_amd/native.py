@@ -69,6 +69,9 @@ SIGNATURES = [
     ("hidft_group_create", ctypes.c_int, [_vp, _u64, _vp, _pp]),
     ("hidft_group_execute", ctypes.c_int, [_vp, _vp]),
     ("hidft_group_destroy", ctypes.c_int, [_vp]),
+    ("hidft_group_set_config", ctypes.c_int, [_vp, _vp, _vp]),
+    ("hidft_group_get_config", ctypes.c_int, [_vp, _vp]),
+    ("hidft_group_autotune", ctypes.c_int, [_vp, _u32, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     ("hidft_group_get_info", ctypes.c_int, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                                             ctypes.POINTER(ctypes.c_size_t)]),
     ("hidft_server_create", ctypes.c_int, [_vp, _pp]),
@@ -155,6 +158,18 @@ def _stream_handle(stream) -> Optional[int]:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+class GroupConfig(ctypes.Structure):
+    """hidft_group_config: schedule and pack order of a grouped launch."""
+    _fields_ = [("schedule", ctypes.c_uint32), ("order", ctypes.c_uint32)]
+
+    def __repr__(self):
+        return f"GroupConfig(schedule={self.schedule}, order={self.order})"
+
+
+GROUP_ORDER_LARGEST_FIRST = 0
+GROUP_ORDER_ALTERNATE = 1
 
 
 class ExecConfig(ctypes.Structure):
@@ -340,6 +355,26 @@ class Group:
 
     def execute(self, stream=None) -> None:
         _check(lib().hidft_group_execute(self._h, _stream_handle(stream)))
+
+    def set_config(self, schedule: int, order: int, stream=None) -> None:
+        cfg = GroupConfig(schedule, order)
+        _check(lib().hidft_group_set_config(self._h, ctypes.cast(ctypes.byref(cfg), ctypes.c_void_p),
+                                            _stream_handle(stream)))
+
+    def config(self) -> GroupConfig:
+        cfg = GroupConfig(0, 0)
+        _check(lib().hidft_group_get_config(self._h, ctypes.cast(ctypes.byref(cfg), ctypes.c_void_p)))
+        return cfg
+
+    def autotune(self, reps: int = 10, stream=None):
+        """Times every launch configuration, keeps the fastest; returns it and
+        its mean launch time in microseconds."""
+        cfg = GroupConfig(0, 0)
+        us = ctypes.c_double(0.0)
+        _check(lib().hidft_group_autotune(self._h, reps, _stream_handle(stream),
+                                          ctypes.cast(ctypes.byref(cfg), ctypes.c_void_p),
+                                          ctypes.byref(us)))
+        return cfg, us.value
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

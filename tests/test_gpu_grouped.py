@@ -156,3 +156,63 @@ def test_group_argument_errors():
         native.Group([(plan, x.data_ptr(), plan.k - 1, x.data_ptr(), plan.k, 1)])
     with pytest.raises(native.HiDFTError):
         native.Group([])
+
+
+def test_group_configurations_and_autotune():
+    """Every launch configuration of a group (short group first or last, packs
+    largest first or alternating) gives each instance exactly the result of
+    hidft_execute_config with the same schedule; the order changes nothing.
+    More packs than the persistent grid, so the alternating order reorders.
+    The autotuner leaves the group in one of the configurations."""
+    rng = rng_for(3, 7000)
+    sizes = [14] * 200 + [13] * 200 + [12] * 100 + [s for s in range(0, 12) for _ in range(4)]
+    plans, xs, ys = [], [], []
+    for s in sizes:
+        M = max(s, 1) + int(rng.integers(0, 8))
+        plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
+        plans.append(plan)
+        xs.append(torch.from_numpy(sample_values(M, plan.k, 1, rng)[0]).cuda())
+        ys.append(torch.empty(plan.k, dtype=torch.complex64, device="cuda"))
+    grp = native.Group([(p, x.data_ptr(), p.k, y.data_ptr(), p.k, 1)
+                        for p, x, y in zip(plans, xs, ys)])
+    assert grp.n_packs > 256
+    _say(f"group: {grp.n_instances} instances, {grp.n_packs} packs")
+    want = {}
+    for sched in (native.SCHED_SHORT_LAST, native.SCHED_SHORT_FIRST):
+        out = []
+        for p, x in zip(plans, xs):
+            z = torch.empty(p.k, dtype=torch.complex64, device="cuda")
+            p.execute_ptr(x.data_ptr(), p.k, z.data_ptr(), p.k, 1,
+                          config=native.ExecConfig(native.PREC_FP32, sched, 16, 0))
+            out.append(z)
+        torch.cuda.synchronize()
+        want[sched] = [z.cpu().numpy() for z in out]
+
+    def check(sched, what):
+        torch.cuda.synchronize()
+        bad = sum(not np.array_equal(y.cpu().numpy(), w) for y, w in zip(ys, want[sched]))
+        assert bad == 0, f"{what}: {bad} instances differ"
+
+    for sched in (native.SCHED_SHORT_LAST, native.SCHED_SHORT_FIRST):
+        for order in (native.GROUP_ORDER_LARGEST_FIRST, native.GROUP_ORDER_ALTERNATE):
+            for y in ys:
+                y.fill_(complex(np.nan, np.nan))
+            grp.set_config(sched, order)
+            assert (grp.config().schedule, grp.config().order) == (sched, order)
+            grp.execute()
+            check(sched, f"schedule {sched}, order {order}")
+    cfg, us = grp.autotune(reps=3)
+    _say(f"group autotune: schedule {cfg.schedule}, order {cfg.order}, {us:.1f} us")
+    assert us > 0 and cfg.schedule in (native.SCHED_SHORT_LAST, native.SCHED_SHORT_FIRST)
+    assert (grp.config().schedule, grp.config().order) == (cfg.schedule, cfg.order)
+    for y in ys:
+        y.fill_(complex(np.nan, np.nan))
+    grp.execute()
+    check(cfg.schedule, "tuned")
+    with pytest.raises(native.HiDFTError):
+        grp.set_config(7, 0)
+    with pytest.raises(native.HiDFTError):
+        grp.set_config(0, 5)
+    grp.close()
+    for p in plans:
+        p.close()
