@@ -1403,13 +1403,16 @@ sas_apply_lds_kernel(const float2* __restrict__ y, uint32_t n_nodes, uint32_t mu
       const cplx64* m = inv + row[i];
       double ar = 0.0, ai = 0.0;
       if constexpr (MU > 0) {
+        // rows read unconditionally (padded table), terms j < mu(v) summed
+        cplx64 w[MU];
+#pragma unroll
+        for (int j = 0; j < MU; ++j) w[j] = m[j];
 #pragma unroll
         for (int j = 0; j < MU; ++j) {
           if ((uint32_t)j < cnt[i]) {
             const float2 q = sm[j * n_nodes + v];
-            const cplx64 w = m[j];
-            ar = fma(w.x, (double)q.x, fma(-w.y, (double)q.y, ar));
-            ai = fma(w.x, (double)q.y, fma(w.y, (double)q.x, ai));
+            ar = fma(w[j].x, (double)q.x, fma(-w[j].y, (double)q.y, ar));
+            ai = fma(w[j].x, (double)q.y, fma(w[j].y, (double)q.x, ai));
           }
         }
       } else {

@@ -105,6 +105,9 @@ hipError_t launch_sas_inverse(uint32_t n_nodes, const uint32_t* node_first,
 // of its inverse row, mu(v), 0} as uint4; required when the plan's
 // mu* n_nodes + k values fit in SAS_LDS_VALUES (one block per signal).
 constexpr uint32_t SAS_LDS_VALUES = 8192;  // 64 KB of complex64
+// Zero entries after the inverse table: the solve kernels read four entries
+// of every row whatever its length.
+constexpr uint32_t SAS_INV_PAD = 16;
 hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star, uint64_t batch,
                             uint32_t k, const uint32_t* elem_node, const uint32_t* node_first,
                             const uint32_t* node_count, const uint32_t* inv_off, const void* inv,

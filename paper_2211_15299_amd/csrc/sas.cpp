@@ -108,10 +108,12 @@ hidft_status upload(hidft_sas p, hipStream_t st) {
   uint8_t* d_den = nullptr;
   uint64_t* d_elem_val = nullptr;
   size_t total = 0, tmp = 0;
-  const size_t inv_bytes = (size_t)std::max<uint64_t>(inv_entries, 1) * 16;
+  const size_t inv_bytes = (size_t)(inv_entries + hidft::SAS_INV_PAD) * 16;
   hidft_status status = HIDFT_OK;
   if ((e = hipMalloc(&p->d_tw, (ntw ? ntw : 1) * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&p->d_inv, inv_bytes)) != hipSuccess ||
+      (e = hipMemsetAsync(static_cast<char*>(p->d_inv) + inv_entries * 16, 0,
+                          hidft::SAS_INV_PAD * 16, st)) != hipSuccess ||
       (e = upload_vec(&d_num, num, st, &tmp)) != hipSuccess ||
       (e = upload_vec(&d_den, den, st, &tmp)) != hipSuccess ||
       (e = upload_vec(&d_elem_val, elem_val, st, &tmp)) != hipSuccess ||
