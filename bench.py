@@ -99,7 +99,7 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the batched "
               "transform shards by splitting the batch across GPUs with no exchange; "
-              "multi-GPU runs are not part of this build.", file=sys.stderr)
+              "this benchmark runs on one GPU.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -54,7 +54,7 @@ typedef enum hidft_status {
   HIDFT_ERR_NOT_HOMOGENEOUS = 5,    /* k = 2^s but J has more than s pivots */
   HIDFT_ERR_OUT_OF_MEMORY = 6,      /* host or device allocation failed */
   HIDFT_ERR_DEVICE = 7,             /* a HIP runtime call failed */
-  HIDFT_ERR_UNSUPPORTED = 8         /* valid request outside what this build executes */
+  HIDFT_ERR_UNSUPPORTED = 8         /* valid request outside what the library executes */
 } hidft_status;
 
 /* Opaque plan: immutable after creation; safe to execute concurrently from
@@ -62,7 +62,7 @@ typedef enum hidft_status {
  * use it are still in flight is the caller's error: synchronise first. */
 typedef struct hidft_plan_s* hidft_plan;
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define HIDFT_MAX_LOG2_N 63u        /* N = 2^M with M <= 63 */
 #define HIDFT_MAX_LOG2_K_HOST 26u   /* planner (HOST_ONLY plans): k <= 2^26 */
 #define HIDFT_MAX_LOG2_K_DEVICE 14u /* executor: one signal is staged whole in LDS */
