@@ -107,3 +107,22 @@ def test_rejects():
     with pytest.raises(native.HiDFTError) as ei:       # refused before any device call
         plan.execute_ptr(8, 64, 8 + 4096, 64, 1, 8 + 8192)
     assert ei.value.status_name == "HIDFT_ERR_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("M", [3, 5, 8, 11, 14])
+def test_powers_of_two_support(M):
+    """J* = {1, 2, 4, ..., 2^{M-1}} (Sec. X).  Two elements 2^i > 2^j first
+    meet at level j (2^i - 2^j = 2^j (2^{i-j} - 1), odd cofactor), so the
+    pivots are {0, ..., M-2}: M - 1 splits separate the M elements (the
+    paper writes {0, ..., M-1}; every internal level is a pivot).  J* is not
+    homogeneous, and Shift-and-Sample with r = all pivots isolates each
+    element (mu* = 1) only with 2^{M-1} = N/2 samples, far beyond the
+    k^2 = M^2 work of the dense submatrix method, as the paper concludes."""
+    J = [1 << i for i in range(M)]
+    assert oracle.pivots(M, J) == list(range(M - 1))
+    piv, hom = native.analyze(M, J)
+    assert piv == list(range(M - 1)) and not hom
+    plan = native.SASPlan(M, J, pivots=piv, host_only=True)
+    assert plan.mu_max == 1
+    assert plan.samples_per_signal == 1 << (M - 1)
+    assert sorted(plan.samples().tolist()) == sorted(oracle.sample_pattern_recursive(M, piv))
