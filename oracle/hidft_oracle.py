@@ -10,7 +10,7 @@ Everything here is written from the paper's definitions, slowly and plainly:
 * index work (pivots, the homogeneity predicate, the pivoted sampling pattern,
   the plan orders and the butterfly twiddle exponents) follows the definitions
   of Sections VI-VIII with exact integer arithmetic;
-* coefficients are obtained by the paper's "trivial" route of Section V-A:
+* coefficients are obtained by the paper's simplest route of Section V-A (a dense solve):
   build the k x k submatrix F^{-1}(I, J) of the inverse DFT and solve the
   linear system f_I = F^{-1}(I, J) c by LU with partial pivoting, in complex128.
   For large k the algebraically identical adjoint form c = (N/k) F(J, I) f_I is
