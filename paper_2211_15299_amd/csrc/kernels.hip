@@ -82,8 +82,9 @@ __device__ __forceinline__ void lds_barrier() {
 // signal's sample loads and at 1 while it gathers and stores the
 // coefficients, and at 0 during the transform, so the memory requests of
 // one block go out ahead of the other blocks' arithmetic.  Measured: 2^12
-// points 50.0 -> 48.7 us, 2^14 points 66.1 -> 63.5 us; 2^13 and the grouped
-// launch unchanged.
+// points 50.0 -> 48.7 us, 2^14 points 66.1 -> 63.5 us, the inverse map at
+// 2^12 points 51.7 -> 50.7 us; 2^13 unchanged.  The grouped launch (slower
+// with it) and the Shift-and-Sample loads (unchanged) do not use it.
 //
 // Occupancy of a kernel: blocks resident per CU and the CU count, queried
 // once per kernel (the first call also raises its dynamic LDS limit).
@@ -878,18 +879,24 @@ hidft_inverse_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __res
   const int slot = tid / T;
   const int tau = tid - slot * T;
   float2* L = lds + slot * Sh::PADK;
+  // Wave priorities as in the forward kernel: 2 while issuing loads, 1 for
+  // the stores, 0 for the transform.
   auto store = [&](const float2 (&v)[R], uint64_t sig) {
+    __builtin_amdgcn_s_setprio(1);
     if (sig < batch) {
       float2* orow = out + sig * (uint64_t)ld_out;
 #pragma unroll
       for (int c = 0; c < R; ++c)
         store_stream(orow + c * T + tau, make_float2(v[c].x * scale, v[c].y * scale));
     }
+    __builtin_amdgcn_s_setprio(0);
   };
   if constexpr (Sh::BIG) {
     const uint64_t sig = blockIdx.x;
     float2 v[R];
+    __builtin_amdgcn_s_setprio(2);
     load_group1<S, SCHED, 4, PREC_FP32>(v, in, ld_in, sig, batch);
+    __builtin_amdgcn_s_setprio(0);
     ThreadState<S, SCHED, 4> unused;
     const FlatMem mem{tw, src, nullptr, 0};
     inverse_signal<S, SCHED, false>(v, L, tau, mem, unused);
@@ -906,8 +913,10 @@ hidft_inverse_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __res
       float2 v[R];
 #pragma unroll
       for (int c = 0; c < R; ++c) v[c] = vn[c];
+      __builtin_amdgcn_s_setprio(2);
       if (grp + gridDim.x < n_groups)
         load_group1<S, SCHED, 4, PREC_FP32>(vn, in, ld_in, (grp + gridDim.x) * SPB, batch);
+      __builtin_amdgcn_s_setprio(0);
       inverse_signal<S, SCHED, true>(v, L, tau, mem, ts);
       store(v, grp * SPB + slot);
       lds_barrier();  // the next group of signals overwrites these LDS slots
