@@ -269,3 +269,20 @@ def test_execute_argument_errors():
     assert status(0, k, y.data_ptr(), k, 1) == 1                     # null
     assert status(x.data_ptr(), k, y.data_ptr(), k, 4) == 0
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("M,s", [(40, 10), (62, 10), (63, 12)])
+def test_largest_N_recovery(M, s):
+    """N up to 2^63 (the ABI's limit): seeded coefficients recovered from
+    samples the oracle synthesised with exact modular phases; the twiddle
+    arguments m / 2^d then carry more than 53 bits, which FP64 rounds far
+    below FP32 resolution."""
+    rng = rng_for(1, 1000 + M)
+    sup = homogeneous_support(M, s, rng)
+    J = sup.J.tolist()
+    plan = native.Plan(M, J)
+    c = complex_normal((3, len(J)), rng)
+    f = oracle.synthesize_samples(M, J, c, plan.samples().tolist())
+    got = _run(plan, f)
+    _check(got, c, f"N=2^{M}, k=2^{s}")
+    plan.close()
