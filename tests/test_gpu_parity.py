@@ -286,3 +286,32 @@ def test_largest_N_recovery(M, s):
     got = _run(plan, f)
     _check(got, c, f"N=2^{M}, k=2^{s}")
     plan.close()
+
+
+@pytest.mark.parametrize("M", [1, 4, 9, 12, 14])
+def test_full_support_is_the_fft(M):
+    """J = Z_N in a shuffled caller order (k = N, the degenerate case where
+    the sample set is the whole signal): the coefficients are numpy's FFT
+    of the signal, read in the caller's order."""
+    rng = rng_for(2001, M)
+    N = 1 << M
+    J = rng.permutation(N).tolist()
+    plan = native.Plan(M, J)
+    assert plan.samples().tolist() == list(range(N))
+    f = complex_normal((3, N), rng)
+    got = _run(plan, f)
+    want = np.fft.fft(f, axis=1)[:, J]
+    _check(got, want, f"J = Z_N, N=2^{M}")
+    plan.close()
+
+
+def test_single_coefficient_at_the_largest_N():
+    """k = 1 (Algorithm 1's base case): the coefficient is N f(0), here with
+    N = 2^63 and the one sample at 0."""
+    rng = rng_for(2002, 0)
+    plan = native.Plan(63, [int(rng.integers(0, 1 << 62)) * 2 + 1])
+    assert plan.samples().tolist() == [0]
+    f = complex_normal((5, 1), rng) * 2.0 ** -63
+    got = _run(plan, f)
+    _check(got, f * 2.0 ** 63, "k = 1, N = 2^63")
+    plan.close()
