@@ -335,3 +335,37 @@ def test_sas_single_element_nodes_need_no_workspace():
     got = y.cpu().numpy().astype(np.complex128)
     assert np.max(oracle.rel_l2(got, c)) <= 1e-5
     plan.close()
+
+
+def test_sas_degenerate_cases():
+    """r = () (no pivots: one node holds all of J; samples f(0..mu*-1)):
+    for J = {0, N/4, N/2, 3N/4} + t the leaf system is a 4-point DFT.  And a
+    homogeneous J with r = all its pivots (mu* = 1) gives exactly the
+    Hi-DFT of the plain plan, bit for bit."""
+    rng = rng_for(821, 0)
+    M = 10
+    t = int(rng.integers(0, 1 << M))
+    J = [(t + q * (1 << (M - 2))) % (1 << M) for q in range(4)]
+    plan = native.SASPlan(M, J, pivots=[])
+    assert plan.s == 0 and plan.mu_max == 4 and plan.n_nodes == 1
+    assert plan.samples().tolist() == [0, 1, 2, 3]
+    c = complex_normal((3, 4), rng)
+    got = _sas_run(plan, oracle.synthesize_samples(M, J, c, [0, 1, 2, 3]))
+    assert np.max(oracle.rel_l2(got, c)) <= 1e-6
+    plan.close()
+    M = 16
+    J = homogeneous_support(M, 9, rng).J.tolist()
+    P, hom = native.analyze(M, J)
+    assert hom
+    sas = native.SASPlan(M, J, pivots=P)
+    hi = native.Plan(M, J)
+    assert sas.mu_max == 1 and sas.samples().tolist() == hi.samples().tolist()
+    x = torch.from_numpy(complex_normal((6, hi.k), rng).astype(np.complex64)).cuda()
+    y1 = torch.empty_like(x)
+    y2 = torch.empty_like(x)
+    sas.execute_ptr(x.data_ptr(), hi.k, y1.data_ptr(), hi.k, 6, 0)
+    hi.execute_ptr(x.data_ptr(), hi.k, y2.data_ptr(), hi.k, 6)
+    torch.cuda.synchronize()
+    assert torch.equal(y1.view(torch.float32), y2.view(torch.float32))
+    sas.close()
+    hi.close()
