@@ -24,6 +24,7 @@ Prints one JSON line.  Modes for profiling runs:
   --mode precision the precision configuration (N = 2^22, k = 2^14, 1024
                    signals, |c| log-uniform on [1e-3, 1e3]): FP32 butterflies
                    against the FP16 / BF16 split-precision matrix-core group
+                   (radix-16 and radix-32 first groups)
   --mode inverse   the inverse map (coefficients -> samples) on the headline
                    workload's shape
   --mode sas       Shift-and-Sample on a random half of a homogeneous set
@@ -480,6 +481,15 @@ PRECISION_WORKLOAD = dict(workload="precision: N=2^22, k=2^14, 1024 signals, |c|
                           batch=1024)
 
 
+def precision_variants(native):
+    """(name, precision, radix) of the group-1 arithmetics compared on the
+    precision workload: FP32 butterflies and the two matrix-core splits, with
+    a radix-16 and a radix-32 first group."""
+    return (("fp32", native.PREC_FP32, 16), ("f16x2", native.PREC_F16X2, 16),
+            ("bf16x3", native.PREC_BF16X3, 16), ("fp32_r32", native.PREC_FP32, 32),
+            ("f16x2_r32", native.PREC_F16X2, 32), ("bf16x3_r32", native.PREC_BF16X3, 32))
+
+
 def _precision_setup(native, stream):
     from workloads import homogeneous_support, rng_for
     rng = rng_for(4, 0)
@@ -508,9 +518,8 @@ def precision_bench(args, native, torch, stream, steps=None):
     steps = steps or args.steps
     out = {"config": PRECISION_WORKLOAD, "sets": sets, "steps": steps}
     ref = None
-    for name, prec in (("fp32", native.PREC_FP32), ("f16x2", native.PREC_F16X2),
-                       ("bf16x3", native.PREC_BF16X3)):
-        cfg = native.ExecConfig(prec, native.SCHED_DEFAULT, 0, 0)
+    for name, prec, radix in precision_variants(native):
+        cfg = native.ExecConfig(prec, native.SCHED_DEFAULT, radix, 0)
         for i in range(3):
             plan.execute_ptr(xs[i % sets].data_ptr(), k, ys[i % sets].data_ptr(), k, batch,
                              stream, config=cfg)
@@ -555,9 +564,8 @@ def precision_vs_oracle(native, torch, stream, n_exact=8):
     x = torch.from_numpy(f.astype(np.complex64)).cuda()
     out = {"instances": n_exact, "synthesis": "oracle.synthesize_samples_fft (FP64)",
            "synthesis_s": synth_s}
-    for name, prec in (("fp32", native.PREC_FP32), ("f16x2", native.PREC_F16X2),
-                       ("bf16x3", native.PREC_BF16X3)):
-        y = plan.execute(x, config=native.ExecConfig(prec, native.SCHED_DEFAULT, 0, 0),
+    for name, prec, radix in precision_variants(native):
+        y = plan.execute(x, config=native.ExecConfig(prec, native.SCHED_DEFAULT, radix, 0),
                          stream=stream)
         torch.cuda.synchronize()
         got = y.cpu().numpy().astype(np.complex128)

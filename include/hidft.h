@@ -184,9 +184,10 @@ hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in
 /*
  * Execution variants of the fused transform (hidft_execute_config).
  *
- * precision -- arithmetic of the first radix-16 group of stages (stages
+ * precision -- arithmetic of the first group of stages (radix 16: stages
  *   1..4 of Lemma 3, the recursion levels of the four lowest pivots, which
- *   form one fixed 16 x 16 matrix per plan); every other stage is FP32:
+ *   form one fixed 16 x 16 matrix per plan; radix 32: stages 1..5, one
+ *   32 x 32 matrix applied as four 16 x 16 blocks); every other stage is FP32:
  *   HIDFT_PREC_FP32   FP32 butterflies (the default).
  *   HIDFT_PREC_F16X2  matrix cores: samples and matrix split into two FP16
  *                     terms (samples scaled per column by a power of two),
@@ -194,7 +195,8 @@ hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in
  *   HIDFT_PREC_BF16X3 matrix cores: three-term BF16 split, six products
  *                     summed in FP32.
  *   The matrix is computed in FP64 on the device at plan creation and split
- *   there.  The matrix-core precisions need k >= 16.
+ *   there.  The matrix-core precisions need k >= 16 (radix 32: k >= 2^13
+ *   and the short group last).
  * schedule -- where the short group of stages goes when 4 does not divide
  *   s = log2 k (the transform runs in groups of four stages):
  *   HIDFT_SCHED_DEFAULT      SHORT_LAST (measured the faster grouping).
@@ -209,8 +211,10 @@ hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in
  *   The schedules compute the same stages in a different grouping; results
  *   agree to rounding.
  * radix -- stages per group (and points per thread): 0 = default (16),
- *   16, or 32 (FP32 and k >= 2^13 only: 13 = 3 + 5 + 5 stages, 14 = 4 + 5 + 5
- *   with SHORT_FIRST).  Like the schedule, changes the grouping only.
+ *   16, or 32 (k >= 2^13 only: 13 = 3 + 5 + 5 stages, 14 = 4 + 5 + 5 with
+ *   SHORT_FIRST, 5 + 5 + 3 and 5 + 5 + 4 with SHORT_LAST, the only grouping
+ *   of the matrix-core precisions at radix 32).  Like the schedule, changes
+ *   the grouping only.
  * blocks_per_cu -- for k <= 2^12 (persistent launches): at most this many
  *   resident workgroups per compute unit, 0 = as many as fit.  Ignored for
  *   larger k (one workgroup per signal).  Does not change results.
@@ -239,8 +243,8 @@ typedef struct hidft_exec_config {
  * hidft_execute is this call with {FP32, DEFAULT, 0, 0}.
  * Errors: as hidft_execute, plus INVALID_ARGUMENT for a NULL config or an
  * unknown precision, schedule or radix, and UNSUPPORTED for a matrix-core
- * precision with k < 16, or with SHORT_FIRST when 4 does not divide s, and
- * for radix 32 outside FP32 with k >= 2^13.
+ * precision with k < 16, or with SHORT_FIRST when the radix's stage count
+ * (4 or 5) does not divide s, and for radix 32 with k < 2^13.
  */
 hidft_status hidft_execute_config(hidft_plan plan, const hidft_exec_config* config,
                                   const void* d_samples, int64_t ld_in, void* d_coefs,

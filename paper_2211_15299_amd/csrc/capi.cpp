@@ -85,14 +85,17 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
     src[t] = static_cast<uint16_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
 
   const size_t ntw_alloc = ntw ? ntw : 1;
-  // The matrix-core group 1 (radix 16) needs its split matrix operands.
+  // The matrix-core group 1 needs its split matrix operands: radix 16 for
+  // k >= 16, and radix 32 after them for k >= 2^13.
   const bool with_amat = c.s >= 4;
+  const bool with_amat32 = c.s >= 13;
+  const size_t amat_bytes = hidft::AMAT_BYTES + (with_amat32 ? hidft::AMAT32_BYTES : 0);
   uint64_t* d_num = nullptr;
   uint8_t* d_den = nullptr;
   hidft_status st = HIDFT_OK;
   if ((e = hipMalloc(&p->d_tw, ntw_alloc * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&p->d_src, k * sizeof(uint16_t))) != hipSuccess ||
-      (with_amat && (e = hipMalloc(&p->d_amat, hidft::AMAT_BYTES)) != hipSuccess) ||
+      (with_amat && (e = hipMalloc(&p->d_amat, amat_bytes)) != hipSuccess) ||
       (e = hipMalloc(&d_num, ntw_alloc * sizeof(uint64_t))) != hipSuccess ||
       (e = hipMalloc(&d_den, ntw_alloc)) != hipSuccess) {
     st = hip_fail(e, "hipMalloc of plan tables");
@@ -107,7 +110,8 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
              hipSuccess) {
     st = hip_fail(e, "twiddle generation launch");
   } else if (with_amat &&
-             (e = hidft::launch_stage_matrix(d_num, d_den, p->d_amat, stream)) != hipSuccess) {
+             (e = hidft::launch_stage_matrix(d_num, d_den, p->d_amat, with_amat32, stream)) !=
+                 hipSuccess) {
     st = hip_fail(e, "stage matrix launch");
   } else if ((e = hipStreamSynchronize(stream)) != hipSuccess) {
     st = hip_fail(e, "hipStreamSynchronize after plan upload");
@@ -119,7 +123,7 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
     return st;
   }
   p->device_bytes =
-      ntw_alloc * sizeof(float2) + k * sizeof(uint16_t) + (with_amat ? hidft::AMAT_BYTES : 0);
+      ntw_alloc * sizeof(float2) + k * sizeof(uint16_t) + (with_amat ? amat_bytes : 0);
   return HIDFT_OK;
 }
 
@@ -238,13 +242,13 @@ hidft_status resolve_config(const hidft_plan plan, const hidft_exec_config* cfg,
     return fail(HIDFT_ERR_UNSUPPORTED,
                 "%s: the matrix-core precisions need k >= 16 (a radix-16 first group), k = %llu",
                 fn, (unsigned long long)plan->core.k);
-  if (c.rho == 5 && (c.prec != PREC_FP32 || s < 13))
-    return fail(HIDFT_ERR_UNSUPPORTED, "%s: radix 32 needs FP32 and k >= 2^13 (s = %u)", fn, s);
+  if (c.rho == 5 && s < 13)
+    return fail(HIDFT_ERR_UNSUPPORTED, "%s: radix 32 needs k >= 2^13 (s = %u)", fn, s);
   if (!fused_variant_exists(s, c.sched, c.prec, c.rho))
     return fail(HIDFT_ERR_UNSUPPORTED,
-                "%s: the matrix-core precisions need the full radix-16 group first "
-                "(schedule SHORT_LAST or DEFAULT) when 4 does not divide s = %u",
-                fn, s);
+                "%s: the matrix-core precisions need a full radix-%u group first "
+                "(schedule SHORT_LAST or DEFAULT) when %u does not divide s = %u",
+                fn, c.rho == 5 ? 32u : 16u, (unsigned)c.rho, s);
   *out = c;
   return HIDFT_OK;
 }

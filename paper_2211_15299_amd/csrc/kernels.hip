@@ -209,6 +209,11 @@ using SigVec = float2[FusedShape<S, SCHED_SHORT_FIRST, RH>::R];
 // + i (i < 4) of block column 64 w + 16 j + (l & 15) before and after the
 // product.
 //
+// Radix 32 (k >= 2^13, short group last): the five stages of group 1 form a
+// 32 x 32 matrix, applied as 2 x 2 blocks of 16 x 16 (four times the
+// products).  A lane then keeps, per tile, the values c = 16 kc + 4 (l >> 4)
+// + i of both 16-value halves kc of its column.
+//
 // Split precision: x = x1 + x2 (+ x3) and W = W1 + W2 (+ W3) in FP16 (two
 // terms) or BF16 (three terms); the products of the leading terms are summed
 // in FP32, smallest first.
@@ -228,118 +233,170 @@ constexpr int AMAT_F16_OPS = 4;   // Re-row hi, lo; Im-row hi, lo
 constexpr int AMAT_BF16_OPS = 6;  // Re-row terms 1..3; Im-row terms 1..3
 constexpr int AMAT_BF16_BASE = AMAT_F16_OPS * 64;
 
-template <int PREC>
+// Operand set of the group-1 matrix: NB = 1 block (radix 16) or NB = 4 blocks
+// b = 2 rb + kc (radix 32).
+template <int PREC, int NB = 1>
 struct MfmaOps {};
-template <>
-struct MfmaOps<PREC_F16X2> {
-  half8_t rh, rl, ih, il;
+template <int NB>
+struct MfmaOps<PREC_F16X2, NB> {
+  half8_t rh[NB], rl[NB], ih[NB], il[NB];
 };
-template <>
-struct MfmaOps<PREC_BF16X3> {
-  bf16x8_t r1, r2, r3, i1, i2, i3;
+template <int NB>
+struct MfmaOps<PREC_BF16X3, NB> {
+  bf16x8_t r1[NB], r2[NB], r3[NB], i1[NB], i2[NB], i3[NB];
 };
 
-template <int PREC>
-__device__ __forceinline__ MfmaOps<PREC> load_mfma_ops(const uint4* __restrict__ amat) {
-  MfmaOps<PREC> op;
+// Blocks of the operand set for groups of RHO stages.
+template <int RHO>
+constexpr int mfma_blocks() { return RHO == 5 ? 4 : 1; }
+
+// The radix-32 operands follow the radix-16 ones in a plan's table.
+template <int PREC, int NB>
+__device__ __forceinline__ MfmaOps<PREC, NB> load_mfma_ops(const uint4* __restrict__ amat) {
+  MfmaOps<PREC, NB> op;
   const int l = threadIdx.x & 63;
-  if constexpr (PREC == PREC_F16X2) {
-    op.rh = __builtin_bit_cast(half8_t, amat[0 * 64 + l]);
-    op.rl = __builtin_bit_cast(half8_t, amat[1 * 64 + l]);
-    op.ih = __builtin_bit_cast(half8_t, amat[2 * 64 + l]);
-    op.il = __builtin_bit_cast(half8_t, amat[3 * 64 + l]);
-  } else if constexpr (PREC == PREC_BF16X3) {
-    const uint4* b = amat + AMAT_BF16_BASE;
-    op.r1 = __builtin_bit_cast(bf16x8_t, b[0 * 64 + l]);
-    op.r2 = __builtin_bit_cast(bf16x8_t, b[1 * 64 + l]);
-    op.r3 = __builtin_bit_cast(bf16x8_t, b[2 * 64 + l]);
-    op.i1 = __builtin_bit_cast(bf16x8_t, b[3 * 64 + l]);
-    op.i2 = __builtin_bit_cast(bf16x8_t, b[4 * 64 + l]);
-    op.i3 = __builtin_bit_cast(bf16x8_t, b[5 * 64 + l]);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const uint4* a = amat + (NB == 4 ? 1 + b : 0) * (AMAT_BYTES / 16);
+    if constexpr (PREC == PREC_F16X2) {
+      op.rh[b] = __builtin_bit_cast(half8_t, a[0 * 64 + l]);
+      op.rl[b] = __builtin_bit_cast(half8_t, a[1 * 64 + l]);
+      op.ih[b] = __builtin_bit_cast(half8_t, a[2 * 64 + l]);
+      op.il[b] = __builtin_bit_cast(half8_t, a[3 * 64 + l]);
+    } else if constexpr (PREC == PREC_BF16X3) {
+      const uint4* q = a + AMAT_BF16_BASE;
+      op.r1[b] = __builtin_bit_cast(bf16x8_t, q[0 * 64 + l]);
+      op.r2[b] = __builtin_bit_cast(bf16x8_t, q[1 * 64 + l]);
+      op.r3[b] = __builtin_bit_cast(bf16x8_t, q[2 * 64 + l]);
+      op.i1[b] = __builtin_bit_cast(bf16x8_t, q[3 * 64 + l]);
+      op.i2[b] = __builtin_bit_cast(bf16x8_t, q[4 * 64 + l]);
+      op.i3[b] = __builtin_bit_cast(bf16x8_t, q[5 * 64 + l]);
+    }
   }
   return op;
 }
 
-// Group 1 of the 64 block columns of this wave (v in the MFMA layout).
-template <int PREC>
-__device__ __forceinline__ void group1_mfma(float2 (&v)[16], const MfmaOps<PREC>& op) {
+// Group 1 of the 64 block columns of this wave (v in the MFMA layout).  Per
+// tile of 16 columns a lane holds NV = R / 4 values: for radix 32 the column's
+// 32 values are two k-chunks kc of 16 (inputs) and two row blocks rb of 16
+// (outputs), and W is multiplied block by block, (rb, kc) = operand block
+// 2 rb + kc.  The products are summed smallest term first over both chunks.
+template <int PREC, int R>
+__device__ __forceinline__ void group1_mfma(float2 (&v)[R],
+                                            const MfmaOps<PREC, (R == 32 ? 4 : 1)>& op) {
+  static_assert(R == 16 || R == 32, "radix-16 or radix-32 group 1");
+  constexpr int NV = R / 4;   // values per lane and tile
+  constexpr int NK = R / 16;  // input chunks = output row blocks
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    float4_t dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+    float2* x = v + NV * j;
     if constexpr (PREC == PREC_F16X2) {
       float mx = 0.f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        mx = fmaxf(mx, fmaxf(fabsf(v[4 * j + i].x), fabsf(v[4 * j + i].y)));
-      // The column's 16 values sit in lanes l, l ^ 16, l ^ 32, l ^ 48.
+      for (int i = 0; i < NV; ++i) mx = fmaxf(mx, fmaxf(fabsf(x[i].x), fabsf(x[i].y)));
+      // The column's values sit in lanes l, l ^ 16, l ^ 32, l ^ 48.
       mx = fmaxf(mx, __shfl_xor(mx, 16));
       mx = fmaxf(mx, __shfl_xor(mx, 32));
       int e = (int)((__builtin_bit_cast(uint32_t, mx) >> 23) & 0xffu);
       e = e < 15 ? 15 : (e > 254 ? 254 : e);
       const float sc = __builtin_bit_cast(float, (uint32_t)(268 - e) << 23);   // 2^(141-e)
       const float inv = __builtin_bit_cast(float, (uint32_t)(e - 14) << 23);   // 2^(e-141)
-      half8_t x1, x2;
+      half8_t x1[NK], x2[NK];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const float xr = v[4 * j + p].x * sc, xi = v[4 * j + p].y * sc;
-        const _Float16 hr = (_Float16)xr, hi = (_Float16)xi;
-        x1[2 * p] = hr;
-        x1[2 * p + 1] = hi;
-        x2[2 * p] = (_Float16)(xr - (float)hr);
-        x2[2 * p + 1] = (_Float16)(xi - (float)hi);
-      }
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.rl, x1, dr, 0, 0, 0);
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.rh, x2, dr, 0, 0, 0);
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.rh, x1, dr, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.il, x1, di, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.ih, x2, di, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.ih, x1, di, 0, 0, 0);
+      for (int kc = 0; kc < NK; ++kc) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[4 * j + i] = make_float2(dr[i] * inv, di[i] * inv);
-    } else {
-      bf16x8_t x1, x2, x3;
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const float x = q ? v[4 * j + p].y : v[4 * j + p].x;
-          const __bf16 b1 = (__bf16)x;
-          const float r1 = x - (float)b1;
-          const __bf16 b2 = (__bf16)r1;
-          const float r2 = r1 - (float)b2;
-          x1[2 * p + q] = b1;
-          x2[2 * p + q] = b2;
-          x3[2 * p + q] = (__bf16)r2;
+        for (int p = 0; p < 4; ++p) {
+          const float xr = x[4 * kc + p].x * sc, xi = x[4 * kc + p].y * sc;
+          const _Float16 hr = (_Float16)xr, hi = (_Float16)xi;
+          x1[kc][2 * p] = hr;
+          x1[kc][2 * p + 1] = hi;
+          x2[kc][2 * p] = (_Float16)(xr - (float)hr);
+          x2[kc][2 * p + 1] = (_Float16)(xi - (float)hi);
         }
       }
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r1, x3, dr, 0, 0, 0);
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r2, x2, dr, 0, 0, 0);
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r3, x1, dr, 0, 0, 0);
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r1, x2, dr, 0, 0, 0);
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r2, x1, dr, 0, 0, 0);
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.r1, x1, dr, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i1, x3, di, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i2, x2, di, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i3, x1, di, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i1, x2, di, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i2, x1, di, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.i1, x1, di, 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[4 * j + i] = make_float2(dr[i], di[i]);
+      for (int rb = 0; rb < NK; ++rb) {
+        float4_t dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < NK; ++kc) {
+          const int bk = NK == 2 ? 2 * rb + kc : 0;
+          dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.rl[bk], x1[kc], dr, 0, 0, 0);
+          di = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.il[bk], x1[kc], di, 0, 0, 0);
+        }
+#pragma unroll
+        for (int kc = 0; kc < NK; ++kc) {
+          const int bk = NK == 2 ? 2 * rb + kc : 0;
+          dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.rh[bk], x2[kc], dr, 0, 0, 0);
+          di = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.ih[bk], x2[kc], di, 0, 0, 0);
+        }
+#pragma unroll
+        for (int kc = 0; kc < NK; ++kc) {
+          const int bk = NK == 2 ? 2 * rb + kc : 0;
+          dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.rh[bk], x1[kc], dr, 0, 0, 0);
+          di = __builtin_amdgcn_mfma_f32_16x16x32_f16(op.ih[bk], x1[kc], di, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[4 * rb + i] = make_float2(dr[i] * inv, di[i] * inv);
+      }
+    } else {
+      bf16x8_t x1[NK], x2[NK], x3[NK];
+#pragma unroll
+      for (int kc = 0; kc < NK; ++kc) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const float xv = q ? x[4 * kc + p].y : x[4 * kc + p].x;
+            const __bf16 b1 = (__bf16)xv;
+            const float r1 = xv - (float)b1;
+            const __bf16 b2 = (__bf16)r1;
+            const float r2 = r1 - (float)b2;
+            x1[kc][2 * p + q] = b1;
+            x2[kc][2 * p + q] = b2;
+            x3[kc][2 * p + q] = (__bf16)r2;
+          }
+        }
+      }
+#pragma unroll
+      for (int rb = 0; rb < NK; ++rb) {
+        float4_t dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+        // Term pairs (W term, x term), smallest first: (1,3) (2,2) (3,1) (1,2) (2,1) (1,1).
+#define HIDFT_BF16_TERM(WR, WI, X)                                                 \
+  _Pragma("unroll") for (int kc = 0; kc < NK; ++kc) {                              \
+    const int bk = NK == 2 ? 2 * rb + kc : 0;                                      \
+    dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.WR[bk], X[kc], dr, 0, 0, 0);    \
+    di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.WI[bk], X[kc], di, 0, 0, 0);    \
+  }
+        HIDFT_BF16_TERM(r1, i1, x3)
+        HIDFT_BF16_TERM(r2, i2, x2)
+        HIDFT_BF16_TERM(r3, i3, x1)
+        HIDFT_BF16_TERM(r1, i1, x2)
+        HIDFT_BF16_TERM(r2, i2, x1)
+        HIDFT_BF16_TERM(r1, i1, x1)
+#undef HIDFT_BF16_TERM
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[4 * rb + i] = make_float2(dr[i], di[i]);
+      }
     }
   }
 }
 
-// Split operands of W from the FP64 twiddles of stages 1..4 (a-order entries
-// 0..14), one wavefront.  Lane l = 16 g + m builds W[m][c] for c = 4g .. 4g+3
-// by running the four stages on the unit vector e_c in FP64.
+// Split operands of the group-1 matrix W (2^RHO x 2^RHO, the product of
+// stages 1..RHO, a-order twiddle entries 0..2^RHO - 2) in FP64, one wavefront
+// per 16 x 16 block of W: block b = 2 rb + kc holds rows 16 rb .. 16 rb + 15
+// and columns 16 kc .. 16 kc + 15 (radix 16: the single block b = 0).  Lane
+// l = 16 g + m builds W[16 rb + m][16 kc + 4 g + p] (p < 4) by running the
+// stages on the unit vectors of those columns, then splits its row operands.
+template <int RHO>
 __global__ void __launch_bounds__(64)
 stage_matrix_kernel(const uint64_t* __restrict__ num, const uint8_t* __restrict__ log2den,
                     uint4* __restrict__ amat) {
+  constexpr int R = 1 << RHO;
   const int l = threadIdx.x;
-  const int g = l >> 4, m = l & 15;
-  double wr[15], wi[15];
-  for (int e = 0; e < 15; ++e) {
+  const int rb = blockIdx.x >> 1, kc = blockIdx.x & 1;
+  const int g = l >> 4, m = 16 * rb + (l & 15);
+  double wr[R - 1], wi[R - 1];
+  for (int e = 0; e < R - 1; ++e) {
     double sn, cs;
     sincospi(ldexp((double)num[e], -(int)log2den[e]), &sn, &cs);
     wr[e] = cs;
@@ -347,12 +404,12 @@ stage_matrix_kernel(const uint64_t* __restrict__ num, const uint8_t* __restrict_
   }
   double Wr[4], Wi[4];
   for (int p = 0; p < 4; ++p) {
-    double xr[16], xi[16];
-    for (int c = 0; c < 16; ++c) xr[c] = xi[c] = 0.0;
-    xr[4 * g + p] = 1.0;
-    for (int u = 1; u <= 4; ++u) {
-      const int bit = 4 - u;
-      for (int c = 0; c < 16; ++c) {
+    double xr[R], xi[R];
+    for (int c = 0; c < R; ++c) xr[c] = xi[c] = 0.0;
+    xr[16 * kc + 4 * g + p] = 1.0;
+    for (int u = 1; u <= RHO; ++u) {
+      const int bit = RHO - u;
+      for (int c = 0; c < R; ++c) {
         if (c & (1 << bit)) continue;
         const int e = (1 << (u - 1)) - 1 + (c >> (bit + 1));
         const int d = c | (1 << bit);
@@ -367,7 +424,7 @@ stage_matrix_kernel(const uint64_t* __restrict__ num, const uint8_t* __restrict_
     Wr[p] = xr[m];
     Wi[p] = xi[m];
   }
-  // Row operands: element e pairs with (re, im)[e & 1] of c = 4g + e/2.
+  // Row operands: element e pairs with (re, im)[e & 1] of column 16 kc + 4g + e/2.
   half8_t f16[4];
   bf16x8_t b16[6];
   for (int e = 0; e < 8; ++e) {
@@ -388,15 +445,20 @@ stage_matrix_kernel(const uint64_t* __restrict__ num, const uint8_t* __restrict_
       b16[3 * q + 2][e] = (__bf16)(float)r2;
     }
   }
-  for (int o = 0; o < AMAT_F16_OPS; ++o) amat[o * 64 + l] = __builtin_bit_cast(uint4, f16[o]);
+  uint4* out = amat + blockIdx.x * (AMAT_BYTES / 16);
+  for (int o = 0; o < AMAT_F16_OPS; ++o) out[o * 64 + l] = __builtin_bit_cast(uint4, f16[o]);
   for (int o = 0; o < AMAT_BF16_OPS; ++o)
-    amat[AMAT_BF16_BASE + o * 64 + l] = __builtin_bit_cast(uint4, b16[o]);
+    out[AMAT_BF16_BASE + o * 64 + l] = __builtin_bit_cast(uint4, b16[o]);
 }
 
 hipError_t launch_stage_matrix(const uint64_t* d_num, const uint8_t* d_den, void* d_amat,
-                               hipStream_t stream) {
-  hipLaunchKernelGGL(stage_matrix_kernel, dim3(1), dim3(64), 0, stream, d_num, d_den,
-                     static_cast<uint4*>(d_amat));
+                               bool radix32, hipStream_t stream) {
+  uint4* am = static_cast<uint4*>(d_amat);
+  hipLaunchKernelGGL(stage_matrix_kernel<4>, dim3(1), dim3(64), 0, stream, d_num, d_den, am);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !radix32) return e;
+  hipLaunchKernelGGL(stage_matrix_kernel<5>, dim3(4), dim3(64), 0, stream, d_num, d_den,
+                     am + AMAT_BYTES / 16);
   return hipGetLastError();
 }
 
@@ -504,14 +566,16 @@ __device__ __forceinline__ void load_row(float2 (&v)[R], const float2* row, uint
   }
 }
 
-// Position of value i of tile j of this thread in the MFMA layout: the
-// block's signal slot and the position a within that signal.
-template <int S>
-__device__ __forceinline__ void mfma_pos(int tid, int j, int i, int& slot, int& a) {
-  constexpr int T = FusedShape<S>::T;  // columns per signal, 2^{S-4}
+// Position of value e < 2^RHO / 4 of tile j of this thread in the MFMA layout
+// (radix 2^RHO, RHO = 4 or 5): the block's signal slot and the position a
+// within that signal.  The value is entry c = 16 (e >> 2) + 4 (lane >> 4) +
+// (e & 3) of block column col.
+template <int S, int RHO>
+__device__ __forceinline__ void mfma_pos(int tid, int j, int e, int& slot, int& a) {
+  constexpr int T = 1 << (S - RHO);  // columns per signal
   const int col = (tid & ~63) + 16 * j + (tid & 15);
-  slot = col >> (S - 4);
-  a = (col & (T - 1)) + (4 * ((tid >> 4) & 3) + i) * T;
+  slot = col >> (S - RHO);
+  a = (col & (T - 1)) + (16 * (e >> 2) + 4 * ((tid >> 4) & 3) + (e & 3)) * T;
 }
 
 // Loads the samples of the signals first_sig + slot (slot < SPB) that this
@@ -533,14 +597,15 @@ __device__ __forceinline__ void load_group1(SigVec<S, RH>& v, const float2* __re
       for (int c = 0; c < R; ++c) v[c] = make_float2(0.f, 0.f);
     }
   } else {
+    constexpr int NV = R / 4;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int e = 0; e < NV; ++e) {
         int slot, a;
-        mfma_pos<S>(tid, j, i, slot, a);
+        mfma_pos<S, Sh::RHO>(tid, j, e, slot, a);
         const uint64_t sig = first_sig + slot;
-        v[4 * j + i] =
+        v[NV * j + e] =
             sig < batch ? load_stream(in + sig * (uint64_t)ld_in + a) : make_float2(0.f, 0.f);
       }
     }
@@ -556,7 +621,7 @@ template <int S, int SCHED, int RH, int PREC, bool HOISTED, class Mem>
 __device__ __forceinline__ void transform_signal(SigVec<S, RH>& v, float2* Lb, int slot, int tau,
                                                  bool store, const Mem& mem, float scale,
                                                  const ThreadState<S, SCHED, RH>& ts,
-                                                 const MfmaOps<PREC>& op) {
+                                                 const MfmaOps<PREC, mfma_blocks<RH>()>& op) {
   using Sh = FusedShape<S, SCHED, RH>;
   constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, G = Sh::G, G1 = Sh::G1;
   float2* L = Lb + slot * Sh::PADK;
@@ -583,17 +648,18 @@ __device__ __forceinline__ void transform_signal(SigVec<S, RH>& v, float2* Lb, i
       for (int c = 0; c < R; ++c) L[lds_pad<RHO>(c * T + tau)] = v[c];
     }
   } else {
-    static_assert(S >= 4 && RHO == 4 && G1 == 4,
-                  "the matrix-core group 1 is a full radix-16 group");
-    group1_mfma<PREC>(v, op);
+    static_assert(S >= RHO && (RHO == 4 || RHO == 5) && G1 == RHO && RH == RHO,
+                  "the matrix-core group 1 is a full radix-16 or radix-32 group");
+    group1_mfma<PREC, R>(v, op);
     const int tid = threadIdx.x;
+    constexpr int NV = R / 4;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int e = 0; e < NV; ++e) {
         int sl, a;
-        mfma_pos<S>(tid, j, i, sl, a);
-        Lb[sl * Sh::PADK + lds_pad<RHO>(a)] = v[4 * j + i];
+        mfma_pos<S, RHO>(tid, j, e, sl, a);
+        Lb[sl * Sh::PADK + lds_pad<RHO>(a)] = v[NV * j + e];
       }
     }
   }
@@ -717,8 +783,8 @@ hidft_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
   const int slot = tid / T;
   const int tau = tid - slot * T;
   const uint64_t n_groups = (batch + SPB - 1) / SPB;
-  MfmaOps<PREC> op;
-  if constexpr (PREC != PREC_FP32) op = load_mfma_ops<PREC>(amat);
+  MfmaOps<PREC, mfma_blocks<RH>()> op;
+  if constexpr (PREC != PREC_FP32) op = load_mfma_ops<PREC, mfma_blocks<RH>()>(amat);
 
   if constexpr (Sh::BIG) {
     // One signal per block, one block per signal (see BIG above).
@@ -1027,10 +1093,11 @@ bool fused_variant_exists(uint32_t s, int sched, int prec, int rho) {
   if (s > HIDFT_MAX_LOG2_K_DEVICE) return false;
   if (sched != SCHED_SHORT_FIRST && sched != SCHED_SHORT_LAST) return false;
   if (rho != 4 && rho != 5) return false;
-  // Radix-32 tiles exist for the one-signal-per-block sizes, in FP32.
-  if (rho == 5) return prec == PREC_FP32 && s >= 13;
+  if (prec != PREC_FP32 && prec != PREC_F16X2 && prec != PREC_BF16X3) return false;
+  // Radix-32 tiles exist for the one-signal-per-block sizes; the matrix-core
+  // group 1 is then a full radix-32 group (short group last).
+  if (rho == 5) return s >= 13 && (prec == PREC_FP32 || sched == SCHED_SHORT_LAST);
   if (prec == PREC_FP32) return true;
-  if (prec != PREC_F16X2 && prec != PREC_BF16X3) return false;
   // Matrix-core group 1 is a full radix-16 group.
   return s >= 4 && (sched == SCHED_SHORT_LAST || s % 4 == 0);
 }
@@ -1054,6 +1121,14 @@ static hipError_t dispatch_fused(const float2* in, int64_t ld_in, float2* out, i
   if constexpr (S >= 13) {
     if (cfg.rho == 5) {
       // Radix 32: 13 = 3 + 5 + 5 or 5 + 5 + 3, 14 = 4 + 5 + 5 or 5 + 5 + 4.
+      if (cfg.prec == PREC_F16X2)
+        return launch_fused_s<S, SCHED_SHORT_LAST, 5, PREC_F16X2>(in, ld_in, out, ld_out, batch,
+                                                                  tw, src, amat, scale, n_out,
+                                                                  bpc, stream);
+      if (cfg.prec == PREC_BF16X3)
+        return launch_fused_s<S, SCHED_SHORT_LAST, 5, PREC_BF16X3>(in, ld_in, out, ld_out,
+                                                                   batch, tw, src, amat, scale,
+                                                                   n_out, bpc, stream);
       if (last)
         return launch_fused_s<S, SCHED_SHORT_LAST, 5, PREC_FP32>(in, ld_in, out, ld_out, batch,
                                                                  tw, src, amat, scale, n_out, bpc,

@@ -32,9 +32,12 @@ struct ExecConfig {
 constexpr size_t AMAT_BYTES = 10 * 64 * 16;
 
 // Split operands of the group-1 matrix in FP64 from the exponents of stages
-// 1..4 (a-order entries 0..14), into d_amat (AMAT_BYTES).
+// 1..4 (a-order entries 0..14), into d_amat (AMAT_BYTES); with radix32 also
+// those of the radix-32 group 1 (stages 1..5, entries 0..30) as four 16 x 16
+// blocks after them (AMAT32_BYTES more).
+constexpr size_t AMAT32_BYTES = 4 * AMAT_BYTES;
 hipError_t launch_stage_matrix(const uint64_t* d_num, const uint8_t* d_den, void* d_amat,
-                               hipStream_t stream);
+                               bool radix32, hipStream_t stream);
 
 // Fused batched transform of size 2^s (s <= HIDFT_MAX_LOG2_K_DEVICE).
 // amat may be NULL for PREC_FP32.  hipErrorInvalidValue for a variant that

@@ -74,7 +74,7 @@ std::vector<hidft_exec_config> candidates(uint32_t s, uint32_t precision) {
     scheds.push_back(HIDFT_SCHED_DEFAULT);
   }
   std::vector<uint32_t> radices = {16};
-  if (precision == HIDFT_PREC_FP32 && s >= 13) radices.push_back(32);
+  if (s >= 13) radices.push_back(32);
   // Persistent sizes: the grid is resident blocks per CU times the CUs.
   std::vector<uint32_t> bpcs = {0};
   if (s <= 12) bpcs = {0, 1, 2, 3};

@@ -31,7 +31,8 @@ def _say(msg):
 
 @pytest.mark.parametrize("s,prec", [(6, native.PREC_FP32), (10, native.PREC_FP32),
                                     (12, native.PREC_FP32), (13, native.PREC_FP32),
-                                    (14, native.PREC_FP32), (11, native.PREC_BF16X3)])
+                                    (14, native.PREC_FP32), (11, native.PREC_BF16X3),
+                                    (14, native.PREC_F16X2)])
 def test_autotune_picks_a_valid_variant(s, prec):
     rng = rng_for(2200, s)
     M = 22 if s >= 13 else 20

@@ -2,8 +2,9 @@
 oracle.
 
 Variants: the two groupings of the stages (short group first or last) in
-FP32, and the first radix-16 group on the matrix cores with a two-term FP16
-or three-term BF16 split (FP32 accumulation).  Every variant must meet the
+FP32, radix-16 or radix-32 groups, and the first group (radix 16, or radix 32
+for k >= 2^13) on the matrix cores with a two-term FP16 or three-term BF16
+split (FP32 accumulation).  Every variant must meet the
 same bar as the default path, rel-L2 <= 1e-5 per transform; the launch shape
 (blocks per CU) must not change a single bit.
 """
@@ -46,7 +47,7 @@ def _variants(s):
     if s >= 4:
         out += [(F16X2, DEFAULT, 0), (BF16X3, DEFAULT, 0)]
     if s >= 13:
-        out += [(FP32, FIRST, 32), (FP32, LAST, 32)]
+        out += [(FP32, FIRST, 32), (FP32, LAST, 32), (F16X2, DEFAULT, 32), (BF16X3, LAST, 32)]
     return out
 
 
@@ -134,10 +135,11 @@ def test_config2_full_size_matrix_cores():
         _check(got, ref, f"C2 prec={prec} vs FP32 (all 4096)", tol=2 * TOL)
 
 
-@pytest.mark.parametrize("prec", [F16X2, BF16X3])
-def test_config4_precision_matrix_cores(prec):
+@pytest.mark.parametrize("prec,radix", [(F16X2, 16), (BF16X3, 16), (F16X2, 32), (BF16X3, 32)])
+def test_config4_precision_matrix_cores(prec, radix):
     """N = 2^22, k = 2^14, 1024 signals, |c| log-uniform on [1e-3, 1e3] with
-    random phase: per-instance error against the seeded coefficients."""
+    random phase: per-instance error against the seeded coefficients, with
+    the radix-16 or radix-32 first group on the matrix cores."""
     rng = rng_for(4, 0)
     M, s, batch = 22, 14, 1024
     sup = homogeneous_support(M, s, rng)
@@ -147,16 +149,16 @@ def test_config4_precision_matrix_cores(prec):
     I = plan.samples().tolist()
     n_exact = 8
     c = log_uniform_coefficients((n_exact, k), rng)
-    _say(f"C4 prec={prec}: synthesising {n_exact} signals with the oracle")
+    _say(f"C4 prec={prec} radix={radix}: synthesising {n_exact} signals with the oracle")
     f_exact = oracle.synthesize_samples_fft(M, J, c, I)
     f = np.empty((batch, k), dtype=np.complex128)
     f[:n_exact] = f_exact
     scale = np.sqrt(np.mean(np.abs(f_exact) ** 2))
     f[n_exact:] = complex_normal((batch - n_exact, k), rng, scale=scale)
-    got = _run(plan, f, native.ExecConfig(prec, DEFAULT, 0, 0))
-    _check(got[:n_exact], c, f"C4 prec={prec} seeded recovery")
+    got = _run(plan, f, native.ExecConfig(prec, DEFAULT, radix, 0))
+    _check(got[:n_exact], c, f"C4 prec={prec} radix={radix} seeded recovery")
     ref = _run(plan, f, native.ExecConfig(FP32, DEFAULT, 0, 0))
-    _check(got, ref, f"C4 prec={prec} vs FP32 (all 1024)", tol=2 * TOL)
+    _check(got, ref, f"C4 prec={prec} radix={radix} vs FP32 (all 1024)", tol=2 * TOL)
 
 
 def test_split_precision_dynamic_range():
@@ -186,6 +188,30 @@ def test_split_precision_dynamic_range():
         _check(got[1:], ref[1:], f"dynamic range prec={prec}", tol=2 * TOL)
         # the single sample: every coefficient has modulus (N/k) * 5
         assert np.allclose(np.abs(got[6]), (2.0 ** M / k) * 5.0, rtol=1e-5)
+
+
+def test_split_precision_dynamic_range_radix32():
+    """The radix-32 matrix-core group scales each 32-value column (two
+    16-value halves in different operands) by one power of two: a column
+    whose halves differ by 40 orders of magnitude, zeros and huge rows."""
+    rng = rng_for(2104, 0)
+    M, s = 16, 13
+    sup = homogeneous_support(M, s, rng)
+    plan = native.Plan(M, sup.J.tolist())
+    k = plan.k
+    base = complex_normal((4, k), rng)
+    f = np.zeros((5, k), dtype=np.complex128)
+    f[1] = base[0] * 1e30
+    # group 1 works on columns a = col + c 2^{s-5}, c < 32; its halves c < 16
+    # and c >= 16 are the positions a < k/2 and a >= k/2
+    f[2] = base[1] * np.where(np.arange(k) < k // 2, 1e-20, 1e20)
+    f[3] = base[2] * 10.0 ** rng.uniform(-6, 6, k)
+    f[4] = base[3]
+    ref = _run(plan, f, native.ExecConfig(FP32, DEFAULT, 0, 0))
+    for prec in (F16X2, BF16X3):
+        got = _run(plan, f, native.ExecConfig(prec, DEFAULT, 32, 0))
+        assert np.all(got[0] == 0), "zero samples must give zero coefficients"
+        _check(got[1:], ref[1:], f"dynamic range radix 32 prec={prec}", tol=2 * TOL)
 
 
 def test_variant_errors():
@@ -231,5 +257,9 @@ def test_variant_errors():
         return "HIDFT_OK"
 
     assert status_big(native.ExecConfig(FP32, LAST, 32, 0)) == "HIDFT_OK"
-    assert status_big(native.ExecConfig(F16X2, DEFAULT, 32, 0)) == "HIDFT_ERR_UNSUPPORTED"
+    assert status_big(native.ExecConfig(F16X2, DEFAULT, 32, 0)) == "HIDFT_OK"
+    assert status_big(native.ExecConfig(BF16X3, LAST, 32, 0)) == "HIDFT_OK"
+    # the radix-32 matrix-core group is a full five stages: 5 divides neither 13 nor 14
+    assert status_big(native.ExecConfig(F16X2, FIRST, 32, 0)) == "HIDFT_ERR_UNSUPPORTED"
+    assert status(odd, native.ExecConfig(BF16X3, DEFAULT, 32, 0)) == "HIDFT_ERR_UNSUPPORTED"
     torch.cuda.synchronize()
