@@ -385,44 +385,40 @@ __device__ __forceinline__ void group1_mfma(float2 (&v)[R],
 // stages 1..RHO, a-order twiddle entries 0..2^RHO - 2) in FP64, one wavefront
 // per 16 x 16 block of W: block b = 2 rb + kc holds rows 16 rb .. 16 rb + 15
 // and columns 16 kc .. 16 kc + 15 (radix 16: the single block b = 0).  Lane
-// l = 16 g + m builds W[16 rb + m][16 kc + 4 g + p] (p < 4) by running the
-// stages on the unit vectors of those columns, then splits its row operands.
+// l = 16 g + m' builds W[m][c] for m = 16 rb + m' and c = 16 kc + 4 g + p
+// (p < 4), then splits its row operands.
+//
+// The butterflies of the group connect input c to output m by exactly one
+// path: stage u (bit b = RHO - u) moves the value from bit b of c to bit b of
+// m, and multiplies it by 1 if bit b of c is 0, else by +w or -w (bit b of m
+// 0 or 1), w the twiddle of the node named by the bits of m above b.  So
+// W[m][c] is the product of those factors, in stage order.
 template <int RHO>
 __global__ void __launch_bounds__(64)
 stage_matrix_kernel(const uint64_t* __restrict__ num, const uint8_t* __restrict__ log2den,
                     uint4* __restrict__ amat) {
-  constexpr int R = 1 << RHO;
   const int l = threadIdx.x;
   const int rb = blockIdx.x >> 1, kc = blockIdx.x & 1;
   const int g = l >> 4, m = 16 * rb + (l & 15);
-  double wr[R - 1], wi[R - 1];
-  for (int e = 0; e < R - 1; ++e) {
-    double sn, cs;
-    sincospi(ldexp((double)num[e], -(int)log2den[e]), &sn, &cs);
-    wr[e] = cs;
-    wi[e] = -sn;
-  }
   double Wr[4], Wi[4];
   for (int p = 0; p < 4; ++p) {
-    double xr[R], xi[R];
-    for (int c = 0; c < R; ++c) xr[c] = xi[c] = 0.0;
-    xr[16 * kc + 4 * g + p] = 1.0;
+    const int c = 16 * kc + 4 * g + p;
+    double xr = 1.0, xi = 0.0;
     for (int u = 1; u <= RHO; ++u) {
       const int bit = RHO - u;
-      for (int c = 0; c < R; ++c) {
-        if (c & (1 << bit)) continue;
-        const int e = (1 << (u - 1)) - 1 + (c >> (bit + 1));
-        const int d = c | (1 << bit);
-        const double qr = wr[e] * xr[d] - wi[e] * xi[d];
-        const double qi = wr[e] * xi[d] + wi[e] * xr[d];
-        xr[d] = xr[c] - qr;
-        xi[d] = xi[c] - qi;
-        xr[c] += qr;
-        xi[c] += qi;
-      }
+      if (!((c >> bit) & 1)) continue;
+      const int e = (1 << (u - 1)) - 1 + (m >> (bit + 1));
+      double sn, cs;
+      sincospi(ldexp((double)num[e], -(int)log2den[e]), &sn, &cs);
+      const double wr = cs, wi = -sn;
+      const double qr = wr * xr - wi * xi;
+      const double qi = wr * xi + wi * xr;
+      const bool neg = (m >> bit) & 1;
+      xr = neg ? -qr : qr;
+      xi = neg ? -qi : qi;
     }
-    Wr[p] = xr[m];
-    Wi[p] = xi[m];
+    Wr[p] = xr;
+    Wi[p] = xi;
   }
   // Row operands: element e pairs with (re, im)[e & 1] of column 16 kc + 4g + e/2.
   half8_t f16[4];
