@@ -316,7 +316,9 @@ hidft_status hidft_execute_plain(hidft_plan plan, const void* d_samples, int64_t
  * the same contract as hidft_execute for that plan.  hidft_group_create
  * validates every item as hidft_execute would, expands the items into
  * instances (one per row), orders them by size, packs instances of equal size
- * into units of up to 2^14 points, and uploads the resulting descriptor list
+ * into units of up to 2^14 points (when the packs leave the persistent grid a
+ * partial last round, that round's packs are split into packs of fewer
+ * instances until every block has one), and uploads the resulting descriptor list
  * (pointers to rows, plan tables and scales) to the current device, waiting
  * for the upload on `stream`.  hidft_group_execute then runs the whole group as
  * one kernel launch on `stream`, asynchronously; it may be called any number

@@ -44,12 +44,17 @@ bool tune_lookup(const hidft_plan plan, uint32_t precision, uint64_t batch,
 // instances of equal size into packs of at most grouped_slots_per_pack(s).
 // short_first: the packs of sizes with two schedules run with the short
 // group first (GROUP_SHORT_FIRST in GroupPack::log2_k), else last.
+// grid > 0 (the persistent grid's block count): when the packs do not fill
+// whole rounds of the grid, the packs of the last, partial round are split
+// into packs of fewer instances until that round has one pack per block (or
+// no pack has two instances left), so the last round spreads over every
+// CU instead of a few; 0 leaves the packs full.
 // snake_rounds > 0: the pack list is reordered so that the persistent grid
 // of snake_rounds blocks takes, in alternate rounds, the largest and the
 // smallest remaining packs (a block with a long first pack gets a short
 // second one); 0 keeps largest first.
 void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
                     std::vector<GroupPack>* packs, std::vector<GroupSlot>* slots,
-                    bool short_first = false, uint32_t snake_rounds = 0);
+                    uint32_t grid, bool short_first = false, uint32_t snake_rounds = 0);
 
 }  // namespace hidft

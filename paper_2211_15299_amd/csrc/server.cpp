@@ -81,6 +81,7 @@ uint64_t hash_support(uint32_t M, const uint64_t* J, uint64_t k) {
 struct hidft_server_s {
   hidft_server_config cfg{};
   int device = -1;
+  uint32_t grid = 0;               // blocks of the grouped kernel's persistent grid
   uint64_t slot_points = 0;        // complex values per slot and direction
 
   // plan cache
@@ -194,7 +195,7 @@ void hidft_server_s::launch(Slot& sl) {
   sl.points = off;
   std::vector<hidft::GroupPack> packs;
   std::vector<hidft::GroupSlot> slots_v;
-  hidft::pack_instances(inst, &packs, &slots_v);
+  hidft::pack_instances(inst, &packs, &slots_v, grid);
   const size_t packs_at = align_up(off * sizeof(float2), 256);
   const size_t slots_at = align_up(packs_at + packs.size() * sizeof(hidft::GroupPack), 64);
   const size_t up_bytes = slots_at + slots_v.size() * sizeof(hidft::GroupSlot);
@@ -313,6 +314,8 @@ hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* o
   sv->cfg = *cfg;
   hipError_t e = hipGetDevice(&sv->device);
   if (e != hipSuccess) return hidft::hip_error(e, "hidft_server_create");
+  if ((e = hidft::grouped_grid(&sv->grid)) != hipSuccess)
+    return hidft::hip_error(e, "hidft_server_create: grid");
   sv->slot_points = cfg->data_bytes / cfg->slots / (2 * sizeof(float2));
   if ((e = hipStreamCreateWithFlags(&sv->plan_stream, hipStreamNonBlocking)) != hipSuccess)
     return hidft::hip_error(e, "hidft_server_create: stream");
