@@ -24,6 +24,8 @@
 
 #include <stdint.h>
 
+#include <atomic>
+
 #include "launch.h"
 
 namespace hidft {
@@ -91,6 +93,25 @@ __device__ __forceinline__ void lds_barrier() {
 struct Occupancy {
   int per_cu = 0;
   int cus = 0;
+};
+
+// A kernel's occupancy, queried on the first call from any thread.  per_cu
+// is stored before cus (release); a reader that sees cus != 0 (acquire) also
+// sees per_cu and the LDS limit the query raised.  Threads racing on the
+// first call each run the query and store the same values.
+struct OccupancyCache {
+  std::atomic<int> per_cu{0}, cus{0};
+  bool get(Occupancy* o) const {
+    const int c = cus.load(std::memory_order_acquire);
+    if (c == 0) return false;
+    o->cus = c;
+    o->per_cu = per_cu.load(std::memory_order_relaxed);
+    return true;
+  }
+  void put(const Occupancy& o) {
+    per_cu.store(o.per_cu, std::memory_order_relaxed);
+    cus.store(o.cus, std::memory_order_release);
+  }
 };
 
 static hipError_t query_occupancy(const void* kernel, int threads, size_t lds_bytes,
@@ -993,13 +1014,13 @@ static hipError_t launch_inverse_s(const float2* in, int64_t ld_in, float2* out,
   // The adjoint of hidft_execute's default grouping (short group last).
   constexpr int SC = S > 4 && S % 4 != 0 ? SCHED_SHORT_LAST : SCHED_SHORT_FIRST;
   using Sh = FusedShape<S, SC, 4>;
-  static Occupancy occ;  // benign race: every thread computes the same value
-  if (occ.cus == 0) {
-    Occupancy o;
+  static OccupancyCache cache;
+  Occupancy occ;
+  if (!cache.get(&occ)) {
     hipError_t e = query_occupancy((const void*)hidft_inverse_kernel<S, SC>, Sh::THREADS,
-                                   Sh::LDS_BYTES, &o);
+                                   Sh::LDS_BYTES, &occ);
     if (e != hipSuccess) return e;
-    occ = o;
+    cache.put(occ);
   }
   if constexpr (Sh::BIG) {
     const uint64_t chunk = 0x7fffffffULL;  // one block per signal
@@ -1052,12 +1073,12 @@ static hipError_t launch_fused_s(const float2* in, int64_t ld_in, float2* out, i
                                  int blocks_per_cu, hipStream_t stream) {
   using Sh = FusedShape<S, SCHED, RH>;
   const void* kernel = (const void*)hidft_fused_kernel<S, SCHED, RH, PREC, PARTIAL>;
-  static Occupancy occ;  // benign race: every thread computes the same value
-  if (occ.cus == 0) {
-    Occupancy o;
-    hipError_t e = query_occupancy(kernel, Sh::THREADS, Sh::LDS_BYTES, &o);
+  static OccupancyCache cache;
+  Occupancy occ;
+  if (!cache.get(&occ)) {
+    hipError_t e = query_occupancy(kernel, Sh::THREADS, Sh::LDS_BYTES, &occ);
     if (e != hipSuccess) return e;
-    occ = o;
+    cache.put(occ);
   }
   if constexpr (Sh::BIG) {
     // One block per signal: launch in chunks that fit the grid dimension.
@@ -1313,7 +1334,9 @@ int grouped_slots_per_pack(uint32_t s) {
 }
 
 hipError_t grouped_grid(uint32_t* blocks) {
-  static int max_grid = 0;  // benign race: every thread computes the same value
+  // Queried on the first call; racing threads store the same value.
+  static std::atomic<int> cached{0};
+  int max_grid = cached.load(std::memory_order_acquire);
   const size_t lds_bytes = (size_t)GROUPED_LDS_SLOTS * sizeof(float2);
   if (max_grid == 0) {
     hipError_t e = hipFuncSetAttribute((const void*)hidft_grouped_kernel,
@@ -1330,6 +1353,7 @@ hipError_t grouped_grid(uint32_t* blocks) {
         hipSuccess)
       return e;
     max_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    cached.store(max_grid, std::memory_order_release);
   }
   *blocks = (uint32_t)max_grid;
   return hipSuccess;
@@ -1533,13 +1557,16 @@ static hipError_t launch_sas_apply_lds(const float2* y, uint32_t n_nodes, uint32
                                        uint64_t batch, uint32_t k, const uint4* rec,
                                        const cplx64* inv, float2* out, int64_t ld_out,
                                        hipStream_t stream) {
-  static int cus = 0;  // benign race: every thread computes the same value
+  // The CU count, queried on the first call; racing threads store the same value.
+  static std::atomic<int> cached_cus{0};
+  int cus = cached_cus.load(std::memory_order_relaxed);
   if (cus == 0) {
     int dev = 0, c = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     cus = c > 0 ? c : 1;
+    cached_cus.store(cus, std::memory_order_relaxed);
   }
   const size_t lds = ((size_t)mu_star * n_nodes + k) * sizeof(float2);
   // Blocks that fit per CU: by LDS (160 KB) and by threads (2048).
@@ -1703,13 +1730,13 @@ static hipError_t launch_sas_fused_s(const float2* in, int64_t ld_in, float2* ou
                                      hipStream_t stream) {
   using Sh = typename SasFused<S>::Sh;
   const size_t lds = SasFused<S>::lds_bytes(mu_star, n_nodes, k);
-  static Occupancy occ;  // benign race: every thread computes the same value
-  if (occ.cus == 0) {
-    Occupancy o;
+  static OccupancyCache cache;
+  Occupancy occ;
+  if (!cache.get(&occ)) {
     hipError_t e = query_occupancy((const void*)sas_fused_kernel<S>, Sh::THREADS,
-                                   SAS_FUSED_MAX_LDS, &o);
+                                   SAS_FUSED_MAX_LDS, &occ);
     if (e != hipSuccess) return e;
-    occ = o;
+    cache.put(occ);
   }
   // Blocks per CU: by this plan's LDS size, and by registers (the occupancy
   // query above, at the largest LDS size, bounds it from below).
@@ -1844,13 +1871,14 @@ hipError_t launch_plain(uint32_t s, const float2* in, float2* out, const float2*
     return hipGetLastError();
   }
   const size_t lds = ((size_t)1 << s) * sizeof(float2);
-  static bool attr_set = false;
-  if (!attr_set) {
+  // The LDS limit is raised on the first call; racing threads set the same value.
+  static std::atomic<bool> attr_set{false};
+  if (!attr_set.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute((const void*)hidft_plain_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(((size_t)1 << HIDFT_MAX_LOG2_K_DEVICE) * sizeof(float2)));
     if (e != hipSuccess) return e;
-    attr_set = true;
+    attr_set.store(true, std::memory_order_release);
   }
   int threads = (1 << s) / 2;
   if (threads < 64) threads = 64;
