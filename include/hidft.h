@@ -394,12 +394,14 @@ hidft_status hidft_group_autotune(hidft_group group, uint32_t reps, void* stream
  *     cache keyed by (N, J), least recently used plans that no request holds
  *     are destroyed once the cache exceeds cfg.plan_bytes);
  *   * admits requests, in arrival order, into batches: a batch slot takes
- *     requests while its device region (cfg.data_bytes / cfg.slots, half for
+ *     requests while its region (cfg.data_bytes / cfg.slots, half for
  *     samples, half for coefficients) and cfg.max_batch allow;
  *   * runs each batch as one grouped launch (see hidft_group_create) on the
- *     slot's own stream, with upload and download through pinned staging
- *     buffers, so up to cfg.slots batches are in flight at once and requests
- *     that arrive while others are on the device fill the next free slot.
+ *     slot's own stream.  A slot's regions are pinned host memory mapped for
+ *     the device: the kernel reads the samples and writes the coefficients
+ *     over the host link, with no copies.  Up to cfg.slots batches are in
+ *     flight at once, and requests that arrive while others are on the
+ *     device fill the next free slot.
  * A request's coefficients do not depend on which other requests share its
  * batch (each instance runs the same per-signal code).
  *
@@ -417,7 +419,8 @@ hidft_status hidft_group_autotune(hidft_group group, uint32_t reps, void* stream
 typedef struct hidft_server_s* hidft_server;
 
 typedef struct hidft_server_config {
-  size_t data_bytes;   /* device bytes for request samples and coefficients, all slots */
+  size_t data_bytes;   /* pinned host bytes (mapped for the device) for request samples
+                          and coefficients, all slots */
   size_t plan_bytes;   /* device bytes of resident plans before LRU eviction */
   uint32_t slots;      /* batches in flight, each with its own stream */
   uint32_t max_batch;  /* requests per batch */
