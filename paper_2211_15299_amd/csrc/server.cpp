@@ -10,7 +10,6 @@
 // the device.  One scheduler thread forms batches, issues the work and
 // retires completed batches; clients collect results by polling.
 #include <hip/hip_runtime.h>
-#include <sys/prctl.h>
 
 #include <algorithm>
 #include <atomic>
@@ -72,6 +71,10 @@ struct Slot {
   uint64_t points = 0;
 };
 
+// How long the scheduler keeps polling after its last launch or completion
+// before it blocks on the request queue.
+constexpr std::chrono::microseconds kSpinWindow{100};
+
 uint64_t hash_support(uint32_t M, const uint64_t* J, uint64_t k) {
   uint64_t h = 0x9e3779b97f4a7c15ULL ^ (M * 0x100000001b3ULL) ^ k;
   for (uint64_t i = 0; i < k; ++i) {
@@ -111,6 +114,7 @@ struct hidft_server_s {
   std::atomic<uint64_t> n_submitted{0}, n_completed{0}, n_rejected{0}, n_batches{0};
   std::atomic<uint64_t> n_plan_hits{0}, n_plan_misses{0}, n_plan_evictions{0};
   std::atomic<uint64_t> max_inflight{0};
+  std::atomic<uint64_t> n_pending{0};  // requests queued and not yet in a batch
   std::atomic<int32_t> worker_error{0};
 
   void loop();
@@ -244,10 +248,8 @@ void hidft_server_s::retire(Slot& sl) {
 
 void hidft_server_s::loop() {
   (void)hipSetDevice(device);
-  // The loop polls in-flight batches with short sleeps; the default timer
-  // slack (50 us) would stretch each of them, and with it every latency.
-  (void)prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
   const uint64_t cap_points = slot_points;
+  auto last_progress = Clock::now();
   for (;;) {
     bool progressed = false;
     uint64_t inflight = 0;
@@ -268,6 +270,7 @@ void hidft_server_s::loop() {
     }
     for (Slot& sl : slots) {
       if (!sl.batch.empty()) continue;
+      if (n_pending.load(std::memory_order_acquire) == 0) break;
       {
         std::lock_guard<std::mutex> lk(mu);
         uint64_t pts = 0;
@@ -276,6 +279,7 @@ void hidft_server_s::loop() {
           pts += pending.front().k;
           sl.batch.push_back(pending.front());
           pending.pop_front();
+          n_pending.fetch_sub(1, std::memory_order_relaxed);
         }
       }
       if (sl.batch.empty()) break;
@@ -286,17 +290,24 @@ void hidft_server_s::loop() {
     uint64_t m = max_inflight.load();
     while (inflight > m && !max_inflight.compare_exchange_weak(m, inflight)) {
     }
-    if (progressed) continue;
-    std::unique_lock<std::mutex> lk(mu);
-    if (stop && pending.empty() && inflight == 0) break;
-    if (inflight > 0) {
-      // batches on the device: poll their events again shortly
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(5));
-    } else {
-      cv_work.wait_for(lk, std::chrono::milliseconds(2),
-                       [&] { return stop || !pending.empty(); });
+    if (progressed) {
+      last_progress = Clock::now();
+      continue;
     }
+    // While batches are on the device, and for a short window after the last
+    // launch or completion, poll again without sleeping: a sleep, or the
+    // wake-up of a condition variable, adds several microseconds to every
+    // latency.  Measured at 20 000 requests/s against 5 us sleeps: p50 33 ->
+    // 25 us, p99 75-77 -> 52-68 us (a 1 ms window was no better).  The
+    // scheduler thread keeps one host core busy while it polls.
+    if (inflight > 0 || Clock::now() - last_progress < kSpinWindow) {
+      for (int i = 0; i < 32; ++i) __builtin_ia32_pause();
+      continue;
+    }
+    std::unique_lock<std::mutex> lk(mu);
+    if (stop && pending.empty()) break;
+    cv_work.wait_for(lk, std::chrono::milliseconds(2),
+                     [&] { return stop || !pending.empty(); });
   }
 }
 
@@ -385,6 +396,7 @@ hidft_status hidft_server_submit(hidft_server s, uint32_t log2_n, const uint64_t
     }
     r.id = s->next_id++;
     s->pending.push_back(r);
+    s->n_pending.fetch_add(1, std::memory_order_release);
     s->in_system++;
   }
   s->n_submitted++;
