@@ -80,6 +80,9 @@ struct GroupPack {
 // GroupPack::log2_k flag: run the pack with the short group first (sizes
 // with two schedules); without it, the short group is last.
 constexpr uint16_t GROUP_SHORT_FIRST = 0x100;
+// GroupPack::log2_k flag: wavefronts whose slots are all empty skip the
+// arithmetic (set by the server, whose batches are mostly empty packs).
+constexpr uint16_t GROUP_SKIP_IDLE = 0x200;
 
 // Instances of size 2^s that one pack holds (the block's 1024 threads).
 int grouped_slots_per_pack(uint32_t s);

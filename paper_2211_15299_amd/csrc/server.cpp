@@ -204,6 +204,8 @@ void hidft_server_s::launch(Slot& sl) {
   std::vector<hidft::GroupPack> packs;
   std::vector<hidft::GroupSlot> slots_v;
   hidft::pack_instances(inst, &packs, &slots_v, grid);
+  // A batch is often a single request: let the empty slots' wavefronts idle.
+  for (auto& pk : packs) pk.log2_k |= hidft::GROUP_SKIP_IDLE;
   const size_t packs_at = align_up(off * sizeof(float2), 256);
   const size_t slots_at = align_up(packs_at + packs.size() * sizeof(hidft::GroupPack), 64);
   std::memcpy(sl.h_up + packs_at, packs.data(), packs.size() * sizeof(hidft::GroupPack));
