@@ -59,6 +59,26 @@ def _instances(n, seed_cfg=3, composites=64):
     return out
 
 
+def _expected_packs(ks, grid):
+    """Pack count of the host packer: instances of one size in packs of
+    1024 / 2^max(s-4, 0) slots, largest size first; when the packs leave a
+    partial last round of the grid, that round's packs are split until it
+    has a pack per block or every pack holds one instance."""
+    sizes = {}
+    for k in ks:
+        s = int(k).bit_length() - 1
+        sizes[s] = sizes.get(s, 0) + 1
+    packs = []
+    for s in sorted(sizes, reverse=True):
+        per = 1024 >> max(s - 4, 0)
+        n = sizes[s]
+        packs += [min(per, n - i) for i in range(0, n, per)]
+    full = len(packs) // grid * grid
+    if full == 0 or full == len(packs):
+        return len(packs)
+    return full + min(grid, sum(packs[full:]))
+
+
 def _energy_rel(c, f, M, k):
     N = float(1 << M)
     return abs(np.sum(np.abs(c) ** 2) - (N * N / k) * np.sum(np.abs(f) ** 2)) / ((N * N / k) * np.sum(np.abs(f) ** 2))
@@ -78,9 +98,12 @@ def test_config3_uneven_batch_one_launch():
     items = [(p, x.data_ptr(), p.k, y.data_ptr(), p.k, 1) for p, x, y in zip(plans, xs, ys)]
     grp = native.Group(items)
     assert grp.n_instances == 2048
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert grp.n_packs == _expected_packs(ks, cus), (grp.n_packs, _expected_packs(ks, cus))
     grp.execute()
     torch.cuda.synchronize()
-    _say(f"C3: {grp.n_packs} packs executed")
+    _say(f"C3: {grp.n_packs} packs executed ({_expected_packs(ks, 10**9)} full packs, "
+         f"the partial last round spread over {cus} blocks)")
     got = [y.cpu().numpy().astype(np.complex128) for y in ys]
     # fused single-plan path on each instance: bit-identical
     n_diff = 0
