@@ -168,6 +168,35 @@ def test_grouped_mixed_batches_and_ragged_packs():
     grp.close()
 
 
+@pytest.mark.parametrize("s,full_rounds,tail_packs,ragged", [(14, 1, 10, 0), (12, 2, 0, 0),
+                                                           (8, 1, 44, 17)])
+def test_grouped_last_round_spreading(s, full_rounds, tail_packs, ragged):
+    """The packer's edge cases, one plan with many rows each: a partial last
+    round of single-instance packs (2^14 points, nothing to split), packs
+    that fill whole rounds (nothing to spread), and a partial round of
+    64-instance packs spread to a pack per block.  Pack count as the model
+    says; every row bit-identical to hidft_execute."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    rng = rng_for(3, 8000 + s)
+    M = s + 6
+    plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
+    k = plan.k
+    per = 1024 >> max(s - 4, 0)    # instances per full pack
+    batch = (full_rounds * cus + tail_packs) * per + ragged
+    _say(f"case s={s} batch={batch} cus={cus}")
+    x = torch.from_numpy(sample_values(M, k, batch, rng)).cuda()
+    y = torch.full_like(x, complex(np.nan, np.nan))
+    grp = native.Group([(plan, x.data_ptr(), k, y.data_ptr(), k, batch)])
+    want_packs = _expected_packs([k] * batch, cus)
+    assert grp.n_packs == want_packs, (grp.n_packs, want_packs)
+    grp.execute()
+    ref = plan.execute(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+    grp.close()
+    plan.close()
+
+
 def test_group_argument_errors():
     M, s = 12, 6
     sup = homogeneous_support(M, s, rng_for(3, 6000))
