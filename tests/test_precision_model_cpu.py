@@ -169,8 +169,10 @@ def test_f16_split_needs_the_column_scaling():
 
 
 def test_stage_matrix_is_unitary_up_to_scale():
-    """Every entry of W has modulus 1 and W W^H = R Id: the product of R/2-fold
-    butterflies with unit twiddles (what lets one scale per column suffice)."""
+    """Every entry of W has modulus 1 and W W^H = R Id (each stage of
+    butterflies with unit twiddles doubles the squared norm), so the outputs
+    of a column have the magnitude of its inputs times at most sqrt(R): one
+    power-of-two scale per column suffices."""
     for rho in (4, 5):
         W, _ = _stage_matrix(rho, rng_for(9102, rho))
         R = 1 << rho
