@@ -295,6 +295,7 @@ def main():
     # the uneven batch in one grouped launch, and Poisson-arrival serving.
     gsteps = args.steps
     args.steps, args.warmup = 20, 3
+    result["config1_single_signal"] = single_signal_bench(native, torch, stream)
     result["config3_grouped"] = grouped_bench(args, native, torch, stream)
     args.steps = gsteps
     result["config5_serving"] = serve_bench(args, native)
@@ -479,6 +480,42 @@ def serve_bench(args, native, seconds=None):
 PRECISION_WORKLOAD = dict(workload="precision: N=2^22, k=2^14, 1024 signals, |c| log-uniform "
                                    "on [1e-3, 1e3] with random phase", log2_n=22, log2_k=14,
                           batch=1024)
+
+
+def single_signal_bench(native, torch, stream, reps=500):
+    """The single-signal configuration: N = 2^10, k = 64, an elementary
+    homogeneous J (a seeded odd dilation and translation of {0..63}) and one
+    signal of seeded samples.  Latency of one transform per launch, fused
+    kernel and plain kernel, each launch between its own pair of events; the
+    two results must agree bit for bit (their accuracy against the oracle is
+    the single-signal parity test's)."""
+    from workloads import elementary_support, rng_for, sample_values
+    rng = rng_for(1, 0)
+    M, s = 10, 6
+    plan = native.Plan(M, elementary_support(M, s, rng).J.tolist(), stream=stream)
+    k = plan.k
+    x = torch.from_numpy(sample_values(M, k, 1, rng)).cuda()
+    out = {"workload": "single signal: N=2^10, k=64, elementary J", "reps": reps}
+    res = {}
+    for name, plain in (("fused", False), ("plain", True)):
+        y = torch.empty_like(x)
+        for _ in range(20):
+            plan.execute_ptr(x.data_ptr(), k, y.data_ptr(), k, 1, stream, plain=plain)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            plan.execute_ptr(x.data_ptr(), k, y.data_ptr(), k, 1, stream, plain=plain)
+            b.record(stream)
+        torch.cuda.synchronize()
+        lat = np.array([a.elapsed_time(b) for a, b in ev]) * 1e3
+        out[name] = {"latency_us": {"p50": float(np.percentile(lat, 50)),
+                                    "p99": float(np.percentile(lat, 99))}}
+        res[name] = y
+    out["fused_equals_plain"] = bool(torch.equal(res["fused"], res["plain"]))
+    plan.close()
+    return out
 
 
 def precision_variants(native):
