@@ -436,10 +436,11 @@ typedef struct hidft_server_result {
 typedef struct hidft_server_stats {
   uint64_t submitted, completed, rejected, batches;
   uint64_t plan_hits, plan_misses, plan_evictions;
-  uint64_t max_inflight_batches;
+  uint64_t max_inflight_batches;  /* most batches on the device at once */
   uint64_t plans_resident;
-  size_t plan_bytes_resident;
-  size_t slot_bytes;
+  size_t plan_bytes_resident;     /* device bytes of the cached plans */
+  size_t slot_bytes;              /* one slot's sample + coefficient region
+                                     (pinned host memory mapped for the device) */
 } hidft_server_stats;
 
 hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* out);
