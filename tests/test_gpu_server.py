@@ -157,3 +157,80 @@ def test_server_concurrent_clients():
         M, J = sups[w]
         assert np.array_equal(o, _alone(M, J, f[None, :]))
     srv.close()
+
+
+def test_serving_configuration_at_full_rate():
+    """The serving configuration as measured: Poisson arrivals at 20 000
+    requests/s (3 s here), 256 supports with N = 2^10..2^22 and k = 2^6..2^13
+    chosen by a Zipf(1.1) law, one sample vector per support.  Every request
+    completes; every 50th result, kept in its own buffer, equals the request
+    run alone bit for bit; 20 of those (k <= 2048) against the FP64 oracle."""
+    import time
+    sups = _supports(256)
+    vecs = [sample_values(M, len(J), 1, rng_for(5, 5000 + i))[0] for i, (M, J) in enumerate(sups)]
+    rng = rng_for(5, 10 ** 6 + 1)
+    rate, seconds = 20000.0, 3.0
+    n = int(rate * seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    pz = np.arange(1, 257, dtype=np.float64) ** -1.1
+    which = rng.choice(256, size=n, p=pz / pz.sum())
+    keep = list(range(0, n, 50))
+    kept = {i: np.full(len(sups[which[i]][1]), np.nan, dtype=np.complex64) for i in keep}
+    pool = np.zeros((4096, 1 << 13), dtype=np.complex64)
+    busy = np.zeros(len(pool), dtype=bool)
+    slot_of, done = {}, 0
+    srv = native.Server(data_bytes=256 << 20, plan_bytes=256 << 20, slots=4, max_batch=1024)
+    for (M, J), f in zip(sups, vecs):  # plans resident before the clock starts
+        srv.submit(M, J, f, pool[0, :len(J)])
+    srv.drain()
+    srv.poll()
+
+    def collect(wait_us=0):
+        nonlocal done
+        res = srv.poll(wait_us)
+        for r in res:
+            assert int(r["status"]) == 0
+            s = slot_of.pop(int(r["id"]))
+            if s >= 0:
+                busy[s] = False
+        done += len(res)
+
+    _say(f"serving at {rate:.0f} requests/s for {seconds} s: {n} requests")
+    t0 = time.perf_counter()
+    for i in range(n):
+        while time.perf_counter() < t0 + arrivals[i]:
+            collect()
+        M, J = sups[which[i]]
+        if i in kept:
+            out, s = kept[i], -1
+        else:
+            s = i % len(pool)
+            while busy[s]:
+                collect(100)
+            out = pool[s, :len(J)]
+            busy[s] = True
+        rid = srv.submit(M, J, vecs[which[i]], out)
+        slot_of[rid] = s
+    srv.drain()
+    while len(slot_of):
+        collect(1000)
+    st = srv.stats()
+    srv.close()
+    assert done == n and st["completed"] >= n and st["rejected"] == 0
+    alone = {}
+    for i in keep:
+        w = int(which[i])
+        if w not in alone:
+            M, J = sups[w]
+            alone[w] = _alone(M, J, vecs[w][None, :])
+        assert np.array_equal(kept[i], alone[w]), f"request {i} (support {w}) differs from alone"
+    picked = [w for w in sorted(set(int(which[i]) for i in keep)) if len(sups[w][1]) <= 2048][:20]
+    for w in picked:
+        M, J = sups[w]
+        plan = native.Plan(M, J.tolist())
+        want = oracle.adjoint_coefficients(M, J.tolist(), plan.samples().tolist(),
+                                           vecs[w][None, :].astype(np.complex128))[0]
+        plan.close()
+        err = np.linalg.norm(alone[w] - want) / np.linalg.norm(want)
+        assert err <= 1e-5, (w, err)
+    _say(f"{len(keep)} kept results equal alone; {len(picked)} supports against the oracle")
