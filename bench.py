@@ -309,16 +309,11 @@ def main():
 
 
 def grouped_instances(n):
-    """(M, J) of the uneven configuration: N log-uniform over 2^12..2^24 and
-    k log-uniform over 2^6..2^14 with k <= N/4, each with its own seeded J."""
-    from workloads import homogeneous_support, rng_for
-    out = []
-    for i in range(n):
-        rng = rng_for(3, i)
-        M = int(rng.integers(12, 25))
-        s = int(rng.integers(6, min(14, M - 2) + 1))
-        out.append((M, homogeneous_support(M, s, rng).J.tolist()))
-    return out
+    """(M, J) of the uneven configuration (workloads.uneven_instances): N
+    log-uniform over 2^12..2^24 and k over 2^6..2^14 with k <= N/4, each with
+    its own seeded J, the first 64 direct sums of homogeneous blocks."""
+    from workloads import uneven_instances
+    return [(M, sup.J.tolist()) for M, sup in uneven_instances(n)]
 
 
 def grouped_bench(args, native, torch, stream):

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import composite_support, homogeneous_support, rng_for, sample_values
+from workloads import homogeneous_support, rng_for, sample_values, uneven_instances
 
 pytestmark = pytest.mark.gpu
 
@@ -35,28 +35,9 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _instances(n, seed_cfg=3, composites=64):
+def _instances(n):
     """(M, J list, levels) for n seeded instances of the uneven configuration."""
-    out = []
-    for i in range(n):
-        rng = rng_for(seed_cfg, i)
-        if i < composites:
-            M = int(rng.integers(14, 25))
-            # two or three blocks on disjoint bit ranges
-            widths = [int(rng.integers(3, 7)) for _ in range(3)]
-            blocks, lo = [], 0
-            for w in widths:
-                if lo + w > M:
-                    break
-                blocks.append((lo, w, int(rng.integers(1, w))))
-                lo += w + int(rng.integers(0, 3))
-            sup = composite_support(M, blocks, rng)
-        else:
-            M = int(rng.integers(12, 25))
-            s = int(rng.integers(6, min(14, M - 2) + 1))
-            sup = homogeneous_support(M, s, rng)
-        out.append((M, sup.J.tolist(), sup.levels))
-    return out
+    return [(M, sup.J.tolist(), sup.levels) for M, sup in uneven_instances(n)]
 
 
 def _expected_packs(ks, grid):

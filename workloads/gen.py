@@ -122,6 +122,36 @@ def composite_support(M: int, blocks: list, rng: np.random.Generator) -> Support
     return Support(M, J, tuple(sorted(levels)))
 
 
+def uneven_instances(n: int, config_id: int = 3, composites: int = 64) -> list:
+    """The uneven batch: n instances, each (M, Support) with its own seeded J.
+
+    Instance i draws from rng_for(config_id, i).  The first `composites` are
+    direct sums of two or three homogeneous blocks on disjoint bit ranges
+    (M uniform on 14..24, block widths 3..6 bits, gaps of 0..2 bits); the
+    others are homogeneous with N = 2^M, M uniform on 12..24, and k = 2^s, s
+    uniform on 6..min(14, M - 2) (so k <= N/4).
+    """
+    out = []
+    for i in range(n):
+        rng = rng_for(config_id, i)
+        if i < composites:
+            M = int(rng.integers(14, 25))
+            widths = [int(rng.integers(3, 7)) for _ in range(3)]
+            blocks, lo = [], 0
+            for w in widths:
+                if lo + w > M:
+                    break
+                blocks.append((lo, w, int(rng.integers(1, w))))
+                lo += w + int(rng.integers(0, 3))
+            sup = composite_support(M, blocks, rng)
+        else:
+            M = int(rng.integers(12, 25))
+            s = int(rng.integers(6, min(14, M - 2) + 1))
+            sup = homogeneous_support(M, s, rng)
+        out.append((M, sup))
+    return out
+
+
 def gap_support(M: int, sizes, rng: np.random.Generator, *, max_tries: int = 1000,
                 shuffle: bool = True) -> Support:
     """A proper generalized arithmetic progression of dimension d = len(sizes)
