@@ -1313,7 +1313,8 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
 
 __global__ void __launch_bounds__(GROUPED_THREADS)
 hidft_grouped_kernel(const GroupPack* __restrict__ packs, uint32_t n_packs,
-                     const GroupSlot* __restrict__ slots) {
+                     const GroupSlot* __restrict__ slots, uint32_t* done_count,
+                     uint32_t count_base, uint32_t* done_flag, uint32_t seq) {
   extern __shared__ float2 lds[];
   for (uint32_t p = blockIdx.x; p < n_packs; p += gridDim.x) {
     const GroupPack pk = packs[p];
@@ -1343,6 +1344,22 @@ hidft_grouped_kernel(const GroupPack* __restrict__ packs, uint32_t n_packs,
         break;
     }
     lds_barrier();  // the next pack overwrites the LDS
+  }
+  if (done_flag != nullptr) {
+    // Completion signal (the server's batches): every block makes its stores
+    // visible at system scope, then counts itself on done_count, which only
+    // grows (count_base = its value before this launch); the last block
+    // stores seq to the host-mapped flag.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t old = __hip_atomic_fetch_add(done_count, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+      if (old == count_base + gridDim.x - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "");
+        __hip_atomic_store(done_flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
   }
 }
 
@@ -1377,7 +1394,7 @@ hipError_t grouped_grid(uint32_t* blocks) {
 }
 
 hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,
-                          hipStream_t stream) {
+                          hipStream_t stream, const GroupDone* done) {
   if (n_packs == 0) return hipSuccess;
   uint32_t max_grid = 0;
   hipError_t e = grouped_grid(&max_grid);
@@ -1385,8 +1402,12 @@ hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const Grou
   const size_t lds_bytes = (size_t)GROUPED_LDS_SLOTS * sizeof(float2);
   const unsigned grid = n_packs < max_grid ? n_packs : max_grid;
   hipLaunchKernelGGL(hidft_grouped_kernel, dim3(grid), dim3(GROUPED_THREADS), lds_bytes, stream,
-                     d_packs, n_packs, d_slots);
-  return hipGetLastError();
+                     d_packs, n_packs, d_slots, done ? done->d_count : nullptr,
+                     done ? *done->count_base : 0u, done ? done->d_flag : nullptr,
+                     done ? done->seq : 0u);
+  e = hipGetLastError();
+  if (e == hipSuccess && done) *done->count_base += grid;
+  return e;
 }
 
 // ---------------------------------------------------------------------------

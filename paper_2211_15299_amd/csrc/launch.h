@@ -90,9 +90,20 @@ int grouped_slots_per_pack(uint32_t s);
 // Blocks of the persistent grouped launch on the current device.
 hipError_t grouped_grid(uint32_t* blocks);
 
-// Grouped persistent launch over n_packs packs.
+// Completion signal of a grouped launch: device counter of finished blocks
+// (only grows; *count_base is its value before the launch and is advanced by
+// the launch's grid), and a host-mapped flag that the last block sets to seq.
+struct GroupDone {
+  uint32_t* d_count;
+  uint32_t* count_base;
+  uint32_t* d_flag;
+  uint32_t seq;
+};
+
+// Grouped persistent launch over n_packs packs; `done` (optional) signals
+// its completion through memory.
 hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,
-                          hipStream_t stream);
+                          hipStream_t stream, const GroupDone* done = nullptr);
 
 // Largest node (number of aliased coefficients) the leaf solves handle.
 constexpr int SAS_MAX_MU = 32;

@@ -66,6 +66,13 @@ struct Slot {
   float2* h_out = nullptr;         // coefficients of the batch
   char* d_up = nullptr;            // device addresses of h_up and h_out
   float2* d_out = nullptr;
+  // Completion: the kernel's last block stores the batch's sequence number
+  // to h_flag (mapped); d_count counts finished blocks over all launches.
+  uint32_t* d_count = nullptr;
+  uint32_t count_base = 0;
+  uint32_t* h_flag = nullptr;
+  uint32_t* d_flag = nullptr;
+  uint32_t seq = 0;
   std::vector<Request> batch;      // requests in flight (empty when free)
   std::vector<uint64_t> offsets;   // point offset of each request in the region
   uint64_t points = 0;
@@ -211,10 +218,11 @@ void hidft_server_s::launch(Slot& sl) {
   std::memcpy(sl.h_up + packs_at, packs.data(), packs.size() * sizeof(hidft::GroupPack));
   std::memcpy(sl.h_up + slots_at, slots_v.data(), slots_v.size() * sizeof(hidft::GroupSlot));
   hipError_t e;
+  const hidft::GroupDone done{sl.d_count, &sl.count_base, sl.d_flag, ++sl.seq};
   if ((e = hidft::launch_grouped(reinterpret_cast<const hidft::GroupPack*>(sl.d_up + packs_at),
                                  (uint32_t)packs.size(),
                                  reinterpret_cast<const hidft::GroupSlot*>(sl.d_up + slots_at),
-                                 sl.stream)) != hipSuccess ||
+                                 sl.stream, &done)) != hipSuccess ||
       (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) {
     worker_error = (int32_t)HIDFT_ERR_DEVICE;
   }
@@ -257,6 +265,13 @@ void hidft_server_s::loop() {
     uint64_t inflight = 0;
     for (Slot& sl : slots) {
       if (sl.batch.empty()) continue;
+      // The kernel's own completion flag is seen a few microseconds before
+      // the event; the event still catches a launch that failed.
+      if (__atomic_load_n(sl.h_flag, __ATOMIC_ACQUIRE) == sl.seq) {
+        retire(sl);
+        progressed = true;
+        continue;
+      }
       const hipError_t q = hipEventQuery(sl.done);
       if (q == hipSuccess) {
         retire(sl);
@@ -348,12 +363,19 @@ hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* o
         (e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.d_up), sl.h_up, 0)) !=
             hipSuccess ||
         (e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.d_out), sl.h_out, 0)) !=
+            hipSuccess ||
+        (e = hipMalloc(&sl.d_count, sizeof(uint32_t))) != hipSuccess ||
+        (e = hipMemset(sl.d_count, 0, sizeof(uint32_t))) != hipSuccess ||
+        (e = hipHostMalloc(&sl.h_flag, sizeof(uint32_t),
+                           hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.d_flag), sl.h_flag, 0)) !=
             hipSuccess) {
       hidft_status st = hidft::hip_error(e, "hidft_server_create: slot resources");
       hidft_server_destroy(sv.release());
       return st;
     }
   }
+  for (Slot& sl : sv->slots) *sl.h_flag = 0;  // no batch has completed
   hidft_server s = sv.release();
   try {
     s->worker = std::thread([s] { s->loop(); });
@@ -465,6 +487,8 @@ hidft_status hidft_server_destroy(hidft_server s) {
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.h_up) (void)hipHostFree(sl.h_up);
+    if (sl.h_flag) (void)hipHostFree(sl.h_flag);
+    if (sl.d_count) (void)hipFree(sl.d_count);
     if (sl.h_out) (void)hipHostFree(sl.h_out);
   }
   for (auto& kv : s->plans) hidft_plan_destroy(kv.second->plan);
