@@ -253,6 +253,9 @@ hidft_status hidft_execute_config(hidft_plan plan, const hidft_exec_config* conf
 /*
  * hidft_autotune -- pick the fastest execution variant by measurement.
  *
+ * No counterpart in the paper: every variant computes the same transform
+ * (Lemma 3, Algorithm 1) with another grouping of its stages or launch shape.
+ *
  * Runs every variant of `precision` for this plan (both schedules where they
  * differ, radix 16 and 32 where both exist, 0..3 blocks per CU for
  * persistent sizes) on the caller's buffers, as hidft_execute_config would:
@@ -311,6 +314,11 @@ hidft_status hidft_execute_plain(hidft_plan plan, const void* d_samples, int64_t
 /*
  * Grouped execution: an uneven batch (instances with different N, J and k) in
  * one persistent kernel launch.
+ *
+ * Each instance is hidft_execute's transform of its own (N, J) (Lemma 3,
+ * Algorithm 1, Sec. VII-B); Sec. II's families of index sets are what such a
+ * batch draws from.  The packing and the single launch have no counterpart in
+ * the paper.
  *
  * One work item is a plan and `batch` rows of samples and coefficients, with
  * the same contract as hidft_execute for that plan.  hidft_group_create
@@ -387,6 +395,11 @@ hidft_status hidft_group_autotune(hidft_group group, uint32_t reps, void* stream
 
 /*
  * Request server (continuous batching).
+ *
+ * Each request is hidft_execute's transform of its (N, J) (Lemma 3,
+ * Algorithm 1, Sec. VII-B), with the plan as the paper's preprocessing
+ * (Sec. II).  Batching, admission and the plan cache have no counterpart in
+ * the paper.
  *
  * Clients submit requests -- (N = 2^log2_n, J, k host samples on I_r in
  * ascending order) -- from any thread and later collect results.  The server:
