@@ -499,14 +499,34 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  * its coefficients (Eq. alg1_system), in FP64 on the GPU.  Sample complexity
  * mu* 2^s; cost per Lemma 4.
  *
+ * Accuracy of the leaf solves (the paper treats arithmetic as exact).  With
+ * V_v the mu(v) x mu(v) system of node v and D_v the mu* x mu(v) matrix of all
+ * its shifted rows, the FP32 errors of the Hi-DFT outputs reach the
+ * coefficients amplified by at most A = max_v |V_v^{-1}|_2 max_v |D_v|_2 (2-norms,
+ * FP64 on the host at plan creation: Gauss-Jordan inverse and power
+ * iteration, nodes of equal shape analysed once).  The plan's relative error
+ * bound is A (2 + s)/2 u + u, u = 2^-24: (2 + s)/2 u models the FP32 Hi-DFT at
+ * 2^s points (measured 1.75 u at 2^6, 2.5 u at 2^14), the last u the rounding
+ * of the result.  Plans that solve must keep it within HIDFT_SAS_MAX_REL_ERR.
+ *
  * hidft_sas_create: pivots == NULL chooses r: the first t pivots of J (J is
  * part-homogeneous at any such prefix) minimising Lemma 4's cost
- * 1.5 t 2^t mu* + 6 sum_v mu(v)^2 under 2^t <= 2^14 and mu* <= 32; else r is
- * validated (ascending in [0, M); part-homogeneity: NOT_HOMOGENEOUS;
- * 2^s <= 2^14: UNSUPPORTED); hidft_sas_execute refuses plans with mu* > 32
- * (UNSUPPORTED, before any device work).  Device tables are built on the
+ * 1.5 t 2^t mu* + 6 sum_v mu(v)^2 under 2^t <= 2^14, mu* <= 32 and an error
+ * bound <= HIDFT_SAS_MAX_REL_ERR (UNSUPPORTED, naming the best bound, if no
+ * prefix qualifies; r = every pivot gives mu* = 1 and qualifies whenever
+ * J has at most 14 pivots).  Else r is validated (ascending in [0, M);
+ * part-homogeneity: NOT_HOMOGENEOUS; 2^s <= 2^14: UNSUPPORTED) and, unless
+ * HIDFT_SAS_WEIGHTS_ONLY is set, refused with UNSUPPORTED when mu* > 32 or the
+ * error bound exceeds HIDFT_SAS_MAX_REL_ERR (the message names the condition
+ * number and the bound).  A HIDFT_SAS_WEIGHTS_ONLY plan serves
+ * hidft_sas_weights only: it holds no leaf-solve tables, and
+ * hidft_sas_execute refuses it (UNSUPPORTED).  Device tables are built on the
  * current device (synchronously on `stream`) unless HIDFT_PLAN_HOST_ONLY.
- * flags: 0, HIDFT_PLAN_HOST_ONLY and/or HIDFT_SAS_TWO_PASS.
+ * flags: 0 or any of HIDFT_PLAN_HOST_ONLY, HIDFT_SAS_TWO_PASS,
+ * HIDFT_SAS_WEIGHTS_ONLY.
+ * hidft_sas_get_accuracy: the largest condition number |V_v|_2 |V_v^{-1}|_2
+ * over the nodes, the amplification A and the relative error bound (each
+ * +infinity when mu* > 32, where they are not analysed); outputs may be NULL.
  * hidft_sas_get_samples: mu* 2^s sample positions, row j = (I_r + j) mod N
  * in ascending order of I_r: the layout of one signal's samples for execute.
  * hidft_sas_get_nodes: node index of each J[t], and the slot of each node.
@@ -526,7 +546,7 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  * complex128 values); per signal each coefficient is one row of that inverse
  * times the node's mu(v) values, accumulated in FP64.  They inherit the
  * conditioning of the node's Vandermonde matrix (nodes e^{2 pi i l/N} on the
- * unit circle), which the paper leaves open.
+ * unit circle), which the accuracy bound above accounts for.
  * Supports with additive structure (Sec. IX-B, Lemma 5): passing every pivot
  * of J (from hidft_analyze) as r gives mu* = 1 -- each node at level
  * r_max + 1 holds one element -- so the call is the Hi-DFT on all pivots,
@@ -542,6 +562,10 @@ typedef struct hidft_sas_s* hidft_sas;
 #define HIDFT_SAS_TWO_PASS 0x2u  /* hidft_sas_create flag: always run the
                                     shifted Hi-DFTs and the leaf solves as two
                                     launches through the caller's workspace */
+#define HIDFT_SAS_WEIGHTS_ONLY 0x4u  /* hidft_sas_create flag: a plan for
+                                        hidft_sas_weights alone (no leaf
+                                        solves, no accuracy or mu* limit) */
+#define HIDFT_SAS_MAX_REL_ERR 1e-5   /* error bound a solving plan must meet */
 
 hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
                               const uint32_t* pivots, uint32_t n_pivots, uint32_t flags,
@@ -549,6 +573,8 @@ hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
 hidft_status hidft_sas_destroy(hidft_sas plan);
 hidft_status hidft_sas_get_info(hidft_sas plan, uint32_t* n_pivots, uint32_t* mu_max,
                                 uint64_t* n_nodes, uint64_t* samples_per_signal, double* cost);
+hidft_status hidft_sas_get_accuracy(hidft_sas plan, double* cond, double* amplification,
+                                    double* rel_err_bound);
 hidft_status hidft_sas_get_pivots(hidft_sas plan, uint32_t* pivots);
 hidft_status hidft_sas_get_samples(hidft_sas plan, uint64_t* sample_idx);
 hidft_status hidft_sas_get_nodes(hidft_sas plan, uint32_t* node_of_t, uint32_t* slot_of_node);

@@ -477,3 +477,26 @@ def solve_on_samples(M: int, J: Sequence[int], S: Sequence[int], f_S: np.ndarray
     f_S = np.asarray(f_S, dtype=np.complex128)
     sol, *_ = np.linalg.lstsq(A, f_S.T if f_S.ndim == 2 else f_S, rcond=None)
     return sol.T if f_S.ndim == 2 else sol
+
+
+def leaf_systems(M: int, J: Sequence[int], r: Sequence[int]) -> list[tuple[np.ndarray, np.ndarray]]:
+    """The leaf systems of Shift-and-Sample at r (Algorithm 2, Eq. alg1_system),
+    one per node v at level r_max + 1: (V_v, D_v), where D_v[j][t] = z_t^j for
+    the mu* shifts j and z_t = exp(2 pi i l_t / N) for the node's elements l_t
+    (exact integer phase j l_t mod N), and V_v its first mu(v) rows, the square
+    system the solve inverts."""
+    J = check_index_set(M, J)
+    level = (max(r) + 1) if len(r) else 0
+    nodes = list(level_nodes(M, J, level).values())
+    mu_star = max(len(ts) for ts in nodes)
+    out = []
+    for ts in nodes:
+        D = np.exp(2j * np.pi * _phase_fraction(M, range(mu_star), [J[t] for t in ts]))
+        out.append((D[: len(ts)], D))
+    return out
+
+
+def leaf_singular_values(M: int, J: Sequence[int], r: Sequence[int]) -> list[tuple[np.ndarray, np.ndarray]]:
+    """Singular values (LAPACK SVD, descending) of each node's V_v and D_v."""
+    return [(np.linalg.svd(V, compute_uv=False), np.linalg.svd(D, compute_uv=False))
+            for V, D in leaf_systems(M, J, r)]

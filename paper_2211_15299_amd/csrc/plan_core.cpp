@@ -10,7 +10,9 @@
 #include "plan_core.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
+#include <map>
 
 namespace hidft {
 
@@ -165,9 +167,195 @@ static void node_sizes(const uint64_t* J, uint64_t k, uint32_t level, uint64_t* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Conditioning of the leaf systems (Algorithm 2, Eq. alg1_system).
+//
+// Node v at level r_max + 1 holds elements l_0..l_{mu-1}; the mu* shifted
+// Hi-DFTs give y_j(v) = sum_t c_t z_t^j (j < mu*), z_t = exp(2 pi i l_t / N),
+// and the leaf solve inverts the square system of its first mu(v) rows,
+// V_v[j][t] = z_t^j.  With D_v the mu* x mu(v) matrix of all the rows, the
+// FP32 errors dy of the Hi-DFT outputs reach the coefficients as
+//   |dc| <= max_v |V_v^{-1}|_2 |dy|   and   |y| <= max_v |D_v|_2 |c|,
+// so their relative error is at most A = max_v |V_v^{-1}|_2 max_v |D_v|_2
+// times the Hi-DFTs' own relative error.  The paper treats arithmetic as
+// exact; this bound is the library's.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct cd {
+  double re, im;
+};
+inline cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+inline cd cconj_mul(cd a, cd b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }
+inline double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
+
+// exp(2 pi i m / 2^M) for the integer m mod 2^M, the fraction reduced to
+// [-1/2, 1/2) before the angle is formed.
+cd unit_root(uint64_t m, uint32_t M) {
+  const uint64_t mask = M >= 64 ? ~0ULL : ((1ULL << M) - 1);
+  m &= mask;
+  double x = std::ldexp((double)m, -(int)M);
+  if (x >= 0.5) x -= 1.0;
+  const double a = 2.0 * 3.14159265358979323846 * x;
+  return {std::cos(a), std::sin(a)};
+}
+
+// Largest singular value of the rows x cols matrix A (row-major): power
+// iteration on A^H A from a fixed generic start, until the estimate settles.
+double spectral_norm(const std::vector<cd>& A, uint32_t rows, uint32_t cols) {
+  std::vector<cd> x(cols), y(rows), z(cols);
+  for (uint32_t t = 0; t < cols; ++t) x[t] = {std::cos(0.7 + 1.3 * t), std::sin(0.3 + 0.9 * t)};
+  double nx = 0;
+  for (const cd& v : x) nx += cabs2(v);
+  nx = std::sqrt(nx);
+  for (cd& v : x) v = {v.re / nx, v.im / nx};
+  double lam = 0;
+  for (int it = 0; it < 300; ++it) {
+    for (uint32_t j = 0; j < rows; ++j) {
+      cd acc{0, 0};
+      for (uint32_t t = 0; t < cols; ++t) {
+        const cd p = cmul(A[(size_t)j * cols + t], x[t]);
+        acc.re += p.re;
+        acc.im += p.im;
+      }
+      y[j] = acc;
+    }
+    for (uint32_t t = 0; t < cols; ++t) {
+      cd acc{0, 0};
+      for (uint32_t j = 0; j < rows; ++j) {
+        const cd p = cconj_mul(A[(size_t)j * cols + t], y[j]);
+        acc.re += p.re;
+        acc.im += p.im;
+      }
+      z[t] = acc;
+    }
+    double nz = 0;
+    for (const cd& v : z) nz += cabs2(v);
+    nz = std::sqrt(nz);  // = |A^H A x| for |x| = 1, a lower bound of sigma_max^2
+    if (!(nz > 0) || !std::isfinite(nz)) return nz > 0 ? nz : 0.0;
+    for (uint32_t t = 0; t < cols; ++t) x[t] = {z[t].re / nz, z[t].im / nz};
+    const bool settled = std::fabs(nz - lam) <= 1e-10 * nz;
+    lam = nz;
+    if (settled) break;
+  }
+  return std::sqrt(lam);
+}
+
+// Inverse of the n x n matrix A by Gauss-Jordan elimination with partial
+// pivoting; false if a pivot vanishes (the matrix is singular in FP64).
+bool invert(std::vector<cd> A, uint32_t n, std::vector<cd>* inv) {
+  std::vector<cd>& B = *inv;
+  B.assign((size_t)n * n, cd{0, 0});
+  for (uint32_t i = 0; i < n; ++i) B[(size_t)i * n + i] = {1, 0};
+  for (uint32_t c = 0; c < n; ++c) {
+    uint32_t piv = c;
+    for (uint32_t r = c + 1; r < n; ++r)
+      if (cabs2(A[(size_t)r * n + c]) > cabs2(A[(size_t)piv * n + c])) piv = r;
+    const double p2 = cabs2(A[(size_t)piv * n + c]);
+    if (!(p2 > 1e-300)) return false;
+    if (piv != c)
+      for (uint32_t t = 0; t < n; ++t) {
+        std::swap(A[(size_t)piv * n + t], A[(size_t)c * n + t]);
+        std::swap(B[(size_t)piv * n + t], B[(size_t)c * n + t]);
+      }
+    const cd pc = A[(size_t)c * n + c];
+    const cd ip = {pc.re / p2, -pc.im / p2};
+    for (uint32_t t = 0; t < n; ++t) {
+      A[(size_t)c * n + t] = cmul(A[(size_t)c * n + t], ip);
+      B[(size_t)c * n + t] = cmul(B[(size_t)c * n + t], ip);
+    }
+    for (uint32_t r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const cd f = A[(size_t)r * n + c];
+      if (f.re == 0 && f.im == 0) continue;
+      for (uint32_t t = 0; t < n; ++t) {
+        const cd a = cmul(f, A[(size_t)c * n + t]);
+        const cd b = cmul(f, B[(size_t)c * n + t]);
+        A[(size_t)r * n + t].re -= a.re;
+        A[(size_t)r * n + t].im -= a.im;
+        B[(size_t)r * n + t].re -= b.re;
+        B[(size_t)r * n + t].im -= b.im;
+      }
+    }
+  }
+  return true;
+}
+
+struct NodeNorms {
+  double fwd = 1, inv = 1, shifts = 1;  // |V_v|_2, |V_v^{-1}|_2, |D_v|_2
+};
+
+// Norms of one node's systems.  They depend only on the differences
+// l_t - l_0 (a common factor z_0^j scales row j by a unit number), which
+// is the key the caller memoises on.
+NodeNorms node_norms(const std::vector<uint64_t>& diff, uint32_t M, uint32_t mu_star) {
+  const uint32_t mu = (uint32_t)diff.size();
+  NodeNorms n;
+  if (mu == 1) {
+    n.shifts = std::sqrt((double)mu_star);
+    return n;
+  }
+  std::vector<cd> D((size_t)mu_star * mu);
+  for (uint32_t j = 0; j < mu_star; ++j)
+    for (uint32_t t = 0; t < mu; ++t) D[(size_t)j * mu + t] = unit_root((uint64_t)j * diff[t], M);
+  const std::vector<cd> V(D.begin(), D.begin() + (size_t)mu * mu);
+  n.shifts = spectral_norm(D, mu_star, mu);
+  n.fwd = spectral_norm(V, mu, mu);
+  std::vector<cd> W;
+  n.inv = invert(V, mu, &W) ? spectral_norm(W, mu, mu) : HUGE_VAL;
+  return n;
+}
+
+// Nodes of J at `level`: the elements of each class modulo 2^level.
+std::vector<std::vector<uint64_t>> level_nodes(const uint64_t* J, uint64_t k, uint32_t level) {
+  const uint64_t mask = level >= 64 ? ~0ULL : ((1ULL << level) - 1);
+  std::vector<std::pair<uint64_t, uint64_t>> v(k);
+  for (uint64_t t = 0; t < k; ++t) v[t] = {J[t] & mask, J[t]};
+  std::sort(v.begin(), v.end());
+  std::vector<std::vector<uint64_t>> out;
+  for (uint64_t a = 0; a < k;) {
+    uint64_t b = a;
+    std::vector<uint64_t> e;
+    while (b < k && v[b].first == v[a].first) e.push_back(v[b++].second);
+    out.push_back(std::move(e));
+    a = b;
+  }
+  return out;
+}
+
+}  // namespace
+
+double sas_hidft_rel_error(uint32_t s) { return 0.5 * (2.0 + s) * std::ldexp(1.0, -24); }
+
+LeafAccuracy leaf_accuracy(uint32_t M, uint32_t s, const uint64_t* J, uint64_t k,
+                           uint32_t level) {
+  const std::vector<std::vector<uint64_t>> nodes = level_nodes(J, k, level);
+  uint32_t mu_star = 1;
+  for (const auto& e : nodes) mu_star = std::max<uint32_t>(mu_star, (uint32_t)e.size());
+  const uint64_t mask = M >= 64 ? ~0ULL : ((1ULL << M) - 1);
+  std::map<std::vector<uint64_t>, NodeNorms> memo;
+  LeafAccuracy a;
+  a.mu_star = mu_star;
+  double inv_max = 0, shift_max = 0;
+  for (const auto& e : nodes) {
+    std::vector<uint64_t> diff(e.size());
+    for (size_t t = 0; t < e.size(); ++t) diff[t] = (e[t] - e[0]) & mask;
+    auto it = memo.find(diff);
+    if (it == memo.end()) it = memo.emplace(diff, node_norms(diff, M, mu_star)).first;
+    const NodeNorms& n = it->second;
+    a.cond = std::max(a.cond, n.fwd * n.inv);
+    inv_max = std::max(inv_max, n.inv);
+    shift_max = std::max(shift_max, n.shifts);
+  }
+  a.amplification = inv_max * shift_max;
+  a.rel_err_bound = a.amplification * sas_hidft_rel_error(s) + std::ldexp(1.0, -24);
+  if (!std::isfinite(a.rel_err_bound)) a.rel_err_bound = HUGE_VAL;
+  return a;
+}
+
 hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const uint32_t* r,
-                             uint32_t nr, uint32_t max_s, uint32_t max_mu, PartPlan* pp,
-                             std::string* err) {
+                             uint32_t nr, uint32_t max_s, uint32_t max_mu, double max_err,
+                             PartPlan* pp, std::string* err) {
   uint64_t mask = 0;
   hidft_status st = analyze_core(M, J, k, &mask, err);
   if (st != HIDFT_OK) return st;
@@ -176,6 +364,8 @@ hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const ui
     if ((mask >> e) & 1) piv.push_back(e);
 
   std::vector<uint32_t> rv;
+  LeafAccuracy acc;
+  bool have_acc = false;
   if (r != nullptr) {
     for (uint32_t u = 0; u < nr; ++u) {
       if (r[u] >= M || (u > 0 && r[u] <= r[u - 1])) {
@@ -196,27 +386,44 @@ hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const ui
       return HIDFT_ERR_UNSUPPORTED;
     }
   } else {
-    double best = -1;
-    uint32_t best_t = 0;
-    bool found = false;
+    // Candidates t (the first t pivots): mu* <= max_mu, 2^t <= 2^max_s, in
+    // ascending order of Lemma 4's cost; the first whose leaf systems keep
+    // the error bound within max_err wins.
+    struct Cand {
+      double cost;
+      uint32_t t;
+    };
+    std::vector<Cand> cands;
     for (uint32_t t = 0; t <= piv.size() && t <= max_s; ++t) {
       uint64_t mu = 0;
       double sq = 0;
       node_sizes(J, k, t ? piv[t - 1] + 1 : 0, &mu, &sq);
       if (mu > max_mu) continue;
-      const double cost = 1.5 * t * (double)(1ULL << t) * (double)mu + 6.0 * sq;
-      if (!found || cost < best) {
-        best = cost;
-        best_t = t;
-        found = true;
+      cands.push_back({1.5 * t * (double)(1ULL << t) * (double)mu + 6.0 * sq, t});
+    }
+    std::stable_sort(cands.begin(), cands.end(),
+                     [](const Cand& a, const Cand& b) { return a.cost < b.cost; });
+    bool found = false;
+    double best_bound = HUGE_VAL;
+    for (const Cand& c : cands) {
+      const LeafAccuracy a = leaf_accuracy(M, c.t, J, k, c.t ? piv[c.t - 1] + 1 : 0);
+      best_bound = std::min(best_bound, a.rel_err_bound);
+      if (a.rel_err_bound <= max_err) {
+        rv.assign(piv.begin(), piv.begin() + c.t);
+        acc = a;
+        have_acc = found = true;
+        break;
       }
     }
     if (!found) {
-      set_err(err, "no prefix of the pivots of J keeps mu* <= %llu with 2^s <= 2^%llu",
-              max_mu, max_s);
+      char buf[320];
+      std::snprintf(buf, sizeof buf,
+                    "no prefix of the pivots of J keeps mu* <= %u with 2^s <= 2^%u and the "
+                    "leaf systems' error bound within %.1e (best bound %.3e)",
+                    max_mu, max_s, max_err, best_bound);
+      if (err) *err = buf;
       return HIDFT_ERR_UNSUPPORTED;
     }
-    rv.assign(piv.begin(), piv.begin() + best_t);
   }
 
   const uint32_t s = (uint32_t)rv.size();
@@ -269,6 +476,15 @@ hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const ui
     a = b;
   }
   pp->cost = 1.5 * s * (double)(1ULL << s) * pp->mu_max + 6.0 * sq;
+  if (!have_acc) {
+    if (pp->mu_max <= max_mu) {
+      acc = leaf_accuracy(M, s, J, k, level);
+    } else {  // too large for the leaf solver: not analysed
+      acc.mu_star = pp->mu_max;
+      acc.cond = acc.amplification = acc.rel_err_bound = HUGE_VAL;
+    }
+  }
+  pp->leaf = acc;
 
   // Sample set I_r ascending, as in build_plan_core.
   const uint64_t ks = 1ULL << s;

@@ -33,6 +33,28 @@ hidft_status analyze_core(uint32_t M, const uint64_t* J, uint64_t k,
 hidft_status build_plan_core(uint32_t M, const uint64_t* J, uint64_t k,
                              uint32_t max_log2_k, PlanCore* pc, std::string* err);
 
+// Accuracy of Shift-and-Sample's leaf solves at one level (Algorithm 2,
+// Eq. alg1_system): with V_v the mu(v) x mu(v) system of node v and D_v its
+// mu* x mu(v) matrix of all shifted rows, the coefficients' relative error is
+// at most `amplification` = max_v |V_v^{-1}|_2 max_v |D_v|_2 times that of the
+// FP32 Hi-DFT outputs.  rel_err_bound adds the model of the latter
+// (sas_hidft_rel_error) and the final rounding to FP32.
+struct LeafAccuracy {
+  uint32_t mu_star = 1;
+  double cond = 1;           // max_v |V_v|_2 |V_v^{-1}|_2
+  double amplification = 1;
+  double rel_err_bound = 0;
+};
+
+// Relative error model of the FP32 Hi-DFT at 2^s points: (2 + s) / 2 units of
+// FP32 roundoff (measured: 1.75 units at 2^6 points, 2.5 at 2^14).
+double sas_hidft_rel_error(uint32_t s);
+
+// Leaf accuracy of J's nodes at `level` with 2^s-point Hi-DFTs.  O(sum_v
+// mu(v)^3) FP64 work; nodes of equal shape are analysed once.
+LeafAccuracy leaf_accuracy(uint32_t M, uint32_t s, const uint64_t* J, uint64_t k,
+                           uint32_t level);
+
 // Plan of the Hi-DFT at a pivot vector r of an r-part-homogeneous J
 // (Sec. VI Def. part-homogeneous, Sec. VII-B, Algorithm 2): nodes of T(J) at
 // level r_max + 1 are indexed by the slot q = sum_u bit_{r_u}(residue) 2^{u-1},
@@ -54,14 +76,17 @@ struct PartPlan {
   std::vector<uint32_t> node_count; // mu(v)
   std::vector<uint32_t> elem_t;     // caller positions, grouped by node, ascending within
   double cost = 0;                  // Lemma 4 with c1 = 3/2, c2 = 6
+  LeafAccuracy leaf;                // conditioning of the leaf systems (infinite if mu* > max_mu)
 };
 
 // Builds the plan.  If r == nullptr the pivot vector is chosen: the first t
 // pivots of J (J is part-homogeneous at any such prefix) for the t that
-// minimises Lemma 4's cost among those with mu* <= max_mu and t <= max_s.
-// A given r is only checked for part-homogeneity and |r| <= max_s.
+// minimises Lemma 4's cost among those with mu* <= max_mu, t <= max_s and a
+// leaf error bound <= max_err (UNSUPPORTED if there is none).  A given r is
+// only checked for part-homogeneity and |r| <= max_s; its accuracy is
+// recorded (when mu* <= max_mu) for the caller to judge.
 hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const uint32_t* r,
-                             uint32_t nr, uint32_t max_s, uint32_t max_mu, PartPlan* pp,
-                             std::string* err);
+                             uint32_t nr, uint32_t max_s, uint32_t max_mu, double max_err,
+                             PartPlan* pp, std::string* err);
 
 }  // namespace hidft

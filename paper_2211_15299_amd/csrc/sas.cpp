@@ -27,6 +27,7 @@ struct hidft_sas_s {
   void* d_inv = nullptr;            // inverse dual Vandermonde matrices, FP64
   uint4* d_elem_rec = nullptr;      // per element: {v | t << 16, row offset, mu(v), 0}
   bool fused = false;               // one kernel per launch, no workspace
+  bool weights_only = false;        // HIDFT_SAS_WEIGHTS_ONLY: no leaf-solve tables
   size_t device_bytes = 0;
 };
 
@@ -74,6 +75,28 @@ hidft_status upload(hidft_sas p, hipStream_t st) {
   const uint32_t n_nodes = (uint32_t)c.node_slot.size();
   std::vector<uint16_t> src(ks), src_node(ks, 0), src_elem;
   for (uint64_t t = 0; t < ks; ++t) src[t] = (uint16_t)hidft::bit_reverse(t, c.s);
+  if (p->weights_only) {
+    // The Hi-DFT alone: twiddles and the slot-order gather table.
+    uint64_t* d_num = nullptr;
+    uint8_t* d_den = nullptr;
+    size_t total = 0, tmp = 0;
+    hidft_status status = HIDFT_OK;
+    if ((e = hipMalloc(&p->d_tw, (ntw ? ntw : 1) * sizeof(float2))) != hipSuccess ||
+        (e = upload_vec(&d_num, num, st, &tmp)) != hipSuccess ||
+        (e = upload_vec(&d_den, den, st, &tmp)) != hipSuccess ||
+        (e = upload_vec(&p->d_src, src, st, &total)) != hipSuccess ||
+        (e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      status = hidft::hip_error(e, "hidft_sas_create: table upload");
+    if (d_num) (void)hipFree(d_num);
+    if (d_den) (void)hipFree(d_den);
+    if (status != HIDFT_OK) {
+      release(p);
+      return status;
+    }
+    p->device_bytes = total + (ntw ? ntw : 1) * sizeof(float2);
+    return HIDFT_OK;
+  }
   for (uint32_t v = 0; v < n_nodes; ++v)
     src_node[v] = (uint16_t)hidft::bit_reverse(c.node_slot[v], c.s);
   std::vector<uint64_t> elem_val(c.k);
@@ -184,7 +207,7 @@ hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
                               void* stream, hidft_sas* out) {
   if (!out) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_create: out is NULL");
   *out = nullptr;
-  if (flags & ~(HIDFT_PLAN_HOST_ONLY | HIDFT_SAS_TWO_PASS))
+  if (flags & ~(HIDFT_PLAN_HOST_ONLY | HIDFT_SAS_TWO_PASS | HIDFT_SAS_WEIGHTS_ONLY))
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_create: unknown flags");
   hidft_sas p = nullptr;
   try {
@@ -192,13 +215,33 @@ hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
     std::string err;
     hidft_status st = hidft::build_part_plan(log2_n, J, k, pivots, n_pivots,
                                              HIDFT_MAX_LOG2_K_DEVICE, HIDFT_SAS_MAX_MU,
-                                             &p->core, &err);
+                                             HIDFT_SAS_MAX_REL_ERR, &p->core, &err);
     if (st != HIDFT_OK) {
       delete p;
       return hidft::set_error(st, "hidft_sas_create: " + err);
     }
+    p->weights_only = (flags & HIDFT_SAS_WEIGHTS_ONLY) != 0;
+    if (!p->weights_only) {
+      // A plan that will solve must be solvable within the accuracy target.
+      const hidft::LeafAccuracy& a = p->core.leaf;
+      char buf[320];
+      buf[0] = 0;
+      if (p->core.mu_max > HIDFT_SAS_MAX_MU)
+        std::snprintf(buf, sizeof buf,
+                      "mu* = %u exceeds the leaf solver's %u (HIDFT_SAS_WEIGHTS_ONLY plans "
+                      "compute the Hi-DFT alone)", p->core.mu_max, HIDFT_SAS_MAX_MU);
+      else if (!(a.rel_err_bound <= HIDFT_SAS_MAX_REL_ERR))
+        std::snprintf(buf, sizeof buf,
+                      "the leaf systems at r are ill-conditioned: condition number %.3e, "
+                      "error amplification %.3e, relative error bound %.3e > %.1e",
+                      a.cond, a.amplification, a.rel_err_bound, HIDFT_SAS_MAX_REL_ERR);
+      if (buf[0]) {
+        delete p;
+        return hidft::set_error(HIDFT_ERR_UNSUPPORTED, std::string("hidft_sas_create: ") + buf);
+      }
+    }
     p->scale = std::ldexp(1.0f, (int)p->core.M - (int)p->core.s);
-    p->fused = !(flags & HIDFT_SAS_TWO_PASS) &&
+    p->fused = !p->weights_only && !(flags & HIDFT_SAS_TWO_PASS) &&
                hidft::sas_fused_fits(p->core.s, p->core.mu_max,
                                      (uint32_t)p->core.node_slot.size(), (uint32_t)p->core.k);
     if (!(flags & HIDFT_PLAN_HOST_ONLY)) {
@@ -237,6 +280,16 @@ hidft_status hidft_sas_get_info(hidft_sas p, uint32_t* n_pivots, uint32_t* mu_ma
   return hidft::set_error(HIDFT_OK, "");
 }
 
+hidft_status hidft_sas_get_accuracy(hidft_sas p, double* cond, double* amplification,
+                                    double* rel_err_bound) {
+  if (!p)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_get_accuracy: plan is NULL");
+  if (cond) *cond = p->core.leaf.cond;
+  if (amplification) *amplification = p->core.leaf.amplification;
+  if (rel_err_bound) *rel_err_bound = p->core.leaf.rel_err_bound;
+  return hidft::set_error(HIDFT_OK, "");
+}
+
 hidft_status hidft_sas_get_pivots(hidft_sas p, uint32_t* pivots) {
   if (!p || !pivots)
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_get_pivots: NULL argument");
@@ -269,7 +322,7 @@ hidft_status hidft_sas_workspace_bytes(hidft_sas p, uint64_t batch, size_t* byte
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_workspace_bytes: NULL");
   // [signal][shift][node]; none when every node holds one element (mu* = 1)
   // or when the plan runs as one kernel.
-  *bytes = p->core.mu_max == 1 || p->fused
+  *bytes = p->core.mu_max == 1 || p->fused || p->weights_only
                ? 0
                : (size_t)batch * p->core.mu_max * p->core.node_slot.size() * sizeof(float2);
   return hidft::set_error(HIDFT_OK, "");
@@ -291,57 +344,57 @@ hidft_status hidft_sas_weights(hidft_sas p, const void* d_samples, int64_t ld_in
   return hidft::set_error(HIDFT_OK, "");
 }
 
-hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in, void* d_coefs,
-                               int64_t ld_out, uint64_t batch, void* d_work, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Validation shared by the execute entry points (HIDFT_OK with batch == 0
+// means there is nothing to do).
+hidft_status check_execute(hidft_sas p, const void* d_samples, int64_t ld_in, void* d_coefs,
+                           int64_t ld_out, uint64_t batch, const char* fn) {
   const uint64_t ks = p ? (1ULL << p->core.s) : 0;
   const uint64_t mu = p ? p->core.mu_max : 0;
   if (p && mu > HIDFT_SAS_MAX_MU)
     return hidft::set_error(HIDFT_ERR_UNSUPPORTED,
-                            "hidft_sas_execute: mu* = " + std::to_string(mu) +
+                            std::string(fn) + ": mu* = " + std::to_string(mu) +
                                 " exceeds the leaf solver's " + std::to_string(HIDFT_SAS_MAX_MU));
   hidft_status st = check_rows(p, d_samples, ld_in, mu * ks, d_coefs, ld_out, p ? p->core.k : 0,
-                               batch, "hidft_sas_execute");
-  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? hidft::set_error(HIDFT_OK, "") : st;
+                               batch, fn);
+  if (st != HIDFT_OK || batch == 0) return st;
   if (!p->d_tw)
-    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_execute: HOST_ONLY plan");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const float2* in = static_cast<const float2*>(d_samples);
-  float2* coefs = static_cast<float2*>(d_coefs);
-  hipError_t e = hipSuccess;
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, std::string(fn) + ": HOST_ONLY plan");
+  if (p->weights_only)
+    return hidft::set_error(HIDFT_ERR_UNSUPPORTED,
+                            std::string(fn) + ": the plan was created for the induced weights only");
+  return HIDFT_OK;
+}
+
+// The paths that need no workspace: mu* = 1 (the Hi-DFT gathered into the
+// caller's order of J is the answer) and the one-kernel form.
+hidft_status run_direct(hidft_sas p, const float2* in, int64_t ld_in, float2* coefs,
+                        int64_t ld_out, uint64_t batch, hipStream_t s, const char* fn) {
+  const uint64_t mu = p->core.mu_max;
+  hipError_t e;
   if (mu == 1) {
-    // One element per node: the Hi-DFT, gathered straight into the caller's
-    // order of J, is the answer (no workspace, no solve).
     e = hidft::launch_fused(p->core.s, in, ld_in, coefs, ld_out, batch, p->d_tw, p->d_src_elem,
                             nullptr, p->scale, hidft::ExecConfig{}, s, (uint32_t)p->core.k);
-    if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
-    return hidft::set_error(HIDFT_OK, "");
-  }
-  const uint64_t nn = p->core.node_slot.size();
-  if (p->fused) {
+  } else {
     // Shifted Hi-DFTs and leaf solves in one kernel, node values in LDS.
     e = hidft::launch_sas_fused(p->core.s, in, ld_in, coefs, ld_out, batch, (uint32_t)mu,
-                                (uint32_t)nn, (uint32_t)p->core.k, p->d_tw, p->d_src_node,
-                                p->scale, p->d_elem_rec, p->d_inv, s);
-    if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
-    return hidft::set_error(HIDFT_OK, "");
+                                (uint32_t)p->core.node_slot.size(), (uint32_t)p->core.k, p->d_tw,
+                                p->d_src_node, p->scale, p->d_elem_rec, p->d_inv, s);
   }
-  if (!d_work || (reinterpret_cast<uintptr_t>(d_work) & 7u))
-    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
-                            "hidft_sas_execute: workspace missing or misaligned");
-  {
-    // The workspace is written while the samples are read and read while the
-    // coefficients are written: it must overlap neither.
-    const uint64_t w0 = reinterpret_cast<uintptr_t>(d_work);
-    const uint64_t w1 = w0 + batch * mu * nn * sizeof(float2);
-    const uint64_t a0 = reinterpret_cast<uintptr_t>(d_samples);
-    const uint64_t a1 = a0 + ((batch - 1) * (uint64_t)ld_in + mu * ks) * sizeof(float2);
-    const uint64_t b0 = reinterpret_cast<uintptr_t>(d_coefs);
-    const uint64_t b1 = b0 + ((batch - 1) * (uint64_t)ld_out + p->core.k) * sizeof(float2);
-    if ((w0 < a1 && a0 < w1) || (w0 < b1 && b0 < w1))
-      return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
-                              "hidft_sas_execute: workspace overlaps the samples or coefficients");
-  }
-  float2* work = static_cast<float2*>(d_work);
+  if (e != hipSuccess) return hidft::hip_error(e, fn);
+  return hidft::set_error(HIDFT_OK, "");
+}
+
+// The two-launch form through a workspace of batch mu* n_nodes values.
+hipError_t run_two_pass(hidft_sas p, const float2* in, int64_t ld_in, float2* coefs,
+                        int64_t ld_out, uint64_t batch, float2* work, hipStream_t s) {
+  const uint64_t ks = 1ULL << p->core.s;
+  const uint64_t mu = p->core.mu_max;
+  const uint64_t nn = p->core.node_slot.size();
+  hipError_t e = hipSuccess;
   // Steps 2-4: the mu* shifted Hi-DFTs, each gathered in node order (the
   // first nn outputs), as one batched launch when the rows are packed, else
   // one launch per shift.
@@ -360,6 +413,42 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
     e = hidft::launch_sas_apply(work, (uint32_t)nn, (uint32_t)mu, batch, (uint32_t)p->core.k,
                                 p->d_elem_node, p->d_node_first, p->d_node_count, p->d_inv_off,
                                 p->d_inv, p->d_elem_t, p->d_elem_rec, coefs, ld_out, s);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in, void* d_coefs,
+                               int64_t ld_out, uint64_t batch, void* d_work, void* stream) {
+  const char* fn = "hidft_sas_execute";
+  hidft_status st = check_execute(p, d_samples, ld_in, d_coefs, ld_out, batch, fn);
+  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? hidft::set_error(HIDFT_OK, "") : st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float2* in = static_cast<const float2*>(d_samples);
+  float2* coefs = static_cast<float2*>(d_coefs);
+  if (p->core.mu_max == 1 || p->fused) return run_direct(p, in, ld_in, coefs, ld_out, batch, s, fn);
+  const uint64_t ks = 1ULL << p->core.s;
+  const uint64_t mu = p->core.mu_max;
+  const uint64_t nn = p->core.node_slot.size();
+  if (!d_work || (reinterpret_cast<uintptr_t>(d_work) & 7u))
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                            "hidft_sas_execute: workspace missing or misaligned");
+  {
+    // The workspace is written while the samples are read and read while the
+    // coefficients are written: it must overlap neither.
+    const uint64_t w0 = reinterpret_cast<uintptr_t>(d_work);
+    const uint64_t w1 = w0 + batch * mu * nn * sizeof(float2);
+    const uint64_t a0 = reinterpret_cast<uintptr_t>(d_samples);
+    const uint64_t a1 = a0 + ((batch - 1) * (uint64_t)ld_in + mu * ks) * sizeof(float2);
+    const uint64_t b0 = reinterpret_cast<uintptr_t>(d_coefs);
+    const uint64_t b1 = b0 + ((batch - 1) * (uint64_t)ld_out + p->core.k) * sizeof(float2);
+    if ((w0 < a1 && a0 < w1) || (w0 < b1 && b0 < w1))
+      return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                              "hidft_sas_execute: workspace overlaps the samples or coefficients");
+  }
+  hipError_t e = run_two_pass(p, in, ld_in, coefs, ld_out, batch, static_cast<float2*>(d_work), s);
   if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
   return hidft::set_error(HIDFT_OK, "");
 }

@@ -26,6 +26,8 @@ LIB_PATH = os.path.join(HERE, "libhidft.so")
 
 HIDFT_PLAN_HOST_ONLY = 0x1
 HIDFT_SAS_TWO_PASS = 0x2
+HIDFT_SAS_WEIGHTS_ONLY = 0x4
+SAS_MAX_REL_ERR = 1e-5
 MAX_LOG2_K_DEVICE = 14
 
 # Execution variants (hidft_exec_config)
@@ -87,6 +89,9 @@ SIGNATURES = [
     ("hidft_sas_get_info", ctypes.c_int, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32),
                                           ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                                           ctypes.POINTER(ctypes.c_double)]),
+    ("hidft_sas_get_accuracy", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double)]),
     ("hidft_sas_get_pivots", ctypes.c_int, [_vp, ctypes.POINTER(_u32)]),
     ("hidft_sas_get_samples", ctypes.c_int, [_vp, ctypes.POINTER(_u64)]),
     ("hidft_sas_get_nodes", ctypes.c_int, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
@@ -453,13 +458,14 @@ class Server:
 class SASPlan:
     """Shift-and-Sample plan of a part-homogeneous support (hidft_sas_*).
 
-    pivots=None lets the planner choose r (Lemma 4's cost).  two_pass=True
-    keeps the shifted Hi-DFTs and the leaf solves in two launches through a
-    workspace even where the plan could run as one kernel.
+    pivots=None lets the planner choose r (Lemma 4's cost within the accuracy
+    bound).  two_pass=True keeps the shifted Hi-DFTs and the leaf solves in
+    two launches through a workspace even where the plan could run as one
+    kernel.  weights_only=True makes a plan for the induced weights alone.
     """
 
     def __init__(self, log2_n: int, J: Sequence[int], pivots=None, host_only: bool = False,
-                 stream=None, two_pass: bool = False):
+                 stream=None, two_pass: bool = False, weights_only: bool = False):
         arr = _u64_array(J)
         self._h = ctypes.c_void_p(None)
         if pivots is None:
@@ -468,7 +474,8 @@ class SASPlan:
             self._r = np.zeros(max(len(pivots), 1), dtype=np.uint32)
             self._r[: len(pivots)] = pivots
             rp, nr = _ptr(self._r, _u32), len(pivots)
-        flags = (HIDFT_PLAN_HOST_ONLY if host_only else 0) | (HIDFT_SAS_TWO_PASS if two_pass else 0)
+        flags = ((HIDFT_PLAN_HOST_ONLY if host_only else 0) | (HIDFT_SAS_TWO_PASS if two_pass else 0)
+                 | (HIDFT_SAS_WEIGHTS_ONLY if weights_only else 0))
         _check(lib().hidft_sas_create(log2_n, _ptr(arr, _u64), len(arr), rp, nr, flags,
                                       None if host_only else _stream_handle(stream),
                                       ctypes.byref(self._h)))
@@ -479,6 +486,10 @@ class SASPlan:
         self.log2_n, self.k = log2_n, len(arr)
         self.s, self.mu_max, self.n_nodes = s.value, mu.value, nn.value
         self.samples_per_signal, self.cost = sp.value, cost.value
+        cond, amp, bound = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        _check(lib().hidft_sas_get_accuracy(self._h, ctypes.byref(cond), ctypes.byref(amp),
+                                            ctypes.byref(bound)))
+        self.leaf_cond, self.amplification, self.err_bound = cond.value, amp.value, bound.value
 
     def pivots(self):
         out = np.zeros(max(self.s, 1), dtype=np.uint32)

@@ -4,8 +4,9 @@
 2^12..2^24, k log-uniform over 2^6..2^14 with k <= N/4, plus composite
 supports (direct sums of homogeneous blocks on disjoint bit ranges).  Every
 instance is checked bit-for-bit against the single-plan fused path (itself
-checked against the oracle), every instance on the energy identity, and a
-sample of instances against the FP64 oracle directly.
+checked against the oracle), every instance on the energy identity and on
+64 seeded coefficient positions against the FP64 oracle (all of them when
+k <= 64), and a sample of instances on every coefficient.
 """
 import sys
 
@@ -13,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.positions import positions_vs_oracle
 from workloads import homogeneous_support, rng_for, sample_values, uneven_instances
 
 pytestmark = pytest.mark.gpu
@@ -114,6 +116,15 @@ def test_config3_uneven_batch_one_launch():
             errs.append(float(oracle.rel_l2(got[i][sel], want)))
     _say(f"C3: oracle on {len(errs)} instances, rel-L2 max {max(errs):.3e}")
     assert max(errs) <= 1e-5
+    # every instance on 64 positions of its own
+    prng = rng_for(3, 4242)
+    per_inst = []
+    for i, (M, J, _) in enumerate(insts):
+        f = xs[i].cpu().numpy()[None, :]
+        per_inst.append(positions_vs_oracle(M, J, plans[i].samples().tolist(), f,
+                                            got[i][None, :], 64, prng)[0])
+    _say(f"C3: all {len(insts)} instances on 64 positions each: rel-L2 max {max(per_inst):.3e}")
+    assert max(per_inst) <= 1e-5
     grp.close()
     for p in plans:
         p.close()

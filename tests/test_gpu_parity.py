@@ -2,10 +2,11 @@
 
 Bar: relative L2 error <= 1e-5 per transform (FP32 arithmetic), reported with
 the max-abs error.  Inputs come from the seeded generators; expected values
-come only from the oracle.  Large configurations are checked on sampled
-transforms (all outputs of each sampled transform) and, for every transform,
-on the energy identity ||c||^2 = (N^2/k) ||f_I||^2, which holds for any
-samples because F(J, I_r) is k times a unitary matrix (Lemma 1).
+come only from the oracle.  Large configurations are checked in full on
+sampled transforms, and every transform on 64 seeded positions of its own
+(tests/positions.py) and on the energy identity ||c||^2 = (N^2/k) ||f_I||^2,
+which holds for any samples because F(J, I_r) is k times a unitary matrix
+(Lemma 1).
 """
 import sys
 
@@ -13,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.positions import positions_vs_oracle
 from workloads import (complex_normal, elementary_support, homogeneous_support,
                        log_uniform_coefficients, rng_for, sample_values)
 
@@ -152,6 +154,10 @@ def test_config2_full_size():
     want = oracle.adjoint_coefficients(M, J, I, f[rows])
     err = _check(got[rows], want, "C2 sampled transforms")
     _energy_ok(got, f, M, k)
+    # every transform on 64 positions of its own
+    per_row = positions_vs_oracle(M, J, I, f, got, 64, rng_for(2, 1))
+    _say(f"C2: all {batch} transforms on 64 positions each: rel-L2 max {per_row.max():.3e}")
+    assert per_row.shape == (batch,) and per_row.max() <= TOL
     # seeded-coefficient recovery for a few signals
     c = complex_normal((3, k), rng)
     fs = oracle.synthesize_samples(M, J, c, I)
@@ -185,6 +191,9 @@ def test_config4_precision_fp32():
     got = _run(plan, f)
     _check(got[:n_exact], c, "C4 seeded recovery (FP32)")
     _energy_ok(got, f.astype(np.complex64), M, k)
+    per_row = positions_vs_oracle(M, J, I, f, got, 64, rng_for(4, 1))
+    _say(f"C4: all {batch} transforms on 64 positions each: rel-L2 max {per_row.max():.3e}")
+    assert per_row.max() <= TOL
 
 
 # --------------------------------------------------------------- properties

@@ -2,7 +2,10 @@
 
 Expected values come from the FP64 oracle: induced weights (Sec. VI) for the
 Hi-DFT, and the dense solve of the submatrix system on the Shift-and-Sample
-samples (or the seeded coefficients) for Algorithm 2.
+samples (or the seeded coefficients) for Algorithm 2.  Every solving plan the
+library accepts carries a relative error bound of at most 1e-5 (the leaf
+systems' amplification times the FP32 Hi-DFT's error model); each recovery
+is checked against that plan's own bound, so against 1e-5 or tighter.
 """
 import numpy as np
 import pytest
@@ -51,7 +54,7 @@ def test_section_ix_example():
     S = plan.samples().tolist()
     f = oracle.synthesize_samples(M, J, c, S)
     got = _sas_run(plan, f)
-    assert np.max(oracle.rel_l2(got, c)) <= 1e-5
+    assert np.max(oracle.rel_l2(got, c)) <= plan.err_bound <= 1e-5
     plan.close()
 
 
@@ -69,10 +72,11 @@ def test_sas_random_subsets_of_homogeneous_sets(seed):
     f = oracle.synthesize_samples(M, J, c, S)
     got = _sas_run(plan, f)
     err = oracle.rel_l2(got, c)
-    assert np.max(err) <= 1e-4, (plan.pivots(), plan.mu_max, np.max(err))
+    assert plan.err_bound <= 1e-5
+    assert np.max(err) <= plan.err_bound, (plan.pivots(), plan.mu_max, np.max(err))
     if len(J) <= 1500:
         want = oracle.solve_on_samples(M, J, S, f[:1].astype(np.complex64).astype(np.complex128))
-        assert oracle.rel_l2(got[0], want[0]) <= 1e-4
+        assert oracle.rel_l2(got[0], want[0]) <= plan.err_bound
     plan.close()
 
 
@@ -90,7 +94,7 @@ def test_sas_unions_of_shifted_homogeneous_blocks():
         S = plan.samples().tolist()
         c = complex_normal((2, len(J)), rng)
         got = _sas_run(plan, oracle.synthesize_samples(M, J, c, S))
-        assert np.max(oracle.rel_l2(got, c)) <= 1e-4
+        assert np.max(oracle.rel_l2(got, c)) <= plan.err_bound <= 1e-5
         plan.close()
 
 
@@ -104,7 +108,8 @@ def test_induced_weights_and_height_n():
         c = complex_normal(len(J), rng)
         for n in range(0, len(K.levels) + 1, 2):
             r = list(K.levels[: len(K.levels) - n])
-            plan = native.SASPlan(M, J, pivots=r)
+            # the Hi-DFT alone: any r, leaf systems not needed
+            plan = native.SASPlan(M, J, pivots=r, weights_only=True)
             ks = 1 << plan.s
             I = sorted(oracle.sample_pattern_recursive(M, r))
             f = oracle.synthesize_samples(M, J, c, I)[None, :]
@@ -123,6 +128,43 @@ def test_induced_weights_and_height_n():
             plan.close()
 
 
+@pytest.mark.parametrize("seed", range(24))
+def test_error_bound_holds_on_accepted_plans(seed):
+    """Across seeded random subsets and explicit pivot prefixes (many near
+    or beyond the accuracy target), every plan the library accepts recovers
+    seeded coefficients within its own error bound, for circular normal
+    coefficients and for magnitudes spread over six decades; the refused
+    prefixes have bounds above 1e-5."""
+    rng = rng_for(822, seed)
+    M = int(rng.integers(10, 21))
+    K, J = _subset(rng, M, int(rng.integers(5, min(M - 1, 12) + 1)), rng.uniform(0.3, 0.9))
+    P, _ = native.analyze(M, J)
+    tried = 0
+    for t in range(max(0, len(P) - 6), min(len(P), 14) + 1):
+        r = P[:t]
+        probe = native.SASPlan(M, J, pivots=r, host_only=True, weights_only=True)
+        if probe.mu_max > 32:
+            continue
+        if probe.err_bound > 1e-5:
+            with pytest.raises(native.HiDFTError) as ei:
+                native.SASPlan(M, J, pivots=r)
+            assert ei.value.status_name == "HIDFT_ERR_UNSUPPORTED"
+            continue
+        plan = native.SASPlan(M, J, pivots=r)
+        assert plan.err_bound == probe.err_bound
+        S = plan.samples().tolist()
+        c = complex_normal((3, len(J)), rng)
+        c[2] *= 10.0 ** rng.uniform(-3, 3, size=len(J))      # six decades of magnitude
+        f = oracle.synthesize_samples_fft(M, J, c, S)
+        err = oracle.rel_l2(_sas_run(plan, f), c)
+        print(f"  M={M} k={len(J)} r={r} mu*={plan.mu_max} cond={plan.leaf_cond:.3g} "
+              f"bound={plan.err_bound:.2e} err={np.max(err):.2e}", flush=True)
+        assert np.max(err) <= plan.err_bound, (r, plan.mu_max, np.max(err), plan.err_bound)
+        plan.close()
+        tried += 1
+    assert tried >= 1
+
+
 # Cases of each leaf-solve kernel form, chosen on the CPU from the node
 # structure: (rng config, seed, M, s, kept fraction or explicit split levels,
 # pivot prefix length).
@@ -131,10 +173,9 @@ def test_induced_weights_and_height_n():
 #   lds_generic_mu: one block per signal, mu* = 32 (a loop over mu(v)).  Its
 #       support splits at bits 0-3 and 9-13, so with r = (0, 1, 2, 3) every
 #       node is a full coset of the top five bits: equispaced points on the
-#       circle, a leaf system with condition number 1.  (A random subset
-#       with mu* = 26 has leaf condition numbers near 6e6, which turns the
-#       FP32 Hi-DFT's rounding into errors of order 1e-2: a property of the
-#       problem, which the paper leaves open, not of the kernel.)
+#       circle, a leaf system with condition number 1.  (A random subset of
+#       that set has far worse leaf systems -- condition number 1.7e3 for an
+#       80 % subset -- and the planner refuses it at this r.)
 #   per_element: mu* n_nodes + k > 8192 values, one thread per element.
 APPLY_CASES = {
     "lds_mu4_ept1": (816, 0, 12, 8, 0.6, 6),
@@ -146,22 +187,11 @@ APPLY_CASES = {
 APPLY_EPT = {"lds_mu4_ept1": (0, 1), "lds_mu4_ept4": (2, 4), "lds_mu2_ept8": (4, 8)}
 
 
-def _leaf_condition(M, J, r):
-    """Largest condition number over the nodes' dual Vandermonde systems
-    (rows z_t^j, j < mu(v), z_t = exp(2 pi i l_t / N))."""
-    worst = 1.0
-    for ts in oracle.level_nodes(M, J, max(r) + 1).values():
-        z = np.exp(2j * np.pi * np.array([J[t] for t in ts], dtype=np.float64) / (1 << M))
-        V = z[None, :] ** np.arange(len(ts))[:, None]
-        worst = max(worst, float(np.linalg.cond(V)))
-    return worst
-
-
 @pytest.mark.parametrize("name", sorted(APPLY_CASES))
 def test_sas_leaf_solve_kernel_forms(name):
     """Each form of the leaf-solve kernel recovers seeded coefficients from
-    samples the oracle synthesised on the plan's sample set (well-conditioned
-    leaf systems, checked here)."""
+    samples the oracle synthesised on the plan's sample set, within the plan's
+    error bound (the cases are accepted: bound <= 1e-5)."""
     cfg, seed, M, s, sel, npiv = APPLY_CASES[name]
     rng = rng_for(cfg, seed)
     if isinstance(sel, tuple):
@@ -170,8 +200,8 @@ def test_sas_leaf_solve_kernel_forms(name):
         K, J = _subset(rng, M, s, sel)
     P, _ = native.analyze(M, J)
     r = P[:npiv]
-    assert _leaf_condition(M, J, r) < 100
     plan = native.SASPlan(M, J, pivots=r, two_pass=True)
+    assert plan.err_bound <= 1e-5
     mu, nn, k = plan.mu_max, plan.n_nodes, plan.k
     fits_lds = mu * nn + k <= 8192
     per_thread = -(-k // 512)
@@ -187,7 +217,7 @@ def test_sas_leaf_solve_kernel_forms(name):
     f = oracle.synthesize_samples_fft(M, J, c, S)
     got = _sas_run(plan, f)
     err = oracle.rel_l2(got, c)
-    assert np.max(err) <= 1e-4, (name, mu, nn, k, np.max(err))
+    assert np.max(err) <= plan.err_bound, (name, mu, nn, k, np.max(err), plan.err_bound)
     plan.close()
 
 
@@ -242,8 +272,7 @@ def test_sas_one_kernel_form_matches_two_launches(case):
     c = complex_normal((2, one.k), rng)
     f = oracle.synthesize_samples_fft(M, J, c, S)
     got = _sas_run(one, f)
-    if _leaf_condition(M, J, r) < 100:
-        assert np.max(oracle.rel_l2(got, c)) <= 1e-4
+    assert np.max(oracle.rel_l2(got, c)) <= one.err_bound <= 1e-5
     one.close()
     two.close()
 
@@ -280,7 +309,7 @@ def test_sas_one_kernel_form_at_every_size(s):
     torch.cuda.synchronize()
     assert torch.equal(y1.view(torch.float32), y2.view(torch.float32))
     err = oracle.rel_l2(y1.cpu().numpy().astype(np.complex128), c)
-    assert np.max(err) <= 1e-5, (s, np.max(err))
+    assert np.max(err) <= one.err_bound <= 1e-5, (s, np.max(err), one.err_bound)
     one.close()
     two.close()
 
@@ -290,7 +319,9 @@ def test_sas_strided_rows_and_errors():
     M = 14
     K, J = _subset(rng, M, 8, 0.5)
     P, _ = native.analyze(M, J)
-    plan = native.SASPlan(M, J, pivots=P[:5], two_pass=True)  # nodes of several elements
+    # nodes of up to 4 elements (P[:5] would give mu* = 7 with an error bound
+    # of 2.5e-5, which the planner refuses)
+    plan = native.SASPlan(M, J, pivots=P[:6], two_pass=True)
     assert plan.mu_max > 1
     assert plan.workspace_bytes(3) == 3 * plan.mu_max * plan.n_nodes * 8
     n = plan.samples_per_signal
@@ -304,7 +335,7 @@ def test_sas_strided_rows_and_errors():
     plan.execute_ptr(x.data_ptr(), n + 5, y.data_ptr(), plan.k + 3, 3, work.data_ptr())
     torch.cuda.synchronize()
     got = y[:, :plan.k].cpu().numpy().astype(np.complex128)
-    assert np.max(oracle.rel_l2(got, c)) <= 1e-4
+    assert np.max(oracle.rel_l2(got, c)) <= plan.err_bound <= 1e-5
     with pytest.raises(native.HiDFTError):
         plan.execute_ptr(x.data_ptr(), n - 1, y.data_ptr(), plan.k, 1, work.data_ptr())
     with pytest.raises(native.HiDFTError):
@@ -333,7 +364,7 @@ def test_sas_single_element_nodes_need_no_workspace():
     plan.execute_ptr(x.data_ptr(), plan.samples_per_signal, y.data_ptr(), plan.k, 5, 0)
     torch.cuda.synchronize()
     got = y.cpu().numpy().astype(np.complex128)
-    assert np.max(oracle.rel_l2(got, c)) <= 1e-5
+    assert np.max(oracle.rel_l2(got, c)) <= plan.err_bound <= 1e-5
     plan.close()
 
 
@@ -351,7 +382,7 @@ def test_sas_degenerate_cases():
     assert plan.samples().tolist() == [0, 1, 2, 3]
     c = complex_normal((3, 4), rng)
     got = _sas_run(plan, oracle.synthesize_samples(M, J, c, [0, 1, 2, 3]))
-    assert np.max(oracle.rel_l2(got, c)) <= 1e-6
+    assert np.max(oracle.rel_l2(got, c)) <= min(1e-6, plan.err_bound)
     plan.close()
     M = 16
     J = homogeneous_support(M, 9, rng).J.tolist()

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.positions import positions_vs_oracle
 from workloads import (complex_normal, homogeneous_support, log_uniform_coefficients, rng_for,
                        sample_values)
 
@@ -159,6 +160,10 @@ def test_config4_precision_matrix_cores(prec, radix):
     _check(got[:n_exact], c, f"C4 prec={prec} radix={radix} seeded recovery")
     ref = _run(plan, f, native.ExecConfig(FP32, DEFAULT, 0, 0))
     _check(got, ref, f"C4 prec={prec} radix={radix} vs FP32 (all 1024)", tol=2 * TOL)
+    per_row = positions_vs_oracle(M, J, I, f, got, 64, rng_for(4, 2))
+    _say(f"C4 prec={prec} radix={radix}: all {batch} transforms on 64 positions each "
+         f"against the oracle: rel-L2 max {per_row.max():.3e}")
+    assert per_row.max() <= TOL
 
 
 def test_split_precision_dynamic_range():

@@ -109,3 +109,26 @@ def test_sas_cost_on_hand_counted_supports():
     # r = all pivots (1, 3, 5): level 6, every element its own node.
     # 1.5 * 3 * 8 * 1 + 6 * 5 = 36 + 30 = 66.
     assert oracle.sas_cost(6, J, [1, 3, 5]) == 66.0
+
+
+def test_positions_check_catches_permutations_and_phase_errors():
+    """The per-row position check used at full size: exact coefficients pass
+    in every row; a permutation of a row's outputs, or a phase error on each
+    coefficient, fails in every row (each row's positions see it)."""
+    from tests.positions import positions_vs_oracle
+    from workloads import complex_normal, homogeneous_support, rng_for
+
+    rng = rng_for(9101, 0)
+    M, s, batch = 14, 8, 150
+    sup = homogeneous_support(M, s, rng)
+    J = sup.J.tolist()
+    I = oracle.sample_set(M, J)
+    c = complex_normal((batch, len(J)), rng)
+    f = oracle.synthesize_samples(M, J, c, I).astype(np.complex64)
+    exact = oracle.adjoint_coefficients(M, J, I, f.astype(np.complex128))
+    ok = positions_vs_oracle(M, J, I, f, exact, 64, rng_for(9101, 1))
+    assert ok.shape == (batch,) and ok.max() < 1e-12
+    perm = exact[:, ::-1]
+    assert positions_vs_oracle(M, J, I, f, perm, 64, rng_for(9101, 1)).min() > 0.1
+    phase = exact * np.exp(1j * rng.uniform(0.01, 0.1, size=len(J)))
+    assert positions_vs_oracle(M, J, I, f, phase, 64, rng_for(9101, 1)).min() > 1e-3

@@ -46,7 +46,8 @@ def test_nodes_slots_and_samples_match_oracle():
         r = list(K.levels[:t])
         level = (max(r) + 1) if r else 0
         mu = max(len(v) for v in oracle.level_nodes(M, J, level).values())
-        plan = native.SASPlan(M, J, pivots=r, host_only=True)
+        # the index work of any r (weights-only plans skip the leaf-solve limits)
+        plan = native.SASPlan(M, J, pivots=r, host_only=True, weights_only=True)
         assert plan.pivots() == r
         node_of_t, slots = plan.nodes()
         want = oracle.level_nodes(M, J, level)
@@ -64,7 +65,49 @@ def test_nodes_slots_and_samples_match_oracle():
         assert abs(plan.cost - oracle.sas_cost(M, J, r)) < 1e-9 * max(1.0, plan.cost)
 
 
+U32 = 2.0 ** -24
+
+
+def _accuracy(M, J, r):
+    """(largest condition number, amplification, relative error bound) of the
+    leaf systems at r, from the oracle's SVDs: amplification = max_v
+    |V_v^{-1}|_2 max_v |D_v|_2, bound = amplification (2 + s)/2 u + u."""
+    sv = oracle.leaf_singular_values(M, J, r)
+    cond = max(v[0] / v[-1] for v, _ in sv)
+    amp = max(1.0 / v[-1] for v, _ in sv) * max(d[0] for _, d in sv)
+    return cond, amp, amp * (2 + len(r)) / 2 * U32 + U32
+
+
+def test_leaf_accuracy_matches_oracle():
+    """The planner's conditioning figures (FP64 power iteration on its own
+    Gauss-Jordan inverse) against LAPACK SVDs of the oracle's leaf systems,
+    on well- and ill-conditioned explicit pivot prefixes."""
+    n_ill = 0
+    for seed in range(40):
+        rng = rng_for(1103, seed)
+        M = int(rng.integers(6, 20))
+        K, J = _subset(rng, M, int(rng.integers(2, min(M, 9) + 1)), rng.uniform(0.2, 0.9))
+        r = list(K.levels[: int(rng.integers(0, len(K.levels) + 1))])
+        level = (max(r) + 1) if r else 0
+        mu = max(len(v) for v in oracle.level_nodes(M, J, level).values())
+        if mu > 32:
+            continue
+        plan = native.SASPlan(M, J, pivots=r, host_only=True, weights_only=True)
+        cond, amp, bound = _accuracy(M, J, r)
+        n_ill += bound > native.SAS_MAX_REL_ERR
+        if cond < 1e10:
+            assert plan.leaf_cond == pytest.approx(cond, rel=1e-6), (seed, r)
+            assert plan.amplification == pytest.approx(amp, rel=1e-6), (seed, r)
+            assert plan.err_bound == pytest.approx(bound, rel=1e-6), (seed, r)
+        else:  # numerically singular: both sides far above any accepted bound
+            assert plan.err_bound > 1e3 * native.SAS_MAX_REL_ERR
+    assert n_ill >= 3   # the set exercises refusals, not only good plans
+
+
 def test_automatic_pivot_choice_minimises_lemma4_cost():
+    """Among the prefixes of the pivots with mu* <= 32, 2^t <= 2^14 and a leaf
+    error bound within the accuracy target, the planner takes the one of
+    least Lemma 4 cost (the first such t on ties)."""
     for seed in range(40):
         rng = rng_for(1101, seed)
         M = int(rng.integers(8, 20))
@@ -75,7 +118,7 @@ def test_automatic_pivot_choice_minimises_lemma4_cost():
             r = P[:t]
             level = (max(r) + 1) if r else 0
             mu = max(len(v) for v in oracle.level_nodes(M, J, level).values())
-            if mu > 32:
+            if mu > 32 or _accuracy(M, J, r)[2] > native.SAS_MAX_REL_ERR:
                 continue
             c = oracle.sas_cost(M, J, r)
             if best is None or c < best[0]:
@@ -83,6 +126,35 @@ def test_automatic_pivot_choice_minimises_lemma4_cost():
         plan = native.SASPlan(M, J, host_only=True)
         assert plan.pivots() == best[1]
         assert abs(plan.cost - best[0]) < 1e-9 * best[0]
+        assert plan.err_bound <= native.SAS_MAX_REL_ERR
+
+
+def test_ill_conditioned_plans_are_refused():
+    """Explicit pivot prefixes whose leaf systems cannot meet the accuracy
+    target are refused at creation, with the condition number in the message;
+    the same r is accepted for the induced weights alone, and Lemma 4's
+    automatic choice moves to a prefix that meets the bound.  Cases: an 80 %
+    subset of a homogeneous set split at bits 0-3 and 9-13 at r = (0, 1, 2, 3)
+    (nodes of up to 28 of 32 equispaced points: condition number 1.7e3), and
+    26 consecutive integers at N = 2^16 with r = () (one node of 26 points
+    within 2 pi 25 / 2^16 of each other: numerically singular)."""
+    rng = rng_for(816, 0)
+    K = homogeneous_support(14, 9, rng, levels=(0, 1, 2, 3, 9, 10, 11, 12, 13))
+    keep = rng.random(len(K.J)) < 0.8
+    sub = [int(j) for j, kp in zip(K.J, keep) if kp]
+    for M, J, r in ((14, sub, [0, 1, 2, 3]), (16, list(range(26)), [])):
+        with pytest.raises(native.HiDFTError) as ei:
+            native.SASPlan(M, J, pivots=r, host_only=True)
+        assert ei.value.status_name == "HIDFT_ERR_UNSUPPORTED"
+        assert "condition number" in str(ei.value)
+        w = native.SASPlan(M, J, pivots=r, host_only=True, weights_only=True)
+        assert w.err_bound > native.SAS_MAX_REL_ERR and w.pivots() == r
+        cond = _accuracy(M, J, r)[0]
+        assert cond > 100
+        if cond < 1e10:
+            assert w.leaf_cond == pytest.approx(cond, rel=1e-6)
+        auto = native.SASPlan(M, J, host_only=True)
+        assert auto.err_bound <= native.SAS_MAX_REL_ERR and auto.pivots() != r
 
 
 def test_homogeneous_support_reduces_to_the_plain_plan():
@@ -102,8 +174,11 @@ def test_rejects():
     with pytest.raises(native.HiDFTError) as ei:
         native.SASPlan(6, J, pivots=[3, 1], host_only=True)        # not ascending
     assert ei.value.status_name == "HIDFT_ERR_INVALID_ARGUMENT"
-    plan = native.SASPlan(10, list(range(64)), pivots=[], host_only=True)   # mu* = 64
-    assert plan.mu_max == 64
+    with pytest.raises(native.HiDFTError) as ei:       # mu* = 64 > 32: no leaf solver
+        native.SASPlan(10, list(range(64)), pivots=[], host_only=True)
+    assert ei.value.status_name == "HIDFT_ERR_UNSUPPORTED"
+    plan = native.SASPlan(10, list(range(64)), pivots=[], host_only=True, weights_only=True)
+    assert plan.mu_max == 64 and plan.err_bound == float("inf")
     with pytest.raises(native.HiDFTError) as ei:       # refused before any device call
         plan.execute_ptr(8, 64, 8 + 4096, 64, 1, 8 + 8192)
     assert ei.value.status_name == "HIDFT_ERR_UNSUPPORTED"
