@@ -585,6 +585,31 @@ hidft_status hidft_sas_execute(hidft_sas plan, const void* d_samples, int64_t ld
 hidft_status hidft_sas_weights(hidft_sas plan, const void* d_samples, int64_t ld_in,
                                void* d_weights, int64_t ld_out, uint64_t batch, void* stream);
 
+/*
+ * hidft_sas_execute_noalloc -- hidft_sas_execute without a workspace argument,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * Same transform, arguments (minus d_work), validation and results as
+ * hidft_sas_execute, bit for bit.  Plans that need no workspace (mu* = 1, the
+ * one-kernel form) run exactly as there.  Otherwise the shifted Hi-DFT
+ * outputs go to the library's own device scratch of HIDFT_SAS_SCRATCH_BYTES
+ * (one static array per GPU, held until the process ends), and the batch runs
+ * in chunks of as many signals as fit it (mu* n_nodes complex64 values per
+ * signal, at most 32 * 2^14 * 8 B = 4 MiB), in stream order on `stream`.  The
+ * call allocates nothing: no hipMalloc, no hipFree, no allocating library
+ * routine.  The scratch is written in full before it is read, so it needs no
+ * clearing.  Every call on a GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.
+ * Errors: as hidft_sas_execute; UNSUPPORTED if one signal's outputs exceed
+ * the scratch; DEVICE if the scratch's address cannot be obtained.
+ */
+#define HIDFT_SAS_SCRATCH_BYTES (16u << 20)
+hidft_status hidft_sas_execute_noalloc(hidft_sas plan, const void* d_samples, int64_t ld_in,
+                                       void* d_coefs, int64_t ld_out, uint64_t batch,
+                                       void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* hidft_status_string(hidft_status status);
 

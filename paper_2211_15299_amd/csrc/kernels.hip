@@ -1866,6 +1866,35 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
 }
 
 // ---------------------------------------------------------------------------
+// Scratch of the allocation-free Shift-and-Sample entry point: the shifted
+// Hi-DFT outputs of a chunk of signals, [signal][shift][node], instead of a
+// caller's workspace.  In host code `scratch` names a host-side stand-in, not
+// device memory: every host use goes through the address hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) float2 scratch[SAS_SCRATCH_BYTES / sizeof(float2)];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+
+hipError_t sas_scratch(void** ptr) {
+  static std::atomic<void*> per_device[SCRATCH_MAX_DEVICES];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  void* p = per_device[dev].load(std::memory_order_acquire);
+  if (p == nullptr) {
+    // Racing first calls on a device each look up the same address.
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    per_device[dev].store(p, std::memory_order_release);
+  }
+  *ptr = p;
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
 // Plain per-signal method (baseline): one block per launch, one signal.
 //
 // Samples are permuted into the recursion order p = bitrev_S(a) in LDS, then

@@ -142,6 +142,13 @@ hipError_t launch_sas_fused(uint32_t s, const float2* in, int64_t ld_in, float2*
                             uint32_t k, const float2* tw, const uint16_t* src_node, float scale,
                             const void* elem_rec, const void* inv, hipStream_t stream);
 
+// Scratch of the allocation-free Shift-and-Sample entry point: a file-scope
+// device array of SAS_SCRATCH_BYTES, one copy per GPU, held until the process
+// ends.  *ptr receives the current device's copy; its address is looked up
+// (hipGetSymbolAddress) on the first call on that device and cached.
+constexpr size_t SAS_SCRATCH_BYTES = HIDFT_SAS_SCRATCH_BYTES;
+hipError_t sas_scratch(void** ptr);
+
 // Plain method: one signal, one block, one radix-2 stage per barrier.
 hipError_t launch_plain(uint32_t s, const float2* in, float2* out, const float2* tw,
                         const uint16_t* src, float scale, hipStream_t stream);

@@ -453,4 +453,35 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
   return hidft::set_error(HIDFT_OK, "");
 }
 
+hidft_status hidft_sas_execute_noalloc(hidft_sas p, const void* d_samples, int64_t ld_in,
+                                       void* d_coefs, int64_t ld_out, uint64_t batch,
+                                       void* stream) {
+  const char* fn = "hidft_sas_execute_noalloc";
+  hidft_status st = check_execute(p, d_samples, ld_in, d_coefs, ld_out, batch, fn);
+  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? hidft::set_error(HIDFT_OK, "") : st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float2* in = static_cast<const float2*>(d_samples);
+  float2* coefs = static_cast<float2*>(d_coefs);
+  if (p->core.mu_max == 1 || p->fused) return run_direct(p, in, ld_in, coefs, ld_out, batch, s, fn);
+  // One signal's shifted Hi-DFT outputs must fit the scratch; the batch runs
+  // in chunks of as many signals as fit, in stream order.
+  const uint64_t per_signal = (uint64_t)p->core.mu_max * p->core.node_slot.size() * sizeof(float2);
+  if (per_signal > hidft::SAS_SCRATCH_BYTES)
+    return hidft::set_error(HIDFT_ERR_UNSUPPORTED,
+                            std::string(fn) + ": one signal needs " + std::to_string(per_signal) +
+                                " bytes of scratch, more than the " +
+                                std::to_string(hidft::SAS_SCRATCH_BYTES) + " available");
+  void* scratch = nullptr;
+  hipError_t e = hidft::sas_scratch(&scratch);
+  if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute_noalloc: scratch lookup");
+  const uint64_t chunk = hidft::SAS_SCRATCH_BYTES / per_signal;
+  for (uint64_t first = 0; first < batch && e == hipSuccess; first += chunk) {
+    const uint64_t n = batch - first < chunk ? batch - first : chunk;
+    e = run_two_pass(p, in + first * (uint64_t)ld_in, ld_in, coefs + first * (uint64_t)ld_out,
+                     ld_out, n, static_cast<float2*>(scratch), s);
+  }
+  if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute_noalloc: kernel launch");
+  return hidft::set_error(HIDFT_OK, "");
+}
+
 }  // extern "C"

@@ -98,6 +98,7 @@ SIGNATURES = [
     ("hidft_sas_workspace_bytes", ctypes.c_int, [_vp, _u64, ctypes.POINTER(ctypes.c_size_t)]),
     ("hidft_sas_execute", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp, _vp]),
     ("hidft_sas_weights", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
+    ("hidft_sas_execute_noalloc", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
     ("hidft_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("hidft_last_error", ctypes.c_char_p, []),
 ]
@@ -516,6 +517,10 @@ class SASPlan:
     def execute_ptr(self, d_in, ld_in, d_out, ld_out, batch, d_work, stream=None):
         _check(lib().hidft_sas_execute(self._h, d_in, ld_in, d_out, ld_out, batch, d_work,
                                        _stream_handle(stream)))
+
+    def execute_noalloc_ptr(self, d_in, ld_in, d_out, ld_out, batch, stream=None):
+        _check(lib().hidft_sas_execute_noalloc(self._h, d_in, ld_in, d_out, ld_out, batch,
+                                               _stream_handle(stream)))
 
     def weights_ptr(self, d_in, ld_in, d_out, ld_out, batch, stream=None):
         _check(lib().hidft_sas_weights(self._h, d_in, ld_in, d_out, ld_out, batch,
