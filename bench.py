@@ -379,17 +379,13 @@ def grouped_bench(args, native, torch, stream):
     return out
 
 
-def serve_bench(args, native, seconds=None):
-    """Poisson arrivals through the continuous-batching server.
+SERVE_SWEEP_RATES = (20000.0, 50000.0, 100000.0, 200000.0, 500000.0, 1000000.0, 2000000.0)
 
-    256 supports (M uniform on 10..22, s uniform on 6..13 with s <= M-2),
-    chosen per request by a Zipf(1.1) law over their rank; one sample vector
-    per support.  Plans are made resident before the clock starts (their
-    creation is timed separately).  Latency is from submit to the
-    coefficients being in the request's host buffer.
-    """
+
+def _serve_supports():
+    """256 supports (M uniform on 10..22, s uniform on 6..13 with s <= M-2)
+    and one sample vector per support."""
     from workloads import homogeneous_support, rng_for, sample_values
-    seconds = args.serve_seconds if seconds is None else seconds
     sups, vecs = [], []
     for i in range(256):
         rng = rng_for(5, i)
@@ -398,78 +394,125 @@ def serve_bench(args, native, seconds=None):
         sup = homogeneous_support(M, s, rng)
         sups.append((M, np.ascontiguousarray(sup.J, dtype=np.uint64)))
         vecs.append(sample_values(M, len(sup.J), 1, rng)[0])
-    rng = rng_for(5, 10 ** 6)
-    n = int(args.serve_rate * seconds)
-    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=n))
-    ranks = np.arange(1, 257, dtype=np.float64)
-    pz = ranks ** -1.1
+    return sups, vecs
+
+
+def serve_run(native, srv, sups, vecs, rate, seconds, seed):
+    """Poisson arrivals at `rate` requests/s for `seconds`, supports drawn by
+    a Zipf(1.1) law over their rank.  Requests whose arrival time has passed
+    go to the server in one hidft_server_submit_many call; results are
+    polled between bursts.  Latency is the server's (submit to coefficients
+    in the request's host buffer); the client's own lag behind the arrival
+    times is reported beside it."""
+    from workloads import rng_for
+    rng = rng_for(5, seed)
+    n = max(1, int(rate * seconds))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    pz = np.arange(1, 257, dtype=np.float64) ** -1.1
     which = rng.choice(256, size=n, p=pz / pz.sum())
-    pool_n = 8192
-    pool = np.zeros((pool_n, 1 << 13), dtype=np.complex64)
-    busy = np.zeros(pool_n, dtype=bool)
-    slot_of = {}
-    srv = native.Server(data_bytes=512 << 20, plan_bytes=256 << 20, slots=4, max_batch=1024)
-    t0 = time.perf_counter()
-    for (M, J), f in zip(sups, vecs):  # make every plan resident
-        srv.submit(M, J, f, pool[0, :len(J)])
-        srv.drain()
-    srv.poll()
-    plan_warm_s = time.perf_counter() - t0
+    pool_n, width = 4096, 1 << 13
+    pool = np.zeros((pool_n, width), dtype=np.complex64)
+    recs = np.zeros(n, dtype=native.REQUEST_DTYPE)
+    recs["log2_n"] = np.array([M for M, _ in sups], dtype=np.uint32)[which]
+    recs["J"] = np.array([J.ctypes.data for _, J in sups], dtype=np.uint64)[which]
+    ks = np.array([len(J) for _, J in sups], dtype=np.uint64)[which]
+    recs["k"] = ks
+    recs["host_samples"] = np.array([v.ctypes.data for v in vecs], dtype=np.uint64)[which]
+    recs["host_coefs"] = (pool.ctypes.data + (np.arange(n) % pool_n) * width * 8).astype(np.uint64)
+    done = np.zeros(n, dtype=bool)
+    idx_of_rank = np.zeros(n, dtype=np.int64)
     lat, bsz = [], []
+    state = {"id0": None, "rank": 0, "rejected": 0, "failed": 0, "lag": 0.0}
 
     def collect(wait_us=0):
         res = srv.poll(wait_us)
-        for r in res:
-            busy[slot_of.pop(int(r["id"]))] = False
-        lat.extend(res["latency_us"].tolist())
-        bsz.extend(res["batch_size"].tolist())
+        if len(res):
+            r = (res["id"].astype(np.int64) - state["id0"])
+            done[idx_of_rank[r]] = True
+            ok = res["status"] == 0
+            state["failed"] += int((~ok).sum())
+            lat.append(res["latency_us"][ok])
+            bsz.append(res["batch_size"][ok])
         return len(res)
 
     st0 = srv.stats()
-    t_start = time.perf_counter()
-    late = 0
-    for i in range(n):
-        target = t_start + arrivals[i]
-        while True:
-            now = time.perf_counter()
-            if now >= target:
-                break
-            if target - now > 200e-6:
-                collect()
-        late = max(late, now - target)
-        slot = i % pool_n
-        while busy[slot]:
-            collect(100)
-        M, J = sups[which[i]]
-        rid = srv.submit(M, J, vecs[which[i]], pool[slot, :len(J)])
-        busy[slot] = True
-        slot_of[rid] = slot
-        if (i & 63) == 0:
-            collect()
+    t0 = time.perf_counter()
+    i = 0
+    while i < n:
+        now = time.perf_counter() - t0
+        j = int(np.searchsorted(arrivals, now, side="right"))
+        j = min(j, i + 4096)
+        if j > pool_n:  # request x reuses the buffer of request x - pool_n
+            lo = max(i - pool_n, 0)
+            seg = done[lo: j - pool_n]
+            if not seg.all():
+                j = lo + int(np.argmin(seg)) + pool_n
+        if j > i:
+            ids, sts = srv.submit_many(recs[i:j])
+            acc = sts == 0
+            if state["id0"] is None and acc.any():
+                state["id0"] = int(ids[acc][0])
+            na = int(acc.sum())
+            idx_of_rank[state["rank"]: state["rank"] + na] = np.arange(i, j)[acc]
+            state["rank"] += na
+            done[np.arange(i, j)[~acc]] = True
+            state["rejected"] += j - i - na
+            state["lag"] = max(state["lag"], now - arrivals[i])
+            i = j
+        collect()
     srv.drain()
-    t_end = time.perf_counter()
+    wall = time.perf_counter() - t0
     while collect():
         pass
     st = srv.stats()
-    srv.close()
-    lat = np.array(lat)
-    wall = t_end - t_start
-    ks = np.array([len(sups[w][1]) for w in which], dtype=np.int64)
-    return {"mode": "serve", "requests": n, "rate_per_s": args.serve_rate, "seconds": seconds,
+    lat = np.concatenate(lat) if lat else np.zeros(1)
+    bsz = np.concatenate(bsz) if bsz else np.zeros(1)
+    return {"offered_per_s": rate, "requests": n, "seconds": seconds,
             "completed": int(st["completed"] - st0["completed"]),
-            "rejected": int(st["rejected"] - st0["rejected"]),
+            "rejected": state["rejected"], "failed": state["failed"],
             "transforms_per_s": n / wall, "wall_s": wall,
             "data_GBps": float(ks.sum()) * 16 / wall / 1e9,
-            "data_plus_plan_GBps": float(ks.sum()) * 20 / wall / 1e9,
             "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "max": float(lat.max())},
-            "batch_size_mean": float(np.mean(bsz)), "batches": int(st["batches"] - st0["batches"]),
-            "max_inflight_batches": int(st["max_inflight_batches"]),
-            "plan_hits": int(st["plan_hits"] - st0["plan_hits"]),
-            "plan_misses": int(st["plan_misses"] - st0["plan_misses"]),
-            "plans_resident": int(st["plans_resident"]),
-            "plan_warmup_s": plan_warm_s, "max_submit_lag_us": late * 1e6,
-            "supports": 256, "zipf": 1.1}
+            "batch_size_mean": float(bsz.mean()), "batches": int(st["batches"] - st0["batches"]),
+            "max_client_lag_us": state["lag"] * 1e6}
+
+
+def serve_bench(args, native, seconds=None):
+    """The serving configuration through the continuous-batching server:
+    Poisson arrivals at --serve-rate (20 000 requests/s) for --serve-seconds
+    over 256 supports reused Zipf(1.1), then a load curve (2 s per rate) up
+    to 2 * 10^6 requests/s.  Plans are made resident before the clock starts
+    (their creation is timed separately)."""
+    seconds = args.serve_seconds if seconds is None else seconds
+    sups, vecs = _serve_supports()
+    srv = native.Server(data_bytes=512 << 20, plan_bytes=256 << 20, slots=4, max_batch=1024)
+    warm = np.zeros(1 << 13, dtype=np.complex64)
+    t0 = time.perf_counter()
+    for (M, J), f in zip(sups, vecs):  # make every plan resident
+        srv.submit(M, J, f, warm[:len(J)])
+        srv.drain()
+    srv.poll()
+    plan_warm_s = time.perf_counter() - t0
+    st = srv.stats()
+    out = serve_run(native, srv, sups, vecs, args.serve_rate, seconds, 10 ** 6)
+    out.update({"mode": "serve", "rate_per_s": args.serve_rate, "supports": 256, "zipf": 1.1,
+                "plan_warmup_s": plan_warm_s, "plans_resident": int(st["plans_resident"]),
+                "plan_bytes_resident": int(st["plan_bytes_resident"])})
+    curve = []
+    for q, rate in enumerate(SERVE_SWEEP_RATES):
+        r = serve_run(native, srv, sups, vecs, rate, 2.0, 2 * 10 ** 6 + q)
+        curve.append({k: r[k] for k in ("offered_per_s", "transforms_per_s", "completed",
+                                        "rejected", "failed", "latency_us", "batch_size_mean",
+                                        "data_GBps", "max_client_lag_us")})
+        print(f"serve sweep: offered {rate:.0f}/s sustained {r['transforms_per_s']:.0f}/s "
+              f"p50 {r['latency_us']['p50']:.1f} us p99 {r['latency_us']['p99']:.1f} us "
+              f"batch {r['batch_size_mean']:.1f}", file=sys.stderr, flush=True)
+    out["load_curve"] = curve
+    st = srv.stats()
+    out["max_inflight_batches"] = int(st["max_inflight_batches"])
+    srv.close()
+    return out
 
 
 PRECISION_WORKLOAD = dict(workload="precision: N=2^22, k=2^14, 1024 signals, |c| log-uniform "

@@ -403,12 +403,19 @@ hidft_status hidft_group_autotune(hidft_group group, uint32_t reps, void* stream
  *
  * Clients submit requests -- (N = 2^log2_n, J, k host samples on I_r in
  * ascending order) -- from any thread and later collect results.  The server:
- *   * keeps the plans of recently seen supports resident on the device (a plan
- *     cache keyed by (N, J), least recently used plans that no request holds
- *     are destroyed once the cache exceeds cfg.plan_bytes);
- *   * admits requests, in arrival order, into batches: a batch slot takes
- *     requests while its region (cfg.data_bytes / cfg.slots, half for
- *     samples, half for coefficients) and cfg.max_batch allow;
+ *   * keeps the plans of recently seen supports resident on the device in a
+ *     cache keyed by (N, J) whose device bytes never exceed cfg.plan_bytes:
+ *     resident plans, a plan being created and evicted plans not yet freed
+ *     all count.  A request whose plan is not resident waits while a planner
+ *     thread creates it; when the plan does not fit, the planner evicts least
+ *     recently used plans that no request holds, and if all are held, keeps
+ *     the request (and those queued behind it) waiting until requests retire.
+ *     Plan creation and the freeing of evicted plans happen on the planner
+ *     thread only, never on a client's or the scheduler's;
+ *   * admits requests with resident plans, in arrival order, into batches: a
+ *     batch slot takes requests while its region (cfg.data_bytes /
+ *     cfg.slots, half for samples, half for coefficients) and cfg.max_batch
+ *     allow;
  *   * runs each batch as one grouped launch (see hidft_group_create) on the
  *     slot's own stream.  A slot's regions are pinned host memory mapped for
  *     the device: the kernel reads the samples and writes the coefficients
@@ -418,31 +425,46 @@ hidft_status hidft_group_autotune(hidft_group group, uint32_t reps, void* stream
  * A request's coefficients do not depend on which other requests share its
  * batch (each instance runs the same per-signal code).
  *
- * hidft_server_submit: validates and plans the support synchronously (errors
- * as hidft_plan_create; OUT_OF_MEMORY if k samples and k coefficients exceed a
- * slot's region), then queues the request and returns its id.  host_samples
- * (k complex64) must stay readable and host_coefs (k complex64) writable until
- * the request's result has been polled.  Thread-safe.
+ * hidft_server_submit: validates the request synchronously (errors as
+ * hidft_plan_create for a support that is not resident; OUT_OF_MEMORY if k
+ * samples and k coefficients exceed a slot's region, or the plan's tables
+ * alone exceed cfg.plan_bytes), queues it and returns its id.  Makes no HIP
+ * call and does not change the calling thread's device.  A failure after
+ * submission (the device plan cannot be created) completes the request with
+ * that status.  host_samples (k complex64) must stay readable and host_coefs
+ * (k complex64) writable until the request's result has been polled.
+ * Thread-safe.
+ * hidft_server_submit_many: hidft_server_submit for n requests in one call;
+ * statuses[i] and ids[i] (0 when refused) per request, *n_accepted (may be
+ * NULL) the number accepted.
  * hidft_server_poll: moves up to `cap` finished results into `out`, waiting
  * up to wait_us microseconds for the first one; *n receives the count.
  * hidft_server_drain: waits until every submitted request has finished.
- * hidft_server_destroy: finishes queued work, then frees everything (plans
- * included).
+ * hidft_server_destroy: refuses new requests, finishes queued work, then
+ * frees everything (plans included).
  */
 typedef struct hidft_server_s* hidft_server;
 
 typedef struct hidft_server_config {
   size_t data_bytes;   /* pinned host bytes (mapped for the device) for request samples
                           and coefficients, all slots */
-  size_t plan_bytes;   /* device bytes of resident plans before LRU eviction */
+  size_t plan_bytes;   /* device bytes of the plan cache: a hard limit (> 0) */
   uint32_t slots;      /* batches in flight, each with its own stream */
   uint32_t max_batch;  /* requests per batch */
 } hidft_server_config;
 
+typedef struct hidft_server_request {
+  uint32_t log2_n;
+  const uint64_t* J;
+  uint64_t k;
+  const void* host_samples;
+  void* host_coefs;
+} hidft_server_request;
+
 typedef struct hidft_server_result {
   uint64_t id;
   int32_t status;      /* hidft_status of the request */
-  uint32_t batch_size; /* requests in the batch that served it */
+  uint32_t batch_size; /* requests in the batch that served it (0 if it failed before) */
   double latency_us;   /* from submit to the coefficients being in host_coefs */
 } hidft_server_result;
 
@@ -451,15 +473,22 @@ typedef struct hidft_server_stats {
   uint64_t plan_hits, plan_misses, plan_evictions;
   uint64_t max_inflight_batches;  /* most batches on the device at once */
   uint64_t plans_resident;
-  size_t plan_bytes_resident;     /* device bytes of the cached plans */
+  size_t plan_bytes_resident;     /* device bytes counted against plan_bytes now */
   size_t slot_bytes;              /* one slot's sample + coefficient region
                                      (pinned host memory mapped for the device) */
+  size_t plan_bytes_peak;         /* most device bytes ever counted (<= plan_bytes) */
+  uint64_t waiting_for_plan;      /* requests queued for a plan now */
+  uint64_t plan_waits;            /* plans that had to wait for held plans to retire */
+  uint64_t failed;                /* requests completed with an error after submission */
 } hidft_server_stats;
 
 hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* out);
 hidft_status hidft_server_submit(hidft_server server, uint32_t log2_n, const uint64_t* J,
                                  uint64_t k, const void* host_samples, void* host_coefs,
                                  uint64_t* id);
+hidft_status hidft_server_submit_many(hidft_server server, const hidft_server_request* reqs,
+                                      uint64_t n, uint64_t* ids, int32_t* statuses,
+                                      uint64_t* n_accepted);
 hidft_status hidft_server_poll(hidft_server server, hidft_server_result* out, uint32_t cap,
                                uint32_t* n, int32_t wait_us);
 hidft_status hidft_server_drain(hidft_server server);

@@ -54,10 +54,27 @@ hidft_status hip_fail(hipError_t e, const char* what) {
 void release_device(hidft_plan p) {
   if (p->d_tw) (void)hipFree(p->d_tw);
   if (p->d_src) (void)hipFree(p->d_src);
-  if (p->d_amat) (void)hipFree(p->d_amat);
+  void* am = p->d_amat.exchange(nullptr);
+  if (am) (void)hipFree(am);
   p->d_tw = nullptr;
   p->d_src = nullptr;
-  p->d_amat = nullptr;
+}
+
+// Twiddle exponents in the device order of the twiddle table: entry
+// (2^{u-1}-1) + bitrev_{u-1}(q_lo) holds the twiddle of stage u, node q_lo.
+void device_exponents(const hidft::PlanCore& c, std::vector<uint64_t>* num,
+                      std::vector<uint8_t>* den) {
+  const uint64_t ntw = c.k - 1;
+  num->assign(ntw ? ntw : 1, 0);
+  den->assign(ntw ? ntw : 1, 0);
+  for (uint32_t u = 1; u <= c.s; ++u) {
+    const uint64_t off = (1ULL << (u - 1)) - 1;
+    for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
+      const uint64_t h = hidft::bit_reverse(q_lo, u - 1);
+      (*num)[off + h] = c.tw_num[off + q_lo];
+      (*den)[off + h] = c.tw_log2den[off + q_lo];
+    }
+  }
 }
 
 // Uploads the device tables and generates the twiddles on `stream`.
@@ -68,34 +85,19 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
 
-  // Device order of the twiddle table: entry (2^{u-1}-1) + bitrev_{u-1}(q_lo)
-  // holds the twiddle of stage u, node q_lo.
-  std::vector<uint64_t> num(ntw ? ntw : 1, 0);
-  std::vector<uint8_t> den(ntw ? ntw : 1, 0);
-  for (uint32_t u = 1; u <= c.s; ++u) {
-    const uint64_t off = (1ULL << (u - 1)) - 1;
-    for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
-      const uint64_t h = hidft::bit_reverse(q_lo, u - 1);
-      num[off + h] = c.tw_num[off + q_lo];
-      den[off + h] = c.tw_log2den[off + q_lo];
-    }
-  }
+  std::vector<uint64_t> num;
+  std::vector<uint8_t> den;
+  device_exponents(c, &num, &den);
   std::vector<uint16_t> src(k);
   for (uint64_t t = 0; t < k; ++t)
     src[t] = static_cast<uint16_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
 
   const size_t ntw_alloc = ntw ? ntw : 1;
-  // The matrix-core group 1 needs its split matrix operands: radix 16 for
-  // k >= 16, and radix 32 after them for k >= 2^13.
-  const bool with_amat = c.s >= 4;
-  const bool with_amat32 = c.s >= 13;
-  const size_t amat_bytes = hidft::AMAT_BYTES + (with_amat32 ? hidft::AMAT32_BYTES : 0);
   uint64_t* d_num = nullptr;
   uint8_t* d_den = nullptr;
   hidft_status st = HIDFT_OK;
   if ((e = hipMalloc(&p->d_tw, ntw_alloc * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&p->d_src, k * sizeof(uint16_t))) != hipSuccess ||
-      (with_amat && (e = hipMalloc(&p->d_amat, amat_bytes)) != hipSuccess) ||
       (e = hipMalloc(&d_num, ntw_alloc * sizeof(uint64_t))) != hipSuccess ||
       (e = hipMalloc(&d_den, ntw_alloc)) != hipSuccess) {
     st = hip_fail(e, "hipMalloc of plan tables");
@@ -109,10 +111,6 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
   } else if ((e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, stream)) !=
              hipSuccess) {
     st = hip_fail(e, "twiddle generation launch");
-  } else if (with_amat &&
-             (e = hidft::launch_stage_matrix(d_num, d_den, p->d_amat, with_amat32, stream)) !=
-                 hipSuccess) {
-    st = hip_fail(e, "stage matrix launch");
   } else if ((e = hipStreamSynchronize(stream)) != hipSuccess) {
     st = hip_fail(e, "hipStreamSynchronize after plan upload");
   }
@@ -122,8 +120,7 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
     release_device(p);
     return st;
   }
-  p->device_bytes =
-      ntw_alloc * sizeof(float2) + k * sizeof(uint16_t) + (with_amat ? amat_bytes : 0);
+  p->device_bytes = hidft::plan_table_bytes(k);
   return HIDFT_OK;
 }
 
@@ -164,6 +161,56 @@ hidft_status check_exec(hidft_plan plan, const void* d_in, int64_t ld_in, const 
 }  // namespace
 
 namespace hidft {
+
+size_t plan_table_bytes(uint64_t k) {
+  return (k > 1 ? k - 1 : 1) * sizeof(float2) + k * sizeof(uint16_t);
+}
+
+hidft_status plan_amat(hidft_plan p, hipStream_t stream, void** amat, const char* fn) {
+  void* am = p->d_amat.load(std::memory_order_acquire);
+  if (am) {
+    *amat = am;
+    return HIDFT_OK;
+  }
+  std::lock_guard<std::mutex> lk(p->amat_mu);
+  am = p->d_amat.load(std::memory_order_acquire);
+  if (am) {
+    *amat = am;
+    return HIDFT_OK;
+  }
+  const hidft::PlanCore& c = p->core;
+  if (c.s < 4) return fail(HIDFT_ERR_UNSUPPORTED, "%s: matrix cores need k >= 16", fn);
+  // Radix-16 operands for k >= 16, the radix-32 ones after them for k >= 2^13.
+  const bool with_amat32 = c.s >= 13;
+  const size_t amat_bytes = AMAT_BYTES + (with_amat32 ? AMAT32_BYTES : 0);
+  std::vector<uint64_t> num;
+  std::vector<uint8_t> den;
+  device_exponents(c, &num, &den);
+  uint64_t* d_num = nullptr;
+  uint8_t* d_den = nullptr;
+  hipError_t e;
+  hidft_status st = HIDFT_OK;
+  if ((e = hipMalloc(&am, amat_bytes)) != hipSuccess ||
+      (e = hipMalloc(&d_num, num.size() * sizeof(uint64_t))) != hipSuccess ||
+      (e = hipMalloc(&d_den, den.size())) != hipSuccess ||
+      (e = hipMemcpyAsync(d_num, num.data(), num.size() * sizeof(uint64_t),
+                          hipMemcpyHostToDevice, stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(d_den, den.data(), den.size(), hipMemcpyHostToDevice, stream)) !=
+          hipSuccess ||
+      (e = launch_stage_matrix(d_num, d_den, am, with_amat32, stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(stream)) != hipSuccess)
+    st = hip_fail(e, "matrix operands of the first group");
+  if (d_num) (void)hipFree(d_num);
+  if (d_den) (void)hipFree(d_den);
+  if (st != HIDFT_OK) {
+    if (am) (void)hipFree(am);
+    return st;
+  }
+  p->device_bytes.fetch_add(amat_bytes, std::memory_order_relaxed);
+  p->d_amat.store(am, std::memory_order_release);
+  *amat = am;
+  return HIDFT_OK;
+}
 
 hidft_status set_error(hidft_status st, const std::string& msg) {
   g_last_error = msg;
@@ -428,7 +475,7 @@ hidft_status hidft_plan_get_twiddles(hidft_plan plan, float* twiddles) {
 hidft_status hidft_plan_device_bytes(hidft_plan plan, size_t* bytes) {
   if (!plan || !bytes)
     return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_device_bytes: NULL argument");
-  *bytes = plan->device_bytes;
+  *bytes = plan->device_bytes.load(std::memory_order_relaxed);
   return ok();
 }
 
@@ -438,7 +485,7 @@ hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in
   if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
   hipError_t e = hidft::launch_fused(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
                                      static_cast<float2*>(d_coefs), ld_out, batch, plan->d_tw,
-                                     plan->d_src, plan->d_amat, plan->scale, hidft::ExecConfig{},
+                                     plan->d_src, nullptr, plan->scale, hidft::ExecConfig{},
                                      static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hidft_execute: kernel launch");
   return ok();
@@ -463,9 +510,13 @@ hidft_status hidft_execute_config(hidft_plan plan, const hidft_exec_config* conf
   hidft::ExecConfig c;
   if ((st = hidft::resolve_config(plan, &eff, &c, fn)) != HIDFT_OK) return st;
   if (batch == 0) return ok();
+  void* amat = nullptr;
+  if (c.prec != hidft::PREC_FP32 &&
+      (st = hidft::plan_amat(plan, static_cast<hipStream_t>(stream), &amat, fn)) != HIDFT_OK)
+    return st;
   hipError_t e = hidft::launch_fused(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
                                      static_cast<float2*>(d_coefs), ld_out, batch, plan->d_tw,
-                                     plan->d_src, plan->d_amat, plan->scale, c,
+                                     plan->d_src, amat, plan->scale, c,
                                      static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hidft_execute_config: kernel launch");
   return ok();

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -17,12 +19,24 @@ struct hidft_plan_s {
   int device = -1;
   float2* d_tw = nullptr;      // k-1 twiddles in a-order (at least one slot)
   uint16_t* d_src = nullptr;   // k output gather positions
-  void* d_amat = nullptr;      // split operands of the group-1 matrix (k >= 16)
-  size_t device_bytes = 0;
+  // Split operands of the group-1 matrix (k >= 16), built on the first
+  // matrix-core execution (hidft::plan_amat) and kept until destroy.
+  std::atomic<void*> d_amat{nullptr};
+  std::mutex amat_mu;
+  std::atomic<size_t> device_bytes{0};
   float scale = 1.0f;          // N / k
 };
 
 namespace hidft {
+
+// Device bytes of a plan's tables at creation: k - 1 twiddles (at least one)
+// and k gather positions.  (The matrix-core operands come later, on demand.)
+size_t plan_table_bytes(uint64_t k);
+
+// The plan's matrix-core operands, built on first use: allocated, computed
+// in FP64 on the device on `stream` and waited for (the first matrix-core
+// execution of a plan is synchronous).  Thread-safe.
+hidft_status plan_amat(hidft_plan plan, hipStream_t stream, void** amat, const char* fn);
 
 // Records a failure message for hidft_last_error() and returns `st`.
 hidft_status set_error(hidft_status st, const std::string& msg);

@@ -1,14 +1,22 @@
 // Continuous-batching request server for homogeneous-support DFTs.
 //
-// Clients submit (N, J, samples) requests from any thread.  The server keeps
-// the plans of recently used supports resident on the device (a plan cache
-// with an LRU bound on device bytes), admits requests into batches as batch
-// slots and their device memory free up, and runs every batch -- requests of
-// different sizes and supports -- as one grouped kernel launch.  Each slot
-// owns a stream, a device region and pinned staging buffers, so the upload of
-// one batch, the transform of another and the download of a third overlap on
-// the device.  One scheduler thread forms batches, issues the work and
-// retires completed batches; clients collect results by polling.
+// Clients submit (N, J, samples) requests from any thread and collect results
+// by polling.  Three parts:
+//   * a plan cache with a hard budget of device bytes: every byte of a
+//     resident plan, of a plan being created and of an evicted plan not yet
+//     freed counts against cfg.plan_bytes, which is never exceeded;
+//   * a planner thread that creates the plans of requests whose support is
+//     not resident (outside the cache lock, so clients and the scheduler never
+//     wait for a plan upload), evicts least recently used plans that no
+//     request holds, frees evicted plans itself (hipFree may wait for the
+//     device), and holds a request back until its plan fits the budget;
+//   * a scheduler thread that admits requests with resident plans into batch
+//     slots in arrival order, runs each batch -- requests of different sizes
+//     and supports -- as one grouped kernel launch that reads the samples and
+//     writes the coefficients in pinned host memory mapped for the device,
+//     and retires batches as the kernel signals their completion.
+// A request holds a reference on its plan from admission to retirement, so
+// a plan in use is never evicted.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +28,7 @@
 #include <list>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -36,14 +45,18 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct PlanEntry {
   uint32_t M = 0;
   std::vector<uint64_t> J;
+  uint64_t hash = 0;
   hidft_plan plan = nullptr;
-  uint64_t refs = 0;               // pending or in-flight requests using it
+  size_t bytes = 0;                // device bytes counted against the budget
+  uint64_t refs = 0;               // admitted requests (queued or in flight)
   std::list<PlanEntry*>::iterator lru;
 };
 
 struct Request {
   uint64_t id = 0;
-  PlanEntry* entry = nullptr;
+  PlanEntry* entry = nullptr;      // set once the plan is resident
+  uint32_t M = 0;
+  std::vector<uint64_t> J;         // kept only while the plan is not resident
   const float2* host_in = nullptr;
   float2* host_out = nullptr;
   uint64_t k = 0;
@@ -56,9 +69,7 @@ struct Request {
 // then (from the next 256-byte boundary) its pack descriptors, then its
 // instance descriptors; the output region the coefficients.  The grouped
 // kernel loads the samples and stores the coefficients over the host link,
-// so a batch is one launch and an event, with no copies.  Measured at the
-// serving configuration (20 000 requests/s): p50 36 -> 32 us, p99 99 -> 72
-// us, mean 47-53 -> 34 us, against an upload and a download per batch.
+// so a batch is one launch and an event, with no copies.
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
@@ -98,91 +109,195 @@ struct hidft_server_s {
   uint32_t grid = 0;               // blocks of the grouped kernel's persistent grid
   uint64_t slot_points = 0;        // complex values per slot and direction
 
-  // plan cache
+  // plan cache (plan_mu)
   std::mutex plan_mu;
+  std::condition_variable cv_plan;  // planner: work, or a plan reference dropped
   std::unordered_multimap<uint64_t, std::unique_ptr<PlanEntry>> plans;
   std::list<PlanEntry*> lru;       // front = most recently used
-  size_t plan_bytes_resident = 0;
+  std::deque<Request> need_plan;   // requests whose plan is not resident
+  std::vector<std::pair<hidft_plan, size_t>> to_free;  // evicted, not yet freed
+  size_t bytes_held = 0;           // resident + reserved + evicted-not-freed
+  size_t bytes_peak = 0;
+  bool planner_stop = false;
   hipStream_t plan_stream = nullptr;
 
-  // requests
+  // requests (mu)
   std::mutex mu;
   std::condition_variable cv_work;   // scheduler: new requests or stop
   std::condition_variable cv_done;   // clients: results available
-  std::deque<Request> pending;
+  std::deque<Request> pending;       // admitted (plan resident), not yet in a batch
   std::deque<hidft_server_result> results;
   uint64_t next_id = 1;
   uint64_t in_system = 0;            // submitted and not yet completed
   bool stop = false;
 
   std::vector<Slot> slots;
-  std::thread worker;
+  std::thread worker, planner;
+  std::atomic<bool> planner_done{false};
 
   std::atomic<uint64_t> n_submitted{0}, n_completed{0}, n_rejected{0}, n_batches{0};
   std::atomic<uint64_t> n_plan_hits{0}, n_plan_misses{0}, n_plan_evictions{0};
+  std::atomic<uint64_t> n_plan_waits{0}, n_failed{0};
   std::atomic<uint64_t> max_inflight{0};
   std::atomic<uint64_t> n_pending{0};  // requests queued and not yet in a batch
   std::atomic<int32_t> worker_error{0};
 
   void loop();
+  void plan_loop();
   void launch(Slot& sl);
   void retire(Slot& sl);
-  PlanEntry* resolve(uint32_t M, const uint64_t* J, uint64_t k, hidft_status* st);
+  PlanEntry* find(uint32_t M, const uint64_t* J, uint64_t k, uint64_t h);
+  void admit(Request&& r);
+  void fail_request(const Request& r, hidft_status st);
   void release(PlanEntry* e);
+  hidft_status submit_one(uint32_t M, const uint64_t* J, uint64_t k, const void* in, void* out,
+                          uint64_t* id);
 };
 
-// Finds or creates the plan of (M, J); takes a reference on it.
-PlanEntry* hidft_server_s::resolve(uint32_t M, const uint64_t* J, uint64_t k, hidft_status* st) {
-  const uint64_t h = hash_support(M, J, k);
-  std::lock_guard<std::mutex> lk(plan_mu);
+// The resident plan of (M, J), or null.  plan_mu held.
+PlanEntry* hidft_server_s::find(uint32_t M, const uint64_t* J, uint64_t k, uint64_t h) {
   auto range = plans.equal_range(h);
   for (auto it = range.first; it != range.second; ++it) {
     PlanEntry* e = it->second.get();
-    if (e->M == M && e->J.size() == k && std::equal(e->J.begin(), e->J.end(), J)) {
-      ++e->refs;
-      lru.splice(lru.begin(), lru, e->lru);
-      n_plan_hits++;
-      *st = HIDFT_OK;
-      return e;
-    }
+    if (e->M == M && e->J.size() == k && std::equal(e->J.begin(), e->J.end(), J)) return e;
   }
-  n_plan_misses++;
-  hidft_plan p = nullptr;
-  *st = hidft_plan_create(M, J, k, 0, plan_stream, &p);
-  if (*st != HIDFT_OK) return nullptr;
-  auto owned = std::make_unique<PlanEntry>();
-  PlanEntry* e = owned.get();
-  e->M = M;
-  e->J.assign(J, J + k);
-  e->plan = p;
-  e->refs = 1;
-  lru.push_front(e);
-  e->lru = lru.begin();
-  plan_bytes_resident += p->device_bytes;
-  plans.emplace(h, std::move(owned));
-  // Evict least recently used plans that no request holds, down to budget.
-  for (auto it = lru.end(); plan_bytes_resident > cfg.plan_bytes && it != lru.begin();) {
-    --it;
-    PlanEntry* v = *it;
-    if (v->refs != 0) continue;
-    plan_bytes_resident -= v->plan->device_bytes;
-    hidft_plan_destroy(v->plan);
-    it = lru.erase(it);
-    const uint64_t vh = hash_support(v->M, v->J.data(), v->J.size());
-    auto r = plans.equal_range(vh);
-    for (auto pi = r.first; pi != r.second; ++pi)
-      if (pi->second.get() == v) {
-        plans.erase(pi);  // frees v
-        break;
-      }
-    n_plan_evictions++;
+  return nullptr;
+}
+
+// Queues a request whose plan reference is taken for the scheduler.
+void hidft_server_s::admit(Request&& r) {
+  r.J.clear();
+  r.J.shrink_to_fit();
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    pending.push_back(std::move(r));
+    n_pending.fetch_add(1, std::memory_order_release);
   }
-  return e;
+  cv_work.notify_one();
+}
+
+// Completes a request that could not be planned, with its status.
+void hidft_server_s::fail_request(const Request& r, hidft_status st) {
+  hidft_server_result res;
+  res.id = r.id;
+  res.status = st;
+  res.batch_size = 0;
+  res.latency_us = std::chrono::duration<double, std::micro>(Clock::now() - r.t_submit).count();
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    results.push_back(res);
+    in_system--;
+  }
+  n_failed++;
+  n_completed++;
+  cv_done.notify_all();
 }
 
 void hidft_server_s::release(PlanEntry* e) {
-  std::lock_guard<std::mutex> lk(plan_mu);
-  --e->refs;
+  bool freed;
+  {
+    std::lock_guard<std::mutex> lk(plan_mu);
+    freed = --e->refs == 0;
+  }
+  if (freed) cv_plan.notify_one();
+}
+
+// The planner: resolves each queued request's plan, in arrival order.
+void hidft_server_s::plan_loop() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(plan_mu);
+  for (;;) {
+    cv_plan.wait(lk, [&] { return planner_stop || !need_plan.empty(); });
+    if (need_plan.empty()) break;  // stopping, nothing left
+    Request r = std::move(need_plan.front());
+    need_plan.pop_front();
+    const uint64_t h = hash_support(r.M, r.J.data(), r.k);
+    if (PlanEntry* e = find(r.M, r.J.data(), r.k, h)) {
+      // created for an earlier request of the same support
+      ++e->refs;
+      lru.splice(lru.begin(), lru, e->lru);
+      n_plan_hits++;
+      r.entry = e;
+      r.s = e->plan->core.s;
+      lk.unlock();
+      admit(std::move(r));
+      lk.lock();
+      continue;
+    }
+    const size_t need = hidft::plan_table_bytes(r.k);
+    bool waited = false;
+    for (;;) {
+      // Evict least recently used plans that no request holds, until the new
+      // plan fits once they are freed.
+      size_t freeing = 0;
+      for (auto it = lru.end(); bytes_held - freeing + need > cfg.plan_bytes && it != lru.begin();) {
+        --it;
+        PlanEntry* v = *it;
+        if (v->refs != 0) continue;
+        to_free.emplace_back(v->plan, v->bytes);
+        freeing += v->bytes;
+        it = lru.erase(it);
+        auto rg = plans.equal_range(v->hash);
+        for (auto pi = rg.first; pi != rg.second; ++pi)
+          if (pi->second.get() == v) {
+            plans.erase(pi);  // frees v
+            break;
+          }
+        n_plan_evictions++;
+      }
+      if (!to_free.empty()) {
+        // Free outside the lock (hipFree may wait for the device), then scan
+        // again: references may have dropped meanwhile.
+        std::vector<std::pair<hidft_plan, size_t>> fr;
+        fr.swap(to_free);
+        lk.unlock();
+        for (auto& p : fr) hidft_plan_destroy(p.first);
+        lk.lock();
+        for (auto& p : fr) bytes_held -= p.second;
+        continue;
+      }
+      if (bytes_held + need <= cfg.plan_bytes) break;
+      // Every resident plan is held by an admitted request, and the scan above
+      // ran under the lock that release() takes: wait for the next reference
+      // to drop (each admitted request retires, so this wait ends).
+      if (!waited) n_plan_waits++;
+      waited = true;
+      cv_plan.wait(lk);
+    }
+    bytes_held += need;  // reserved for the plan being created
+    bytes_peak = std::max(bytes_peak, bytes_held);
+    lk.unlock();
+    hidft_plan p = nullptr;
+    const hidft_status st = hidft_plan_create(r.M, r.J.data(), r.k, 0, plan_stream, &p);
+    lk.lock();
+    if (st != HIDFT_OK) {
+      bytes_held -= need;
+      lk.unlock();
+      fail_request(r, st);
+      lk.lock();
+      continue;
+    }
+    n_plan_misses++;
+    auto owned = std::make_unique<PlanEntry>();
+    PlanEntry* e = owned.get();
+    e->M = r.M;
+    e->J = r.J;
+    e->hash = h;
+    e->plan = p;
+    e->bytes = need;
+    e->refs = 1;
+    lru.push_front(e);
+    e->lru = lru.begin();
+    plans.emplace(h, std::move(owned));
+    r.entry = e;
+    r.s = p->core.s;
+    lk.unlock();
+    admit(std::move(r));
+    lk.lock();
+  }
+  planner_done.store(true, std::memory_order_release);
+  lk.unlock();
+  cv_work.notify_all();
 }
 
 // Stages the batch in `sl` and issues the grouped transform.
@@ -294,7 +409,7 @@ void hidft_server_s::loop() {
         while (!pending.empty() && sl.batch.size() < cfg.max_batch &&
                pts + pending.front().k <= cap_points) {
           pts += pending.front().k;
-          sl.batch.push_back(pending.front());
+          sl.batch.push_back(std::move(pending.front()));
           pending.pop_front();
           n_pending.fetch_sub(1, std::memory_order_relaxed);
         }
@@ -322,10 +437,105 @@ void hidft_server_s::loop() {
       continue;
     }
     std::unique_lock<std::mutex> lk(mu);
-    if (stop && pending.empty()) break;
+    // Stop once the planner has handed over every request and none is left.
+    if (stop && pending.empty() && planner_done.load(std::memory_order_acquire)) break;
     cv_work.wait_for(lk, std::chrono::milliseconds(2),
                      [&] { return stop || !pending.empty(); });
   }
+}
+
+hidft_status hidft_server_s::submit_one(uint32_t M, const uint64_t* J, uint64_t k,
+                                        const void* in, void* out, uint64_t* id) {
+  if (!J || !in || !out || !id)
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: NULL argument");
+  if (k == 0 || k > slot_points) {
+    n_rejected++;
+    return hidft::set_error(HIDFT_ERR_OUT_OF_MEMORY,
+                            "hidft_server_submit: request larger than a batch slot's memory");
+  }
+  if (hidft::plan_table_bytes(k) > cfg.plan_bytes) {
+    n_rejected++;
+    return hidft::set_error(HIDFT_ERR_OUT_OF_MEMORY,
+                            "hidft_server_submit: the plan alone exceeds the plan-cache budget");
+  }
+  Request r;
+  r.M = M;
+  r.host_in = static_cast<const float2*>(in);
+  r.host_out = static_cast<float2*>(out);
+  r.k = k;
+  r.t_submit = Clock::now();
+  const uint64_t h = hash_support(M, J, k);
+  {
+    std::lock_guard<std::mutex> lk(plan_mu);
+    if (PlanEntry* e = find(M, J, k, h)) {
+      ++e->refs;
+      lru.splice(lru.begin(), lru, e->lru);
+      n_plan_hits++;
+      r.entry = e;
+      r.s = e->plan->core.s;
+    }
+  }
+  if (!r.entry) {
+    // Not resident: validate now, so that support errors return here; the
+    // planner creates the plan.
+    uint64_t mask = 0;
+    std::string err;
+    hidft_status st = hidft::analyze_core(M, J, k, &mask, &err);
+    if (st == HIDFT_OK && (k & (k - 1)) != 0) {
+      st = HIDFT_ERR_SIZE_NOT_POW2;
+      err = "k is not a power of two";
+    } else if (st == HIDFT_OK && (uint32_t)__builtin_popcountll(mask) != (uint32_t)__builtin_ctzll(k)) {
+      st = HIDFT_ERR_NOT_HOMOGENEOUS;
+      err = "J is not homogeneous";
+    } else if (st == HIDFT_OK && __builtin_ctzll(k) > (int)HIDFT_MAX_LOG2_K_DEVICE) {
+      st = HIDFT_ERR_UNSUPPORTED;
+      err = "k exceeds the executor's limit";
+    }
+    if (st != HIDFT_OK) {
+      n_rejected++;
+      return hidft::set_error(st, "hidft_server_submit: " + err);
+    }
+    r.J.assign(J, J + k);
+  }
+  const bool resident = r.entry != nullptr;
+  PlanEntry* held = r.entry;
+  bool stopping = false;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (stop) {
+      stopping = true;
+    } else {
+      r.id = next_id++;
+      *id = r.id;
+      in_system++;
+      if (resident) {
+        pending.push_back(std::move(r));
+        n_pending.fetch_add(1, std::memory_order_release);
+      }
+    }
+  }
+  if (stopping) {
+    if (held) release(held);
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: server stopping");
+  }
+  n_submitted++;
+  if (resident) {
+    cv_work.notify_one();
+    return hidft::set_error(HIDFT_OK, "");
+  }
+  bool queued = false;
+  {
+    std::lock_guard<std::mutex> lk(plan_mu);
+    if (!planner_stop) {
+      need_plan.push_back(std::move(r));
+      queued = true;
+    }
+  }
+  if (queued)
+    cv_plan.notify_one();
+  else
+    fail_request(r, HIDFT_ERR_INVALID_ARGUMENT);  // the server stopped meanwhile
+  return hidft::set_error(HIDFT_OK, "");
 }
 
 extern "C" {
@@ -334,9 +544,11 @@ hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* o
   if (!out || !cfg)
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_create: NULL argument");
   *out = nullptr;
-  if (cfg->slots == 0 || cfg->max_batch == 0 || cfg->data_bytes < 2 * 16 * cfg->slots)
+  if (cfg->slots == 0 || cfg->max_batch == 0 || cfg->data_bytes < 2 * 16 * cfg->slots ||
+      cfg->plan_bytes == 0)
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
-                            "hidft_server_create: slots, max_batch and data_bytes must be positive");
+                            "hidft_server_create: slots, max_batch, data_bytes and plan_bytes "
+                            "must be positive");
   auto sv = std::make_unique<hidft_server_s>();
   sv->cfg = *cfg;
   hipError_t e = hipGetDevice(&sv->device);
@@ -378,10 +590,11 @@ hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* o
   for (Slot& sl : sv->slots) *sl.h_flag = 0;  // no batch has completed
   hidft_server s = sv.release();
   try {
+    s->planner = std::thread([s] { s->plan_loop(); });
     s->worker = std::thread([s] { s->loop(); });
   } catch (...) {
     hidft_server_destroy(s);
-    return hidft::set_error(HIDFT_ERR_DEVICE, "hidft_server_create: cannot start the scheduler");
+    return hidft::set_error(HIDFT_ERR_DEVICE, "hidft_server_create: cannot start the threads");
   }
   *out = s;
   return hidft::set_error(HIDFT_OK, "");
@@ -389,43 +602,25 @@ hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* o
 
 hidft_status hidft_server_submit(hidft_server s, uint32_t log2_n, const uint64_t* J, uint64_t k,
                                  const void* host_samples, void* host_coefs, uint64_t* id) {
-  if (!s || !J || !host_samples || !host_coefs || !id)
-    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: NULL argument");
-  if (k == 0 || 2 * k > 2 * s->slot_points) {
-    s->n_rejected++;
-    return hidft::set_error(HIDFT_ERR_OUT_OF_MEMORY,
-                            "hidft_server_submit: request larger than a batch slot's memory");
+  if (!s) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: NULL server");
+  return s->submit_one(log2_n, J, k, host_samples, host_coefs, id);
+}
+
+hidft_status hidft_server_submit_many(hidft_server s, const hidft_server_request* reqs,
+                                      uint64_t n, uint64_t* ids, int32_t* statuses,
+                                      uint64_t* n_accepted) {
+  if (!s || (n > 0 && (!reqs || !ids || !statuses)))
+    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
+                            "hidft_server_submit_many: NULL argument");
+  uint64_t acc = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    const hidft_server_request& q = reqs[i];
+    ids[i] = 0;
+    statuses[i] = (int32_t)s->submit_one(q.log2_n, q.J, q.k, q.host_samples, q.host_coefs,
+                                         &ids[i]);
+    acc += statuses[i] == HIDFT_OK;
   }
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess || dev != s->device)
-    (void)hipSetDevice(s->device);
-  hidft_status st;
-  PlanEntry* e = s->resolve(log2_n, J, k, &st);
-  if (!e) {
-    s->n_rejected++;
-    return st;
-  }
-  Request r;
-  r.entry = e;
-  r.host_in = static_cast<const float2*>(host_samples);
-  r.host_out = static_cast<float2*>(host_coefs);
-  r.k = k;
-  r.s = e->plan->core.s;
-  r.t_submit = Clock::now();
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) {
-      s->release(e);
-      return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: server stopping");
-    }
-    r.id = s->next_id++;
-    s->pending.push_back(r);
-    s->n_pending.fetch_add(1, std::memory_order_release);
-    s->in_system++;
-  }
-  s->n_submitted++;
-  s->cv_work.notify_one();
-  *id = r.id;
+  if (n_accepted) *n_accepted = acc;
   return hidft::set_error(HIDFT_OK, "");
 }
 
@@ -467,19 +662,34 @@ hidft_status hidft_server_get_stats(hidft_server s, hidft_server_stats* st) {
   st->max_inflight_batches = s->max_inflight;
   {
     std::lock_guard<std::mutex> lk(s->plan_mu);
-    st->plan_bytes_resident = s->plan_bytes_resident;
+    st->plan_bytes_resident = s->bytes_held;
     st->plans_resident = s->plans.size();
+    st->plan_bytes_peak = s->bytes_peak;
+    st->waiting_for_plan = s->need_plan.size();
   }
   st->slot_bytes = 2 * s->slot_points * sizeof(float2);
+  st->plan_waits = s->n_plan_waits;
+  st->failed = s->n_failed;
   return hidft::set_error(HIDFT_OK, "");
 }
 
 hidft_status hidft_server_destroy(hidft_server s) {
   if (!s) return hidft::set_error(HIDFT_OK, "");
+  // New submissions are refused from here.  The planner hands over every
+  // request already queued for a plan (the scheduler keeps running, so plans
+  // held by admitted requests keep being released), then the scheduler
+  // finishes the admitted ones.
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
   }
+  {
+    std::lock_guard<std::mutex> lk(s->plan_mu);
+    s->planner_stop = true;
+  }
+  s->cv_plan.notify_all();
+  if (s->planner.joinable()) s->planner.join();
+  s->planner_done.store(true, std::memory_order_release);
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (Slot& sl : s->slots) {
@@ -492,6 +702,7 @@ hidft_status hidft_server_destroy(hidft_server s) {
     if (sl.h_out) (void)hipHostFree(sl.h_out);
   }
   for (auto& kv : s->plans) hidft_plan_destroy(kv.second->plan);
+  for (auto& p : s->to_free) hidft_plan_destroy(p.first);
   if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
   delete s;
   return hidft::set_error(HIDFT_OK, "");

@@ -79,6 +79,7 @@ SIGNATURES = [
     ("hidft_server_create", ctypes.c_int, [_vp, _pp]),
     ("hidft_server_submit", ctypes.c_int, [_vp, _u32, ctypes.POINTER(_u64), _u64, _vp, _vp,
                                            ctypes.POINTER(_u64)]),
+    ("hidft_server_submit_many", ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, ctypes.POINTER(_u64)]),
     ("hidft_server_poll", ctypes.c_int, [_vp, _vp, _u32, ctypes.POINTER(_u32), _i32]),
     ("hidft_server_drain", ctypes.c_int, [_vp]),
     ("hidft_server_get_stats", ctypes.c_int, [_vp, _vp]),
@@ -407,7 +408,14 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("submitted", "completed", "rejected", "batches", "plan_hits", "plan_misses",
                  "plan_evictions", "max_inflight_batches", "plans_resident")] + \
-               [("plan_bytes_resident", ctypes.c_size_t), ("slot_bytes", ctypes.c_size_t)]
+               [("plan_bytes_resident", ctypes.c_size_t), ("slot_bytes", ctypes.c_size_t),
+                ("plan_bytes_peak", ctypes.c_size_t)] + \
+               [(n, ctypes.c_uint64) for n in ("waiting_for_plan", "plan_waits", "failed")]
+
+
+# hidft_server_request, as a numpy record (one call submits many)
+REQUEST_DTYPE = np.dtype([("log2_n", np.uint32), ("J", np.uint64), ("k", np.uint64),
+                          ("host_samples", np.uint64), ("host_coefs", np.uint64)], align=True)
 
 
 class Server:
@@ -429,6 +437,18 @@ class Server:
                                          J.shape[0], samples.ctypes.data, out.ctypes.data,
                                          ctypes.byref(rid)))
         return rid.value
+
+    def submit_many(self, reqs: np.ndarray):
+        """Submits the REQUEST_DTYPE records `reqs` (pointers as integers; the
+        arrays they point to must stay alive) in one call; returns (ids,
+        statuses) per request (id 0 where refused)."""
+        n = len(reqs)
+        ids = np.zeros(max(n, 1), dtype=np.uint64)
+        sts = np.zeros(max(n, 1), dtype=np.int32)
+        acc = _u64(0)
+        _check(lib().hidft_server_submit_many(self._h, reqs.ctypes.data, n, ids.ctypes.data,
+                                              sts.ctypes.data, ctypes.byref(acc)))
+        return ids[:n], sts[:n]
 
     def poll(self, wait_us: int = 0) -> np.ndarray:
         n = _u32(0)

@@ -92,8 +92,18 @@ def test_server_mix_equals_alone_and_oracle():
 
 
 def test_server_admission_errors_and_eviction():
-    srv = native.Server(data_bytes=2 * 16 * 1024 * 2, plan_bytes=1, slots=2, max_batch=8)
     rng = rng_for(5, 2000)
+    # a budget smaller than any plan's tables refuses every support at submit
+    tiny = native.Server(data_bytes=2 * 16 * 1024 * 2, plan_bytes=1, slots=2, max_batch=8)
+    sup = homogeneous_support(10, 6, rng)
+    J6 = np.ascontiguousarray(sup.J, dtype=np.uint64)
+    with pytest.raises(native.HiDFTError) as ei:
+        tiny.submit(10, J6, np.zeros(64, np.complex64), np.zeros(64, np.complex64))
+    assert ei.value.status_name == "HIDFT_ERR_OUT_OF_MEMORY"
+    tiny.close()
+    # budget for about two plans of up to 1024 points
+    budget = 2 * (8 * 1023 + 2 * 1024)
+    srv = native.Server(data_bytes=2 * 16 * 1024 * 2, plan_bytes=budget, slots=2, max_batch=8)
     # a request larger than one slot's region is rejected
     big = homogeneous_support(16, 12, rng)
     J = np.ascontiguousarray(big.J, dtype=np.uint64)
@@ -107,7 +117,7 @@ def test_server_admission_errors_and_eviction():
     with pytest.raises(native.HiDFTError) as ei:
         srv.submit(4, bad, np.zeros(4, np.complex64), np.zeros(4, np.complex64))
     assert ei.value.status_name == "HIDFT_ERR_NOT_HOMOGENEOUS"
-    # tiny plan budget: plans are evicted once no request holds them
+    # plans are evicted once no request holds them, within the budget
     sups = _supports(12, cfg=6)
     keep = []
     for M, J in sups:
@@ -119,9 +129,95 @@ def test_server_admission_errors_and_eviction():
         srv.submit(M, J, f, o)
         srv.drain()
     st = srv.stats()
-    assert st["plan_evictions"] >= len(keep) - 2, st
+    need = sum(8 * (len(J) - 1) + 2 * len(J) for _, J, _, _ in keep)
+    assert need > budget and st["plan_evictions"] >= 1, (need, st)
+    assert st["plan_bytes_peak"] <= budget and st["plan_bytes_resident"] <= budget, st
+    assert st["failed"] == 0 and st["plan_misses"] == len(keep), st
     for M, J, f, o in keep:
         assert np.array_equal(o, _alone(M, J, f[None, :]))
+    srv.close()
+
+
+def test_server_hard_plan_budget_under_load():
+    """Four client threads submit, without waiting, 1200 requests over 24
+    supports whose plans need about 4.5 times the plan budget.  The device
+    bytes counted for plans never exceed the budget (peak reported by the
+    server), plans are evicted and recreated, requests wait for plan memory
+    instead of failing, and every result equals the request run alone, bit
+    for bit."""
+    sups = [x for x in _supports(40, cfg=8) if len(x[1]) <= 2048][:24]
+    assert len(sups) == 24
+    need = [8 * (len(J) - 1) + 2 * len(J) for _, J in sups]
+    budget = sum(need) * 2 // 9
+    assert max(need) <= budget < sum(need)
+    srv = native.Server(data_bytes=16 << 20, plan_bytes=budget, slots=3, max_batch=32)
+    results, errors = {}, []
+
+    def client(cid):
+        try:
+            rng = rng_for(8, 300 + cid)
+            for r in range(300):
+                w = int(rng.integers(0, len(sups)))
+                M, J = sups[w]
+                f = sample_values(M, len(J), 1, rng)[0]
+                o = np.full(len(J), np.nan, dtype=np.complex64)
+                rid = srv.submit(M, J, f, o)
+                results[(cid, r)] = (w, f, o, rid)
+        except Exception as e:  # pragma: no cover
+            errors.append(e)
+
+    th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    srv.drain()
+    st = srv.stats()
+    _say(f"budget {budget} B (working set {sum(need)} B): {st}")
+    assert not errors
+    assert st["completed"] == 1200 and st["failed"] == 0 and st["rejected"] == 0, st
+    assert st["plan_bytes_peak"] <= budget, st
+    assert st["plan_evictions"] > 0 and st["plan_misses"] > len(sups), st
+    statuses = []
+    while True:
+        res = srv.poll()
+        if len(res) == 0:
+            break
+        statuses.extend(res["status"].tolist())
+    assert statuses and all(x == 0 for x in statuses)
+    alone = {}
+    for key in list(results)[::5]:
+        w, f, o, _ = results[key]
+        if w not in alone:
+            alone[w] = {}
+        M, J = sups[w]
+        assert np.array_equal(o, _alone(M, J, f[None, :])), key
+    srv.close()
+
+
+def test_server_submit_many():
+    """One call submits a burst of requests (one refused in the middle);
+    each accepted request completes with the result of the request alone."""
+    sups = _supports(6, cfg=9)
+    rng = rng_for(9, 77)
+    srv = native.Server(data_bytes=32 << 20, plan_bytes=16 << 20, slots=2, max_batch=64)
+    recs = np.zeros(9, dtype=native.REQUEST_DTYPE)
+    keep = []
+    for i in range(9):
+        M, J = sups[i % len(sups)]
+        f = sample_values(M, len(J), 1, rng)[0]
+        o = np.full(len(J), np.nan, dtype=np.complex64)
+        keep.append((M, J, f, o))
+        recs[i] = (M, J.ctypes.data, len(J), f.ctypes.data, o.ctypes.data)
+    bad = np.array([1, 2, 4, 8], dtype=np.uint64)
+    recs[4] = (4, bad.ctypes.data, 4, keep[4][2].ctypes.data, keep[4][3].ctypes.data)
+    ids, sts = srv.submit_many(recs)
+    assert sts[4] == 5 and ids[4] == 0               # HIDFT_ERR_NOT_HOMOGENEOUS
+    assert all(sts[i] == 0 and ids[i] > 0 for i in range(9) if i != 4)
+    srv.drain()
+    for i, (M, J, f, o) in enumerate(keep):
+        if i != 4:
+            assert np.array_equal(o, _alone(M, J, f[None, :])), i
     srv.close()
 
 
