@@ -324,13 +324,18 @@ hidft_status hidft_execute_plain(hidft_plan plan, const void* d_samples, int64_t
  * the same contract as hidft_execute for that plan.  hidft_group_create
  * validates every item as hidft_execute would, expands the items into
  * instances (one per row), orders them by size, packs instances of equal size
- * into units of up to 2^14 points (when the packs leave the persistent grid a
+ * -- k >= 2^13 into wide packs of up to 2^14 points, smaller ones into narrow
+ * packs of up to 2^12 points (when the wide packs leave the persistent grid a
  * partial last round, that round's packs are split into packs of fewer
- * instances until every block has one), and uploads the resulting descriptor list
- * (pointers to rows, plan tables and scales) to the current device, waiting
- * for the upload on `stream`.  hidft_group_execute then runs the whole group as
- * one kernel launch on `stream`, asynchronously; it may be called any number
- * of times (the samples may change between calls; the pointers may not).
+ * instances until every block has one; narrow packs likewise up to four per
+ * block), schedules the narrow packs over the quarters of the blocks, and
+ * uploads the resulting descriptor list (pointers to rows, plan tables and
+ * scales, and the schedule) to the current device, waiting for the upload on
+ * `stream`.  hidft_group_execute then runs the whole group as one kernel
+ * launch on `stream`, asynchronously: each block of the persistent grid runs
+ * its wide packs, then splits into four quarters that run their narrow
+ * packs.  It may be called any number of times (the samples may change
+ * between calls; the pointers may not), also from a captured graph.
  *
  * Ownership: the group copies the items; the plans and buffers they name must
  * outlive every execution of the group.  Outputs of different instances must

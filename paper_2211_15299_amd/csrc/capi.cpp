@@ -10,6 +10,8 @@
 #include <string>
 
 #include <algorithm>
+#include <functional>
+#include <queue>
 #include <vector>
 
 #include "hidft.h"
@@ -19,7 +21,10 @@ struct hidft_group_s {
   int device = -1;
   uint64_t n_instances = 0;
   uint32_t n_packs = 0;
+  uint32_t n_wide = 0;          // the first n_wide packs are wide
+  uint32_t grid = 0;            // blocks of the launch
   hidft::GroupPack* d_packs = nullptr;
+  uint32_t* d_lanes = nullptr;  // lane_end of the schedule (4 per block)
   hidft::GroupSlot* d_slots = nullptr;
   size_t device_bytes = 0;
   std::vector<std::pair<uint32_t, hidft::GroupSlot>> inst;  // for re-packing
@@ -219,9 +224,28 @@ hidft_status set_error(hidft_status st, const std::string& msg) {
 
 hidft_status hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
 
-void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
-                    std::vector<GroupPack>* packs, std::vector<GroupSlot>* slots,
-                    uint32_t grid, bool short_first, uint32_t snake_rounds) {
+namespace {
+
+// Splits the largest packs of `tail` in two (its first slots stay, the rest
+// become a new pack) until it has `want` packs or no pack has two instances.
+void spread_packs(std::vector<GroupPack>* tail, size_t want) {
+  while (tail->size() < want) {
+    size_t big = 0;
+    for (size_t i = 1; i < tail->size(); ++i)
+      if ((*tail)[i].n_slots > (*tail)[big].n_slots) big = i;
+    if (tail->empty() || (*tail)[big].n_slots < 2) break;
+    GroupPack rest = (*tail)[big];
+    (*tail)[big].n_slots = (uint16_t)((rest.n_slots + 1) / 2);
+    rest.first_slot += (*tail)[big].n_slots;
+    rest.n_slots = (uint16_t)(rest.n_slots - (*tail)[big].n_slots);
+    tail->push_back(rest);
+  }
+}
+
+}  // namespace
+
+void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst, uint32_t max_grid,
+                    bool short_first, bool alternate, GroupSchedule* out) {
   std::vector<uint64_t> per_size(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
   for (const auto& x : inst) per_size[x.first]++;
   std::vector<uint64_t> next(HIDFT_MAX_LOG2_K_DEVICE + 1, 0);
@@ -230,9 +254,9 @@ void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
     next[s] = off;
     off += per_size[s];
   }
-  slots->resize(inst.size());
-  for (const auto& x : inst) (*slots)[next[x.first]++] = x.second;
-  packs->clear();
+  out->slots.resize(inst.size());
+  for (const auto& x : inst) out->slots[next[x.first]++] = x.second;
+  std::vector<GroupPack> wide, narrow;
   off = 0;
   for (int s = HIDFT_MAX_LOG2_K_DEVICE; s >= 0; --s) {
     const uint64_t per = (uint64_t)grouped_slots_per_pack((uint32_t)s);
@@ -241,50 +265,81 @@ void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
       pk.first_slot = (uint32_t)(off + first);
       pk.log2_k = (uint16_t)(s | (short_first ? GROUP_SHORT_FIRST : 0));
       pk.n_slots = (uint16_t)std::min<uint64_t>(per, per_size[s] - first);
-      packs->push_back(pk);
+      ((uint32_t)s >= GROUP_WIDE_MIN_S ? wide : narrow).push_back(pk);
     }
     off += per_size[s];
   }
-  const size_t full = grid > 0 ? packs->size() / grid * grid : packs->size();
-  if (full > 0 && full < packs->size()) {
-    // Split the largest pack of the partial last round in two (its first
-    // slots stay, the rest become a new pack) until the round has a pack
-    // per block.  Measured on the uneven configuration (348 packs on 256
-    // blocks): 46 -> 38.5 us, the same results.
-    std::vector<GroupPack> tail(packs->begin() + full, packs->end());
-    while (tail.size() < grid) {
-      size_t big = 0;
-      for (size_t i = 1; i < tail.size(); ++i)
-        if (tail[i].n_slots > tail[big].n_slots) big = i;
-      if (tail[big].n_slots < 2) break;
-      GroupPack rest = tail[big];
-      tail[big].n_slots = (uint16_t)((rest.n_slots + 1) / 2);
-      rest.first_slot += tail[big].n_slots;
-      rest.n_slots = (uint16_t)(rest.n_slots - tail[big].n_slots);
-      tail.push_back(rest);
-    }
-    packs->resize(full);
-    packs->insert(packs->end(), tail.begin(), tail.end());
+  if (max_grid == 0) max_grid = 1;
+  const size_t full = wide.size() / max_grid * max_grid;
+  if (full > 0 && full < wide.size()) {
+    // Measured on the uneven configuration with whole-block packs only (348
+    // packs on 256 blocks): 46 -> 38.5 us, the same results.
+    std::vector<GroupPack> tail(wide.begin() + full, wide.end());
+    spread_packs(&tail, max_grid);
+    wide.resize(full);
+    wide.insert(wide.end(), tail.begin(), tail.end());
   }
-  if (snake_rounds > 0 && packs->size() > snake_rounds) {
+  if (alternate && wide.size() > max_grid) {
     // Round r of the grid takes packs [r G, (r + 1) G) of the new list;
     // rounds alternate between the largest and the smallest packs left.
-    std::vector<GroupPack> out;
-    out.reserve(packs->size());
-    size_t lo = 0, hi = packs->size();
+    std::vector<GroupPack> alt;
+    alt.reserve(wide.size());
+    size_t lo = 0, hi = wide.size();
     for (uint32_t r = 0; lo < hi; ++r) {
-      const size_t n = std::min<size_t>(snake_rounds, hi - lo);
+      const size_t n = std::min<size_t>(max_grid, hi - lo);
       if (r % 2 == 0) {
-        for (size_t i = 0; i < n; ++i) out.push_back((*packs)[lo + i]);
+        for (size_t i = 0; i < n; ++i) alt.push_back(wide[lo + i]);
         lo += n;
       } else {
         // smallest first, so that block b (whose first pack was among the
         // largest) gets one of the smallest
-        for (size_t i = 0; i < n; ++i) out.push_back((*packs)[hi - 1 - i]);
+        for (size_t i = 0; i < n; ++i) alt.push_back(wide[hi - 1 - i]);
         hi -= n;
       }
     }
-    packs->swap(out);
+    wide.swap(alt);
+  }
+  spread_packs(&narrow, (size_t)max_grid * GROUP_NARROW_PER_BLOCK);
+  const size_t blocks = std::max(wide.size(), narrow.size());
+  out->grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(max_grid, blocks));
+  out->n_wide = (uint32_t)wide.size();
+  const uint32_t grid = out->grid, lanes = grid * GROUP_NARROW_PER_BLOCK;
+  // A CU's packs share its throughput: the estimated time of a block is the
+  // points of its packs, plus a fixed cost per pack for its latency.
+  auto cost = [](const GroupPack& pk) {
+    return ((uint64_t)pk.n_slots << (pk.log2_k & 0xffu)) + GROUP_PACK_COST_POINTS;
+  };
+  // Longest-first greedy over the blocks (ties: lower block first), the
+  // blocks starting from their wide packs; then, within a block, over its
+  // lanes (ties: lower quarter first).
+  std::vector<uint64_t> block_time(grid, 0);
+  for (size_t i = 0; i < wide.size(); ++i) block_time[i % grid] += cost(wide[i]);
+  using Key = std::pair<uint64_t, uint32_t>;
+  std::priority_queue<Key, std::vector<Key>, std::greater<Key>> heap;
+  for (uint32_t b = 0; b < grid; ++b) heap.emplace(block_time[b], b);
+  std::vector<std::vector<uint32_t>> block_packs(grid);
+  for (uint32_t i = 0; i < (uint32_t)narrow.size(); ++i) {
+    const Key top = heap.top();
+    heap.pop();
+    block_packs[top.second].push_back(i);
+    heap.emplace(top.first + cost(narrow[i]), top.second);
+  }
+  std::vector<std::vector<uint32_t>> lane_packs(lanes);
+  for (uint32_t b = 0; b < grid; ++b) {
+    uint64_t lane_time[GROUP_NARROW_PER_BLOCK] = {};
+    for (uint32_t i : block_packs[b]) {
+      uint32_t q = 0;
+      for (uint32_t j = 1; j < GROUP_NARROW_PER_BLOCK; ++j)
+        if (lane_time[j] < lane_time[q]) q = j;
+      lane_time[q] += cost(narrow[i]);
+      lane_packs[b * GROUP_NARROW_PER_BLOCK + q].push_back(i);
+    }
+  }
+  out->packs.swap(wide);
+  out->lane_end.assign(lanes, 0);
+  for (uint32_t l = 0; l < lanes; ++l) {
+    for (uint32_t i : lane_packs[l]) out->packs.push_back(narrow[i]);
+    out->lane_end[l] = (uint32_t)out->packs.size() - out->n_wide;
   }
 }
 
@@ -591,33 +646,38 @@ hidft_status hidft_group_create(const hidft_work* items, uint64_t n_items, void*
         inst.emplace_back(p->core.s, d);
       }
     }
-    std::vector<hidft::GroupPack> packs;
-    std::vector<hidft::GroupSlot> slots;
-    uint32_t grid = 0;
-    hipError_t ge = hidft::grouped_grid(&grid);
+    uint32_t max_grid = 0;
+    hipError_t ge = hidft::grouped_grid(&max_grid);
     if (ge != hipSuccess) return hip_fail(ge, "hidft_group_create: grid");
-    hidft::pack_instances(inst, &packs, &slots, grid);
+    hidft::GroupSchedule sch;
+    hidft::pack_instances(inst, max_grid, false, false, &sch);
     g = new hidft_group_s;
     g->device = device;
     g->n_instances = n_inst;
-    g->n_packs = (uint32_t)packs.size();
+    g->n_packs = (uint32_t)sch.packs.size();
+    g->n_wide = sch.n_wide;
+    g->grid = sch.grid;
     g->inst = std::move(inst);
-    const size_t pack_bytes = packs.size() * sizeof(hidft::GroupPack);
-    const size_t slot_bytes = slots.size() * sizeof(hidft::GroupSlot);
+    const size_t pack_bytes = sch.packs.size() * sizeof(hidft::GroupPack);
+    const size_t slot_bytes = sch.slots.size() * sizeof(hidft::GroupSlot);
+    const size_t lane_bytes = sch.lane_end.size() * sizeof(uint32_t);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
     if ((e = hipMalloc(&g->d_packs, pack_bytes)) != hipSuccess ||
         (e = hipMalloc(&g->d_slots, slot_bytes)) != hipSuccess ||
-        (e = hipMemcpyAsync(g->d_packs, packs.data(), pack_bytes, hipMemcpyHostToDevice, st)) !=
-            hipSuccess ||
-        (e = hipMemcpyAsync(g->d_slots, slots.data(), slot_bytes, hipMemcpyHostToDevice, st)) !=
-            hipSuccess ||
+        (e = hipMalloc(&g->d_lanes, lane_bytes)) != hipSuccess ||
+        (e = hipMemcpyAsync(g->d_packs, sch.packs.data(), pack_bytes, hipMemcpyHostToDevice,
+                            st)) != hipSuccess ||
+        (e = hipMemcpyAsync(g->d_slots, sch.slots.data(), slot_bytes, hipMemcpyHostToDevice,
+                            st)) != hipSuccess ||
+        (e = hipMemcpyAsync(g->d_lanes, sch.lane_end.data(), lane_bytes, hipMemcpyHostToDevice,
+                            st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
       hidft_status r = hip_fail(e, "hidft_group_create: descriptor upload");
       hidft_group_destroy(g);
       return r;
     }
-    g->device_bytes = pack_bytes + slot_bytes;
+    g->device_bytes = pack_bytes + slot_bytes + lane_bytes;
     *out = g;
     return ok();
   } catch (const std::bad_alloc&) {
@@ -638,7 +698,8 @@ hidft_status hidft_group_execute(hidft_group g, void* stream) {
     return fail(HIDFT_ERR_INVALID_ARGUMENT,
                 "hidft_group_execute: current device %d, group lives on device %d", dev,
                 g->device);
-  e = hidft::launch_grouped(g->d_packs, g->n_packs, g->d_slots, static_cast<hipStream_t>(stream));
+  e = hidft::launch_grouped(g->d_packs, g->n_wide, g->n_packs - g->n_wide, g->d_slots,
+                            g->d_lanes, g->grid, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hidft_group_execute: kernel launch");
   return ok();
 }
@@ -657,24 +718,27 @@ hidft_status hidft_group_set_config(hidft_group g, const hidft_group_config* cfg
   if (dev != g->device)
     return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_set_config: group lives on device %d",
                 g->device);
-  uint32_t grid = 0;
-  if ((e = hidft::grouped_grid(&grid)) != hipSuccess)
+  uint32_t max_grid = 0;
+  if ((e = hidft::grouped_grid(&max_grid)) != hipSuccess)
     return hip_fail(e, "hidft_group_set_config: grid");
   try {
-    std::vector<hidft::GroupPack> packs;
-    std::vector<hidft::GroupSlot> slots;
-    hidft::pack_instances(g->inst, &packs, &slots, grid,
-                          cfg->schedule == HIDFT_SCHED_SHORT_FIRST,
-                          cfg->order == HIDFT_GROUP_ORDER_ALTERNATE ? grid : 0);
+    hidft::GroupSchedule sch;
+    hidft::pack_instances(g->inst, max_grid, cfg->schedule == HIDFT_SCHED_SHORT_FIRST,
+                          cfg->order == HIDFT_GROUP_ORDER_ALTERNATE, &sch);
     // The same packs and slots as at creation, in another order or with the
     // schedule flag: the device arrays keep their sizes.
-    if (packs.size() != g->n_packs)
+    if (sch.packs.size() != g->n_packs || sch.n_wide != g->n_wide || sch.grid != g->grid)
       return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_group_set_config: the grid changed");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if ((e = hipMemcpyAsync(g->d_packs, packs.data(), packs.size() * sizeof(hidft::GroupPack),
-                            hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(g->d_slots, slots.data(), slots.size() * sizeof(hidft::GroupSlot),
-                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+    if ((e = hipMemcpyAsync(g->d_packs, sch.packs.data(),
+                            sch.packs.size() * sizeof(hidft::GroupPack), hipMemcpyHostToDevice,
+                            st)) != hipSuccess ||
+        (e = hipMemcpyAsync(g->d_slots, sch.slots.data(),
+                            sch.slots.size() * sizeof(hidft::GroupSlot), hipMemcpyHostToDevice,
+                            st)) != hipSuccess ||
+        (e = hipMemcpyAsync(g->d_lanes, sch.lane_end.data(),
+                            sch.lane_end.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                            st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "hidft_group_set_config: descriptor upload");
   } catch (const std::bad_alloc&) {
@@ -749,6 +813,7 @@ hidft_status hidft_group_destroy(hidft_group g) {
   if (!g) return ok();
   if (g->d_packs) (void)hipFree(g->d_packs);
   if (g->d_slots) (void)hipFree(g->d_slots);
+  if (g->d_lanes) (void)hipFree(g->d_lanes);
   delete g;
   return ok();
 }

@@ -54,21 +54,40 @@ hidft_status resolve_config(const hidft_plan plan, const hidft_exec_config* cfg,
 bool tune_lookup(const hidft_plan plan, uint32_t precision, uint64_t batch,
                  hidft_exec_config* cfg);
 
+// The schedule of one grouped launch.
+struct GroupSchedule {
+  std::vector<GroupPack> packs;    // n_wide wide packs, then the narrow packs by lane
+  std::vector<GroupSlot> slots;    // instance descriptors, in pack order
+  std::vector<uint32_t> lane_end;  // GROUP_NARROW_PER_BLOCK * grid entries
+  uint32_t n_wide = 0;
+  uint32_t grid = 0;               // blocks of the launch
+  uint32_t n_narrow() const { return (uint32_t)packs.size() - n_wide; }
+};
+
 // Orders instances (size log2, descriptor) by size, largest first, and packs
-// instances of equal size into packs of at most grouped_slots_per_pack(s).
+// instances of equal size into packs of at most grouped_slots_per_pack(s):
+// wide packs for s >= GROUP_WIDE_MIN_S, narrow ones below.  max_grid is the
+// persistent grid's block count.
+//
+// Wide packs: block b of the launch takes wide packs b, b + grid, ...  When
+// they do not fill whole rounds of max_grid, the packs of the last, partial
+// round are split into packs of fewer instances until that round has one
+// pack per block (or no pack has two instances left), so the last round
+// spreads over every CU instead of a few.  alternate: the wide packs are
+// reordered so that the blocks take, in alternate rounds, the largest and
+// the smallest remaining packs (a block with a long first pack gets a short
+// second one); else largest first.
+//
+// Narrow packs: split likewise until there are GROUP_NARROW_PER_BLOCK per
+// block of max_grid (or single instances), then scheduled by a longest-first
+// greedy: each pack, largest first, goes to the block with the least
+// estimated time so far (a block starts from its wide packs), and a block's
+// narrow packs go, in the same way, to its four lanes (quarter blocks, lane
+// = 4 block + quarter).  The estimate of a pack is its points plus
+// GROUP_PACK_COST_POINTS: the lanes of a CU share its throughput.
 // short_first: the packs of sizes with two schedules run with the short
 // group first (GROUP_SHORT_FIRST in GroupPack::log2_k), else last.
-// grid > 0 (the persistent grid's block count): when the packs do not fill
-// whole rounds of the grid, the packs of the last, partial round are split
-// into packs of fewer instances until that round has one pack per block (or
-// no pack has two instances left), so the last round spreads over every
-// CU instead of a few; 0 leaves the packs full.
-// snake_rounds > 0: the pack list is reordered so that the persistent grid
-// of snake_rounds blocks takes, in alternate rounds, the largest and the
-// smallest remaining packs (a block with a long first pack gets a short
-// second one); 0 keeps largest first.
-void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst,
-                    std::vector<GroupPack>* packs, std::vector<GroupSlot>* slots,
-                    uint32_t grid, bool short_first = false, uint32_t snake_rounds = 0);
+void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst, uint32_t max_grid,
+                    bool short_first, bool alternate, GroupSchedule* out);
 
 }  // namespace hidft

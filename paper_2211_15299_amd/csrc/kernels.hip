@@ -634,11 +634,18 @@ __device__ __forceinline__ void load_group1(SigVec<S, RH>& v, const float2* __re
 // thread's signal slot through `mem`.  Lb is the block's LDS.  HOISTED:
 // twiddles and gather positions come from `ts`, else from the tables behind
 // `mem`.
-template <int S, int SCHED, int RH, int PREC, bool HOISTED, class Mem>
+// The block-wide barrier of transform_signal (every wave of the block takes
+// part in each transform).
+struct BlockSync {
+  __device__ __forceinline__ void sync() { lds_barrier(); }
+};
+
+template <int S, int SCHED, int RH, int PREC, bool HOISTED, class Mem, class Sync = BlockSync>
 __device__ __forceinline__ void transform_signal(SigVec<S, RH>& v, float2* Lb, int slot, int tau,
                                                  bool store, const Mem& mem, float scale,
                                                  const ThreadState<S, SCHED, RH>& ts,
-                                                 const MfmaOps<PREC, mfma_blocks<RH>()>& op) {
+                                                 const MfmaOps<PREC, mfma_blocks<RH>()>& op,
+                                                 Sync sync = Sync()) {
   using Sh = FusedShape<S, SCHED, RH>;
   constexpr int RHO = Sh::RHO, R = Sh::R, T = Sh::T, G = Sh::G, G1 = Sh::G1;
   float2* L = Lb + slot * Sh::PADK;
@@ -701,7 +708,7 @@ __device__ __forceinline__ void transform_signal(SigVec<S, RH>& v, float2* Lb, i
           wq[(1 << t) - 1 + h] = mem.tw_at(((1 << (u - 1)) - 1) + h, a_hi << t);
       }
     }
-    lds_barrier();
+    sync.sync();
     const int pb = lds_pad<RHO>(base);
 #pragma unroll
     for (int c = 0; c < R; ++c) v[c] = L[pb + lds_window_off<RHO>(c, lo)];
@@ -734,7 +741,7 @@ __device__ __forceinline__ void transform_signal(SigVec<S, RH>& v, float2* Lb, i
       for (int c = 0; c < R; ++c) pq[c] = mem.src_at(c * T, tau);
     }
   }
-  lds_barrier();
+  sync.sync();
 
   // Wave priority 1 for the gather and stores (note on wave priority above).
   __builtin_amdgcn_s_setprio(1);
@@ -1225,16 +1232,91 @@ size_t fused_lds_bytes(uint32_t s) {
 // Grouped transform: an uneven batch (each instance with its own plan and
 // size) in one persistent launch.
 //
-// The host packs instances of equal size 2^S into packs of up to 2^14 points:
-// 1024 / T(S) instances per pack, T(S) = 2^{max(S-4, 0)} threads each, so a
-// pack always fills the block's 1024 threads and at most its 136 KB of LDS.
-// Each block walks the pack list with a grid stride; for a pack it loads its
-// slot's descriptor (rows, twiddle and gather tables, scale), then runs the
-// same per-signal transform as the fused kernel, specialised on S by a switch
-// that is uniform over the block.
+// Wide phase.  Instances of 2^13 and 2^14 points go in packs that fill the
+// whole block (1024 threads, up to 2^14 points and 136 KB of LDS: one block
+// per CU); the blocks walk the wide packs with a grid stride.
+// Narrow phase.  Then each block splits into four 256-thread sub-blocks
+// (lanes) with a quarter of the LDS each and their own barriers (an LDS
+// counter), and each lane runs the narrow packs (instances of up to 2^12
+// points, packed into at most 2^12 points) that the host's schedule gave it.
+// The lanes progress independently, so the load, transform and store phases
+// of four packs overlap on a CU, as four fused blocks would.  (A device-wide
+// work queue instead cost more in same-address atomics than it gained in
+// balance: 74 us against 38.5 us on the uneven configuration.)
+// Every instance runs the fused kernel's per-signal code (transform_signal),
+// so its result is bit-identical to hidft_execute's.
 // ---------------------------------------------------------------------------
 constexpr int GROUPED_THREADS = 1024;
 constexpr int GROUPED_LDS_SLOTS = (1 << HIDFT_MAX_LOG2_K_DEVICE) + ((1 << HIDFT_MAX_LOG2_K_DEVICE) >> 4);
+constexpr int NARROW_THREADS = 256;
+constexpr int NARROW_SUBBLOCKS = GROUPED_THREADS / NARROW_THREADS;
+static_assert(NARROW_SUBBLOCKS == (int)GROUP_NARROW_PER_BLOCK, "sub-blocks per block");
+constexpr int NARROW_LDS_SLOTS = GROUPED_LDS_SLOTS / NARROW_SUBBLOCKS;  // 2^12 + 2^8
+static_assert(NARROW_LDS_SLOTS >= (1 << 12) + (1 << 8), "a narrow pack's LDS");
+// After the transform areas: the sub-blocks' barrier counters (one word
+// each), in float2 slots.
+constexpr int GROUPED_CTL_SLOTS = NARROW_SUBBLOCKS / 2;
+constexpr size_t GROUPED_LDS_BYTES = (size_t)(GROUPED_LDS_SLOTS + GROUPED_CTL_SLOTS) * sizeof(float2);
+
+// Pointers into LDS, typed so: the compiler then emits LDS instructions
+// through them also in a function that is not inlined into the kernel (a
+// plain pointer there would give flat accesses, each of which waits for the
+// wavefront's outstanding global loads too).
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+
+template <typename T>
+__device__ __forceinline__ lds_ptr<T> to_lds(T* p) {
+  return (lds_ptr<T>)p;
+}
+
+// The same for global memory: the descriptors the grouped kernel reads
+// hold plain pointers, through which the compiler would emit flat accesses
+// (which also count against the LDS wait counter).
+template <typename T>
+using glb_ptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ glb_ptr<T> to_glb(T* p) {
+  return (glb_ptr<T>)p;
+}
+
+// Per-lane table and output accesses of an instance with fewer than 64
+// threads (its rows are not wave-uniform), through global pointers.
+struct GlbMem {
+  glb_ptr<const f2v_t> tw;
+  glb_ptr<const uint16_t> src;
+  glb_ptr<f2v_t> out;
+  __device__ __forceinline__ float2 tw_at(int uni, int lane) const {
+    return __builtin_bit_cast(float2, tw[uni + lane]);
+  }
+  __device__ __forceinline__ int src_at(int uni, int lane) const { return src[uni + lane]; }
+  __device__ __forceinline__ void put(int uni, int lane, float2 x) const {
+    __builtin_nontemporal_store(__builtin_bit_cast(f2v_t, x), out + uni + lane);
+  }
+};
+
+// Barrier of one 256-thread sub-block (four wavefronts) through an LDS
+// counter: at each sync every wave adds 1 and waits until the counter reaches
+// the next multiple of 4 above the value it found.  That multiple is reached
+// exactly when all four waves have arrived, and no wave can arrive at the
+// following sync before then, so the target needs no state of its own.
+struct SubSync {
+  lds_ptr<uint32_t> cnt;
+  __device__ __forceinline__ void sync() const {
+    constexpr uint32_t W = NARROW_THREADS / 64;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    uint32_t old = 0;
+    if ((threadIdx.x & 63) == 0)
+      old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    old = __builtin_amdgcn_readfirstlane(old);
+    const uint32_t target = (old & ~(W - 1)) + W;
+    while ((int32_t)(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) -
+                     target) < 0)
+      __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  }
+};
 
 // A descriptor field that is the same in every lane of the wavefront (a slot
 // spans whole wavefronts when T >= 64), moved to scalar registers.
@@ -1246,9 +1328,10 @@ __device__ __forceinline__ P* uniform_ptr(P* p) {
   return reinterpret_cast<P*>(((uint64_t)hi << 32) | lo);
 }
 
-// One pack of 2^S-point instances, short group first or last (SC).  Not
-// inlined: each size gets a register allocation of its own instead of one
-// shared by the whole switch.
+// One pack of 2^S-point instances, short group first or last (SC), on
+// THREADS threads (the block, or a sub-block) whose thread index is `tid` and
+// whose barrier is `sync`.  Not inlined: each size gets a register
+// allocation of its own instead of one shared by the whole switch.
 //
 // skip_idle (GROUP_SKIP_IDLE): a wavefront whose slots are all empty does no
 // arithmetic and only takes part in the transform's barriers, one per group
@@ -1257,13 +1340,15 @@ __device__ __forceinline__ P* uniform_ptr(P* p) {
 // wavefront (scalar branch).  Measured: in the server's batches, mostly
 // single requests, p50 latency 25 -> 22 us; in the partial packs of the
 // uneven configuration 38.5 -> 39.3 us, so only the server sets it.
-template <int S, int SC>
+template <int S, int SC, int THREADS, class Sync>
 __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restrict__ slots,
-                                                       int n_slots, float2* lds, int skip_idle) {
+                                                       int n_slots, lds_ptr<float2> lds_as,
+                                                       int skip_idle, int tid, Sync sync) {
+  float2* lds = (float2*)lds_as;
   using Sh = FusedShape<S, SC, 4>;
   constexpr int R = Sh::R, T = Sh::T;
+  static_assert(T <= THREADS && THREADS % T == 0, "instances tile the threads");
   constexpr uint32_t K = 1u << S;
-  const int tid = threadIdx.x;
   const int slot = tid / T;
   const int tau = tid - slot * T;
   const bool valid = slot < n_slots;
@@ -1272,7 +1357,7 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
           __builtin_amdgcn_readfirstlane(n_slots)) {
     constexpr int NB = Sh::G > 1 ? Sh::G : 1;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) lds_barrier();
+    for (int i = 0; i < NB; ++i) sync.sync();
     return;
   }
   // Threads of empty slots (a partial pack) run the transform on zeros with
@@ -1299,51 +1384,101 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
     mem.tw = make_rsrc(d.tw, (K > 1 ? K - 1 : 1) * 8u);
     mem.src = make_rsrc(d.src, K * 2u);
     mem.out = make_rsrc(d.out, K * 8u);
-    transform_signal<S, SC, 4, PREC_FP32, false>(v, lds, slot, tau, valid, mem, d.scale, unused,
-                                               no_mfma);
+    transform_signal<S, SC, 4, PREC_FP32, false, BufMem, Sync>(v, lds, slot, tau, valid, mem,
+                                                               d.scale, unused, no_mfma, sync);
   } else {
+    const glb_ptr<const f2v_t> in = to_glb(reinterpret_cast<const f2v_t*>(d.in));
 #pragma unroll
     for (int c = 0; c < R; ++c)
-      v[c] = valid ? load_stream(d.in + c * T + tau) : make_float2(0.f, 0.f);
-    const FlatMem mem{d.tw, d.src, d.out, K};
-    transform_signal<S, SC, 4, PREC_FP32, false>(v, lds, slot, tau, valid, mem, d.scale, unused,
-                                               no_mfma);
+      v[c] = valid ? __builtin_bit_cast(float2, __builtin_nontemporal_load(in + c * T + tau))
+                   : make_float2(0.f, 0.f);
+    const GlbMem mem{to_glb(reinterpret_cast<const f2v_t*>(d.tw)), to_glb(d.src),
+                     to_glb(reinterpret_cast<f2v_t*>(d.out))};
+    transform_signal<S, SC, 4, PREC_FP32, false, GlbMem, Sync>(v, lds, slot, tau, valid, mem,
+                                                               d.scale, unused, no_mfma, sync);
   }
 }
 
 __global__ void __launch_bounds__(GROUPED_THREADS)
-hidft_grouped_kernel(const GroupPack* __restrict__ packs, uint32_t n_packs,
-                     const GroupSlot* __restrict__ slots, uint32_t* done_count,
-                     uint32_t count_base, uint32_t* done_flag, uint32_t seq) {
+hidft_grouped_kernel(const GroupPack* __restrict__ packs, uint32_t n_wide, uint32_t n_narrow,
+                     const GroupSlot* __restrict__ slots, const uint32_t* __restrict__ lane_end,
+                     uint32_t* done_count, uint32_t count_base, uint32_t* done_flag,
+                     uint32_t seq) {
   extern __shared__ float2 lds[];
-  for (uint32_t p = blockIdx.x; p < n_packs; p += gridDim.x) {
+  // Wide phase: whole-block packs, grid stride.
+  for (uint32_t p = blockIdx.x; p < n_wide; p += gridDim.x) {
     const GroupPack pk = packs[p];
     const GroupSlot* sl = slots + pk.first_slot;
     // Sizes with two schedules (S > 4, 4 does not divide S) have a body for
     // each; the others ignore the flag.
     const int skip = (pk.log2_k & GROUP_SKIP_IDLE) != 0;
+    const int tid = threadIdx.x;
+    const lds_ptr<float2> L = to_lds(lds);
     switch (pk.log2_k & ~GROUP_SKIP_IDLE) {
-#define HIDFT_ONE(S)                                          \
-  case S:                                                     \
-  case S | GROUP_SHORT_FIRST:                                 \
-    grouped_pack<S, SCHED_SHORT_FIRST>(sl, (int)pk.n_slots, lds, skip); \
-    break;
-#define HIDFT_TWO(S)                                          \
-  case S:                                                     \
-    grouped_pack<S, SCHED_SHORT_LAST>(sl, (int)pk.n_slots, lds, skip); \
-    break;                                                    \
-  case S | GROUP_SHORT_FIRST:                                 \
-    grouped_pack<S, SCHED_SHORT_FIRST>(sl, (int)pk.n_slots, lds, skip); \
-    break;
-      HIDFT_ONE(0) HIDFT_ONE(1) HIDFT_ONE(2) HIDFT_ONE(3) HIDFT_ONE(4) HIDFT_TWO(5)
-      HIDFT_TWO(6) HIDFT_TWO(7) HIDFT_ONE(8) HIDFT_TWO(9) HIDFT_TWO(10) HIDFT_TWO(11)
-      HIDFT_ONE(12) HIDFT_TWO(13) HIDFT_TWO(14)
-#undef HIDFT_ONE
-#undef HIDFT_TWO
+      case 13:
+        grouped_pack<13, SCHED_SHORT_LAST, GROUPED_THREADS>(sl, (int)pk.n_slots, L, skip, tid,
+                                                            BlockSync());
+        break;
+      case 13 | GROUP_SHORT_FIRST:
+        grouped_pack<13, SCHED_SHORT_FIRST, GROUPED_THREADS>(sl, (int)pk.n_slots, L, skip, tid,
+                                                             BlockSync());
+        break;
+      case 14:
+        grouped_pack<14, SCHED_SHORT_LAST, GROUPED_THREADS>(sl, (int)pk.n_slots, L, skip, tid,
+                                                            BlockSync());
+        break;
+      case 14 | GROUP_SHORT_FIRST:
+        grouped_pack<14, SCHED_SHORT_FIRST, GROUPED_THREADS>(sl, (int)pk.n_slots, L, skip, tid,
+                                                             BlockSync());
+        break;
       default:
         break;
     }
     lds_barrier();  // the next pack overwrites the LDS
+  }
+  if (n_narrow > 0) {
+    // Narrow phase: four lanes, each with its own LDS quarter and barrier
+    // counter, and its packs [lane_end[lane - 1], lane_end[lane]).
+    const lds_ptr<uint32_t> ctl = to_lds(reinterpret_cast<uint32_t*>(lds + GROUPED_LDS_SLOTS));
+    const int sub = __builtin_amdgcn_readfirstlane(threadIdx.x / NARROW_THREADS);
+    const int stid = threadIdx.x % NARROW_THREADS;
+    const uint32_t lane = blockIdx.x * NARROW_SUBBLOCKS + sub;
+    const uint32_t begin = lane == 0 ? 0u : lane_end[lane - 1];
+    const uint32_t end = lane_end[lane];
+    if (threadIdx.x < NARROW_SUBBLOCKS) ctl[threadIdx.x] = 0u;
+    lds_barrier();
+    const SubSync sync{ctl + sub};
+    const lds_ptr<float2> L = to_lds(lds + sub * NARROW_LDS_SLOTS);
+    for (uint32_t q = begin; q < end; ++q) {
+      const GroupPack pk = packs[n_wide + q];
+      const GroupSlot* sl = slots + pk.first_slot;
+      const int skip = (pk.log2_k & GROUP_SKIP_IDLE) != 0;
+      switch (pk.log2_k & ~GROUP_SKIP_IDLE) {
+#define HIDFT_ONE(S)                                                                 \
+  case S:                                                                            \
+  case S | GROUP_SHORT_FIRST:                                                        \
+    grouped_pack<S, SCHED_SHORT_FIRST, NARROW_THREADS>(sl, (int)pk.n_slots, L, skip, \
+                                                       stid, sync);                  \
+    break;
+#define HIDFT_TWO(S)                                                                 \
+  case S:                                                                            \
+    grouped_pack<S, SCHED_SHORT_LAST, NARROW_THREADS>(sl, (int)pk.n_slots, L, skip,  \
+                                                      stid, sync);                   \
+    break;                                                                           \
+  case S | GROUP_SHORT_FIRST:                                                        \
+    grouped_pack<S, SCHED_SHORT_FIRST, NARROW_THREADS>(sl, (int)pk.n_slots, L, skip, \
+                                                       stid, sync);                  \
+    break;
+        HIDFT_ONE(0) HIDFT_ONE(1) HIDFT_ONE(2) HIDFT_ONE(3) HIDFT_ONE(4) HIDFT_TWO(5)
+        HIDFT_TWO(6) HIDFT_TWO(7) HIDFT_ONE(8) HIDFT_TWO(9) HIDFT_TWO(10) HIDFT_TWO(11)
+        HIDFT_ONE(12)
+#undef HIDFT_ONE
+#undef HIDFT_TWO
+        default:
+          break;
+      }
+      sync.sync();  // the next pack overwrites this lane's LDS
+    }
   }
   if (done_flag != nullptr) {
     // Completion signal (the server's batches): every block makes its stores
@@ -1364,18 +1499,18 @@ hidft_grouped_kernel(const GroupPack* __restrict__ packs, uint32_t n_packs,
 }
 
 int grouped_slots_per_pack(uint32_t s) {
-  return GROUPED_THREADS >> (s > 4 ? s - 4 : 0);
+  if (s >= GROUP_WIDE_MIN_S) return GROUPED_THREADS >> (s - 4);
+  return NARROW_THREADS >> (s > 4 ? s - 4 : 0);
 }
 
 hipError_t grouped_grid(uint32_t* blocks) {
   // Queried on the first call; racing threads store the same value.
   static std::atomic<int> cached{0};
   int max_grid = cached.load(std::memory_order_acquire);
-  const size_t lds_bytes = (size_t)GROUPED_LDS_SLOTS * sizeof(float2);
   if (max_grid == 0) {
     hipError_t e = hipFuncSetAttribute((const void*)hidft_grouped_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds_bytes);
+                                       (int)GROUPED_LDS_BYTES);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0, per_cu = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
@@ -1383,7 +1518,7 @@ hipError_t grouped_grid(uint32_t* blocks) {
         hipSuccess)
       return e;
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-             &per_cu, (const void*)hidft_grouped_kernel, GROUPED_THREADS, lds_bytes)) !=
+             &per_cu, (const void*)hidft_grouped_kernel, GROUPED_THREADS, GROUPED_LDS_BYTES)) !=
         hipSuccess)
       return e;
     max_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
@@ -1393,18 +1528,18 @@ hipError_t grouped_grid(uint32_t* blocks) {
   return hipSuccess;
 }
 
-hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,
+hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_wide, uint32_t n_narrow,
+                          const GroupSlot* d_slots, const uint32_t* d_lane_end, uint32_t grid,
                           hipStream_t stream, const GroupDone* done) {
-  if (n_packs == 0) return hipSuccess;
+  if (n_wide == 0 && n_narrow == 0) return hipSuccess;
   uint32_t max_grid = 0;
   hipError_t e = grouped_grid(&max_grid);
   if (e != hipSuccess) return e;
-  const size_t lds_bytes = (size_t)GROUPED_LDS_SLOTS * sizeof(float2);
-  const unsigned grid = n_packs < max_grid ? n_packs : max_grid;
-  hipLaunchKernelGGL(hidft_grouped_kernel, dim3(grid), dim3(GROUPED_THREADS), lds_bytes, stream,
-                     d_packs, n_packs, d_slots, done ? done->d_count : nullptr,
-                     done ? *done->count_base : 0u, done ? done->d_flag : nullptr,
-                     done ? done->seq : 0u);
+  if (grid == 0 || grid > max_grid) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(hidft_grouped_kernel, dim3(grid), dim3(GROUPED_THREADS), GROUPED_LDS_BYTES,
+                     stream, d_packs, n_wide, n_narrow, d_slots, d_lane_end,
+                     done ? done->d_count : nullptr, done ? *done->count_base : 0u,
+                     done ? done->d_flag : nullptr, done ? done->seq : 0u);
   e = hipGetLastError();
   if (e == hipSuccess && done) *done->count_base += grid;
   return e;

@@ -84,7 +84,16 @@ constexpr uint16_t GROUP_SHORT_FIRST = 0x100;
 // arithmetic (set by the server, whose batches are mostly empty packs).
 constexpr uint16_t GROUP_SKIP_IDLE = 0x200;
 
-// Instances of size 2^s that one pack holds (the block's 1024 threads).
+// Sizes 2^s with s >= GROUP_WIDE_MIN_S go in wide packs (the whole block:
+// 1024 threads, up to 2^14 points), smaller ones in narrow packs (a 256-thread
+// sub-block: up to 2^12 points).
+constexpr uint32_t GROUP_WIDE_MIN_S = 13;
+// Narrow sub-blocks per block of the grouped kernel.
+constexpr uint32_t GROUP_NARROW_PER_BLOCK = 4;
+// The host schedule's fixed cost of a pack, in points (its latency).
+constexpr uint64_t GROUP_PACK_COST_POINTS = 2048;
+
+// Instances of size 2^s that one pack holds.
 int grouped_slots_per_pack(uint32_t s);
 
 // Blocks of the persistent grouped launch on the current device.
@@ -100,9 +109,15 @@ struct GroupDone {
   uint32_t seq;
 };
 
-// Grouped persistent launch over n_packs packs; `done` (optional) signals
-// its completion through memory.
-hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_packs, const GroupSlot* d_slots,
+// Grouped persistent launch of `grid` blocks (at most grouped_grid's): the
+// first n_wide packs of d_packs are wide (block b takes packs b, b + grid,
+// ...), the next n_narrow narrow; lane l (quarter l % 4 of block l / 4) takes
+// narrow packs [d_lane_end[l - 1], d_lane_end[l]) (from 0 for l = 0), so
+// d_lane_end holds GROUP_NARROW_PER_BLOCK * grid non-decreasing entries, the
+// last n_narrow.  `done` (optional) signals the launch's completion through
+// memory.
+hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_wide, uint32_t n_narrow,
+                          const GroupSlot* d_slots, const uint32_t* d_lane_end, uint32_t grid,
                           hipStream_t stream, const GroupDone* done = nullptr);
 
 // Largest node (number of aliased coefficients) the leaf solves handle.

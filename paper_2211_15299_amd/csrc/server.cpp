@@ -323,20 +323,22 @@ void hidft_server_s::launch(Slot& sl) {
     off += r.k;
   }
   sl.points = off;
-  std::vector<hidft::GroupPack> packs;
-  std::vector<hidft::GroupSlot> slots_v;
-  hidft::pack_instances(inst, &packs, &slots_v, grid);
+  hidft::GroupSchedule sch;
+  hidft::pack_instances(inst, grid, false, false, &sch);
   // A batch is often a single request: let the empty slots' wavefronts idle.
-  for (auto& pk : packs) pk.log2_k |= hidft::GROUP_SKIP_IDLE;
+  for (auto& pk : sch.packs) pk.log2_k |= hidft::GROUP_SKIP_IDLE;
   const size_t packs_at = align_up(off * sizeof(float2), 256);
-  const size_t slots_at = align_up(packs_at + packs.size() * sizeof(hidft::GroupPack), 64);
-  std::memcpy(sl.h_up + packs_at, packs.data(), packs.size() * sizeof(hidft::GroupPack));
-  std::memcpy(sl.h_up + slots_at, slots_v.data(), slots_v.size() * sizeof(hidft::GroupSlot));
+  const size_t slots_at = align_up(packs_at + sch.packs.size() * sizeof(hidft::GroupPack), 64);
+  const size_t lanes_at = slots_at + sch.slots.size() * sizeof(hidft::GroupSlot);
+  std::memcpy(sl.h_up + packs_at, sch.packs.data(), sch.packs.size() * sizeof(hidft::GroupPack));
+  std::memcpy(sl.h_up + slots_at, sch.slots.data(), sch.slots.size() * sizeof(hidft::GroupSlot));
+  std::memcpy(sl.h_up + lanes_at, sch.lane_end.data(), sch.lane_end.size() * sizeof(uint32_t));
   hipError_t e;
   const hidft::GroupDone done{sl.d_count, &sl.count_base, sl.d_flag, ++sl.seq};
   if ((e = hidft::launch_grouped(reinterpret_cast<const hidft::GroupPack*>(sl.d_up + packs_at),
-                                 (uint32_t)packs.size(),
+                                 sch.n_wide, sch.n_narrow(),
                                  reinterpret_cast<const hidft::GroupSlot*>(sl.d_up + slots_at),
+                                 reinterpret_cast<const uint32_t*>(sl.d_up + lanes_at), sch.grid,
                                  sl.stream, &done)) != hipSuccess ||
       (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) {
     worker_error = (int32_t)HIDFT_ERR_DEVICE;
@@ -562,10 +564,11 @@ hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* o
   for (Slot& sl : sv->slots) {
     const size_t data = sv->slot_points * sizeof(float2);
     // samples, then packs and instance descriptors (one pack per instance at
-    // most) after their alignment padding
+    // most) after their alignment padding, then the schedule's lane table
     const size_t up = align_up(data, 256) +
                       align_up((size_t)cfg->max_batch * sizeof(hidft::GroupPack), 64) +
-                      (size_t)cfg->max_batch * sizeof(hidft::GroupSlot);
+                      (size_t)cfg->max_batch * sizeof(hidft::GroupSlot) +
+                      (size_t)sv->grid * hidft::GROUP_NARROW_PER_BLOCK * sizeof(uint32_t);
     if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
         (e = hipHostMalloc(&sl.h_up, up, hipHostMallocMapped | hipHostMallocCoherent)) !=

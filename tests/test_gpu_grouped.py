@@ -43,23 +43,24 @@ def _instances(n):
 
 
 def _expected_packs(ks, grid):
-    """Pack count of the host packer: instances of one size in packs of
-    1024 / 2^max(s-4, 0) slots, largest size first; when the packs leave a
-    partial last round of the grid, that round's packs are split until it
-    has a pack per block or every pack holds one instance."""
+    """Pack count of the host packer: k >= 2^13 in wide packs of
+    1024 / 2^(s-4) slots, whose partial last round of the grid is split until
+    it has a pack per block or every pack holds one instance; smaller sizes in
+    narrow packs of 256 / 2^max(s-4, 0) slots, split likewise up to one per
+    quarter block (4 per block of the grid)."""
     sizes = {}
     for k in ks:
         s = int(k).bit_length() - 1
         sizes[s] = sizes.get(s, 0) + 1
-    packs = []
+    wide, narrow = [], []
     for s in sorted(sizes, reverse=True):
-        per = 1024 >> max(s - 4, 0)
+        per = (1024 >> (s - 4)) if s >= 13 else (256 >> max(s - 4, 0))
         n = sizes[s]
-        packs += [min(per, n - i) for i in range(0, n, per)]
-    full = len(packs) // grid * grid
-    if full == 0 or full == len(packs):
-        return len(packs)
-    return full + min(grid, sum(packs[full:]))
+        (wide if s >= 13 else narrow).extend(min(per, n - i) for i in range(0, n, per))
+    full = len(wide) // grid * grid
+    n_wide = len(wide) if full in (0, len(wide)) else full + min(grid, sum(wide[full:]))
+    n_narrow = len(narrow) if len(narrow) >= 4 * grid else min(4 * grid, sum(narrow))
+    return n_wide + n_narrow
 
 
 def _energy_rel(c, f, M, k):
@@ -85,8 +86,7 @@ def test_config3_uneven_batch_one_launch():
     assert grp.n_packs == _expected_packs(ks, cus), (grp.n_packs, _expected_packs(ks, cus))
     grp.execute()
     torch.cuda.synchronize()
-    _say(f"C3: {grp.n_packs} packs executed ({_expected_packs(ks, 10**9)} full packs, "
-         f"the partial last round spread over {cus} blocks)")
+    _say(f"C3: {grp.n_packs} packs executed on {cus} blocks")
     got = [y.cpu().numpy().astype(np.complex128) for y in ys]
     # fused single-plan path on each instance: bit-identical
     n_diff = 0
@@ -160,21 +160,26 @@ def test_grouped_mixed_batches_and_ragged_packs():
     grp.close()
 
 
-@pytest.mark.parametrize("s,full_rounds,tail_packs,ragged", [(14, 1, 10, 0), (12, 2, 0, 0),
-                                                           (8, 1, 44, 17)])
+@pytest.mark.parametrize("s,full_rounds,tail_packs,ragged", [(14, 1, 10, 0), (13, 1, 37, 1),
+                                                           (12, 1, 0, 0), (8, 0, 44, 17),
+                                                           (6, 1, 44, 3)])
 def test_grouped_last_round_spreading(s, full_rounds, tail_packs, ragged):
-    """The packer's edge cases, one plan with many rows each: a partial last
-    round of single-instance packs (2^14 points, nothing to split), packs
-    that fill whole rounds (nothing to spread), and a partial round of
-    64-instance packs spread to a pack per block.  Pack count as the model
-    says; every row bit-identical to hidft_execute."""
+    """The packer's edge cases, one plan with many rows each.  Wide packs
+    (a round is one pack per block): a partial last round of single-instance
+    packs (2^14 points, nothing to split), and a partial round of 2-instance
+    packs split to single ones.  Narrow packs (a round is one pack per quarter
+    block): exactly one round (nothing to spread), fewer packs than a round
+    (split until every instance has its own), and more than a round (kept
+    full).  Pack count as the model says; every row bit-identical to
+    hidft_execute."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     rng = rng_for(3, 8000 + s)
     M = s + 6
     plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
     k = plan.k
-    per = 1024 >> max(s - 4, 0)    # instances per full pack
-    batch = (full_rounds * cus + tail_packs) * per + ragged
+    per = (1024 >> (s - 4)) if s >= 13 else (256 >> max(s - 4, 0))  # instances per full pack
+    round_packs = cus if s >= 13 else 4 * cus
+    batch = (full_rounds * round_packs + tail_packs) * per + ragged
     _say(f"case s={s} batch={batch} cus={cus}")
     x = torch.from_numpy(sample_values(M, k, batch, rng)).cuda()
     y = torch.full_like(x, complex(np.nan, np.nan))
@@ -183,6 +188,11 @@ def test_grouped_last_round_spreading(s, full_rounds, tail_packs, ragged):
     assert grp.n_packs == want_packs, (grp.n_packs, want_packs)
     grp.execute()
     ref = plan.execute(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+    # a second launch finds the narrow-pack queue back at zero
+    y.fill_(complex(np.nan, np.nan))
+    grp.execute()
     torch.cuda.synchronize()
     assert torch.equal(y, ref)
     grp.close()
