@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="duration of the Poisson arrival process (serving)")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="arrivals per second")
+    ap.add_argument("--no-serve-sweep", action="store_true",
+                    help="serving: skip the load curve after the --serve-rate run")
     ap.add_argument("--cpu-sample", type=int, default=512,
                     help="signals in the bounded oracle sample (cpu_baseline)")
     ap.add_argument("--plain-signals", type=int, default=4096,
@@ -500,7 +502,7 @@ def serve_bench(args, native, seconds=None):
                 "plan_warmup_s": plan_warm_s, "plans_resident": int(st["plans_resident"]),
                 "plan_bytes_resident": int(st["plan_bytes_resident"])})
     curve = []
-    for q, rate in enumerate(SERVE_SWEEP_RATES):
+    for q, rate in enumerate(() if args.no_serve_sweep else SERVE_SWEEP_RATES):
         r = serve_run(native, srv, sups, vecs, rate, 2.0, 2 * 10 ** 6 + q)
         curve.append({k: r[k] for k in ("offered_per_s", "transforms_per_s", "completed",
                                         "rejected", "failed", "latency_us", "batch_size_mean",
