@@ -66,6 +66,7 @@ typedef struct hidft_plan_s* hidft_plan;
 #define HIDFT_MAX_LOG2_N 63u        /* N = 2^M with M <= 63 */
 #define HIDFT_MAX_LOG2_K_HOST 26u   /* planner (HOST_ONLY plans): k <= 2^26 */
 #define HIDFT_MAX_LOG2_K_DEVICE 14u /* executor: one signal is staged whole in LDS */
+#define HIDFT_MAX_LOG2_K_LARGE 18u  /* hidft_execute / _ws: larger k in passes through a workspace */
 
 /* Plan flags. */
 #define HIDFT_PLAN_HOST_ONLY 0x1u   /* derive the schedule on the host only: no
@@ -113,8 +114,10 @@ hidft_status hidft_analyze(uint32_t log2_n, const uint64_t* J, uint64_t k,
  *   out           receives the plan; set to NULL on failure.
  * Errors: INVALID_ARGUMENT, INDEX_OUT_OF_RANGE, DUPLICATE_INDEX,
  * SIZE_NOT_POW2, NOT_HOMOGENEOUS, UNSUPPORTED (device plan with
- * k > 2^HIDFT_MAX_LOG2_K_DEVICE, or k > 2^HIDFT_MAX_LOG2_K_HOST),
- * OUT_OF_MEMORY, DEVICE.
+ * k > 2^HIDFT_MAX_LOG2_K_LARGE, or k > 2^HIDFT_MAX_LOG2_K_HOST),
+ * OUT_OF_MEMORY, DEVICE.  A device plan with k > 2^HIDFT_MAX_LOG2_K_DEVICE
+ * runs only through hidft_execute and hidft_execute_ws (the other execute
+ * calls, the group and the autotuner return UNSUPPORTED for it).
  */
 hidft_status hidft_plan_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
                                uint32_t flags, void* stream, hidft_plan* out);
@@ -167,6 +170,17 @@ hidft_status hidft_plan_device_bytes(hidft_plan plan, size_t* bytes);
  * One fused kernel launch: each signal is read once from HBM, transformed in
  * LDS and registers, and written once.
  *
+ * k > 2^HIDFT_MAX_LOG2_K_DEVICE (up to 2^HIDFT_MAX_LOG2_K_LARGE): the stages
+ * run in three passes through a workspace of hidft_plan_workspace_bytes
+ * (Corollary 2: the recursion splits at any level): the top s1 = s - s2
+ * stages (s1 <= 4) on the 2^s2 columns of each signal, the other s2 stages
+ * (12 <= s2 <= 14) on each of the 2^s1 subtrees with the fused kernel's
+ * per-signal code, then a gather into the caller's order of J, scaled by
+ * N/k.  The stage arithmetic and order are those of one pass.  Here
+ * hidft_execute takes the workspace from the stream-ordered allocator
+ * (hipMallocAsync / hipFreeAsync on `stream`); hidft_execute_ws takes it
+ * from the caller instead and allocates nothing.
+ *
  *   d_samples  device, complex64, batch rows of ld_in >= k values.
  *   d_coefs    device, complex64, batch rows of ld_out >= k values.
  *              May equal d_samples (in place) when ld_out == ld_in; any other
@@ -180,6 +194,29 @@ hidft_status hidft_plan_device_bytes(hidft_plan plan, size_t* bytes);
 hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in,
                            void* d_coefs, int64_t ld_out, uint64_t batch,
                            void* stream);
+
+/*
+ * Workspace of hidft_execute_ws for `batch` signals: 0 for
+ * k <= 2^HIDFT_MAX_LOG2_K_DEVICE (one pass, no workspace), else
+ * batch * k * 8 bytes (one complex64 intermediate per point).  Any plan
+ * (also HOST_ONLY).  Errors: INVALID_ARGUMENT (NULL, or a size that
+ * overflows).
+ */
+hidft_status hidft_plan_workspace_bytes(hidft_plan plan, uint64_t batch, size_t* bytes);
+
+/*
+ * hidft_execute_ws -- hidft_execute with the caller's workspace: the same
+ * result, bit for bit, and no allocation.  d_work: device, 8-byte aligned,
+ * at least hidft_plan_workspace_bytes(plan, batch) bytes, not overlapping
+ * the samples or coefficients (d_samples may still equal d_coefs as for
+ * hidft_execute); its contents are overwritten.  For
+ * k <= 2^HIDFT_MAX_LOG2_K_DEVICE d_work is not used (may be NULL).
+ * Errors: those of hidft_execute, and INVALID_ARGUMENT for a missing,
+ * small, misaligned or overlapping workspace.
+ */
+hidft_status hidft_execute_ws(hidft_plan plan, const void* d_samples, int64_t ld_in,
+                              void* d_coefs, int64_t ld_out, uint64_t batch, void* d_work,
+                              size_t work_bytes, void* stream);
 
 /*
  * Execution variants of the fused transform (hidft_execute_config).

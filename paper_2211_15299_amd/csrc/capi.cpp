@@ -59,14 +59,30 @@ hidft_status hip_fail(hipError_t e, const char* what) {
 void release_device(hidft_plan p) {
   if (p->d_tw) (void)hipFree(p->d_tw);
   if (p->d_src) (void)hipFree(p->d_src);
+  if (p->d_pos) (void)hipFree(p->d_pos);
+  p->d_pos = nullptr;
   void* am = p->d_amat.exchange(nullptr);
   if (am) (void)hipFree(am);
   p->d_tw = nullptr;
   p->d_src = nullptr;
 }
 
-// Twiddle exponents in the device order of the twiddle table: entry
-// (2^{u-1}-1) + bitrev_{u-1}(q_lo) holds the twiddle of stage u, node q_lo.
+// Entry of the device twiddle table that holds stage u's twiddle for the
+// node named by the top u - 1 bits n of the position (a-order).  Up to
+// 2^HIDFT_MAX_LOG2_K_DEVICE points: (2^{u-1} - 1) + n.  Above, the split
+// layout of the passes (launch_large): stages 1..s1 as before, then for each
+// subtree (the top s1 bits of n) the table of its 2^s2-point transform.
+uint64_t device_tw_index(uint32_t s, uint32_t u, uint64_t n) {
+  if (s <= HIDFT_MAX_LOG2_K_DEVICE) return ((1ULL << (u - 1)) - 1) + n;
+  const uint32_t s2 = hidft::large_split(s), s1 = s - s2;
+  if (u <= s1) return ((1ULL << (u - 1)) - 1) + n;
+  const uint32_t u2 = u - s1;
+  const uint64_t sub = n >> (u2 - 1), n2 = n & ((1ULL << (u2 - 1)) - 1);
+  return ((1ULL << s1) - 1) + sub * ((1ULL << s2) - 1) + ((1ULL << (u2 - 1)) - 1) + n2;
+}
+
+// Twiddle exponents in the device order of the twiddle table: stage u's
+// node q_lo (schedule order) is node bitrev_{u-1}(q_lo) in a-order.
 void device_exponents(const hidft::PlanCore& c, std::vector<uint64_t>* num,
                       std::vector<uint8_t>* den) {
   const uint64_t ntw = c.k - 1;
@@ -75,9 +91,9 @@ void device_exponents(const hidft::PlanCore& c, std::vector<uint64_t>* num,
   for (uint32_t u = 1; u <= c.s; ++u) {
     const uint64_t off = (1ULL << (u - 1)) - 1;
     for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
-      const uint64_t h = hidft::bit_reverse(q_lo, u - 1);
-      (*num)[off + h] = c.tw_num[off + q_lo];
-      (*den)[off + h] = c.tw_log2den[off + q_lo];
+      const uint64_t at = device_tw_index(c.s, u, hidft::bit_reverse(q_lo, u - 1));
+      (*num)[at] = c.tw_num[off + q_lo];
+      (*den)[at] = c.tw_log2den[off + q_lo];
     }
   }
 }
@@ -93,16 +109,26 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
   std::vector<uint64_t> num;
   std::vector<uint8_t> den;
   device_exponents(c, &num, &den);
-  std::vector<uint16_t> src(k);
-  for (uint64_t t = 0; t < k; ++t)
-    src[t] = static_cast<uint16_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
+  // Output positions (a-order) of the caller's coefficients: 16-bit for the
+  // single-pass kernels, 32-bit for the passes of larger plans.
+  const bool large = c.s > HIDFT_MAX_LOG2_K_DEVICE;
+  std::vector<uint16_t> src(large ? 0 : k);
+  std::vector<uint32_t> pos(large ? k : 0);
+  for (uint64_t t = 0; t < k; ++t) {
+    const uint64_t pt = hidft::bit_reverse(c.freq_pos[t], c.s);
+    if (large)
+      pos[t] = static_cast<uint32_t>(pt);
+    else
+      src[t] = static_cast<uint16_t>(pt);
+  }
 
   const size_t ntw_alloc = ntw ? ntw : 1;
   uint64_t* d_num = nullptr;
   uint8_t* d_den = nullptr;
   hidft_status st = HIDFT_OK;
   if ((e = hipMalloc(&p->d_tw, ntw_alloc * sizeof(float2))) != hipSuccess ||
-      (e = hipMalloc(&p->d_src, k * sizeof(uint16_t))) != hipSuccess ||
+      (e = large ? hipMalloc(&p->d_pos, k * sizeof(uint32_t))
+                 : hipMalloc(&p->d_src, k * sizeof(uint16_t))) != hipSuccess ||
       (e = hipMalloc(&d_num, ntw_alloc * sizeof(uint64_t))) != hipSuccess ||
       (e = hipMalloc(&d_den, ntw_alloc)) != hipSuccess) {
     st = hip_fail(e, "hipMalloc of plan tables");
@@ -110,8 +136,10 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
                                  hipMemcpyHostToDevice, stream)) != hipSuccess ||
              (e = hipMemcpyAsync(d_den, den.data(), ntw_alloc, hipMemcpyHostToDevice,
                                  stream)) != hipSuccess ||
-             (e = hipMemcpyAsync(p->d_src, src.data(), k * sizeof(uint16_t),
-                                 hipMemcpyHostToDevice, stream)) != hipSuccess) {
+             (e = large ? hipMemcpyAsync(p->d_pos, pos.data(), k * sizeof(uint32_t),
+                                         hipMemcpyHostToDevice, stream)
+                        : hipMemcpyAsync(p->d_src, src.data(), k * sizeof(uint16_t),
+                                         hipMemcpyHostToDevice, stream)) != hipSuccess) {
     st = hip_fail(e, "hipMemcpyAsync of plan tables");
   } else if ((e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, stream)) !=
              hipSuccess) {
@@ -168,7 +196,17 @@ hidft_status check_exec(hidft_plan plan, const void* d_in, int64_t ld_in, const 
 namespace hidft {
 
 size_t plan_table_bytes(uint64_t k) {
-  return (k > 1 ? k - 1 : 1) * sizeof(float2) + k * sizeof(uint16_t);
+  const size_t pos_bytes = k > (1ULL << HIDFT_MAX_LOG2_K_DEVICE) ? 4 : 2;
+  return (k > 1 ? k - 1 : 1) * sizeof(float2) + k * pos_bytes;
+}
+
+hidft_status require_single_pass(const hidft_plan plan, const char* fn) {
+  if (plan && plan->core.s > HIDFT_MAX_LOG2_K_DEVICE)
+    return fail(HIDFT_ERR_UNSUPPORTED,
+                "%s: k = 2^%u runs only through hidft_execute / hidft_execute_ws (this call "
+                "needs k <= 2^%u, one signal staged in LDS)",
+                fn, plan->core.s, HIDFT_MAX_LOG2_K_DEVICE);
+  return HIDFT_OK;
 }
 
 hidft_status plan_amat(hidft_plan p, hipStream_t stream, void** amat, const char* fn) {
@@ -185,6 +223,7 @@ hidft_status plan_amat(hidft_plan p, hipStream_t stream, void** amat, const char
   }
   const hidft::PlanCore& c = p->core;
   if (c.s < 4) return fail(HIDFT_ERR_UNSUPPORTED, "%s: matrix cores need k >= 16", fn);
+  if (hidft_status st = require_single_pass(p, fn)) return st;
   // Radix-16 operands for k >= 16, the radix-32 ones after them for k >= 2^13.
   const bool with_amat32 = c.s >= 13;
   const size_t amat_bytes = AMAT_BYTES + (with_amat32 ? AMAT32_BYTES : 0);
@@ -350,6 +389,7 @@ namespace hidft {
 hidft_status resolve_config(const hidft_plan plan, const hidft_exec_config* cfg, ExecConfig* out,
                             const char* fn) {
   const uint32_t s = plan->core.s;
+  if (hidft_status st = require_single_pass(plan, fn)) return st;
   if (cfg->precision > HIDFT_PREC_BF16X3)
     return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: unknown precision %u", fn, cfg->precision);
   if (cfg->schedule > HIDFT_SCHED_SHORT_LAST)
@@ -432,7 +472,7 @@ hidft_status hidft_plan_create(uint32_t log2_n, const uint64_t* J, uint64_t k, u
   try {
     p = new hidft_plan_s;
     std::string err;
-    const uint32_t max_s = host_only ? HIDFT_MAX_LOG2_K_HOST : HIDFT_MAX_LOG2_K_DEVICE;
+    const uint32_t max_s = host_only ? HIDFT_MAX_LOG2_K_HOST : HIDFT_MAX_LOG2_K_LARGE;
     hidft_status st = hidft::build_plan_core(log2_n, J, k, max_s, &p->core, &err);
     if (st != HIDFT_OK) {
       delete p;
@@ -519,7 +559,7 @@ hidft_status hidft_plan_get_twiddles(hidft_plan plan, float* twiddles) {
   for (uint32_t u = 1; u <= c.s; ++u) {
     const uint64_t off = (1ULL << (u - 1)) - 1;
     for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
-      const float2 w = dev[off + hidft::bit_reverse(q_lo, u - 1)];
+      const float2 w = dev[device_tw_index(c.s, u, hidft::bit_reverse(q_lo, u - 1))];
       twiddles[2 * (off + q_lo)] = w.x;
       twiddles[2 * (off + q_lo) + 1] = w.y;
     }
@@ -534,10 +574,71 @@ hidft_status hidft_plan_device_bytes(hidft_plan plan, size_t* bytes) {
   return ok();
 }
 
+hidft_status hidft_plan_workspace_bytes(hidft_plan plan, uint64_t batch, size_t* bytes) {
+  if (!plan || !bytes)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_workspace_bytes: NULL argument");
+  *bytes = 0;
+  if (plan->core.s <= HIDFT_MAX_LOG2_K_DEVICE || batch == 0) return ok();
+  if (batch > (~0ULL >> (plan->core.s + 4)))
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "hidft_plan_workspace_bytes: batch too large");
+  *bytes = (size_t)(batch << plan->core.s) * sizeof(float2);
+  return ok();
+}
+
+hidft_status hidft_execute_ws(hidft_plan plan, const void* d_samples, int64_t ld_in,
+                              void* d_coefs, int64_t ld_out, uint64_t batch, void* d_work,
+                              size_t work_bytes, void* stream) {
+  const char* fn = "hidft_execute_ws";
+  hidft_status st = check_exec(plan, d_samples, ld_in, d_coefs, ld_out, batch, fn);
+  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
+  if (plan->core.s <= HIDFT_MAX_LOG2_K_DEVICE) return hidft_execute(plan, d_samples, ld_in,
+                                                                    d_coefs, ld_out, batch,
+                                                                    stream);
+  size_t need = 0;
+  if ((st = hidft_plan_workspace_bytes(plan, batch, &need)) != HIDFT_OK) return st;
+  if (!d_work || work_bytes < need)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: workspace of %zu bytes needed, %zu given", fn,
+                need, d_work ? work_bytes : (size_t)0);
+  if (reinterpret_cast<uintptr_t>(d_work) & 7u)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: workspace must be 8-byte aligned", fn);
+  const uintptr_t w0 = reinterpret_cast<uintptr_t>(d_work), w1 = w0 + need;
+  const uint64_t k = plan->core.k;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(d_samples);
+  const uintptr_t a1 = a0 + ((batch - 1) * (uint64_t)ld_in + k) * sizeof(float2);
+  const uintptr_t b0 = reinterpret_cast<uintptr_t>(d_coefs);
+  const uintptr_t b1 = b0 + ((batch - 1) * (uint64_t)ld_out + k) * sizeof(float2);
+  if ((w0 < a1 && a0 < w1) || (w0 < b1 && b0 < w1))
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: the workspace overlaps the samples or coefficients",
+                fn);
+  hipError_t e = hidft::launch_large(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
+                                     static_cast<float2*>(d_coefs), ld_out, batch,
+                                     static_cast<float2*>(d_work), plan->d_tw, plan->d_pos,
+                                     plan->scale, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hidft_execute_ws: kernel launch");
+  return ok();
+}
+
 hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in,
                            void* d_coefs, int64_t ld_out, uint64_t batch, void* stream) {
   hidft_status st = check_exec(plan, d_samples, ld_in, d_coefs, ld_out, batch, "hidft_execute");
   if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
+  if (plan->core.s > HIDFT_MAX_LOG2_K_DEVICE) {
+    // The passes' workspace, from the stream-ordered allocator: taken and
+    // returned on `stream`, around the launches.
+    size_t need = 0;
+    if ((st = hidft_plan_workspace_bytes(plan, batch, &need)) != HIDFT_OK) return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    void* work = nullptr;
+    hipError_t e = hipMallocAsync(&work, need, hs);
+    if (e != hipSuccess) return hip_fail(e, "hidft_execute: workspace allocation");
+    e = hidft::launch_large(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
+                            static_cast<float2*>(d_coefs), ld_out, batch,
+                            static_cast<float2*>(work), plan->d_tw, plan->d_pos, plan->scale, hs);
+    const hipError_t ef = hipFreeAsync(work, hs);
+    if (e != hipSuccess) return hip_fail(e, "hidft_execute: kernel launch");
+    if (ef != hipSuccess) return hip_fail(ef, "hidft_execute: workspace release");
+    return ok();
+  }
   hipError_t e = hidft::launch_fused(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
                                      static_cast<float2*>(d_coefs), ld_out, batch, plan->d_tw,
                                      plan->d_src, nullptr, plan->scale, hidft::ExecConfig{},
@@ -582,6 +683,7 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
                                    void* stream) {
   hidft_status st =
       check_exec(plan, d_coefs, ld_in, d_samples, ld_out, batch, "hidft_execute_inverse");
+  if (st == HIDFT_OK) st = hidft::require_single_pass(plan, "hidft_execute_inverse");
   if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
   const float inv_n = std::ldexp(1.0f, -(int)plan->core.M);
   hipError_t e = hidft::launch_inverse(plan->core.s, static_cast<const float2*>(d_coefs), ld_in,
@@ -595,6 +697,7 @@ hidft_status hidft_execute_plain(hidft_plan plan, const void* d_samples, int64_t
                                  void* d_coefs, int64_t ld_out, uint64_t batch, void* stream) {
   hidft_status st =
       check_exec(plan, d_samples, ld_in, d_coefs, ld_out, batch, "hidft_execute_plain");
+  if (st == HIDFT_OK) st = hidft::require_single_pass(plan, "hidft_execute_plain");
   if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
   const float2* in = static_cast<const float2*>(d_samples);
   float2* out = static_cast<float2*>(d_coefs);
@@ -623,6 +726,7 @@ hidft_status hidft_group_create(const hidft_work* items, uint64_t n_items, void*
       char fn[64];
       std::snprintf(fn, sizeof fn, "hidft_group_create: item %llu", (unsigned long long)i);
       hidft_status st = check_exec(w.plan, w.d_samples, w.ld_in, w.d_coefs, w.ld_out, w.batch, fn);
+      if (st == HIDFT_OK) st = hidft::require_single_pass(w.plan, fn);
       if (st != HIDFT_OK) return st;
       if (w.batch == 0) continue;
       device = w.plan->device;

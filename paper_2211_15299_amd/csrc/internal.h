@@ -18,7 +18,8 @@ struct hidft_plan_s {
   bool host_only = true;
   int device = -1;
   float2* d_tw = nullptr;      // k-1 twiddles in a-order (at least one slot)
-  uint16_t* d_src = nullptr;   // k output gather positions
+  uint16_t* d_src = nullptr;   // k output gather positions (k <= 2^14)
+  uint32_t* d_pos = nullptr;   // the same, 32-bit, for k > 2^14 (passes through a workspace)
   // Split operands of the group-1 matrix (k >= 16), built on the first
   // matrix-core execution (hidft::plan_amat) and kept until destroy.
   std::atomic<void*> d_amat{nullptr};
@@ -30,8 +31,14 @@ struct hidft_plan_s {
 namespace hidft {
 
 // Device bytes of a plan's tables at creation: k - 1 twiddles (at least one)
-// and k gather positions.  (The matrix-core operands come later, on demand.)
+// and k gather positions (2 bytes each up to 2^14, else 4).  (The
+// matrix-core operands come later, on demand.)
 size_t plan_table_bytes(uint64_t k);
+
+// HIDFT_ERR_UNSUPPORTED (with a message naming fn) for a plan of more than
+// 2^HIDFT_MAX_LOG2_K_DEVICE points, which only hidft_execute and
+// hidft_execute_ws run; HIDFT_OK otherwise.
+hidft_status require_single_pass(const hidft_plan plan, const char* fn);
 
 // The plan's matrix-core operands, built on first use: allocated, computed
 // in FP64 on the device on `stream` and waited for (the first matrix-core

@@ -2001,6 +2001,191 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
 }
 
 // ---------------------------------------------------------------------------
+// Transforms of more than 2^14 points, in passes through a workspace.
+//
+// The recursion splits at any level (Corollary 2).  With s = s1 + s2
+// (s1 <= 4, 12 <= s2 <= 14):
+//  * pass 1: stages 1..s1 pair only the top s1 bits of the position a, and
+//    their twiddles depend on those bits alone, so for every value of the
+//    low s2 bits (a column) the 2^s1 values of the column form a transform
+//    with the same s1-stage twiddles.  A thread takes one column, in
+//    registers.
+//  * pass 2: stages s1+1..s never mix values whose top s1 bits differ, so
+//    each subtree (2^s2 consecutive positions) is a transform of 2^s2 points
+//    whose stage-u' twiddles are the run of stage s1+u' starting at
+//    subtree * 2^(u'-1).  The plan keeps these runs in the fused kernel's
+//    table layout, one table per subtree, and the fused kernel's per-signal
+//    code runs each subtree in place, leaving its values in position order.
+//  * pass 3: the coefficients are gathered from position order into the
+//    caller's order of J (32-bit positions) and scaled by N/k.
+// Every stage's arithmetic is the single-pass kernel's, in the same order.
+// ---------------------------------------------------------------------------
+constexpr int LARGE_THREADS = 256;
+
+template <int S1>
+__global__ void __launch_bounds__(LARGE_THREADS)
+large_top_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ work,
+                 uint64_t batch, uint32_t s2, const float2* __restrict__ tw) {
+  constexpr int R1 = 1 << S1;
+  float2 w[R1 - 1];
+#pragma unroll
+  for (int i = 0; i < R1 - 1; ++i) w[i] = make_uniform(tw[i]);
+  const uint64_t cols = 1ULL << s2;
+  const uint64_t k = cols << S1;
+  const uint64_t n = batch << s2;
+  const uint64_t stride = (uint64_t)gridDim.x * LARGE_THREADS;
+  for (uint64_t i = (uint64_t)blockIdx.x * LARGE_THREADS + threadIdx.x; i < n; i += stride) {
+    const uint64_t b = i >> s2, col = i & (cols - 1);
+    const float2* x = in + b * (uint64_t)ld_in + col;
+    float2 v[R1];
+#pragma unroll
+    for (int h = 0; h < R1; ++h) v[h] = load_stream(x + (uint64_t)h * cols);
+#pragma unroll
+    for (int u = 1; u <= S1; ++u) {
+      const int bit = S1 - u;
+#pragma unroll
+      for (int c = 0; c < R1; ++c) {
+        if (c & (1 << bit)) continue;
+        butterfly(v[c], v[c | (1 << bit)], w[(1 << (u - 1)) - 1 + (c >> (bit + 1))]);
+      }
+    }
+    float2* y = work + b * k + col;
+#pragma unroll
+    for (int h = 0; h < R1; ++h) y[(uint64_t)h * cols] = v[h];
+  }
+}
+
+// A subtree's transform: its own twiddle table, outputs in position order
+// (identity gather), stored over its inputs.
+struct SubtreeMem {
+  const float2* tw;
+  float2* out;
+  __device__ __forceinline__ float2 tw_at(int uni, int lane) const { return tw[uni + lane]; }
+  __device__ __forceinline__ int src_at(int uni, int lane) const { return uni + lane; }
+  __device__ __forceinline__ void put(int uni, int lane, float2 x) const { out[uni + lane] = x; }
+};
+
+template <int S2, int SCHED>
+__global__ void __launch_bounds__((FusedShape<S2, SCHED, 4>::THREADS))
+large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint32_t s1,
+                 const float2* __restrict__ tw2) {
+  using Sh = FusedShape<S2, SCHED, 4>;
+  static_assert(Sh::SPB == 1 && Sh::THREADS == Sh::T, "one subtree per block");
+  constexpr int R = Sh::R, T = Sh::T;
+  constexpr uint64_t K2 = 1ULL << S2;
+  extern __shared__ float2 lds[];
+  const uint64_t unit = first + blockIdx.x;
+  if (unit >= units) return;  // uniform over the block
+  const uint64_t sub = unit & ((1ULL << s1) - 1);
+  float2* row = work + unit * K2;  // unit = signal * 2^s1 + subtree
+  float2 v[R];
+  __builtin_amdgcn_s_setprio(2);
+  load_row<R, T, false>(v, row, (uint32_t)K2);
+  __builtin_amdgcn_s_setprio(0);
+  const SubtreeMem mem{tw2 + sub * (K2 - 1), row};
+  ThreadState<S2, SCHED, 4> unused;
+  const MfmaOps<PREC_FP32> no_mfma;
+  transform_signal<S2, SCHED, 4, PREC_FP32, false>(v, lds, 0, (int)threadIdx.x, true, mem, 1.0f,
+                                                    unused, no_mfma);
+}
+
+__global__ void __launch_bounds__(LARGE_THREADS)
+large_gather_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
+                    uint64_t batch, uint32_t s, const uint32_t* __restrict__ pos, float scale) {
+  const uint64_t k = 1ULL << s;
+  const uint64_t n = batch << s;
+  const uint64_t stride = (uint64_t)gridDim.x * LARGE_THREADS;
+  for (uint64_t i = (uint64_t)blockIdx.x * LARGE_THREADS + threadIdx.x; i < n; i += stride) {
+    const uint64_t b = i >> s, t = i & (k - 1);
+    const float2 x = work[b * k + pos[t]];
+    store_stream(out + b * (uint64_t)ld_out + t, make_float2(x.x * scale, x.y * scale));
+  }
+}
+
+uint32_t large_split(uint32_t s) { return s > 16 ? s - 4 : 12; }
+
+static hipError_t stream_grid(uint64_t threads, unsigned* grid) {
+  static OccupancyCache cache;
+  Occupancy occ;
+  if (!cache.get(&occ)) {
+    int dev = 0, cus = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+      return e;
+    occ.cus = cus > 0 ? cus : 1;
+    occ.per_cu = 8;
+    cache.put(occ);
+  }
+  const uint64_t want = (threads + LARGE_THREADS - 1) / LARGE_THREADS;
+  const uint64_t cap = (uint64_t)occ.per_cu * occ.cus;
+  *grid = (unsigned)(want < cap ? want : cap);
+  return hipSuccess;
+}
+
+template <int S2, int SCHED>
+static hipError_t launch_large_sub(float2* work, uint64_t units, uint32_t s1, const float2* tw2,
+                                   hipStream_t stream) {
+  using Sh = FusedShape<S2, SCHED, 4>;
+  static OccupancyCache cache;
+  Occupancy occ;
+  if (!cache.get(&occ)) {
+    hipError_t e = query_occupancy((const void*)large_sub_kernel<S2, SCHED>, Sh::THREADS,
+                                   Sh::LDS_BYTES, &occ);
+    if (e != hipSuccess) return e;
+    cache.put(occ);
+  }
+  const uint64_t chunk = 0x7fffffffULL;
+  for (uint64_t first = 0; first < units; first += chunk) {
+    const uint64_t n = units - first < chunk ? units - first : chunk;
+    hipLaunchKernelGGL((large_sub_kernel<S2, SCHED>), dim3((unsigned)n), dim3(Sh::THREADS),
+                       Sh::LDS_BYTES, stream, work, first, units, s1, tw2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out,
+                        int64_t ld_out, uint64_t batch, float2* work, const float2* tw,
+                        const uint32_t* pos, float scale, hipStream_t stream) {
+  if (batch == 0) return hipSuccess;
+  if (s <= HIDFT_MAX_LOG2_K_DEVICE || s > HIDFT_MAX_LOG2_K_LARGE) return hipErrorInvalidValue;
+  const uint32_t s2 = large_split(s), s1 = s - s2;
+  const uint64_t k = 1ULL << s;
+  if (batch > (~0ULL >> (s + 1))) return hipErrorInvalidValue;
+  unsigned grid = 0;
+  hipError_t e = stream_grid(batch << s2, &grid);
+  if (e != hipSuccess) return e;
+  switch (s1) {
+#define HIDFT_TOP(S1)                                                                       \
+  case S1:                                                                                  \
+    hipLaunchKernelGGL(large_top_kernel<S1>, dim3(grid), dim3(LARGE_THREADS), 0, stream, in, \
+                       ld_in, work, batch, s2, tw);                                         \
+    break;
+    HIDFT_TOP(1) HIDFT_TOP(2) HIDFT_TOP(3) HIDFT_TOP(4)
+#undef HIDFT_TOP
+    default:
+      return hipErrorInvalidValue;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const float2* tw2 = tw + ((1u << s1) - 1);
+  const uint64_t units = batch << s1;
+  switch (s2) {
+    case 12: e = launch_large_sub<12, SCHED_SHORT_LAST>(work, units, s1, tw2, stream); break;
+    case 13: e = launch_large_sub<13, SCHED_SHORT_LAST>(work, units, s1, tw2, stream); break;
+    case 14: e = launch_large_sub<14, SCHED_SHORT_LAST>(work, units, s1, tw2, stream); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if ((e = stream_grid(batch * k, &grid)) != hipSuccess) return e;
+  hipLaunchKernelGGL(large_gather_kernel, dim3(grid), dim3(LARGE_THREADS), 0, stream, work, out,
+                     ld_out, batch, s, pos, scale);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Scratch of the allocation-free Shift-and-Sample entry point: the shifted
 // Hi-DFT outputs of a chunk of signals, [signal][shift][node], instead of a
 // caller's workspace.  In host code `scratch` names a host-side stand-in, not

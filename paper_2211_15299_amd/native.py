@@ -29,6 +29,7 @@ HIDFT_SAS_TWO_PASS = 0x2
 HIDFT_SAS_WEIGHTS_ONLY = 0x4
 SAS_MAX_REL_ERR = 1e-5
 MAX_LOG2_K_DEVICE = 14
+MAX_LOG2_K_LARGE = 18
 
 # Execution variants (hidft_exec_config)
 PREC_FP32, PREC_F16X2, PREC_BF16X3 = 0, 1, 2
@@ -59,6 +60,9 @@ SIGNATURES = [
     ("hidft_plan_get_twiddles", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float)]),
     ("hidft_plan_device_bytes", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("hidft_execute", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
+    ("hidft_plan_workspace_bytes", ctypes.c_int, [_vp, _u64, ctypes.POINTER(ctypes.c_size_t)]),
+    ("hidft_execute_ws", ctypes.c_int,
+     [_vp, _vp, _i64, _vp, _i64, _u64, _vp, ctypes.c_size_t, _vp]),
     ("hidft_execute_config", ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _u64, _vp]),
     ("hidft_autotune", ctypes.c_int, [_vp, _u32, _vp, _i64, _vp, _i64, _u64, _u32, _vp, _vp,
                                       ctypes.POINTER(ctypes.c_double)]),
@@ -263,7 +267,18 @@ class Plan:
         _check(lib().hidft_plan_device_bytes(self.handle, ctypes.byref(b)))
         return b.value
 
+    def workspace_bytes(self, batch: int) -> int:
+        """hidft_plan_workspace_bytes: 0 up to 2^14 points, else batch * k * 8."""
+        b = ctypes.c_size_t(0)
+        _check(lib().hidft_plan_workspace_bytes(self.handle, batch, ctypes.byref(b)))
+        return b.value
+
     # -- execution on raw device pointers
+    def execute_ws_ptr(self, d_in: int, ld_in: int, d_out: int, ld_out: int, batch: int,
+                       d_work: int, work_bytes: int, stream=None) -> None:
+        _check(lib().hidft_execute_ws(self.handle, d_in, ld_in, d_out, ld_out, batch, d_work,
+                                      work_bytes, _stream_handle(stream)))
+
     def execute_ptr(self, d_in: int, ld_in: int, d_out: int, ld_out: int, batch: int,
                     stream=None, plain: bool = False,
                     config: Optional[ExecConfig] = None) -> None:
@@ -315,9 +330,17 @@ class Plan:
         y = out.unsqueeze(0) if out.dim() == 1 else out
         if y.dtype != torch.complex64 or y.dim() != 2 or y.shape != x.shape or y.stride(1) != 1:
             raise HiDFTError(1, "out must match samples' shape, complex64, unit inner stride")
-        self.execute_ptr(x.data_ptr(), x.stride(0) if x.shape[0] > 1 else self.k,
-                         y.data_ptr(), y.stride(0) if y.shape[0] > 1 else self.k,
-                         x.shape[0], stream, plain, config)
+        ld_in = x.stride(0) if x.shape[0] > 1 else self.k
+        ld_out = y.stride(0) if y.shape[0] > 1 else self.k
+        wb = self.workspace_bytes(x.shape[0])
+        if wb and not plain and config is None:
+            # k > 2^14: the passes' workspace from torch's allocator
+            work = torch.empty(wb // 8, dtype=torch.complex64, device=x.device)
+            self.execute_ws_ptr(x.data_ptr(), ld_in, y.data_ptr(), ld_out, x.shape[0],
+                                work.data_ptr(), wb, stream)
+        else:
+            self.execute_ptr(x.data_ptr(), ld_in, y.data_ptr(), ld_out, x.shape[0], stream,
+                             plain, config)
         return out
 
 

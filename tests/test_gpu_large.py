@@ -1,0 +1,198 @@
+"""GPU parity of transforms with more than 2^14 points.
+
+Above one signal per LDS the plan splits the recursion (Corollary 2): the
+top stages run per column, the rest per subtree, and a gather puts the
+coefficients in the caller's order (three kernels through a workspace).
+Checks, through the C ABI:
+  * every coefficient of seeded transforms against the coefficients the
+    samples were synthesised from (FP64 full-length inverse DFT read at I_r),
+    and seeded positions of the same rows against the FP64 oracle;
+  * a batch: every row on 64 seeded positions of its own against the oracle
+    and on the energy identity ||c||^2 = (N^2/k) ||f_I||^2 (Lemma 1);
+  * hidft_execute (stream-ordered workspace), hidft_execute_ws (caller's
+    workspace), in place, strided rows and a captured graph give the same
+    bits;
+  * the split twiddle table holds every twiddle rounded once from FP64;
+  * the calls that need one signal in LDS refuse these plans.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.positions import positions_vs_oracle
+from workloads import complex_normal, homogeneous_support, rng_for, sample_values
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+native = pytest.importorskip("paper_2211_15299_amd.native")
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _energy_rel(c, f, M, k):
+    N = float(1 << M)
+    e_c = np.sum(np.abs(c.astype(np.complex128)) ** 2, axis=-1)
+    e_f = (N * N / k) * np.sum(np.abs(f.astype(np.complex128)) ** 2, axis=-1)
+    return np.abs(e_c - e_f) / e_f
+
+
+@pytest.mark.parametrize("M,s", [(20, 15), (22, 16), (24, 17), (24, 18)])
+def test_large_recovers_every_coefficient(M, s):
+    rng = rng_for(4100, s)
+    sup = homogeneous_support(M, s, rng)
+    J = sup.J.tolist()
+    plan = native.Plan(M, J)
+    k = plan.k
+    assert k == 1 << s and plan.workspace_bytes(2) == 2 * k * 8
+    I = plan.samples().tolist()
+    c = complex_normal((2, k), rng)
+    f = oracle.synthesize_samples_fft(M, J, c, I).astype(np.complex64)
+    _say(f"large: M={M} s={s} k={k}, 2 rows")
+    x = torch.from_numpy(f).cuda()
+    got = plan.execute(x).cpu().numpy()
+    err = oracle.rel_l2(got.astype(np.complex128), c)
+    _say(f"large: every coefficient against the synthesised ones, rel-L2 {np.max(err):.3e}")
+    assert np.max(err) <= TOL, err
+    pe = positions_vs_oracle(M, J, I, f, got, 256, rng_for(4101, s))
+    _say(f"large: 256 positions per row against the oracle, rel-L2 {np.max(pe):.3e}")
+    assert np.max(pe) <= TOL, pe
+    plan.close()
+
+
+def test_large_batch_every_row():
+    M, s, batch = 18, 15, 96
+    rng = rng_for(4102, 0)
+    sup = homogeneous_support(M, s, rng)
+    J = sup.J.tolist()
+    plan = native.Plan(M, J)
+    k = plan.k
+    I = plan.samples().tolist()
+    f = sample_values(M, k, batch, rng)
+    x = torch.from_numpy(f).cuda()
+    y = plan.execute(x)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    pe = positions_vs_oracle(M, J, I, f, got, 64, rng_for(4103, 0), group=16)
+    _say(f"large batch: {batch} rows on 64 positions each, rel-L2 max {np.max(pe):.3e}")
+    assert np.max(pe) <= TOL
+    en = _energy_rel(got, f, M, k)
+    assert np.max(en) <= 2 * TOL, np.max(en)
+    # hidft_execute (stream-ordered workspace) gives the same bits
+    z = torch.full_like(x, complex(np.nan, np.nan))
+    plan.execute_ptr(x.data_ptr(), k, z.data_ptr(), k, batch)
+    torch.cuda.synchronize()
+    assert torch.equal(z, y)
+    # strided rows through the caller's workspace
+    xs = torch.zeros((batch, k + 5), dtype=torch.complex64, device="cuda")
+    xs[:, :k] = x
+    ys = torch.full((batch, k + 3), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda")
+    wb = plan.workspace_bytes(batch)
+    work = torch.empty(wb // 8, dtype=torch.complex64, device="cuda")
+    plan.execute_ws_ptr(xs.data_ptr(), k + 5, ys.data_ptr(), k + 3, batch, work.data_ptr(), wb)
+    torch.cuda.synchronize()
+    assert torch.equal(ys[:, :k], y)
+    assert torch.isnan(ys[:, k:]).all()  # nothing written past k
+    # in place
+    w = x.clone()
+    plan.execute_ws_ptr(w.data_ptr(), k, w.data_ptr(), k, batch, work.data_ptr(), wb)
+    torch.cuda.synchronize()
+    assert torch.equal(w, y)
+    plan.close()
+
+
+def test_large_in_a_graph():
+    M, s, batch = 19, 16, 8
+    rng = rng_for(4104, 0)
+    plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
+    k = plan.k
+    x = torch.from_numpy(sample_values(M, k, batch, rng)).cuda()
+    ref = plan.execute(x)
+    y = torch.empty_like(x)
+    wb = plan.workspace_bytes(batch)
+    work = torch.empty(wb // 8, dtype=torch.complex64, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, batch, work.data_ptr(), wb,
+                            stream=torch.cuda.current_stream())
+    for rep in range(3):
+        y.fill_(complex(np.nan, np.nan))
+        work.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), f"replay {rep}"
+    plan.close()
+
+
+def test_large_twiddles_are_fp64_rounded_once():
+    rng = rng_for(4105, 0)
+    for M, s in [(20, 16), (40, 18)]:
+        plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
+        fp, num, den = plan.schedule()
+        tw = plan.twiddles()
+        exact = np.exp(-1j * np.pi * (num.astype(np.float64) / np.exp2(den.astype(np.float64))))
+        for part_gpu, part_ref in ((tw.real, exact.real), (tw.imag, exact.imag)):
+            ulp = np.spacing(np.abs(part_ref).astype(np.float32)).astype(np.float64)
+            err = np.abs(part_gpu.astype(np.float64) - part_ref)
+            assert np.all(err <= ulp + 1e-15), np.max(err - ulp)
+        plan.close()
+
+
+def test_large_plans_refused_where_one_signal_must_fit():
+    M, s = 18, 15
+    rng = rng_for(4106, 0)
+    plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
+    k = plan.k
+    x = torch.zeros((2, k), dtype=torch.complex64, device="cuda")
+    y = torch.zeros_like(x)
+
+    def status(fn):
+        with pytest.raises(native.HiDFTError) as ei:
+            fn()
+        return ei.value.status_name
+
+    cfg = native.ExecConfig(native.PREC_FP32, native.SCHED_SHORT_LAST, 16, 0)
+    assert status(lambda: plan.execute_ptr(x.data_ptr(), k, y.data_ptr(), k, 2, config=cfg)) == \
+        "HIDFT_ERR_UNSUPPORTED"
+    assert status(lambda: plan.execute_ptr(x.data_ptr(), k, y.data_ptr(), k, 2, plain=True)) == \
+        "HIDFT_ERR_UNSUPPORTED"
+    assert status(lambda: plan.inverse_ptr(x.data_ptr(), k, y.data_ptr(), k, 2)) == \
+        "HIDFT_ERR_UNSUPPORTED"
+    assert status(lambda: native.Group([(plan, x.data_ptr(), k, y.data_ptr(), k, 2)])) == \
+        "HIDFT_ERR_UNSUPPORTED"
+    assert status(lambda: plan.autotune_ptr(x.data_ptr(), k, y.data_ptr(), k, 2, reps=1)) == \
+        "HIDFT_ERR_UNSUPPORTED"
+    wb = plan.workspace_bytes(2)
+    work = torch.empty(wb // 8 + 8, dtype=torch.complex64, device="cuda")
+    # too small, missing, misaligned, overlapping
+    assert status(lambda: plan.execute_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, 2,
+                                              work.data_ptr(), wb - 8)) == "HIDFT_ERR_INVALID_ARGUMENT"
+    assert status(lambda: plan.execute_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, 2, 0, wb)) == \
+        "HIDFT_ERR_INVALID_ARGUMENT"
+    assert status(lambda: plan.execute_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, 2,
+                                              work.data_ptr() + 4, wb)) == "HIDFT_ERR_INVALID_ARGUMENT"
+    assert status(lambda: plan.execute_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, 2,
+                                              y.data_ptr(), wb)) == "HIDFT_ERR_INVALID_ARGUMENT"
+    # the single-pass sizes need no workspace
+    small = native.Plan(12, homogeneous_support(12, 10, rng).J.tolist())
+    assert small.workspace_bytes(1000) == 0
+    small.close()
+    plan.close()
