@@ -30,6 +30,8 @@ Prints one JSON line.  Modes for profiling runs:
   --mode sas       Shift-and-Sample on a random half of a homogeneous set
   --mode gap       GAP and arithmetic-progression supports through
                    Shift-and-Sample
+  --mode large     transforms of 2^15..2^18 points (N = 2^24), which run in
+                   passes through a workspace
 The full run also reports the autotuned variant of the headline workload
 (hidft_autotune, then hidft_execute_config with the tuned variant).
 """
@@ -62,7 +64,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--mode", choices=["full", "execute", "copy", "grouped", "serve", "precision",
-                                       "inverse", "sas", "gap"],
+                                       "inverse", "sas", "gap", "large"],
                     default="full")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="duration of the Poisson arrival process (serving)")
@@ -153,10 +155,12 @@ def main():
         del xs, ys, x, y
         print(json.dumps(precision_bench(args, native, torch, stream)), flush=True)
         return
-    if args.mode in ("inverse", "sas", "gap"):
+    if args.mode in ("inverse", "sas", "gap", "large"):
         del xs, ys, x, y
         if args.mode == "inverse":
             r = inverse_bench(args, native, torch, stream, steps=args.steps)
+        elif args.mode == "large":
+            r = large_bench(native, torch, stream, steps=args.steps)
         elif args.mode == "sas":
             r = sas_bench(native, torch, stream, steps=args.steps)
         else:
@@ -305,6 +309,7 @@ def main():
     result["gap_supports"] = gap_bench(native, torch, stream)
     result["inverse"] = inverse_bench(args, native, torch, stream)
     result["shift_and_sample"] = sas_bench(native, torch, stream)
+    result["large"] = large_bench(native, torch, stream)
     if not args.no_cpu:
         result["cpu_baseline"]["precision_vs_oracle"] = precision_vs_oracle(native, torch, stream)
     print(json.dumps(result), flush=True)
@@ -689,6 +694,50 @@ def inverse_bench(args, native, torch, stream, steps=50):
     return {"workload": "N=2^20, k=2^12, 4096 signals", "ms_per_launch": ms,
             "transforms_per_s": batch / (ms * 1e-3), "GBps": batch * k * 16 / (ms * 1e-3) / 1e9,
             "round_trip_rel_l2_max": rt, "steps": steps, "sets": sets}
+
+
+def large_bench(native, torch, stream, steps=20):
+    """Transforms of 2^15..2^18 points at N = 2^24, 256 MB of samples and
+    coefficients per launch, 4 rotating (input, output) sets and one shared
+    workspace (hidft_execute_ws: three passes, no allocation).  GB/s counts
+    the algorithmic 16 B per point; the passes move about 48 (each reads and
+    writes the signal once, the last reads it in gather order)."""
+    from workloads import homogeneous_support, rng_for, sample_values
+    M = 24
+    out = {"workload": "N=2^24, k=2^15..2^18, 256 MB per launch", "steps": steps}
+    for s in range(15, 19):
+        rng = rng_for(24, s)
+        plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist(), stream=stream)
+        k = plan.k
+        batch = (256 << 20) // (16 * k)
+        sets = ROTATE_SETS
+        xs = [torch.from_numpy(sample_values(M, k, batch, rng)).cuda()]
+        xs += [xs[0].clone() for _ in range(sets - 1)]
+        ys = [torch.empty_like(xs[0]) for _ in range(sets)]
+        wb = plan.workspace_bytes(batch)
+        work = torch.empty(wb // 8, dtype=torch.complex64, device="cuda")
+
+        def run(i):
+            plan.execute_ws_ptr(xs[i % sets].data_ptr(), k, ys[i % sets].data_ptr(), k, batch,
+                                work.data_ptr(), wb, stream)
+
+        for i in range(3):
+            run(i)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            run(i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[f"k=2^{s}"] = {"batch": batch, "ms_per_launch": ms,
+                           "transforms_per_s": batch / (ms * 1e-3),
+                           "GBps": batch * k * 16 / (ms * 1e-3) / 1e9}
+        plan.close()
+        del xs, ys, work
+        torch.cuda.empty_cache()
+    return out
 
 
 ROTATE_SETS = 4               # input/output buffer sets cycled through by a leg

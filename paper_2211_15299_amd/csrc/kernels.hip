@@ -2089,16 +2089,29 @@ large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint
                                                     unused, no_mfma);
 }
 
+// The gather reads each row at random positions.  Blocks are dispatched to
+// the XCDs in turn (block b to XCD b mod LARGE_XCDS), each with its own L2,
+// so with groups >= LARGE_XCDS the blocks of XCD x take rows x, x + groups,
+// ... whole: a row is read into one L2 only.  With fewer rows than XCDs
+// (groups = 1) every block walks every row.
+constexpr uint32_t LARGE_XCDS = 8;
+
 __global__ void __launch_bounds__(LARGE_THREADS)
 large_gather_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
-                    uint64_t batch, uint32_t s, const uint32_t* __restrict__ pos, float scale) {
+                    uint64_t batch, uint32_t s, const uint32_t* __restrict__ pos, float scale,
+                    uint32_t groups) {
   const uint64_t k = 1ULL << s;
-  const uint64_t n = batch << s;
-  const uint64_t stride = (uint64_t)gridDim.x * LARGE_THREADS;
-  for (uint64_t i = (uint64_t)blockIdx.x * LARGE_THREADS + threadIdx.x; i < n; i += stride) {
-    const uint64_t b = i >> s, t = i & (k - 1);
-    const float2 x = work[b * k + pos[t]];
-    store_stream(out + b * (uint64_t)ld_out + t, make_float2(x.x * scale, x.y * scale));
+  const uint32_t group = blockIdx.x % groups;
+  const uint64_t in_group = blockIdx.x / groups;
+  const uint64_t per_group = gridDim.x / groups;
+  const uint64_t stride = per_group * LARGE_THREADS;
+  for (uint64_t b = group; b < batch; b += groups) {
+    const float2* w = work + b * k;
+    float2* o = out + b * (uint64_t)ld_out;
+    for (uint64_t t = in_group * LARGE_THREADS + threadIdx.x; t < k; t += stride) {
+      const float2 x = w[pos[t]];
+      store_stream(o + t, make_float2(x.x * scale, x.y * scale));
+    }
   }
 }
 
@@ -2180,8 +2193,10 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
   }
   if (e != hipSuccess) return e;
   if ((e = stream_grid(batch * k, &grid)) != hipSuccess) return e;
+  const uint32_t groups = batch >= LARGE_XCDS && grid >= LARGE_XCDS ? LARGE_XCDS : 1u;
+  grid -= grid % groups;  // whole groups
   hipLaunchKernelGGL(large_gather_kernel, dim3(grid), dim3(LARGE_THREADS), 0, stream, work, out,
-                     ld_out, batch, s, pos, scale);
+                     ld_out, batch, s, pos, scale, groups);
   return hipGetLastError();
 }
 
