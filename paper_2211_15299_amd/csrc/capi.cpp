@@ -81,6 +81,44 @@ uint64_t device_tw_index(uint32_t s, uint32_t u, uint64_t n) {
   return ((1ULL << s1) - 1) + sub * ((1ULL << s2) - 1) + ((1ULL << (u2 - 1)) - 1) + n2;
 }
 
+// Tables of the passes of a plan above 2^HIDFT_MAX_LOG2_K_DEVICE points
+// (launch_large).  With p(t) = bitrev_s(q(J[t])) the position of output t,
+// subtree j holds the outputs t with p(t) >> s2 == j; L_j lists them by
+// increasing t (exactly 2^s2 of them).
+//   src16[0, k): per subtree j, entry i = p(L_j[i]) mod 2^s2 (the subtree's
+//                gather, so its outputs come out ordered by t);
+//   src16[k, 2k) and src32[0, k): per output chunk of LARGE_CHUNK
+//                consecutive t, the chunk's values subtree by subtree: the
+//                workspace index j 2^s2 + i of L_j[i] (src32) and its place
+//                L_j[i] - chunk start (src16[k + ...]).
+void large_tables(const hidft::PlanCore& c, std::vector<uint16_t>* src16,
+                  std::vector<uint32_t>* src32) {
+  const uint64_t k = c.k;
+  const uint32_t s2 = hidft::large_split(c.s), s1 = c.s - s2;
+  const uint64_t K2 = 1ULL << s2, C = hidft::LARGE_CHUNK;
+  std::vector<std::vector<uint32_t>> L(1ULL << s1);
+  std::vector<uint32_t> p(k);
+  for (uint64_t t = 0; t < k; ++t) {
+    p[t] = static_cast<uint32_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
+    L[p[t] >> s2].push_back(static_cast<uint32_t>(t));
+  }
+  src16->assign(2 * k, 0);
+  src32->assign(k, 0);
+  for (uint64_t j = 0; j < L.size(); ++j)
+    for (uint64_t i = 0; i < K2; ++i)
+      (*src16)[j * K2 + i] = static_cast<uint16_t>(p[L[j][i]] & (K2 - 1));
+  std::vector<uint64_t> next(L.size(), 0);
+  for (uint64_t ch = 0; ch < k / C; ++ch) {
+    uint64_t e = ch * C;
+    for (uint64_t j = 0; j < L.size(); ++j) {
+      for (uint64_t& i = next[j]; i < K2 && L[j][i] < (ch + 1) * C; ++i, ++e) {
+        (*src32)[e] = static_cast<uint32_t>(j * K2 + i);
+        (*src16)[k + e] = static_cast<uint16_t>(L[j][i] - ch * C);
+      }
+    }
+  }
+}
+
 // Twiddle exponents in the device order of the twiddle table: stage u's
 // node q_lo (schedule order) is node bitrev_{u-1}(q_lo) in a-order.
 void device_exponents(const hidft::PlanCore& c, std::vector<uint64_t>* num,
@@ -109,17 +147,17 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
   std::vector<uint64_t> num;
   std::vector<uint8_t> den;
   device_exponents(c, &num, &den);
-  // Output positions (a-order) of the caller's coefficients: 16-bit for the
-  // single-pass kernels, 32-bit for the passes of larger plans.
+  // Output positions (a-order) of the caller's coefficients, for the
+  // single-pass gather; larger plans get the tables of their passes.
   const bool large = c.s > HIDFT_MAX_LOG2_K_DEVICE;
-  std::vector<uint16_t> src(large ? 0 : k);
-  std::vector<uint32_t> pos(large ? k : 0);
-  for (uint64_t t = 0; t < k; ++t) {
-    const uint64_t pt = hidft::bit_reverse(c.freq_pos[t], c.s);
-    if (large)
-      pos[t] = static_cast<uint32_t>(pt);
-    else
-      src[t] = static_cast<uint16_t>(pt);
+  std::vector<uint16_t> src;
+  std::vector<uint32_t> pos;
+  if (!large) {
+    src.resize(k);
+    for (uint64_t t = 0; t < k; ++t)
+      src[t] = static_cast<uint16_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
+  } else {
+    large_tables(c, &src, &pos);
   }
 
   const size_t ntw_alloc = ntw ? ntw : 1;
@@ -127,8 +165,8 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
   uint8_t* d_den = nullptr;
   hidft_status st = HIDFT_OK;
   if ((e = hipMalloc(&p->d_tw, ntw_alloc * sizeof(float2))) != hipSuccess ||
-      (e = large ? hipMalloc(&p->d_pos, k * sizeof(uint32_t))
-                 : hipMalloc(&p->d_src, k * sizeof(uint16_t))) != hipSuccess ||
+      (e = hipMalloc(&p->d_src, src.size() * sizeof(uint16_t))) != hipSuccess ||
+      (large && (e = hipMalloc(&p->d_pos, pos.size() * sizeof(uint32_t))) != hipSuccess) ||
       (e = hipMalloc(&d_num, ntw_alloc * sizeof(uint64_t))) != hipSuccess ||
       (e = hipMalloc(&d_den, ntw_alloc)) != hipSuccess) {
     st = hip_fail(e, "hipMalloc of plan tables");
@@ -136,10 +174,10 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
                                  hipMemcpyHostToDevice, stream)) != hipSuccess ||
              (e = hipMemcpyAsync(d_den, den.data(), ntw_alloc, hipMemcpyHostToDevice,
                                  stream)) != hipSuccess ||
-             (e = large ? hipMemcpyAsync(p->d_pos, pos.data(), k * sizeof(uint32_t),
-                                         hipMemcpyHostToDevice, stream)
-                        : hipMemcpyAsync(p->d_src, src.data(), k * sizeof(uint16_t),
-                                         hipMemcpyHostToDevice, stream)) != hipSuccess) {
+             (e = hipMemcpyAsync(p->d_src, src.data(), src.size() * sizeof(uint16_t),
+                                 hipMemcpyHostToDevice, stream)) != hipSuccess ||
+             (large && (e = hipMemcpyAsync(p->d_pos, pos.data(), pos.size() * sizeof(uint32_t),
+                                           hipMemcpyHostToDevice, stream)) != hipSuccess)) {
     st = hip_fail(e, "hipMemcpyAsync of plan tables");
   } else if ((e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, stream)) !=
              hipSuccess) {
@@ -196,7 +234,8 @@ hidft_status check_exec(hidft_plan plan, const void* d_in, int64_t ld_in, const 
 namespace hidft {
 
 size_t plan_table_bytes(uint64_t k) {
-  const size_t pos_bytes = k > (1ULL << HIDFT_MAX_LOG2_K_DEVICE) ? 4 : 2;
+  // gather positions: 2 bytes per point; the passes of larger plans: 8
+  const size_t pos_bytes = k > (1ULL << HIDFT_MAX_LOG2_K_DEVICE) ? 8 : 2;
   return (k > 1 ? k - 1 : 1) * sizeof(float2) + k * pos_bytes;
 }
 
@@ -612,8 +651,9 @@ hidft_status hidft_execute_ws(hidft_plan plan, const void* d_samples, int64_t ld
                 fn);
   hipError_t e = hidft::launch_large(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
                                      static_cast<float2*>(d_coefs), ld_out, batch,
-                                     static_cast<float2*>(d_work), plan->d_tw, plan->d_pos,
-                                     plan->scale, static_cast<hipStream_t>(stream));
+                                     static_cast<float2*>(d_work), plan->d_tw, plan->d_src,
+                                     plan->d_pos, plan->d_src + k, plan->scale,
+                                     static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hidft_execute_ws: kernel launch");
   return ok();
 }
@@ -633,7 +673,8 @@ hidft_status hidft_execute(hidft_plan plan, const void* d_samples, int64_t ld_in
     if (e != hipSuccess) return hip_fail(e, "hidft_execute: workspace allocation");
     e = hidft::launch_large(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
                             static_cast<float2*>(d_coefs), ld_out, batch,
-                            static_cast<float2*>(work), plan->d_tw, plan->d_pos, plan->scale, hs);
+                            static_cast<float2*>(work), plan->d_tw, plan->d_src, plan->d_pos,
+                            plan->d_src + plan->core.k, plan->scale, hs);
     const hipError_t ef = hipFreeAsync(work, hs);
     if (e != hipSuccess) return hip_fail(e, "hidft_execute: kernel launch");
     if (ef != hipSuccess) return hip_fail(ef, "hidft_execute: workspace release");

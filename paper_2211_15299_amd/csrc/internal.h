@@ -18,8 +18,8 @@ struct hidft_plan_s {
   bool host_only = true;
   int device = -1;
   float2* d_tw = nullptr;      // k-1 twiddles in a-order (at least one slot)
-  uint16_t* d_src = nullptr;   // k output gather positions (k <= 2^14)
-  uint32_t* d_pos = nullptr;   // the same, 32-bit, for k > 2^14 (passes through a workspace)
+  uint16_t* d_src = nullptr;   // k output gather positions (k <= 2^14); 2k for larger plans
+  uint32_t* d_pos = nullptr;   // k > 2^14: the placement pass's workspace indices
   // Split operands of the group-1 matrix (k >= 16), built on the first
   // matrix-core execution (hidft::plan_amat) and kept until destroy.
   std::atomic<void*> d_amat{nullptr};
@@ -31,7 +31,8 @@ struct hidft_plan_s {
 namespace hidft {
 
 // Device bytes of a plan's tables at creation: k - 1 twiddles (at least one)
-// and k gather positions (2 bytes each up to 2^14, else 4).  (The
+// and k gather positions (2 bytes each up to 2^14; larger plans: 8 bytes
+// per point of pass tables).  (The
 // matrix-core operands come later, on demand.)
 size_t plan_table_bytes(uint64_t k);
 

@@ -2015,12 +2015,17 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
 //    whose stage-u' twiddles are the run of stage s1+u' starting at
 //    subtree * 2^(u'-1).  The plan keeps these runs in the fused kernel's
 //    table layout, one table per subtree, and the fused kernel's per-signal
-//    code runs each subtree in place, leaving its values in position order.
-//  * pass 3: the coefficients are gathered from position order into the
-//    caller's order of J (32-bit positions) and scaled by N/k.
+//    code runs each subtree in place.  Its gather writes the subtree's
+//    outputs ordered by their index t in the caller's order of J.
+//  * pass 3: output chunk c (LARGE_CHUNK consecutive t) takes from each
+//    subtree the contiguous run of its outputs whose t fall in the chunk,
+//    puts each value at its place in LDS, scales by N/k and stores the chunk
+//    in order.  Every read and write of the pass is a contiguous run; only
+//    the LDS writes are scattered.
 // Every stage's arithmetic is the single-pass kernel's, in the same order.
 // ---------------------------------------------------------------------------
 constexpr int LARGE_THREADS = 256;
+static_assert(LARGE_CHUNK <= 65536 && (LARGE_CHUNK << 3) <= (1u << 15), "chunk in LDS, 16-bit places");
 
 template <int S1>
 __global__ void __launch_bounds__(LARGE_THREADS)
@@ -2055,20 +2060,21 @@ large_top_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restric
   }
 }
 
-// A subtree's transform: its own twiddle table, outputs in position order
-// (identity gather), stored over its inputs.
+// A subtree's transform: its own twiddle and gather tables, outputs stored
+// over its inputs.
 struct SubtreeMem {
   const float2* tw;
+  const uint16_t* src;
   float2* out;
   __device__ __forceinline__ float2 tw_at(int uni, int lane) const { return tw[uni + lane]; }
-  __device__ __forceinline__ int src_at(int uni, int lane) const { return uni + lane; }
+  __device__ __forceinline__ int src_at(int uni, int lane) const { return src[uni + lane]; }
   __device__ __forceinline__ void put(int uni, int lane, float2 x) const { out[uni + lane] = x; }
 };
 
 template <int S2, int SCHED>
 __global__ void __launch_bounds__((FusedShape<S2, SCHED, 4>::THREADS))
 large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint32_t s1,
-                 const float2* __restrict__ tw2) {
+                 const float2* __restrict__ tw2, const uint16_t* __restrict__ src2) {
   using Sh = FusedShape<S2, SCHED, 4>;
   static_assert(Sh::SPB == 1 && Sh::THREADS == Sh::T, "one subtree per block");
   constexpr int R = Sh::R, T = Sh::T;
@@ -2082,36 +2088,33 @@ large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint
   __builtin_amdgcn_s_setprio(2);
   load_row<R, T, false>(v, row, (uint32_t)K2);
   __builtin_amdgcn_s_setprio(0);
-  const SubtreeMem mem{tw2 + sub * (K2 - 1), row};
+  const SubtreeMem mem{tw2 + sub * (K2 - 1), src2 + sub * K2, row};
   ThreadState<S2, SCHED, 4> unused;
   const MfmaOps<PREC_FP32> no_mfma;
   transform_signal<S2, SCHED, 4, PREC_FP32, false>(v, lds, 0, (int)threadIdx.x, true, mem, 1.0f,
                                                     unused, no_mfma);
 }
 
-// The gather reads each row at random positions.  Blocks are dispatched to
-// the XCDs in turn (block b to XCD b mod LARGE_XCDS), each with its own L2,
-// so with groups >= LARGE_XCDS the blocks of XCD x take rows x, x + groups,
-// ... whole: a row is read into one L2 only.  With fewer rows than XCDs
-// (groups = 1) every block walks every row.
-constexpr uint32_t LARGE_XCDS = 8;
-
 __global__ void __launch_bounds__(LARGE_THREADS)
-large_gather_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
-                    uint64_t batch, uint32_t s, const uint32_t* __restrict__ pos, float scale,
-                    uint32_t groups) {
+large_place_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
+                   uint64_t batch, uint32_t s, const uint32_t* __restrict__ src3,
+                   const uint16_t* __restrict__ dest3, float scale) {
+  __shared__ float2 chunk[LARGE_CHUNK];
   const uint64_t k = 1ULL << s;
-  const uint32_t group = blockIdx.x % groups;
-  const uint64_t in_group = blockIdx.x / groups;
-  const uint64_t per_group = gridDim.x / groups;
-  const uint64_t stride = per_group * LARGE_THREADS;
-  for (uint64_t b = group; b < batch; b += groups) {
+  const uint64_t chunks = k / LARGE_CHUNK;
+  for (uint64_t unit = blockIdx.x; unit < batch * chunks; unit += gridDim.x) {
+    const uint64_t b = unit / chunks, c = unit - b * chunks;
     const float2* w = work + b * k;
-    float2* o = out + b * (uint64_t)ld_out;
-    for (uint64_t t = in_group * LARGE_THREADS + threadIdx.x; t < k; t += stride) {
-      const float2 x = w[pos[t]];
-      store_stream(o + t, make_float2(x.x * scale, x.y * scale));
+    const uint32_t* s3 = src3 + c * LARGE_CHUNK;
+    const uint16_t* d3 = dest3 + c * LARGE_CHUNK;
+    for (uint32_t e = threadIdx.x; e < LARGE_CHUNK; e += LARGE_THREADS) {
+      const float2 x = w[s3[e]];
+      chunk[d3[e]] = make_float2(x.x * scale, x.y * scale);
     }
+    __syncthreads();
+    float2* o = out + b * (uint64_t)ld_out + c * LARGE_CHUNK;
+    for (uint32_t e = threadIdx.x; e < LARGE_CHUNK; e += LARGE_THREADS) store_stream(o + e, chunk[e]);
+    __syncthreads();  // the next unit overwrites the chunk
   }
 }
 
@@ -2139,7 +2142,7 @@ static hipError_t stream_grid(uint64_t threads, unsigned* grid) {
 
 template <int S2, int SCHED>
 static hipError_t launch_large_sub(float2* work, uint64_t units, uint32_t s1, const float2* tw2,
-                                   hipStream_t stream) {
+                                   const uint16_t* src2, hipStream_t stream) {
   using Sh = FusedShape<S2, SCHED, 4>;
   static OccupancyCache cache;
   Occupancy occ;
@@ -2153,7 +2156,7 @@ static hipError_t launch_large_sub(float2* work, uint64_t units, uint32_t s1, co
   for (uint64_t first = 0; first < units; first += chunk) {
     const uint64_t n = units - first < chunk ? units - first : chunk;
     hipLaunchKernelGGL((large_sub_kernel<S2, SCHED>), dim3((unsigned)n), dim3(Sh::THREADS),
-                       Sh::LDS_BYTES, stream, work, first, units, s1, tw2);
+                       Sh::LDS_BYTES, stream, work, first, units, s1, tw2, src2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -2162,7 +2165,8 @@ static hipError_t launch_large_sub(float2* work, uint64_t units, uint32_t s1, co
 
 hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out,
                         int64_t ld_out, uint64_t batch, float2* work, const float2* tw,
-                        const uint32_t* pos, float scale, hipStream_t stream) {
+                        const uint16_t* src2, const uint32_t* src3, const uint16_t* dest3,
+                        float scale, hipStream_t stream) {
   if (batch == 0) return hipSuccess;
   if (s <= HIDFT_MAX_LOG2_K_DEVICE || s > HIDFT_MAX_LOG2_K_LARGE) return hipErrorInvalidValue;
   const uint32_t s2 = large_split(s), s1 = s - s2;
@@ -2186,17 +2190,15 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
   const float2* tw2 = tw + ((1u << s1) - 1);
   const uint64_t units = batch << s1;
   switch (s2) {
-    case 12: e = launch_large_sub<12, SCHED_SHORT_LAST>(work, units, s1, tw2, stream); break;
-    case 13: e = launch_large_sub<13, SCHED_SHORT_LAST>(work, units, s1, tw2, stream); break;
-    case 14: e = launch_large_sub<14, SCHED_SHORT_LAST>(work, units, s1, tw2, stream); break;
+    case 12: e = launch_large_sub<12, SCHED_SHORT_LAST>(work, units, s1, tw2, src2, stream); break;
+    case 13: e = launch_large_sub<13, SCHED_SHORT_LAST>(work, units, s1, tw2, src2, stream); break;
+    case 14: e = launch_large_sub<14, SCHED_SHORT_LAST>(work, units, s1, tw2, src2, stream); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
   if ((e = stream_grid(batch * k, &grid)) != hipSuccess) return e;
-  const uint32_t groups = batch >= LARGE_XCDS && grid >= LARGE_XCDS ? LARGE_XCDS : 1u;
-  grid -= grid % groups;  // whole groups
-  hipLaunchKernelGGL(large_gather_kernel, dim3(grid), dim3(LARGE_THREADS), 0, stream, work, out,
-                     ld_out, batch, s, pos, scale, groups);
+  hipLaunchKernelGGL(large_place_kernel, dim3(grid), dim3(LARGE_THREADS), 0, stream, work, out,
+                     ld_out, batch, s, src3, dest3, scale);
   return hipGetLastError();
 }
 
