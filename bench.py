@@ -30,7 +30,7 @@ Prints one JSON line.  Modes for profiling runs:
   --mode sas       Shift-and-Sample on a random half of a homogeneous set
   --mode gap       GAP and arithmetic-progression supports through
                    Shift-and-Sample
-  --mode large     transforms of 2^15..2^18 points (N = 2^24), which run in
+  --mode large     transforms of 2^15..2^22 points (N = 2^24), which run in
                    passes through a workspace
 The full run also reports the autotuned variant of the headline workload
 (hidft_autotune, then hidft_execute_config with the tuned variant).
@@ -697,15 +697,15 @@ def inverse_bench(args, native, torch, stream, steps=50):
 
 
 def large_bench(native, torch, stream, steps=20):
-    """Transforms of 2^15..2^18 points at N = 2^24, 256 MB of samples and
+    """Transforms of 2^15..2^22 points at N = 2^24, 256 MB of samples and
     coefficients per launch, 4 rotating (input, output) sets and one shared
     workspace (hidft_execute_ws: three passes, no allocation).  GB/s counts
     the algorithmic 16 B per point; the passes move about 48 (each reads and
     writes the signal once, the last reads it in gather order)."""
     from workloads import homogeneous_support, rng_for, sample_values
     M = 24
-    out = {"workload": "N=2^24, k=2^15..2^18, 256 MB per launch", "steps": steps}
-    for s in range(15, 19):
+    out = {"workload": "N=2^24, k=2^15..2^22, 256 MB per launch", "steps": steps}
+    for s in range(15, 23):
         rng = rng_for(24, s)
         plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist(), stream=stream)
         k = plan.k

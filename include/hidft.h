@@ -66,7 +66,7 @@ typedef struct hidft_plan_s* hidft_plan;
 #define HIDFT_MAX_LOG2_N 63u        /* N = 2^M with M <= 63 */
 #define HIDFT_MAX_LOG2_K_HOST 26u   /* planner (HOST_ONLY plans): k <= 2^26 */
 #define HIDFT_MAX_LOG2_K_DEVICE 14u /* executor: one signal is staged whole in LDS */
-#define HIDFT_MAX_LOG2_K_LARGE 18u  /* hidft_execute / _ws: larger k in passes through a workspace */
+#define HIDFT_MAX_LOG2_K_LARGE 22u  /* hidft_execute / _ws: larger k in passes through a workspace */
 
 /* Plan flags. */
 #define HIDFT_PLAN_HOST_ONLY 0x1u   /* derive the schedule on the host only: no
@@ -173,10 +173,10 @@ hidft_status hidft_plan_device_bytes(hidft_plan plan, size_t* bytes);
  * k > 2^HIDFT_MAX_LOG2_K_DEVICE (up to 2^HIDFT_MAX_LOG2_K_LARGE): the stages
  * run in three passes through a workspace of hidft_plan_workspace_bytes
  * (Corollary 2: the recursion splits at any level): the top s1 = s - s2
- * stages (s1 <= 4) on the 2^s2 columns of each signal, the other s2 stages
- * (12 <= s2 <= 14) on each of the 2^s1 subtrees with the fused kernel's
- * per-signal code, then a gather into the caller's order of J, scaled by
- * N/k.  The stage arithmetic and order are those of one pass.  Here
+ * stages (s1 <= 8) on the 2^s2 columns of each signal, the other s2 stages
+ * (s2 = 12 up to k = 2^20, else s - 8) on each of the 2^s1 subtrees with the
+ * fused kernel's per-signal code, then a placement into the caller's order
+ * of J, scaled by N/k.  The stage arithmetic and order are those of one pass.  Here
  * hidft_execute takes the workspace from the stream-ordered allocator
  * (hipMallocAsync / hipFreeAsync on `stream`); hidft_execute_ws takes it
  * from the caller instead and allocates nothing.

@@ -2004,12 +2004,14 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
 // Transforms of more than 2^14 points, in passes through a workspace.
 //
 // The recursion splits at any level (Corollary 2).  With s = s1 + s2
-// (s1 <= 4, 12 <= s2 <= 14):
+// (s1 <= 8, 12 <= s2 <= 14):
 //  * pass 1: stages 1..s1 pair only the top s1 bits of the position a, and
 //    their twiddles depend on those bits alone, so for every value of the
 //    low s2 bits (a column) the 2^s1 values of the column form a transform
-//    with the same s1-stage twiddles.  A thread takes one column, in
-//    registers.
+//    with the same s1-stage twiddles.  Up to s1 = 4 a thread takes one
+//    column, in registers; above, a block takes a tile of columns through
+//    two groups (stages 1..4 on the top four bits, stages 5..s1 on the rest)
+//    with an exchange in LDS.
 //  * pass 2: stages s1+1..s never mix values whose top s1 bits differ, so
 //    each subtree (2^s2 consecutive positions) is a transform of 2^s2 points
 //    whose stage-u' twiddles are the run of stage s1+u' starting at
@@ -2057,6 +2059,78 @@ large_top_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restric
     float2* y = work + b * k + col;
 #pragma unroll
     for (int h = 0; h < R1; ++h) y[(uint64_t)h * cols] = v[h];
+  }
+}
+
+// Columns for s1 = 5..8: a block takes COLS consecutive columns of one
+// signal.  Group A: thread (g, col) holds the 16 values h = c RB + g (c <
+// 16) of column col and runs stages 1..4 (the top four bits of h, uniform
+// twiddles).  Group B, after an exchange in LDS: unit (c, col) holds the RB
+// values h = c RB + g (g < RB) and runs stages 5..s1, whose twiddles depend
+// on the bits of h above the stage's bit (the table's first 2^s1 - 1 entries,
+// copied to LDS).
+template <int S1>
+__global__ void __launch_bounds__(LARGE_THREADS)
+large_top2_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ work,
+                  uint64_t batch, uint32_t s2, const float2* __restrict__ tw) {
+  static_assert(S1 >= 5 && S1 <= 8, "two groups of at most four stages");
+  constexpr int RB = 1 << (S1 - 4);
+  constexpr int COLS = LARGE_THREADS / RB;
+  constexpr int H = 1 << S1;
+  constexpr int PAD_H = H + 1;  // odd column stride in LDS
+  __shared__ float2 L[COLS * PAD_H];
+  __shared__ float2 T[H - 1];
+  for (int i = threadIdx.x; i < H - 1; i += LARGE_THREADS) T[i] = tw[i];
+  float2 w1[15];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) w1[i] = make_uniform(tw[i]);
+  __syncthreads();
+  const uint64_t cols = 1ULL << s2;
+  const uint64_t k = cols << S1;
+  const uint64_t tiles_per_signal = cols / COLS;
+  const uint64_t tiles = batch * tiles_per_signal;
+  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const uint64_t b = tile / tiles_per_signal;
+    const uint64_t col0 = (tile - b * tiles_per_signal) * COLS;
+    {
+      const int col = threadIdx.x % COLS, g = threadIdx.x / COLS;
+      const float2* x = in + b * (uint64_t)ld_in + col0 + col;
+      float2 v[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] = load_stream(x + (uint64_t)(c * RB + g) * cols);
+#pragma unroll
+      for (int u = 1; u <= 4; ++u) {
+        const int bit = 4 - u;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c & (1 << bit)) continue;
+          butterfly(v[c], v[c | (1 << bit)], w1[(1 << (u - 1)) - 1 + (c >> (bit + 1))]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) L[col * PAD_H + c * RB + g] = v[c];
+    }
+    __syncthreads();
+    for (int unit = threadIdx.x; unit < COLS * 16; unit += LARGE_THREADS) {
+      const int col = unit % COLS, c = unit / COLS;
+      float2 v[RB];
+#pragma unroll
+      for (int g = 0; g < RB; ++g) v[g] = L[col * PAD_H + c * RB + g];
+#pragma unroll
+      for (int u = 5; u <= S1; ++u) {
+        const int bit = S1 - u;
+#pragma unroll
+        for (int g = 0; g < RB; ++g) {
+          if (g & (1 << bit)) continue;
+          const int h = c * RB + g;
+          butterfly(v[g], v[g | (1 << bit)], T[(1 << (u - 1)) - 1 + (h >> (bit + 1))]);
+        }
+      }
+      float2* y = work + b * k + col0 + col;
+#pragma unroll
+      for (int g = 0; g < RB; ++g) y[(uint64_t)(c * RB + g) * cols] = v[g];
+    }
+    __syncthreads();  // the next tile overwrites L
   }
 }
 
@@ -2118,7 +2192,7 @@ large_place_kernel(const float2* __restrict__ work, float2* __restrict__ out, in
   }
 }
 
-uint32_t large_split(uint32_t s) { return s > 16 ? s - 4 : 12; }
+uint32_t large_split(uint32_t s) { return s > 20 ? s - 8 : 12; }
 
 static hipError_t stream_grid(uint64_t threads, unsigned* grid) {
   static OccupancyCache cache;
@@ -2175,14 +2249,26 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
   unsigned grid = 0;
   hipError_t e = stream_grid(batch << s2, &grid);
   if (e != hipSuccess) return e;
+  // the two-group column kernel: one block per tile of 2^(12 - s1) columns
+  unsigned grid2 = 0;
+  if (s1 > 4 && (e = stream_grid(((batch << s2) >> (12 - s1)) * LARGE_THREADS, &grid2)) !=
+                    hipSuccess)
+    return e;
   switch (s1) {
 #define HIDFT_TOP(S1)                                                                       \
   case S1:                                                                                  \
     hipLaunchKernelGGL(large_top_kernel<S1>, dim3(grid), dim3(LARGE_THREADS), 0, stream, in, \
                        ld_in, work, batch, s2, tw);                                         \
     break;
+#define HIDFT_TOP2(S1)                                                                    \
+  case S1:                                                                                \
+    hipLaunchKernelGGL(large_top2_kernel<S1>, dim3(grid2), dim3(LARGE_THREADS), 0, stream, \
+                       in, ld_in, work, batch, s2, tw);                                   \
+    break;
     HIDFT_TOP(1) HIDFT_TOP(2) HIDFT_TOP(3) HIDFT_TOP(4)
+    HIDFT_TOP2(5) HIDFT_TOP2(6) HIDFT_TOP2(7) HIDFT_TOP2(8)
 #undef HIDFT_TOP
+#undef HIDFT_TOP2
     default:
       return hipErrorInvalidValue;
   }

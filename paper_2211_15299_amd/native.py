@@ -29,7 +29,7 @@ HIDFT_SAS_TWO_PASS = 0x2
 HIDFT_SAS_WEIGHTS_ONLY = 0x4
 SAS_MAX_REL_ERR = 1e-5
 MAX_LOG2_K_DEVICE = 14
-MAX_LOG2_K_LARGE = 18
+MAX_LOG2_K_LARGE = 22
 
 # Execution variants (hidft_exec_config)
 PREC_FP32, PREC_F16X2, PREC_BF16X3 = 0, 1, 2

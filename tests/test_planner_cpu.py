@@ -182,7 +182,7 @@ def test_special_families_and_composites():
     (10, [5, 6, 5, 7], "HIDFT_ERR_DUPLICATE_INDEX"),
     (64, [0], "HIDFT_ERR_INVALID_ARGUMENT"),
     (2, [0, 1, 2, 3, 4], "HIDFT_ERR_INVALID_ARGUMENT"),         # k > N
-    (30, list(range(1 << 19)), "HIDFT_ERR_UNSUPPORTED"),         # device plan above 2^18
+    (30, np.arange(1 << 23, dtype=np.uint64), "HIDFT_ERR_UNSUPPORTED"),  # device plan above 2^22
 ])
 def test_plan_create_rejects(M, J, status):
     with pytest.raises(native.HiDFTError) as ei:
