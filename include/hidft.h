@@ -582,11 +582,12 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  *
  * hidft_sas_create: pivots == NULL chooses r: the first t pivots of J (J is
  * part-homogeneous at any such prefix) minimising Lemma 4's cost
- * 1.5 t 2^t mu* + 6 sum_v mu(v)^2 under 2^t <= 2^14, mu* <= 32 and an error
- * bound <= HIDFT_SAS_MAX_REL_ERR (UNSUPPORTED, naming the best bound, if no
- * prefix qualifies; r = every pivot gives mu* = 1 and qualifies whenever
- * J has at most 14 pivots).  Else r is validated (ascending in [0, M);
- * part-homogeneity: NOT_HOMOGENEOUS; 2^s <= 2^14: UNSUPPORTED) and, unless
+ * 1.5 t 2^t mu* + 6 sum_v mu(v)^2 under 2^t <= 2^14 (2^22 when mu* = 1),
+ * mu* <= 32 and an error bound <= HIDFT_SAS_MAX_REL_ERR (UNSUPPORTED, naming
+ * the best bound, if no prefix qualifies; r = every pivot gives mu* = 1 and
+ * qualifies whenever J has at most 22 pivots).  Else r is validated
+ * (ascending in [0, M); part-homogeneity: NOT_HOMOGENEOUS; 2^s <= 2^14, or
+ * 2^s <= 2^22 with mu* = 1: UNSUPPORTED) and, unless
  * HIDFT_SAS_WEIGHTS_ONLY is set, refused with UNSUPPORTED when mu* > 32 or the
  * error bound exceeds HIDFT_SAS_MAX_REL_ERR (the message names the condition
  * number and the bound).  A HIDFT_SAS_WEIGHTS_ONLY plan serves
@@ -606,7 +607,9 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  * hidft_sas_workspace_bytes(batch) bytes (mu* n_nodes complex64 values per
  * signal), 8-byte aligned, owned by the caller (no allocation happens in the
  * call); when that size is 0 d_work may be NULL.  It is 0 when mu* = 1 (the
- * Hi-DFT output is the answer) and when the plan runs as one kernel: for
+ * Hi-DFT output is the answer) with 2^s <= 2^14 -- above, the Hi-DFT runs in
+ * the passes of hidft_execute_ws and needs 2^s complex64 values per signal --
+ * and when the plan runs as one kernel: for
  * 2^s <= 2^13, mu* = 2..4 and node values that fit in LDS beside the
  * transform, the shifted Hi-DFTs gather their node values into LDS and the
  * leaf solves read them there (bit-identical results, no workspace
@@ -621,9 +624,10 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
  * Supports with additive structure (Sec. IX-B, Lemma 5): passing every pivot
  * of J (from hidft_analyze) as r gives mu* = 1 -- each node at level
  * r_max + 1 holds one element -- so the call is the Hi-DFT on all pivots,
- * 2^n samples for n pivots, with trivial leaf solves.  For a proper GAP of
- * dimension d, 2^n <= n^d 2^d k (the bound in the proof of Lemma 5).
- * hidft_sas_weights: d_samples rows of 2^s samples on I_r (ascending) ->
+ * 2^n samples for n pivots (up to n = 22), with trivial leaf solves.  For a
+ * proper GAP of dimension d, 2^n <= n^d 2^d k (the bound in the proof of
+ * Lemma 5).
+ * hidft_sas_weights (2^s <= 2^14): d_samples rows of 2^s samples on I_r (ascending) ->
  * 2^s induced weights mu_J(v, Ff) in slot order (0 at slots with no node, up
  * to rounding); with r truncated to its first s-n pivots this is the Hi-DFT
  * at height n.
@@ -667,7 +671,8 @@ hidft_status hidft_sas_weights(hidft_sas plan, const void* d_samples, int64_t ld
  * outputs go to the library's own device scratch of HIDFT_SAS_SCRATCH_BYTES
  * (one static array per GPU, held until the process ends), and the batch runs
  * in chunks of as many signals as fit it (mu* n_nodes complex64 values per
- * signal, at most 32 * 2^14 * 8 B = 4 MiB), in stream order on `stream`.  The
+ * signal, at most 32 * 2^14 * 8 B = 4 MiB; 2^s values above 2^14 samples,
+ * so up to 2^21), in stream order on `stream`.  The
  * call allocates nothing: no hipMalloc, no hipFree, no allocating library
  * routine.  The scratch is written in full before it is read, so it needs no
  * clearing.  Every call on a GPU shares that GPU's scratch: calls that

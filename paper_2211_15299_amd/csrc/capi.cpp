@@ -67,58 +67,6 @@ void release_device(hidft_plan p) {
   p->d_src = nullptr;
 }
 
-// Entry of the device twiddle table that holds stage u's twiddle for the
-// node named by the top u - 1 bits n of the position (a-order).  Up to
-// 2^HIDFT_MAX_LOG2_K_DEVICE points: (2^{u-1} - 1) + n.  Above, the split
-// layout of the passes (launch_large): stages 1..s1 as before, then for each
-// subtree (the top s1 bits of n) the table of its 2^s2-point transform.
-uint64_t device_tw_index(uint32_t s, uint32_t u, uint64_t n) {
-  if (s <= HIDFT_MAX_LOG2_K_DEVICE) return ((1ULL << (u - 1)) - 1) + n;
-  const uint32_t s2 = hidft::large_split(s), s1 = s - s2;
-  if (u <= s1) return ((1ULL << (u - 1)) - 1) + n;
-  const uint32_t u2 = u - s1;
-  const uint64_t sub = n >> (u2 - 1), n2 = n & ((1ULL << (u2 - 1)) - 1);
-  return ((1ULL << s1) - 1) + sub * ((1ULL << s2) - 1) + ((1ULL << (u2 - 1)) - 1) + n2;
-}
-
-// Tables of the passes of a plan above 2^HIDFT_MAX_LOG2_K_DEVICE points
-// (launch_large).  With p(t) = bitrev_s(q(J[t])) the position of output t,
-// subtree j holds the outputs t with p(t) >> s2 == j; L_j lists them by
-// increasing t (exactly 2^s2 of them).
-//   src16[0, k): per subtree j, entry i = p(L_j[i]) mod 2^s2 (the subtree's
-//                gather, so its outputs come out ordered by t);
-//   src16[k, 2k) and src32[0, k): per output chunk of LARGE_CHUNK
-//                consecutive t, the chunk's values subtree by subtree: the
-//                workspace index j 2^s2 + i of L_j[i] (src32) and its place
-//                L_j[i] - chunk start (src16[k + ...]).
-void large_tables(const hidft::PlanCore& c, std::vector<uint16_t>* src16,
-                  std::vector<uint32_t>* src32) {
-  const uint64_t k = c.k;
-  const uint32_t s2 = hidft::large_split(c.s), s1 = c.s - s2;
-  const uint64_t K2 = 1ULL << s2, C = hidft::LARGE_CHUNK;
-  std::vector<std::vector<uint32_t>> L(1ULL << s1);
-  std::vector<uint32_t> p(k);
-  for (uint64_t t = 0; t < k; ++t) {
-    p[t] = static_cast<uint32_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
-    L[p[t] >> s2].push_back(static_cast<uint32_t>(t));
-  }
-  src16->assign(2 * k, 0);
-  src32->assign(k, 0);
-  for (uint64_t j = 0; j < L.size(); ++j)
-    for (uint64_t i = 0; i < K2; ++i)
-      (*src16)[j * K2 + i] = static_cast<uint16_t>(p[L[j][i]] & (K2 - 1));
-  std::vector<uint64_t> next(L.size(), 0);
-  for (uint64_t ch = 0; ch < k / C; ++ch) {
-    uint64_t e = ch * C;
-    for (uint64_t j = 0; j < L.size(); ++j) {
-      for (uint64_t& i = next[j]; i < K2 && L[j][i] < (ch + 1) * C; ++i, ++e) {
-        (*src32)[e] = static_cast<uint32_t>(j * K2 + i);
-        (*src16)[k + e] = static_cast<uint16_t>(L[j][i] - ch * C);
-      }
-    }
-  }
-}
-
 // Twiddle exponents in the device order of the twiddle table: stage u's
 // node q_lo (schedule order) is node bitrev_{u-1}(q_lo) in a-order.
 void device_exponents(const hidft::PlanCore& c, std::vector<uint64_t>* num,
@@ -129,7 +77,7 @@ void device_exponents(const hidft::PlanCore& c, std::vector<uint64_t>* num,
   for (uint32_t u = 1; u <= c.s; ++u) {
     const uint64_t off = (1ULL << (u - 1)) - 1;
     for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
-      const uint64_t at = device_tw_index(c.s, u, hidft::bit_reverse(q_lo, u - 1));
+      const uint64_t at = hidft::device_tw_index(c.s, u, hidft::bit_reverse(q_lo, u - 1));
       (*num)[at] = c.tw_num[off + q_lo];
       (*den)[at] = c.tw_log2den[off + q_lo];
     }
@@ -157,7 +105,10 @@ hidft_status upload(hidft_plan p, hipStream_t stream) {
     for (uint64_t t = 0; t < k; ++t)
       src[t] = static_cast<uint16_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
   } else {
-    large_tables(c, &src, &pos);
+    std::vector<uint32_t> p(k);
+    for (uint64_t t = 0; t < k; ++t)
+      p[t] = static_cast<uint32_t>(hidft::bit_reverse(c.freq_pos[t], c.s));
+    hidft::large_tables(c.s, p, &src, &pos);
   }
 
   const size_t ntw_alloc = ntw ? ntw : 1;
@@ -232,6 +183,45 @@ hidft_status check_exec(hidft_plan plan, const void* d_in, int64_t ld_in, const 
 }  // namespace
 
 namespace hidft {
+
+// Entry of the device twiddle table that holds stage u's twiddle for the
+// node named by the top u - 1 bits n of the position (a-order).  Up to
+// 2^HIDFT_MAX_LOG2_K_DEVICE points: (2^{u-1} - 1) + n.  Above, the split
+// layout of the passes (launch_large): stages 1..s1 as before, then for each
+// subtree (the top s1 bits of n) the table of its 2^s2-point transform.
+uint64_t device_tw_index(uint32_t s, uint32_t u, uint64_t n) {
+  if (s <= HIDFT_MAX_LOG2_K_DEVICE) return ((1ULL << (u - 1)) - 1) + n;
+  const uint32_t s2 = hidft::large_split(s), s1 = s - s2;
+  if (u <= s1) return ((1ULL << (u - 1)) - 1) + n;
+  const uint32_t u2 = u - s1;
+  const uint64_t sub = n >> (u2 - 1), n2 = n & ((1ULL << (u2 - 1)) - 1);
+  return ((1ULL << s1) - 1) + sub * ((1ULL << s2) - 1) + ((1ULL << (u2 - 1)) - 1) + n2;
+}
+
+void large_tables(uint32_t s, const std::vector<uint32_t>& pos, std::vector<uint16_t>* src16,
+                  std::vector<uint32_t>* src32) {
+  const uint64_t k = 1ULL << s, n_out = pos.size();
+  const uint32_t s2 = large_split(s), s1 = s - s2;
+  const uint64_t K2 = 1ULL << s2, C = LARGE_CHUNK;
+  const uint64_t chunks = (n_out + C - 1) / C;
+  std::vector<std::vector<uint32_t>> L(1ULL << s1);
+  for (uint64_t t = 0; t < n_out; ++t) L[pos[t] >> s2].push_back(static_cast<uint32_t>(t));
+  src16->assign(k + chunks * C, 0);
+  src32->assign(chunks * C, 0);
+  for (uint64_t j = 0; j < L.size(); ++j)
+    for (uint64_t i = 0; i < L[j].size(); ++i)
+      (*src16)[j * K2 + i] = static_cast<uint16_t>(pos[L[j][i]] & (K2 - 1));
+  std::vector<uint64_t> next(L.size(), 0);
+  for (uint64_t ch = 0; ch < chunks; ++ch) {
+    uint64_t e = ch * C;
+    for (uint64_t j = 0; j < L.size(); ++j) {
+      for (uint64_t& i = next[j]; i < L[j].size() && L[j][i] < (ch + 1) * C; ++i, ++e) {
+        (*src32)[e] = static_cast<uint32_t>(j * K2 + i);
+        (*src16)[k + e] = static_cast<uint16_t>(L[j][i] - ch * C);
+      }
+    }
+  }
+}
 
 size_t plan_table_bytes(uint64_t k) {
   // gather positions: 2 bytes per point; the passes of larger plans: 8
@@ -598,7 +588,7 @@ hidft_status hidft_plan_get_twiddles(hidft_plan plan, float* twiddles) {
   for (uint32_t u = 1; u <= c.s; ++u) {
     const uint64_t off = (1ULL << (u - 1)) - 1;
     for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
-      const float2 w = dev[device_tw_index(c.s, u, hidft::bit_reverse(q_lo, u - 1))];
+      const float2 w = dev[hidft::device_tw_index(c.s, u, hidft::bit_reverse(q_lo, u - 1))];
       twiddles[2 * (off + q_lo)] = w.x;
       twiddles[2 * (off + q_lo) + 1] = w.y;
     }

@@ -36,6 +36,27 @@ namespace hidft {
 // matrix-core operands come later, on demand.)
 size_t plan_table_bytes(uint64_t k);
 
+// Entry of the device twiddle table that holds stage u's twiddle for the
+// node named by the top u - 1 bits n of the position (a-order).  Up to
+// 2^HIDFT_MAX_LOG2_K_DEVICE points: (2^{u-1} - 1) + n.  Above, the split
+// layout of the passes (launch_large): stages 1..s1 as before, then for each
+// subtree (the top s1 bits of n) the table of its 2^s2-point transform.
+uint64_t device_tw_index(uint32_t s, uint32_t u, uint64_t n);
+
+// Tables of the passes of a transform of 2^s > 2^HIDFT_MAX_LOG2_K_DEVICE
+// points (launch_large) that keeps n_out = pos.size() outputs, output t
+// being the value at position pos[t] (distinct, < 2^s).  Subtree j holds
+// the outputs t with pos[t] >> s2 == j; L_j lists them by increasing t.
+//   src16[0, 2^s): per subtree j, entry i < |L_j| = pos[L_j[i]] mod 2^s2 (the
+//                subtree's gather, so its kept outputs come first, ordered by
+//                t; the other entries are 0);
+//   src16[2^s, 2^s + n) and src32[0, n), n = n_out rounded up to whole
+//                LARGE_CHUNKs: per output chunk, the chunk's values subtree
+//                by subtree: the workspace index j 2^s2 + i of L_j[i] (src32)
+//                and its place L_j[i] - chunk start (src16[2^s + ...]).
+void large_tables(uint32_t s, const std::vector<uint32_t>& pos, std::vector<uint16_t>* src16,
+                  std::vector<uint32_t>* src32);
+
 // HIDFT_ERR_UNSUPPORTED (with a message naming fn) for a plan of more than
 // 2^HIDFT_MAX_LOG2_K_DEVICE points, which only hidft_execute and
 // hidft_execute_ws run; HIDFT_OK otherwise.

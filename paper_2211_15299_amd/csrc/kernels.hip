@@ -2019,7 +2019,8 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
 //    table layout, one table per subtree, and the fused kernel's per-signal
 //    code runs each subtree in place.  Its gather writes the subtree's
 //    outputs ordered by their index t in the caller's order of J.
-//  * pass 3: output chunk c (LARGE_CHUNK consecutive t) takes from each
+//  * pass 3: output chunk c (LARGE_CHUNK consecutive t, of the n_out <= 2^s
+//    outputs kept; the last chunk may be partial) takes from each
 //    subtree the contiguous run of its outputs whose t fall in the chunk,
 //    puts each value at its place in LDS, scales by N/k and stores the chunk
 //    in order.  Every read and write of the pass is a contiguous run; only
@@ -2171,23 +2172,26 @@ large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint
 
 __global__ void __launch_bounds__(LARGE_THREADS)
 large_place_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
-                   uint64_t batch, uint32_t s, const uint32_t* __restrict__ src3,
+                   uint64_t batch, uint32_t s, uint64_t n_out, const uint32_t* __restrict__ src3,
                    const uint16_t* __restrict__ dest3, float scale) {
   __shared__ float2 chunk[LARGE_CHUNK];
   const uint64_t k = 1ULL << s;
-  const uint64_t chunks = k / LARGE_CHUNK;
+  const uint64_t chunks = (n_out + LARGE_CHUNK - 1) / LARGE_CHUNK;
   for (uint64_t unit = blockIdx.x; unit < batch * chunks; unit += gridDim.x) {
     const uint64_t b = unit / chunks, c = unit - b * chunks;
+    const uint32_t count = (uint32_t)(n_out - c * LARGE_CHUNK < LARGE_CHUNK
+                                          ? n_out - c * LARGE_CHUNK
+                                          : LARGE_CHUNK);
     const float2* w = work + b * k;
     const uint32_t* s3 = src3 + c * LARGE_CHUNK;
     const uint16_t* d3 = dest3 + c * LARGE_CHUNK;
-    for (uint32_t e = threadIdx.x; e < LARGE_CHUNK; e += LARGE_THREADS) {
+    for (uint32_t e = threadIdx.x; e < count; e += LARGE_THREADS) {
       const float2 x = w[s3[e]];
       chunk[d3[e]] = make_float2(x.x * scale, x.y * scale);
     }
     __syncthreads();
     float2* o = out + b * (uint64_t)ld_out + c * LARGE_CHUNK;
-    for (uint32_t e = threadIdx.x; e < LARGE_CHUNK; e += LARGE_THREADS) store_stream(o + e, chunk[e]);
+    for (uint32_t e = threadIdx.x; e < count; e += LARGE_THREADS) store_stream(o + e, chunk[e]);
     __syncthreads();  // the next unit overwrites the chunk
   }
 }
@@ -2240,12 +2244,14 @@ static hipError_t launch_large_sub(float2* work, uint64_t units, uint32_t s1, co
 hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out,
                         int64_t ld_out, uint64_t batch, float2* work, const float2* tw,
                         const uint16_t* src2, const uint32_t* src3, const uint16_t* dest3,
-                        float scale, hipStream_t stream) {
+                        float scale, hipStream_t stream, uint64_t n_out) {
   if (batch == 0) return hipSuccess;
   if (s <= HIDFT_MAX_LOG2_K_DEVICE || s > HIDFT_MAX_LOG2_K_LARGE) return hipErrorInvalidValue;
   const uint32_t s2 = large_split(s), s1 = s - s2;
   const uint64_t k = 1ULL << s;
   if (batch > (~0ULL >> (s + 1))) return hipErrorInvalidValue;
+  if (n_out == 0) n_out = k;
+  if (n_out > k) return hipErrorInvalidValue;
   unsigned grid = 0;
   hipError_t e = stream_grid(batch << s2, &grid);
   if (e != hipSuccess) return e;
@@ -2284,7 +2290,7 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
   if (e != hipSuccess) return e;
   if ((e = stream_grid(batch * k, &grid)) != hipSuccess) return e;
   hipLaunchKernelGGL(large_place_kernel, dim3(grid), dim3(LARGE_THREADS), 0, stream, work, out,
-                     ld_out, batch, s, src3, dest3, scale);
+                     ld_out, batch, s, n_out, src3, dest3, scale);
   return hipGetLastError();
 }
 

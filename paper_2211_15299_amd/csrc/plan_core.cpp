@@ -354,8 +354,8 @@ LeafAccuracy leaf_accuracy(uint32_t M, uint32_t s, const uint64_t* J, uint64_t k
 }
 
 hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const uint32_t* r,
-                             uint32_t nr, uint32_t max_s, uint32_t max_mu, double max_err,
-                             PartPlan* pp, std::string* err) {
+                             uint32_t nr, uint32_t max_s, uint32_t max_s_mu1, uint32_t max_mu,
+                             double max_err, PartPlan* pp, std::string* err) {
   uint64_t mask = 0;
   hidft_status st = analyze_core(M, J, k, &mask, err);
   if (st != HIDFT_OK) return st;
@@ -381,8 +381,9 @@ hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const ui
                        "not part-homogeneous at r", p, rv.back());
           return HIDFT_ERR_NOT_HOMOGENEOUS;
         }
-    if (rv.size() > max_s) {
-      set_err(err, "2^%llu samples per Hi-DFT exceed the supported 2^%llu", rv.size(), max_s);
+    if (rv.size() > max_s_mu1) {
+      set_err(err, "2^%llu samples per Hi-DFT exceed the supported 2^%llu", rv.size(),
+              max_s_mu1);
       return HIDFT_ERR_UNSUPPORTED;
     }
   } else {
@@ -394,11 +395,11 @@ hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const ui
       uint32_t t;
     };
     std::vector<Cand> cands;
-    for (uint32_t t = 0; t <= piv.size() && t <= max_s; ++t) {
+    for (uint32_t t = 0; t <= piv.size() && t <= max_s_mu1; ++t) {
       uint64_t mu = 0;
       double sq = 0;
       node_sizes(J, k, t ? piv[t - 1] + 1 : 0, &mu, &sq);
-      if (mu > max_mu) continue;
+      if (mu > max_mu || (t > max_s && mu > 1)) continue;
       cands.push_back({1.5 * t * (double)(1ULL << t) * (double)mu + 6.0 * sq, t});
     }
     std::stable_sort(cands.begin(), cands.end(),
@@ -418,9 +419,10 @@ hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const ui
     if (!found) {
       char buf[320];
       std::snprintf(buf, sizeof buf,
-                    "no prefix of the pivots of J keeps mu* <= %u with 2^s <= 2^%u and the "
-                    "leaf systems' error bound within %.1e (best bound %.3e)",
-                    max_mu, max_s, max_err, best_bound);
+                    "no prefix of the pivots of J keeps mu* <= %u with 2^s <= 2^%u (2^%u "
+                    "for mu* = 1) and the leaf systems' error bound within %.1e (best bound "
+                    "%.3e)",
+                    max_mu, max_s, max_s_mu1, max_err, best_bound);
       if (err) *err = buf;
       return HIDFT_ERR_UNSUPPORTED;
     }
@@ -476,6 +478,17 @@ hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const ui
     a = b;
   }
   pp->cost = 1.5 * s * (double)(1ULL << s) * pp->mu_max + 6.0 * sq;
+  if (s > max_s && pp->mu_max > 1) {
+    if (err) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf,
+                    "2^%u samples per Hi-DFT exceed the supported 2^%u for mu* = %u (above "
+                    "it, only plans with one element per node)",
+                    s, max_s, pp->mu_max);
+      *err = buf;
+    }
+    return HIDFT_ERR_UNSUPPORTED;
+  }
   if (!have_acc) {
     if (pp->mu_max <= max_mu) {
       acc = leaf_accuracy(M, s, J, k, level);

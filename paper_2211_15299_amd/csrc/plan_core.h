@@ -81,12 +81,13 @@ struct PartPlan {
 
 // Builds the plan.  If r == nullptr the pivot vector is chosen: the first t
 // pivots of J (J is part-homogeneous at any such prefix) for the t that
-// minimises Lemma 4's cost among those with mu* <= max_mu, t <= max_s and a
-// leaf error bound <= max_err (UNSUPPORTED if there is none).  A given r is
-// only checked for part-homogeneity and |r| <= max_s; its accuracy is
-// recorded (when mu* <= max_mu) for the caller to judge.
+// minimises Lemma 4's cost among those with mu* <= max_mu, t <= max_s (or
+// t <= max_s_mu1 when every node holds one element) and a leaf error bound
+// <= max_err (UNSUPPORTED if there is none).  A given r is only checked for
+// part-homogeneity and the same size limits; its accuracy is recorded (when
+// mu* <= max_mu) for the caller to judge.
 hidft_status build_part_plan(uint32_t M, const uint64_t* J, uint64_t k, const uint32_t* r,
-                             uint32_t nr, uint32_t max_s, uint32_t max_mu, double max_err,
-                             PartPlan* pp, std::string* err);
+                             uint32_t nr, uint32_t max_s, uint32_t max_s_mu1, uint32_t max_mu,
+                             double max_err, PartPlan* pp, std::string* err);
 
 }  // namespace hidft

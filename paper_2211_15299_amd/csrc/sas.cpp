@@ -26,6 +26,11 @@ struct hidft_sas_s {
   uint32_t* d_inv_off = nullptr;    // offset of each node's inverse (complex128 units)
   void* d_inv = nullptr;            // inverse dual Vandermonde matrices, FP64
   uint4* d_elem_rec = nullptr;      // per element: {v | t << 16, row offset, mu(v), 0}
+  // 2^s > 2^HIDFT_MAX_LOG2_K_DEVICE (mu* = 1): the passes of launch_large.
+  // d_src holds their 16-bit tables, d_pos the 32-bit ones, d_tw the split
+  // twiddle layout.
+  uint32_t* d_pos = nullptr;
+  bool large = false;
   bool fused = false;               // one kernel per launch, no workspace
   bool weights_only = false;        // HIDFT_SAS_WEIGHTS_ONLY: no leaf-solve tables
   size_t device_bytes = 0;
@@ -36,7 +41,7 @@ namespace {
 void release(hidft_sas p) {
   void* ptrs[] = {p->d_tw,         p->d_src,      p->d_src_node,  p->d_src_elem, p->d_node_first,
                   p->d_node_count, p->d_elem_t,   p->d_elem_node, p->d_inv_off,  p->d_inv,
-                  p->d_elem_rec};
+                  p->d_elem_rec,   p->d_pos};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   p->d_tw = nullptr;
@@ -44,6 +49,7 @@ void release(hidft_sas p) {
   p->d_node_first = p->d_node_count = p->d_elem_t = p->d_elem_node = p->d_inv_off = nullptr;
   p->d_inv = nullptr;
   p->d_elem_rec = nullptr;
+  p->d_pos = nullptr;
 }
 
 template <typename T>
@@ -73,6 +79,44 @@ hidft_status upload(hidft_sas p, hipStream_t st) {
     }
   }
   const uint32_t n_nodes = (uint32_t)c.node_slot.size();
+  if (p->large) {
+    // One element per node: the Hi-DFT's value at the slot of J[t]'s node is
+    // the answer for t, through the passes of launch_large.
+    std::vector<uint32_t> pos(c.k);
+    for (uint32_t v = 0; v < n_nodes; ++v)
+      pos[c.elem_t[c.node_first[v]]] = (uint32_t)hidft::bit_reverse(c.node_slot[v], c.s);
+    std::vector<uint16_t> src16;
+    std::vector<uint32_t> src32;
+    hidft::large_tables(c.s, pos, &src16, &src32);
+    for (uint32_t u = 1; u <= c.s; ++u) {
+      const uint64_t off = (1ULL << (u - 1)) - 1;
+      for (uint64_t q_lo = 0; q_lo < (1ULL << (u - 1)); ++q_lo) {
+        const uint64_t at = hidft::device_tw_index(c.s, u, hidft::bit_reverse(q_lo, u - 1));
+        num[at] = c.tw_num[off + q_lo];
+        den[at] = c.tw_log2den[off + q_lo];
+      }
+    }
+    uint64_t* d_num = nullptr;
+    uint8_t* d_den = nullptr;
+    size_t total = 0, tmp = 0;
+    hidft_status status = HIDFT_OK;
+    if ((e = hipMalloc(&p->d_tw, (ntw ? ntw : 1) * sizeof(float2))) != hipSuccess ||
+        (e = upload_vec(&d_num, num, st, &tmp)) != hipSuccess ||
+        (e = upload_vec(&d_den, den, st, &tmp)) != hipSuccess ||
+        (e = upload_vec(&p->d_src, src16, st, &total)) != hipSuccess ||
+        (e = upload_vec(&p->d_pos, src32, st, &total)) != hipSuccess ||
+        (e = hidft::launch_twiddle_gen(d_num, d_den, p->d_tw, ntw, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      status = hidft::hip_error(e, "hidft_sas_create: table upload");
+    if (d_num) (void)hipFree(d_num);
+    if (d_den) (void)hipFree(d_den);
+    if (status != HIDFT_OK) {
+      release(p);
+      return status;
+    }
+    p->device_bytes = total + (ntw ? ntw : 1) * sizeof(float2);
+    return HIDFT_OK;
+  }
   std::vector<uint16_t> src(ks), src_node(ks, 0), src_elem;
   for (uint64_t t = 0; t < ks; ++t) src[t] = (uint16_t)hidft::bit_reverse(t, c.s);
   if (p->weights_only) {
@@ -214,13 +258,21 @@ hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
     p = new hidft_sas_s;
     std::string err;
     hidft_status st = hidft::build_part_plan(log2_n, J, k, pivots, n_pivots,
-                                             HIDFT_MAX_LOG2_K_DEVICE, HIDFT_SAS_MAX_MU,
-                                             HIDFT_SAS_MAX_REL_ERR, &p->core, &err);
+                                             HIDFT_MAX_LOG2_K_DEVICE, HIDFT_MAX_LOG2_K_LARGE,
+                                             HIDFT_SAS_MAX_MU, HIDFT_SAS_MAX_REL_ERR, &p->core,
+                                             &err);
     if (st != HIDFT_OK) {
       delete p;
       return hidft::set_error(st, "hidft_sas_create: " + err);
     }
     p->weights_only = (flags & HIDFT_SAS_WEIGHTS_ONLY) != 0;
+    p->large = p->core.s > HIDFT_MAX_LOG2_K_DEVICE;  // then mu* = 1 (build_part_plan)
+    if (p->large && p->weights_only) {
+      delete p;
+      return hidft::set_error(HIDFT_ERR_UNSUPPORTED,
+                              "hidft_sas_create: the induced weights need 2^s <= 2^" +
+                                  std::to_string(HIDFT_MAX_LOG2_K_DEVICE));
+    }
     if (!p->weights_only) {
       // A plan that will solve must be solvable within the accuracy target.
       const hidft::LeafAccuracy& a = p->core.leaf;
@@ -241,7 +293,7 @@ hidft_status hidft_sas_create(uint32_t log2_n, const uint64_t* J, uint64_t k,
       }
     }
     p->scale = std::ldexp(1.0f, (int)p->core.M - (int)p->core.s);
-    p->fused = !p->weights_only && !(flags & HIDFT_SAS_TWO_PASS) &&
+    p->fused = !p->weights_only && !p->large && !(flags & HIDFT_SAS_TWO_PASS) &&
                hidft::sas_fused_fits(p->core.s, p->core.mu_max,
                                      (uint32_t)p->core.node_slot.size(), (uint32_t)p->core.k);
     if (!(flags & HIDFT_PLAN_HOST_ONLY)) {
@@ -321,10 +373,14 @@ hidft_status hidft_sas_workspace_bytes(hidft_sas p, uint64_t batch, size_t* byte
   if (!p || !bytes)
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_workspace_bytes: NULL");
   // [signal][shift][node]; none when every node holds one element (mu* = 1)
-  // or when the plan runs as one kernel.
-  *bytes = p->core.mu_max == 1 || p->fused || p->weights_only
-               ? 0
-               : (size_t)batch * p->core.mu_max * p->core.node_slot.size() * sizeof(float2);
+  // or when the plan runs as one kernel.  Above 2^HIDFT_MAX_LOG2_K_DEVICE
+  // samples per Hi-DFT: the passes' intermediate, 2^s values per signal.
+  if (p->large)
+    *bytes = (size_t)(batch << p->core.s) * sizeof(float2);
+  else
+    *bytes = p->core.mu_max == 1 || p->fused || p->weights_only
+                 ? 0
+                 : (size_t)batch * p->core.mu_max * p->core.node_slot.size() * sizeof(float2);
   return hidft::set_error(HIDFT_OK, "");
 }
 
@@ -336,6 +392,10 @@ hidft_status hidft_sas_weights(hidft_sas p, const void* d_samples, int64_t ld_in
   if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? hidft::set_error(HIDFT_OK, "") : st;
   if (!p->d_tw)
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_sas_weights: HOST_ONLY plan");
+  if (p->large)
+    return hidft::set_error(HIDFT_ERR_UNSUPPORTED,
+                            "hidft_sas_weights: the induced weights need 2^s <= 2^" +
+                                std::to_string(HIDFT_MAX_LOG2_K_DEVICE));
   hipError_t e = hidft::launch_fused(p->core.s, static_cast<const float2*>(d_samples), ld_in,
                                      static_cast<float2*>(d_weights), ld_out, batch, p->d_tw,
                                      p->d_src, nullptr, p->scale, hidft::ExecConfig{},
@@ -416,6 +476,15 @@ hipError_t run_two_pass(hidft_sas p, const float2* in, int64_t ld_in, float2* co
   return e;
 }
 
+// 2^s > 2^HIDFT_MAX_LOG2_K_DEVICE with mu* = 1: the Hi-DFT in passes through
+// a workspace of 2^s values per signal, its k kept outputs in J's order.
+hipError_t run_large(hidft_sas p, const float2* in, int64_t ld_in, float2* coefs,
+                     int64_t ld_out, uint64_t batch, float2* work, hipStream_t s) {
+  const uint64_t ks = 1ULL << p->core.s;
+  return hidft::launch_large(p->core.s, in, ld_in, coefs, ld_out, batch, work, p->d_tw, p->d_src,
+                             p->d_pos, p->d_src + ks, p->scale, s, p->core.k);
+}
+
 }  // namespace
 
 extern "C" {
@@ -428,7 +497,8 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float2* in = static_cast<const float2*>(d_samples);
   float2* coefs = static_cast<float2*>(d_coefs);
-  if (p->core.mu_max == 1 || p->fused) return run_direct(p, in, ld_in, coefs, ld_out, batch, s, fn);
+  if (!p->large && (p->core.mu_max == 1 || p->fused))
+    return run_direct(p, in, ld_in, coefs, ld_out, batch, s, fn);
   const uint64_t ks = 1ULL << p->core.s;
   const uint64_t mu = p->core.mu_max;
   const uint64_t nn = p->core.node_slot.size();
@@ -438,8 +508,10 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
   {
     // The workspace is written while the samples are read and read while the
     // coefficients are written: it must overlap neither.
+    size_t wbytes = 0;
+    (void)hidft_sas_workspace_bytes(p, batch, &wbytes);
     const uint64_t w0 = reinterpret_cast<uintptr_t>(d_work);
-    const uint64_t w1 = w0 + batch * mu * nn * sizeof(float2);
+    const uint64_t w1 = w0 + wbytes;
     const uint64_t a0 = reinterpret_cast<uintptr_t>(d_samples);
     const uint64_t a1 = a0 + ((batch - 1) * (uint64_t)ld_in + mu * ks) * sizeof(float2);
     const uint64_t b0 = reinterpret_cast<uintptr_t>(d_coefs);
@@ -448,7 +520,10 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
       return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
                               "hidft_sas_execute: workspace overlaps the samples or coefficients");
   }
-  hipError_t e = run_two_pass(p, in, ld_in, coefs, ld_out, batch, static_cast<float2*>(d_work), s);
+  hipError_t e = p->large ? run_large(p, in, ld_in, coefs, ld_out, batch,
+                                      static_cast<float2*>(d_work), s)
+                          : run_two_pass(p, in, ld_in, coefs, ld_out, batch,
+                                         static_cast<float2*>(d_work), s);
   if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute: kernel launch");
   return hidft::set_error(HIDFT_OK, "");
 }
@@ -462,10 +537,14 @@ hidft_status hidft_sas_execute_noalloc(hidft_sas p, const void* d_samples, int64
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float2* in = static_cast<const float2*>(d_samples);
   float2* coefs = static_cast<float2*>(d_coefs);
-  if (p->core.mu_max == 1 || p->fused) return run_direct(p, in, ld_in, coefs, ld_out, batch, s, fn);
-  // One signal's shifted Hi-DFT outputs must fit the scratch; the batch runs
-  // in chunks of as many signals as fit, in stream order.
-  const uint64_t per_signal = (uint64_t)p->core.mu_max * p->core.node_slot.size() * sizeof(float2);
+  if (!p->large && (p->core.mu_max == 1 || p->fused))
+    return run_direct(p, in, ld_in, coefs, ld_out, batch, s, fn);
+  // One signal's intermediate values (the shifted Hi-DFT outputs, or the
+  // passes' 2^s values) must fit the scratch; the batch runs in chunks of as
+  // many signals as fit, in stream order.
+  const uint64_t per_signal =
+      p->large ? (uint64_t)sizeof(float2) << p->core.s
+               : (uint64_t)p->core.mu_max * p->core.node_slot.size() * sizeof(float2);
   if (per_signal > hidft::SAS_SCRATCH_BYTES)
     return hidft::set_error(HIDFT_ERR_UNSUPPORTED,
                             std::string(fn) + ": one signal needs " + std::to_string(per_signal) +
@@ -477,8 +556,12 @@ hidft_status hidft_sas_execute_noalloc(hidft_sas p, const void* d_samples, int64
   const uint64_t chunk = hidft::SAS_SCRATCH_BYTES / per_signal;
   for (uint64_t first = 0; first < batch && e == hipSuccess; first += chunk) {
     const uint64_t n = batch - first < chunk ? batch - first : chunk;
-    e = run_two_pass(p, in + first * (uint64_t)ld_in, ld_in, coefs + first * (uint64_t)ld_out,
-                     ld_out, n, static_cast<float2*>(scratch), s);
+    e = p->large ? run_large(p, in + first * (uint64_t)ld_in, ld_in,
+                             coefs + first * (uint64_t)ld_out, ld_out, n,
+                             static_cast<float2*>(scratch), s)
+                 : run_two_pass(p, in + first * (uint64_t)ld_in, ld_in,
+                                coefs + first * (uint64_t)ld_out, ld_out, n,
+                                static_cast<float2*>(scratch), s);
   }
   if (e != hipSuccess) return hidft::hip_error(e, "hidft_sas_execute_noalloc: kernel launch");
   return hidft::set_error(HIDFT_OK, "");

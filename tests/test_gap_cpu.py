@@ -89,7 +89,7 @@ def test_gap_pivot_bound_and_subset_sums(sizes):
         # the planner agrees, and plans the Hi-DFT on all pivots with mu* = 1
         got, hom = native.analyze(M, J)
         assert got == P
-        if n <= native.MAX_LOG2_K_DEVICE:
+        if n <= native.MAX_LOG2_K_LARGE:
             plan = native.SASPlan(M, J, pivots=P, host_only=True)
             assert plan.mu_max == 1 and plan.samples_per_signal == 1 << n
             assert plan.samples().tolist() == oracle.sas_sample_set(M, P, 1)[0]

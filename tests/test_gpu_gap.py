@@ -59,8 +59,8 @@ def test_gap_hidft_on_all_pivots(sizes):
     J = g.J.tolist()
     P, _ = native.analyze(M, J)
     print(f"case GAP sizes={sizes} M={M} k={len(J)} pivots={len(P)}", flush=True)
-    if len(P) > native.MAX_LOG2_K_DEVICE:
-        pytest.skip("more pivots than the executor's 2^14 samples")
+    if len(P) > native.MAX_LOG2_K_LARGE:
+        pytest.skip("more pivots than the executor's 2^22 samples")
     full = native.SASPlan(M, J, pivots=P)
     assert full.mu_max == 1
     _check(M, J, full, rng, full.err_bound)
@@ -87,3 +87,38 @@ def test_arithmetic_progressions(alpha):
     assert full.mu_max == 1 and full.samples_per_signal == 1 << len(P)
     _check(M, J, full, rng, full.err_bound)
     full.close()
+
+
+@pytest.mark.parametrize("kind,M,size,alpha", [("ap", 22, 20000, 1), ("ap", 22, 40000, 3),
+                                              ("ap", 24, 100000, 5), ("gap", 24, [256, 64], 0),
+                                              ("gap", 24, [64, 64, 16], 0)])
+def test_more_pivots_than_one_signal_in_lds(kind, M, size, alpha):
+    """Lemma 5's Hi-DFT on all n > 14 pivots (2^n samples, mu* = 1) runs in
+    passes through a workspace; every coefficient against the seeded ones
+    the samples were synthesised from (FP64, full-length inverse DFT), and
+    hidft_sas_execute_noalloc gives the same bits."""
+    rng = rng_for(932, M * 7 + (size if kind == "ap" else size[0]))
+    J = (arithmetic_progression(M, size, rng, alpha) if kind == "ap"
+         else gap_support(M, size, rng)).J.tolist()
+    P, _ = native.analyze(M, J)
+    print(f"case {kind} M={M} k={len(J)} pivots={len(P)}", flush=True)
+    assert 14 < len(P) <= native.MAX_LOG2_K_LARGE
+    plan = native.SASPlan(M, J, pivots=P)
+    assert plan.mu_max == 1 and plan.samples_per_signal == 1 << len(P)
+    assert plan.workspace_bytes(2) == 2 * (1 << len(P)) * 8
+    S = plan.samples().tolist()
+    c = complex_normal((2, len(J)), rng)
+    f = oracle.synthesize_samples_fft(M, J, c, S)
+    got = _sas_run(plan, f)
+    err = oracle.rel_l2(got, c)
+    print(f"  rel-L2 max {np.max(err):.2e} (bound {plan.err_bound:.2e})", flush=True)
+    assert np.max(err) <= plan.err_bound <= 1e-5
+    x = torch.from_numpy(f.astype(np.complex64)).cuda()
+    y = torch.empty((2, plan.k), dtype=torch.complex64, device="cuda")
+    plan.execute_noalloc_ptr(x.data_ptr(), len(S), y.data_ptr(), plan.k, 2)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy().astype(np.complex128), got)
+    # the induced weights stay within one signal in LDS
+    with pytest.raises(native.HiDFTError):
+        native.SASPlan(M, J, pivots=P, weights_only=True)
+    plan.close()
