@@ -548,11 +548,18 @@ hidft_status hidft_server_destroy(hidft_server server);
  * computed as the adjoint of the radix-2 stages of hidft_execute (reverse
  * order, conjugated twiddles), O(k log k) per signal, one kernel launch.
  * Same plans, layouts, alignment, overlap and error rules as hidft_execute,
- * with the roles of the two buffers exchanged.
+ * with the roles of the two buffers exchanged.  Above 2^HIDFT_MAX_LOG2_K_DEVICE
+ * points, the adjoint of hidft_execute's passes, in reverse order, through a
+ * workspace taken from the stream-ordered allocator; hidft_execute_inverse_ws
+ * takes it from the caller (hidft_plan_workspace_bytes, the rules of
+ * hidft_execute_ws) and allocates nothing.
  */
 hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t ld_in,
                                    void* d_samples, int64_t ld_out, uint64_t batch,
                                    void* stream);
+hidft_status hidft_execute_inverse_ws(hidft_plan plan, const void* d_coefs, int64_t ld_in,
+                                      void* d_samples, int64_t ld_out, uint64_t batch,
+                                      void* d_work, size_t work_bytes, void* stream);
 
 /*
  * Shift-and-Sample (Sec. IX, Algorithm 2) and the Hi-DFT of part-homogeneous

@@ -614,6 +614,39 @@ hidft_status hidft_plan_workspace_bytes(hidft_plan plan, uint64_t batch, size_t*
   return ok();
 }
 
+}  // extern "C"
+
+namespace {
+
+// The workspace of the passes: present, large enough, aligned, and
+// overlapping neither the input rows nor the output rows.
+hidft_status check_workspace(hidft_plan plan, const void* d_in, int64_t ld_in, const void* d_out,
+                             int64_t ld_out, uint64_t batch, const void* d_work,
+                             size_t work_bytes, const char* fn) {
+  size_t need = 0;
+  hidft_status st = hidft_plan_workspace_bytes(plan, batch, &need);
+  if (st != HIDFT_OK) return st;
+  if (!d_work || work_bytes < need)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: workspace of %zu bytes needed, %zu given", fn,
+                need, d_work ? work_bytes : (size_t)0);
+  if (reinterpret_cast<uintptr_t>(d_work) & 7u)
+    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: workspace must be 8-byte aligned", fn);
+  const uintptr_t w0 = reinterpret_cast<uintptr_t>(d_work), w1 = w0 + need;
+  const uint64_t k = plan->core.k;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(d_in);
+  const uintptr_t a1 = a0 + ((batch - 1) * (uint64_t)ld_in + k) * sizeof(float2);
+  const uintptr_t b0 = reinterpret_cast<uintptr_t>(d_out);
+  const uintptr_t b1 = b0 + ((batch - 1) * (uint64_t)ld_out + k) * sizeof(float2);
+  if ((w0 < a1 && a0 < w1) || (w0 < b1 && b0 < w1))
+    return fail(HIDFT_ERR_INVALID_ARGUMENT,
+                "%s: the workspace overlaps the input or output rows", fn);
+  return HIDFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 hidft_status hidft_execute_ws(hidft_plan plan, const void* d_samples, int64_t ld_in,
                               void* d_coefs, int64_t ld_out, uint64_t batch, void* d_work,
                               size_t work_bytes, void* stream) {
@@ -623,26 +656,13 @@ hidft_status hidft_execute_ws(hidft_plan plan, const void* d_samples, int64_t ld
   if (plan->core.s <= HIDFT_MAX_LOG2_K_DEVICE) return hidft_execute(plan, d_samples, ld_in,
                                                                     d_coefs, ld_out, batch,
                                                                     stream);
-  size_t need = 0;
-  if ((st = hidft_plan_workspace_bytes(plan, batch, &need)) != HIDFT_OK) return st;
-  if (!d_work || work_bytes < need)
-    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: workspace of %zu bytes needed, %zu given", fn,
-                need, d_work ? work_bytes : (size_t)0);
-  if (reinterpret_cast<uintptr_t>(d_work) & 7u)
-    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: workspace must be 8-byte aligned", fn);
-  const uintptr_t w0 = reinterpret_cast<uintptr_t>(d_work), w1 = w0 + need;
-  const uint64_t k = plan->core.k;
-  const uintptr_t a0 = reinterpret_cast<uintptr_t>(d_samples);
-  const uintptr_t a1 = a0 + ((batch - 1) * (uint64_t)ld_in + k) * sizeof(float2);
-  const uintptr_t b0 = reinterpret_cast<uintptr_t>(d_coefs);
-  const uintptr_t b1 = b0 + ((batch - 1) * (uint64_t)ld_out + k) * sizeof(float2);
-  if ((w0 < a1 && a0 < w1) || (w0 < b1 && b0 < w1))
-    return fail(HIDFT_ERR_INVALID_ARGUMENT, "%s: the workspace overlaps the samples or coefficients",
-                fn);
+  if ((st = check_workspace(plan, d_samples, ld_in, d_coefs, ld_out, batch, d_work, work_bytes,
+                            fn)) != HIDFT_OK)
+    return st;
   hipError_t e = hidft::launch_large(plan->core.s, static_cast<const float2*>(d_samples), ld_in,
                                      static_cast<float2*>(d_coefs), ld_out, batch,
                                      static_cast<float2*>(d_work), plan->d_tw, plan->d_src,
-                                     plan->d_pos, plan->d_src + k, plan->scale,
+                                     plan->d_pos, plan->d_src + plan->core.k, plan->scale,
                                      static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hidft_execute_ws: kernel launch");
   return ok();
@@ -714,13 +734,48 @@ hidft_status hidft_execute_inverse(hidft_plan plan, const void* d_coefs, int64_t
                                    void* stream) {
   hidft_status st =
       check_exec(plan, d_coefs, ld_in, d_samples, ld_out, batch, "hidft_execute_inverse");
-  if (st == HIDFT_OK) st = hidft::require_single_pass(plan, "hidft_execute_inverse");
   if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
   const float inv_n = std::ldexp(1.0f, -(int)plan->core.M);
+  if (plan->core.s > HIDFT_MAX_LOG2_K_DEVICE) {
+    size_t need = 0;
+    if ((st = hidft_plan_workspace_bytes(plan, batch, &need)) != HIDFT_OK) return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    void* work = nullptr;
+    hipError_t e = hipMallocAsync(&work, need, hs);
+    if (e != hipSuccess) return hip_fail(e, "hidft_execute_inverse: workspace allocation");
+    e = hidft::launch_large_inverse(plan->core.s, static_cast<const float2*>(d_coefs), ld_in,
+                                    static_cast<float2*>(d_samples), ld_out, batch,
+                                    static_cast<float2*>(work), plan->d_tw, plan->d_src,
+                                    plan->d_pos, plan->d_src + plan->core.k, inv_n, hs);
+    const hipError_t ef = hipFreeAsync(work, hs);
+    if (e != hipSuccess) return hip_fail(e, "hidft_execute_inverse: kernel launch");
+    if (ef != hipSuccess) return hip_fail(ef, "hidft_execute_inverse: workspace release");
+    return ok();
+  }
   hipError_t e = hidft::launch_inverse(plan->core.s, static_cast<const float2*>(d_coefs), ld_in,
                                        static_cast<float2*>(d_samples), ld_out, batch, plan->d_tw,
                                        plan->d_src, inv_n, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hidft_execute_inverse: kernel launch");
+  return ok();
+}
+
+hidft_status hidft_execute_inverse_ws(hidft_plan plan, const void* d_coefs, int64_t ld_in,
+                                      void* d_samples, int64_t ld_out, uint64_t batch,
+                                      void* d_work, size_t work_bytes, void* stream) {
+  const char* fn = "hidft_execute_inverse_ws";
+  hidft_status st = check_exec(plan, d_coefs, ld_in, d_samples, ld_out, batch, fn);
+  if (st != HIDFT_OK || batch == 0) return st == HIDFT_OK ? ok() : st;
+  if (plan->core.s <= HIDFT_MAX_LOG2_K_DEVICE)
+    return hidft_execute_inverse(plan, d_coefs, ld_in, d_samples, ld_out, batch, stream);
+  if ((st = check_workspace(plan, d_coefs, ld_in, d_samples, ld_out, batch, d_work, work_bytes,
+                            fn)) != HIDFT_OK)
+    return st;
+  hipError_t e = hidft::launch_large_inverse(
+      plan->core.s, static_cast<const float2*>(d_coefs), ld_in, static_cast<float2*>(d_samples),
+      ld_out, batch, static_cast<float2*>(d_work), plan->d_tw, plan->d_src, plan->d_pos,
+      plan->d_src + plan->core.k, std::ldexp(1.0f, -(int)plan->core.M),
+      static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hidft_execute_inverse_ws: kernel launch");
   return ok();
 }
 

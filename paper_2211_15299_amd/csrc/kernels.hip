@@ -2295,6 +2295,239 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
 }
 
 // ---------------------------------------------------------------------------
+// Inverse map above 2^14 points: the adjoint of the three passes, in reverse.
+//  * placement^H: chunk c of the coefficients (LARGE_CHUNK consecutive t) is
+//    read in order into LDS and written to the subtree runs of the workspace
+//    (the forward placement's tables, read the other way);
+//  * subtrees^H: each subtree runs the inverse kernel's per-signal code
+//    (inverse_signal) with its own twiddle and gather tables, in place;
+//  * columns^H: the adjoint of stages s1..1 per column, scaled by `scale`
+//    (1/N), stored as the samples in ascending order of I_r.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(LARGE_THREADS)
+large_unplace_kernel(const float2* __restrict__ coefs, int64_t ld_in, float2* __restrict__ work,
+                     uint64_t batch, uint32_t s, const uint32_t* __restrict__ src3,
+                     const uint16_t* __restrict__ dest3) {
+  __shared__ float2 chunk[LARGE_CHUNK];
+  const uint64_t k = 1ULL << s;
+  const uint64_t chunks = k / LARGE_CHUNK;
+  for (uint64_t unit = blockIdx.x; unit < batch * chunks; unit += gridDim.x) {
+    const uint64_t b = unit / chunks, c = unit - b * chunks;
+    const float2* x = coefs + b * (uint64_t)ld_in + c * LARGE_CHUNK;
+    for (uint32_t e = threadIdx.x; e < LARGE_CHUNK; e += LARGE_THREADS) chunk[e] = load_stream(x + e);
+    __syncthreads();
+    float2* w = work + b * k;
+    const uint32_t* s3 = src3 + c * LARGE_CHUNK;
+    const uint16_t* d3 = dest3 + c * LARGE_CHUNK;
+    for (uint32_t e = threadIdx.x; e < LARGE_CHUNK; e += LARGE_THREADS) w[s3[e]] = chunk[d3[e]];
+    __syncthreads();  // the next unit overwrites the chunk
+  }
+}
+
+template <int S2, int SCHED>
+__global__ void __launch_bounds__((FusedShape<S2, SCHED, 4>::THREADS))
+large_sub_inv_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint32_t s1,
+                     const float2* __restrict__ tw2, const uint16_t* __restrict__ src2) {
+  using Sh = FusedShape<S2, SCHED, 4>;
+  static_assert(Sh::SPB == 1 && Sh::THREADS == Sh::T, "one subtree per block");
+  constexpr int R = Sh::R, T = Sh::T;
+  constexpr uint64_t K2 = 1ULL << S2;
+  extern __shared__ float2 lds[];
+  const uint64_t unit = first + blockIdx.x;
+  if (unit >= units) return;  // uniform over the block
+  const uint64_t sub = unit & ((1ULL << s1) - 1);
+  float2* row = work + unit * K2;
+  const int tau = (int)threadIdx.x;
+  float2 v[R];
+  __builtin_amdgcn_s_setprio(2);
+  load_row<R, T, false>(v, row, (uint32_t)K2);
+  __builtin_amdgcn_s_setprio(0);
+  const SubtreeMem mem{tw2 + sub * (K2 - 1), src2 + sub * K2, nullptr};
+  ThreadState<S2, SCHED, 4> unused;
+  inverse_signal<S2, SCHED, false>(v, lds, tau, mem, unused);
+#pragma unroll
+  for (int c = 0; c < R; ++c) row[c * T + tau] = v[c];
+}
+
+template <int S1>
+__global__ void __launch_bounds__(LARGE_THREADS)
+large_top_inv_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
+                     uint64_t batch, uint32_t s2, const float2* __restrict__ tw, float scale) {
+  constexpr int R1 = 1 << S1;
+  float2 w[R1 - 1];
+#pragma unroll
+  for (int i = 0; i < R1 - 1; ++i) w[i] = make_uniform(tw[i]);
+  const uint64_t cols = 1ULL << s2;
+  const uint64_t k = cols << S1;
+  const uint64_t n = batch << s2;
+  const uint64_t stride = (uint64_t)gridDim.x * LARGE_THREADS;
+  for (uint64_t i = (uint64_t)blockIdx.x * LARGE_THREADS + threadIdx.x; i < n; i += stride) {
+    const uint64_t b = i >> s2, col = i & (cols - 1);
+    const float2* x = work + b * k + col;
+    float2 v[R1];
+#pragma unroll
+    for (int h = 0; h < R1; ++h) v[h] = x[(uint64_t)h * cols];
+#pragma unroll
+    for (int u = S1; u >= 1; --u) {
+      const int bit = S1 - u;
+#pragma unroll
+      for (int c = 0; c < R1; ++c) {
+        if (c & (1 << bit)) continue;
+        butterfly_adj(v[c], v[c | (1 << bit)], w[(1 << (u - 1)) - 1 + (c >> (bit + 1))]);
+      }
+    }
+    float2* y = out + b * (uint64_t)ld_out + col;
+#pragma unroll
+    for (int h = 0; h < R1; ++h)
+      store_stream(y + (uint64_t)h * cols, make_float2(v[h].x * scale, v[h].y * scale));
+  }
+}
+
+// The adjoint of large_top2_kernel: group B's stages s1..5 first, then the
+// exchange, then group A's stages 4..1.
+template <int S1>
+__global__ void __launch_bounds__(LARGE_THREADS)
+large_top2_inv_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
+                      uint64_t batch, uint32_t s2, const float2* __restrict__ tw, float scale) {
+  static_assert(S1 >= 5 && S1 <= 8, "two groups of at most four stages");
+  constexpr int RB = 1 << (S1 - 4);
+  constexpr int COLS = LARGE_THREADS / RB;
+  constexpr int H = 1 << S1;
+  constexpr int PAD_H = H + 1;
+  __shared__ float2 L[COLS * PAD_H];
+  __shared__ float2 T[H - 1];
+  for (int i = threadIdx.x; i < H - 1; i += LARGE_THREADS) T[i] = tw[i];
+  float2 w1[15];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) w1[i] = make_uniform(tw[i]);
+  __syncthreads();
+  const uint64_t cols = 1ULL << s2;
+  const uint64_t k = cols << S1;
+  const uint64_t tiles_per_signal = cols / COLS;
+  const uint64_t tiles = batch * tiles_per_signal;
+  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const uint64_t b = tile / tiles_per_signal;
+    const uint64_t col0 = (tile - b * tiles_per_signal) * COLS;
+    for (int unit = threadIdx.x; unit < COLS * 16; unit += LARGE_THREADS) {
+      const int col = unit % COLS, c = unit / COLS;
+      const float2* x = work + b * k + col0 + col;
+      float2 v[RB];
+#pragma unroll
+      for (int g = 0; g < RB; ++g) v[g] = x[(uint64_t)(c * RB + g) * cols];
+#pragma unroll
+      for (int u = S1; u >= 5; --u) {
+        const int bit = S1 - u;
+#pragma unroll
+        for (int g = 0; g < RB; ++g) {
+          if (g & (1 << bit)) continue;
+          const int h = c * RB + g;
+          butterfly_adj(v[g], v[g | (1 << bit)], T[(1 << (u - 1)) - 1 + (h >> (bit + 1))]);
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < RB; ++g) L[col * PAD_H + c * RB + g] = v[g];
+    }
+    __syncthreads();
+    {
+      const int col = threadIdx.x % COLS, g = threadIdx.x / COLS;
+      float2 v[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] = L[col * PAD_H + c * RB + g];
+#pragma unroll
+      for (int u = 4; u >= 1; --u) {
+        const int bit = 4 - u;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c & (1 << bit)) continue;
+          butterfly_adj(v[c], v[c | (1 << bit)], w1[(1 << (u - 1)) - 1 + (c >> (bit + 1))]);
+        }
+      }
+      float2* y = out + b * (uint64_t)ld_out + col0 + col;
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        store_stream(y + (uint64_t)(c * RB + g) * cols,
+                     make_float2(v[c].x * scale, v[c].y * scale));
+    }
+    __syncthreads();  // the next tile overwrites L
+  }
+}
+
+template <int S2, int SCHED>
+static hipError_t launch_large_sub_inv(float2* work, uint64_t units, uint32_t s1,
+                                       const float2* tw2, const uint16_t* src2,
+                                       hipStream_t stream) {
+  using Sh = FusedShape<S2, SCHED, 4>;
+  static OccupancyCache cache;
+  Occupancy occ;
+  if (!cache.get(&occ)) {
+    hipError_t e = query_occupancy((const void*)large_sub_inv_kernel<S2, SCHED>, Sh::THREADS,
+                                   Sh::LDS_BYTES, &occ);
+    if (e != hipSuccess) return e;
+    cache.put(occ);
+  }
+  const uint64_t chunk = 0x7fffffffULL;
+  for (uint64_t first = 0; first < units; first += chunk) {
+    const uint64_t n = units - first < chunk ? units - first : chunk;
+    hipLaunchKernelGGL((large_sub_inv_kernel<S2, SCHED>), dim3((unsigned)n), dim3(Sh::THREADS),
+                       Sh::LDS_BYTES, stream, work, first, units, s1, tw2, src2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_large_inverse(uint32_t s, const float2* coefs, int64_t ld_in, float2* out,
+                                int64_t ld_out, uint64_t batch, float2* work, const float2* tw,
+                                const uint16_t* src2, const uint32_t* src3,
+                                const uint16_t* dest3, float scale, hipStream_t stream) {
+  if (batch == 0) return hipSuccess;
+  if (s <= HIDFT_MAX_LOG2_K_DEVICE || s > HIDFT_MAX_LOG2_K_LARGE) return hipErrorInvalidValue;
+  const uint32_t s2 = large_split(s), s1 = s - s2;
+  const uint64_t k = 1ULL << s;
+  if (batch > (~0ULL >> (s + 1))) return hipErrorInvalidValue;
+  unsigned grid = 0;
+  hipError_t e = stream_grid(batch * k, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(large_unplace_kernel, dim3(grid), dim3(LARGE_THREADS), 0, stream, coefs,
+                     ld_in, work, batch, s, src3, dest3);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const float2* tw2 = tw + ((1u << s1) - 1);
+  const uint64_t units = batch << s1;
+  switch (s2) {
+    case 12: e = launch_large_sub_inv<12, SCHED_SHORT_LAST>(work, units, s1, tw2, src2, stream); break;
+    case 13: e = launch_large_sub_inv<13, SCHED_SHORT_LAST>(work, units, s1, tw2, src2, stream); break;
+    case 14: e = launch_large_sub_inv<14, SCHED_SHORT_LAST>(work, units, s1, tw2, src2, stream); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (s1 <= 4) {
+    if ((e = stream_grid(batch << s2, &grid)) != hipSuccess) return e;
+  } else if ((e = stream_grid(((batch << s2) >> (12 - s1)) * LARGE_THREADS, &grid)) !=
+             hipSuccess) {
+    return e;
+  }
+  switch (s1) {
+#define HIDFT_TOPI(S1)                                                                          \
+  case S1:                                                                                      \
+    hipLaunchKernelGGL(large_top_inv_kernel<S1>, dim3(grid), dim3(LARGE_THREADS), 0, stream,    \
+                       work, out, ld_out, batch, s2, tw, scale);                                \
+    break;
+#define HIDFT_TOPI2(S1)                                                                         \
+  case S1:                                                                                      \
+    hipLaunchKernelGGL(large_top2_inv_kernel<S1>, dim3(grid), dim3(LARGE_THREADS), 0, stream,   \
+                       work, out, ld_out, batch, s2, tw, scale);                                \
+    break;
+    HIDFT_TOPI(1) HIDFT_TOPI(2) HIDFT_TOPI(3) HIDFT_TOPI(4)
+    HIDFT_TOPI2(5) HIDFT_TOPI2(6) HIDFT_TOPI2(7) HIDFT_TOPI2(8)
+#undef HIDFT_TOPI
+#undef HIDFT_TOPI2
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Scratch of the allocation-free Shift-and-Sample entry point: the shifted
 // Hi-DFT outputs of a chunk of signals, [signal][shift][node], instead of a
 // caller's workspace.  In host code `scratch` names a host-side stand-in, not

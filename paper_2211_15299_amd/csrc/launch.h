@@ -67,6 +67,15 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
                         const uint16_t* src2, const uint32_t* src3, const uint16_t* dest3,
                         float scale, hipStream_t stream, uint64_t n_out = 0);
 
+// Inverse map of the same sizes: the adjoint of launch_large's passes in
+// reverse (coefficients in J's order -> workspace by the placement tables,
+// subtree inverses, the adjoint column stages), samples in ascending order
+// of I_r scaled by `scale`.  Plans that keep all 2^s outputs only.
+hipError_t launch_large_inverse(uint32_t s, const float2* coefs, int64_t ld_in, float2* out,
+                                int64_t ld_out, uint64_t batch, float2* work, const float2* tw,
+                                const uint16_t* src2, const uint32_t* src3,
+                                const uint16_t* dest3, float scale, hipStream_t stream);
+
 // Whether launch_fused has the variant (s, sched, prec, rho).
 bool fused_variant_exists(uint32_t s, int sched, int prec, int rho);
 

@@ -72,6 +72,8 @@ SIGNATURES = [
     ("hidft_tune_load", ctypes.c_int, [ctypes.c_char_p]),
     ("hidft_execute_plain", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
     ("hidft_execute_inverse", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u64, _vp]),
+    ("hidft_execute_inverse_ws", ctypes.c_int,
+     [_vp, _vp, _i64, _vp, _i64, _u64, _vp, ctypes.c_size_t, _vp]),
     ("hidft_group_create", ctypes.c_int, [_vp, _u64, _vp, _pp]),
     ("hidft_group_execute", ctypes.c_int, [_vp, _vp]),
     ("hidft_group_destroy", ctypes.c_int, [_vp]),
@@ -312,6 +314,11 @@ class Plan:
                     stream=None) -> None:
         _check(lib().hidft_execute_inverse(self.handle, d_coefs, ld_in, d_samples, ld_out, batch,
                                            _stream_handle(stream)))
+
+    def inverse_ws_ptr(self, d_coefs: int, ld_in: int, d_samples: int, ld_out: int, batch: int,
+                       d_work: int, work_bytes: int, stream=None) -> None:
+        _check(lib().hidft_execute_inverse_ws(self.handle, d_coefs, ld_in, d_samples, ld_out,
+                                              batch, d_work, work_bytes, _stream_handle(stream)))
 
     # -- execution on torch tensors
     def execute(self, samples, out=None, stream=None, plain: bool = False,

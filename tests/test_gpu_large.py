@@ -14,6 +14,9 @@ Checks, through the C ABI:
     workspace), in place, strided rows and a captured graph give the same
     bits;
   * the split twiddle table holds every twiddle rounded once from FP64;
+  * the inverse map (the adjoint passes in reverse) against the samples the
+    FP64 oracle synthesises from seeded coefficients, and forward after
+    inverse returns the coefficients;
   * the calls that need one signal in LDS refuse these plans.
 """
 import sys
@@ -177,8 +180,6 @@ def test_large_plans_refused_where_one_signal_must_fit():
         "HIDFT_ERR_UNSUPPORTED"
     assert status(lambda: plan.execute_ptr(x.data_ptr(), k, y.data_ptr(), k, 2, plain=True)) == \
         "HIDFT_ERR_UNSUPPORTED"
-    assert status(lambda: plan.inverse_ptr(x.data_ptr(), k, y.data_ptr(), k, 2)) == \
-        "HIDFT_ERR_UNSUPPORTED"
     assert status(lambda: native.Group([(plan, x.data_ptr(), k, y.data_ptr(), k, 2)])) == \
         "HIDFT_ERR_UNSUPPORTED"
     assert status(lambda: plan.autotune_ptr(x.data_ptr(), k, y.data_ptr(), k, 2, reps=1)) == \
@@ -198,4 +199,38 @@ def test_large_plans_refused_where_one_signal_must_fit():
     small = native.Plan(12, homogeneous_support(12, 10, rng).J.tolist())
     assert small.workspace_bytes(1000) == 0
     small.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("M,s", [(20, 15), (22, 17), (24, 20), (24, 22)])
+def test_large_inverse_against_oracle(M, s):
+    rng = rng_for(4107, s)
+    plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
+    k = plan.k
+    J = homogeneous_support(M, s, rng_for(4107, s)).J.tolist()
+    I = plan.samples().tolist()
+    c = complex_normal((2, k), rng).astype(np.complex64)
+    want = oracle.synthesize_samples_fft(M, J, c.astype(np.complex128), I)
+    xc = torch.from_numpy(c).cuda()
+    f = torch.full_like(xc, complex(np.nan, np.nan))
+    plan.inverse_ptr(xc.data_ptr(), k, f.data_ptr(), k, 2)
+    torch.cuda.synchronize()
+    got = f.cpu().numpy().astype(np.complex128)
+    err = oracle.rel_l2(got, want)
+    _say(f"large inverse: M={M} s={s}, every sample against the oracle, rel-L2 {np.max(err):.3e}")
+    assert np.max(err) <= TOL, err
+    # the caller's workspace gives the same bits; in place too
+    wb = plan.workspace_bytes(2)
+    work = torch.empty(wb // 8, dtype=torch.complex64, device="cuda")
+    g = torch.full_like(xc, complex(np.nan, np.nan))
+    plan.inverse_ws_ptr(xc.data_ptr(), k, g.data_ptr(), k, 2, work.data_ptr(), wb)
+    h = xc.clone()
+    plan.inverse_ws_ptr(h.data_ptr(), k, h.data_ptr(), k, 2, work.data_ptr(), wb)
+    torch.cuda.synchronize()
+    assert torch.equal(g, f) and torch.equal(h, f)
+    # forward after inverse: the coefficients back
+    back = plan.execute(f)
+    torch.cuda.synchronize()
+    rt = oracle.rel_l2(back.cpu().numpy().astype(np.complex128), c.astype(np.complex128))
+    assert np.max(rt) <= 2 * TOL, rt
     plan.close()
