@@ -731,9 +731,23 @@ def large_bench(native, torch, stream, steps=20):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+
+        def run_inv(i):  # coefficients -> samples, the adjoint passes
+            plan.inverse_ws_ptr(ys[i % sets].data_ptr(), k, xs[i % sets].data_ptr(), k, batch,
+                                work.data_ptr(), wb, stream)
+
+        run_inv(0)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(steps):
+            run_inv(i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_inv = e0.elapsed_time(e1) / steps
         out[f"k=2^{s}"] = {"batch": batch, "ms_per_launch": ms,
                            "transforms_per_s": batch / (ms * 1e-3),
-                           "GBps": batch * k * 16 / (ms * 1e-3) / 1e9}
+                           "GBps": batch * k * 16 / (ms * 1e-3) / 1e9,
+                           "inverse_ms_per_launch": ms_inv}
         plan.close()
         del xs, ys, work
         torch.cuda.empty_cache()
