@@ -1889,10 +1889,159 @@ sas_fused_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restric
   }
 }
 
+// The one-pass form, for 2^10 and 2^11 points, where the block's signal
+// slots hold all mu* shifted transforms of a signal at once (mu* <= SPB).
+// The form above keeps each thread's twiddles, gather positions and element
+// records in registers for the whole batch and a separate LDS row for the
+// node values: 172-180 registers and up to 59 KB of LDS per block, two
+// blocks per CU.  Here the tables are read per signal (they stay in the
+// caches), each slot's node values are held in registers across the last
+// barrier and then written over the transform area, and the coefficients go
+// to LDS right after the node values: 145-151 registers and
+// max(SPB * PADK, mu* n_nodes + k) slots of LDS, three blocks per CU.  The
+// arithmetic is the form above's, operation for operation, so the results
+// are the same bits.
+template <int T>
+struct RegOut {
+  const float2* tw;
+  const uint16_t* src;
+  float2* vals;  // the thread's R outputs, output c * T + tau in vals[c]
+  __device__ __forceinline__ float2 tw_at(int uni, int lane) const { return tw[uni + lane]; }
+  __device__ __forceinline__ int src_at(int uni, int lane) const { return src[uni + lane]; }
+  __device__ __forceinline__ void put(int uni, int, float2 x) const { vals[uni / T] = x; }
+};
+
+template <int S>
+constexpr bool sas_onepass_shape() { return S == 10 || S == 11; }
+
+template <int S, int MU>
+__global__ void __launch_bounds__(SasFused<S>::Sh::THREADS)
+sas_onepass_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ out,
+                   int64_t ld_out, uint64_t batch, uint32_t mu_star, uint32_t n_nodes,
+                   uint32_t k, const float2* __restrict__ tw,
+                   const uint16_t* __restrict__ src_node, float scale,
+                   const uint4* __restrict__ rec, const cplx64* __restrict__ inv) {
+  constexpr int SC = SasFused<S>::SC;
+  using Sh = typename SasFused<S>::Sh;
+  constexpr int R = Sh::R, T = Sh::T, THREADS = Sh::THREADS;
+  constexpr uint32_t K = 1u << S;
+  extern __shared__ float2 lds[];
+  float2* res = lds + mu_star * n_nodes;
+  const int tid = threadIdx.x;
+  const int slot = tid / T;  // shift j of the signal
+  const int tau = tid - slot * T;
+  const bool live = (uint32_t)slot < mu_star;
+  const MfmaOps<PREC_FP32> no_mfma;
+  ThreadState<S, SC, 4> no_state;  // the tables are read per signal
+  for (uint64_t b = blockIdx.x; b < batch; b += gridDim.x) {
+    float2 v[R];
+    if (live) {
+      const float2* x = in + b * (uint64_t)ld_in + (uint64_t)slot * K;
+#pragma unroll
+      for (int c = 0; c < R; ++c) v[c] = load_stream(x + c * T + tau);
+    } else {
+#pragma unroll
+      for (int c = 0; c < R; ++c) v[c] = make_float2(0.f, 0.f);
+    }
+    float2 vals[R];
+    const RegOut<T> mem{tw, src_node, vals};
+    transform_signal<S, SC, 4, PREC_FP32, false>(v, lds, slot, tau, live, mem, scale, no_state,
+                                                  no_mfma);
+    lds_barrier();  // every gather has read the transform area
+    if (live) {
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        if ((uint32_t)(c * T + tau) < n_nodes) lds[slot * n_nodes + c * T + tau] = vals[c];
+    }
+    lds_barrier();  // node values complete
+    // Leaf solves, element e: {node | caller position << 16, inverse-row
+    // offset, mu(v)}; mu(v) = 0 marks no element.
+    for (uint32_t e = tid; e < k; e += THREADS) {
+      const uint4 r = rec[e];
+      const uint32_t nv = r.x & 0xffffu;
+      const cplx64* m = inv + r.y;
+      double ar = 0.0, ai = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < MU; ++jj) {
+        if ((uint32_t)jj < r.z) {
+          const float2 q = lds[jj * n_nodes + nv];
+          const cplx64 w = m[jj];
+          ar = fma(w.x, (double)q.x, fma(-w.y, (double)q.y, ar));
+          ai = fma(w.x, (double)q.y, fma(w.y, (double)q.x, ai));
+        }
+      }
+      if (r.z != 0) res[r.x >> 16] = make_float2((float)ar, (float)ai);
+    }
+    lds_barrier();
+    float2* ob = out + b * (uint64_t)ld_out;
+    for (uint32_t t = tid; t < k; t += THREADS) store_stream(ob + t, res[t]);
+    lds_barrier();  // the next signal overwrites the LDS
+  }
+}
+
+template <int S>
+static bool sas_onepass_fits_s(uint32_t mu_star, uint32_t n_nodes, uint32_t k) {
+  if constexpr (!sas_onepass_shape<S>()) {
+    return false;
+  } else {
+    constexpr uint64_t SLOTS = SasFused<S>::TRANSFORM_SLOTS;
+    return mu_star <= (uint32_t)SasFused<S>::Sh::SPB && (uint64_t)mu_star * n_nodes <= SLOTS &&
+           (uint64_t)mu_star * n_nodes + k <= 2 * SLOTS;
+  }
+}
+
+template <int S, int MU>
+static hipError_t launch_sas_onepass_mu(const float2* in, int64_t ld_in, float2* out,
+                                        int64_t ld_out, uint64_t batch, uint32_t mu_star,
+                                        uint32_t n_nodes, uint32_t k, const float2* tw,
+                                        const uint16_t* src_node, float scale, const uint4* rec,
+                                        const cplx64* inv, hipStream_t stream) {
+  using Sh = typename SasFused<S>::Sh;
+  constexpr uint64_t SLOTS = SasFused<S>::TRANSFORM_SLOTS;
+  const uint64_t used = (uint64_t)mu_star * n_nodes + k;
+  const size_t lds = (size_t)(used > SLOTS ? used : SLOTS) * sizeof(float2);
+  const void* kernel = (const void*)sas_onepass_kernel<S, MU>;
+  static OccupancyCache cache;
+  Occupancy occ;
+  if (!cache.get(&occ)) {
+    hipError_t e = query_occupancy(kernel, Sh::THREADS, 2 * SLOTS * sizeof(float2), &occ);
+    if (e != hipSuccess) return e;
+    cache.put(occ);
+  }
+  int per_cu_lds = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_lds, kernel, Sh::THREADS,
+                                                              lds);
+  if (e != hipSuccess) return e;
+  uint64_t per_cu = per_cu_lds > 0 ? (uint64_t)per_cu_lds : (uint64_t)occ.per_cu;
+  uint64_t grid = per_cu * (uint64_t)occ.cus;
+  if (grid > batch) grid = batch;
+  hipLaunchKernelGGL((sas_onepass_kernel<S, MU>), dim3((unsigned)grid), dim3(Sh::THREADS), lds,
+                     stream, in, ld_in, out, ld_out, batch, mu_star, n_nodes, k, tw, src_node,
+                     scale, rec, inv);
+  return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_sas_onepass(const float2* in, int64_t ld_in, float2* out, int64_t ld_out,
+                                     uint64_t batch, uint32_t mu_star, uint32_t n_nodes,
+                                     uint32_t k, const float2* tw, const uint16_t* src_node,
+                                     float scale, const uint4* rec, const cplx64* inv,
+                                     hipStream_t stream) {
+  if (mu_star == 2)
+    return launch_sas_onepass_mu<S, 2>(in, ld_in, out, ld_out, batch, mu_star, n_nodes, k, tw,
+                                       src_node, scale, rec, inv, stream);
+  if (mu_star == 3)
+    return launch_sas_onepass_mu<S, 3>(in, ld_in, out, ld_out, batch, mu_star, n_nodes, k, tw,
+                                       src_node, scale, rec, inv, stream);
+  return launch_sas_onepass_mu<S, 4>(in, ld_in, out, ld_out, batch, mu_star, n_nodes, k, tw,
+                                     src_node, scale, rec, inv, stream);
+}
+
 template <int S>
 static bool sas_fused_fits_s(uint32_t mu_star, uint32_t n_nodes, uint32_t k) {
-  return k <= (uint32_t)(SAS_FUSED_EPT * SasFused<S>::Sh::THREADS) &&
-         SasFused<S>::lds_bytes(mu_star, n_nodes, k) <= SAS_FUSED_MAX_LDS;
+  return sas_onepass_fits_s<S>(mu_star, n_nodes, k) ||
+         (k <= (uint32_t)(SAS_FUSED_EPT * SasFused<S>::Sh::THREADS) &&
+          SasFused<S>::lds_bytes(mu_star, n_nodes, k) <= SAS_FUSED_MAX_LDS);
 }
 
 template <int S>
@@ -1901,6 +2050,9 @@ static hipError_t launch_sas_fused_s(const float2* in, int64_t ld_in, float2* ou
                                      uint32_t k, const float2* tw, const uint16_t* src_node,
                                      float scale, const uint4* rec, const cplx64* inv,
                                      hipStream_t stream) {
+  if (sas_onepass_fits_s<S>(mu_star, n_nodes, k))
+    return launch_sas_onepass<S>(in, ld_in, out, ld_out, batch, mu_star, n_nodes, k, tw, src_node,
+                                 scale, rec, inv, stream);
   using Sh = typename SasFused<S>::Sh;
   const size_t lds = SasFused<S>::lds_bytes(mu_star, n_nodes, k);
   static OccupancyCache cache;

@@ -314,6 +314,48 @@ def test_sas_one_kernel_form_at_every_size(s):
     two.close()
 
 
+@pytest.mark.parametrize("s,extra,drop", [(10, 1, 0.0), (10, 2, 0.0), (10, 2, 0.3), (10, 2, -1),
+                                           (11, 1, 0.0), (11, 1, 0.4)])
+def test_sas_one_pass_form_whole_sets(s, extra, drop):
+    """2^10 and 2^11 points with every shift of a signal in one block pass:
+    homogeneous sets of 2^(s+extra) elements (a random part of them, or, with
+    drop = -1, all but the quarter in the top residue class, mu* = 3) whose
+    top `extra` levels are left out of r, so that up to 2^extra elements share
+    a node (mu* = 2..4) and k reaches 4096, past the element count the
+    register-resident form takes.  Bit-identical to the two-launch form, and
+    recovers seeded coefficients."""
+    rng = rng_for(821, s * 10 + extra + int(drop * 10))
+    M = 16
+    levels = sorted(rng.choice(M - extra, size=s, replace=False).tolist()) + \
+        list(range(M - extra, M))
+    J = homogeneous_support(M, s + extra, rng, levels=levels).J.tolist()
+    if drop < 0:
+        J = [j for j in J if (j >> (M - 2)) != 3]
+    elif drop:
+        J = [j for j, d in zip(J, rng.random(len(J)) >= drop) if d]
+    r = levels[:s]
+    one = native.SASPlan(M, J, pivots=r)
+    two = native.SASPlan(M, J, pivots=r, two_pass=True)
+    assert 2 <= one.mu_max <= 1 << extra and one.workspace_bytes(6) == 0, \
+        (one.mu_max, one.n_nodes, one.k)
+    n, k = one.samples_per_signal, one.k
+    print(f"one pass: s={s} mu*={one.mu_max} k={k} nodes={one.n_nodes}", flush=True)
+    c = complex_normal((6, k), rng)
+    f = oracle.synthesize_samples_fft(M, J, c, one.samples().tolist())
+    x = torch.from_numpy(f.astype(np.complex64)).cuda()
+    y1 = torch.full((6, k), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda")
+    y2 = torch.full_like(y1, complex(np.nan, np.nan))
+    work = torch.empty(two.workspace_bytes(6) // 8, dtype=torch.complex64, device="cuda")
+    one.execute_ptr(x.data_ptr(), n, y1.data_ptr(), k, 6, 0)
+    two.execute_ptr(x.data_ptr(), n, y2.data_ptr(), k, 6, work.data_ptr())
+    torch.cuda.synchronize()
+    assert torch.equal(y1.view(torch.float32), y2.view(torch.float32))
+    err = oracle.rel_l2(y1.cpu().numpy().astype(np.complex128), c)
+    assert np.max(err) <= one.err_bound <= 1e-5, (s, np.max(err), one.err_bound)
+    one.close()
+    two.close()
+
+
 def test_sas_strided_rows_and_errors():
     rng = rng_for(814, 0)
     M = 14
