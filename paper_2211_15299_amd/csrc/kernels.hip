@@ -2322,13 +2322,25 @@ large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint
                                                     unused, no_mfma);
 }
 
-__global__ void __launch_bounds__(LARGE_THREADS)
+// Placement of chunk c (outputs t in [c * LARGE_CHUNK, ...)): src3[t] is the
+// output's index in the signal's workspace row (its subtree's run), dest3[t]
+// its slot in the chunk.  A whole chunk gives each thread LARGE_EPT outputs:
+// all of its table reads are issued first, then all of its row reads (through
+// a buffer descriptor, a 32-bit offset each), so that every thread keeps
+// LARGE_EPT reads in flight; the runs are short (about 16 outputs at s1 = 8).
+constexpr int LARGE_EPT = 16;
+constexpr int PLACE_THREADS = (int)(LARGE_CHUNK / LARGE_EPT);
+static_assert(PLACE_THREADS * LARGE_EPT == (int)LARGE_CHUNK && PLACE_THREADS <= 1024,
+              "whole chunks per block");
+
+__global__ void __launch_bounds__(PLACE_THREADS)
 large_place_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
                    uint64_t batch, uint32_t s, uint64_t n_out, const uint32_t* __restrict__ src3,
                    const uint16_t* __restrict__ dest3, float scale) {
   __shared__ float2 chunk[LARGE_CHUNK];
   const uint64_t k = 1ULL << s;
   const uint64_t chunks = (n_out + LARGE_CHUNK - 1) / LARGE_CHUNK;
+  const int tid = (int)threadIdx.x;
   for (uint64_t unit = blockIdx.x; unit < batch * chunks; unit += gridDim.x) {
     const uint64_t b = unit / chunks, c = unit - b * chunks;
     const uint32_t count = (uint32_t)(n_out - c * LARGE_CHUNK < LARGE_CHUNK
@@ -2337,13 +2349,30 @@ large_place_kernel(const float2* __restrict__ work, float2* __restrict__ out, in
     const float2* w = work + b * k;
     const uint32_t* s3 = src3 + c * LARGE_CHUNK;
     const uint16_t* d3 = dest3 + c * LARGE_CHUNK;
-    for (uint32_t e = threadIdx.x; e < count; e += LARGE_THREADS) {
-      const float2 x = w[s3[e]];
-      chunk[d3[e]] = make_float2(x.x * scale, x.y * scale);
+    if (count == LARGE_CHUNK) {
+      const __amdgpu_buffer_rsrc_t row = make_rsrc(w, (uint32_t)(k * sizeof(float2)));
+      uint32_t si[LARGE_EPT], di[LARGE_EPT];
+#pragma unroll
+      for (int i = 0; i < LARGE_EPT; ++i) {
+        si[i] = s3[tid + i * PLACE_THREADS];
+        di[i] = d3[tid + i * PLACE_THREADS];
+      }
+      float2 x[LARGE_EPT];
+#pragma unroll
+      for (int i = 0; i < LARGE_EPT; ++i)
+        x[i] = __builtin_bit_cast(
+            float2, __builtin_amdgcn_raw_buffer_load_b64(row, (int)(si[i] * sizeof(float2)), 0, 0));
+#pragma unroll
+      for (int i = 0; i < LARGE_EPT; ++i) chunk[di[i]] = make_float2(x[i].x * scale, x[i].y * scale);
+    } else {
+      for (uint32_t e = tid; e < count; e += PLACE_THREADS) {
+        const float2 x = w[s3[e]];
+        chunk[d3[e]] = make_float2(x.x * scale, x.y * scale);
+      }
     }
     __syncthreads();
     float2* o = out + b * (uint64_t)ld_out + c * LARGE_CHUNK;
-    for (uint32_t e = threadIdx.x; e < count; e += LARGE_THREADS) store_stream(o + e, chunk[e]);
+    for (uint32_t e = tid; e < count; e += PLACE_THREADS) store_stream(o + e, chunk[e]);
     __syncthreads();  // the next unit overwrites the chunk
   }
 }
@@ -2367,6 +2396,21 @@ static hipError_t stream_grid(uint64_t threads, unsigned* grid) {
   const uint64_t want = (threads + LARGE_THREADS - 1) / LARGE_THREADS;
   const uint64_t cap = (uint64_t)occ.per_cu * occ.cus;
   *grid = (unsigned)(want < cap ? want : cap);
+  return hipSuccess;
+}
+
+// Grid of a placement kernel: the blocks that are resident at once (by its
+// 32 KB of LDS), at most one per chunk.
+static hipError_t place_grid(const void* kernel, OccupancyCache& cache, uint64_t units,
+                             unsigned* grid) {
+  Occupancy occ;
+  if (!cache.get(&occ)) {
+    hipError_t e = query_occupancy(kernel, PLACE_THREADS, 0, &occ);
+    if (e != hipSuccess) return e;
+    cache.put(occ);
+  }
+  const uint64_t cap = (uint64_t)(occ.per_cu > 0 ? occ.per_cu : 1) * (uint64_t)occ.cus;
+  *grid = (unsigned)(units < cap ? units : cap);
   return hipSuccess;
 }
 
@@ -2440,8 +2484,11 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  if ((e = stream_grid(batch * k, &grid)) != hipSuccess) return e;
-  hipLaunchKernelGGL(large_place_kernel, dim3(grid), dim3(LARGE_THREADS), 0, stream, work, out,
+  static OccupancyCache place_cache;
+  if ((e = place_grid((const void*)large_place_kernel, place_cache,
+                      batch * ((n_out + LARGE_CHUNK - 1) / LARGE_CHUNK), &grid)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(large_place_kernel, dim3(grid), dim3(PLACE_THREADS), 0, stream, work, out,
                      ld_out, batch, s, n_out, src3, dest3, scale);
   return hipGetLastError();
 }
@@ -2456,22 +2503,33 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
 //  * columns^H: the adjoint of stages s1..1 per column, scaled by `scale`
 //    (1/N), stored as the samples in ascending order of I_r.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(LARGE_THREADS)
+__global__ void __launch_bounds__(PLACE_THREADS)
 large_unplace_kernel(const float2* __restrict__ coefs, int64_t ld_in, float2* __restrict__ work,
                      uint64_t batch, uint32_t s, const uint32_t* __restrict__ src3,
                      const uint16_t* __restrict__ dest3) {
   __shared__ float2 chunk[LARGE_CHUNK];
   const uint64_t k = 1ULL << s;
   const uint64_t chunks = k / LARGE_CHUNK;
+  const int tid = (int)threadIdx.x;
   for (uint64_t unit = blockIdx.x; unit < batch * chunks; unit += gridDim.x) {
     const uint64_t b = unit / chunks, c = unit - b * chunks;
     const float2* x = coefs + b * (uint64_t)ld_in + c * LARGE_CHUNK;
-    for (uint32_t e = threadIdx.x; e < LARGE_CHUNK; e += LARGE_THREADS) chunk[e] = load_stream(x + e);
-    __syncthreads();
-    float2* w = work + b * k;
     const uint32_t* s3 = src3 + c * LARGE_CHUNK;
     const uint16_t* d3 = dest3 + c * LARGE_CHUNK;
-    for (uint32_t e = threadIdx.x; e < LARGE_CHUNK; e += LARGE_THREADS) w[s3[e]] = chunk[d3[e]];
+    uint32_t si[LARGE_EPT], di[LARGE_EPT];
+#pragma unroll
+    for (int i = 0; i < LARGE_EPT; ++i) {
+      chunk[tid + i * PLACE_THREADS] = load_stream(x + tid + i * PLACE_THREADS);
+      si[i] = s3[tid + i * PLACE_THREADS];
+      di[i] = d3[tid + i * PLACE_THREADS];
+    }
+    __syncthreads();
+    const __amdgpu_buffer_rsrc_t row = make_rsrc(work + b * k, (uint32_t)(k * sizeof(float2)));
+#pragma unroll
+    for (int i = 0; i < LARGE_EPT; ++i)
+      __builtin_amdgcn_raw_buffer_store_b64(
+          __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, chunk[di[i]]), row,
+          (int)(si[i] * sizeof(float2)), 0, 0);
     __syncthreads();  // the next unit overwrites the chunk
   }
 }
@@ -2638,9 +2696,11 @@ hipError_t launch_large_inverse(uint32_t s, const float2* coefs, int64_t ld_in, 
   const uint64_t k = 1ULL << s;
   if (batch > (~0ULL >> (s + 1))) return hipErrorInvalidValue;
   unsigned grid = 0;
-  hipError_t e = stream_grid(batch * k, &grid);
+  static OccupancyCache unplace_cache;
+  hipError_t e = place_grid((const void*)large_unplace_kernel, unplace_cache,
+                            batch * (k / LARGE_CHUNK), &grid);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(large_unplace_kernel, dim3(grid), dim3(LARGE_THREADS), 0, stream, coefs,
+  hipLaunchKernelGGL(large_unplace_kernel, dim3(grid), dim3(PLACE_THREADS), 0, stream, coefs,
                      ld_in, work, batch, s, src3, dest3);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const float2* tw2 = tw + ((1u << s1) - 1);

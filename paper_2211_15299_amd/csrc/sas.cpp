@@ -501,7 +501,6 @@ hidft_status hidft_sas_execute(hidft_sas p, const void* d_samples, int64_t ld_in
     return run_direct(p, in, ld_in, coefs, ld_out, batch, s, fn);
   const uint64_t ks = 1ULL << p->core.s;
   const uint64_t mu = p->core.mu_max;
-  const uint64_t nn = p->core.node_slot.size();
   if (!d_work || (reinterpret_cast<uintptr_t>(d_work) & 7u))
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
                             "hidft_sas_execute: workspace missing or misaligned");
