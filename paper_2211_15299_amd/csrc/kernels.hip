@@ -1913,6 +1913,11 @@ struct RegOut {
 
 template <int S>
 constexpr bool sas_onepass_shape() { return S == 10 || S == 11; }
+// Elements per thread whose reads a solve batch issues together: 8 row
+// entries in flight per thread.
+template <int MU>
+constexpr int sas_solve_batch() { return MU <= 2 ? 4 : 2; }
+static_assert(4 <= SAS_INV_PAD, "a row read of mu* <= 4 entries ends in the padding");
 
 template <int S, int MU>
 __global__ void __launch_bounds__(SasFused<S>::Sh::THREADS)
@@ -1955,22 +1960,38 @@ sas_onepass_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restr
     }
     lds_barrier();  // node values complete
     // Leaf solves, element e: {node | caller position << 16, inverse-row
-    // offset, mu(v)}; mu(v) = 0 marks no element.
-    for (uint32_t e = tid; e < k; e += THREADS) {
-      const uint4 r = rec[e];
-      const uint32_t nv = r.x & 0xffffu;
-      const cplx64* m = inv + r.y;
-      double ar = 0.0, ai = 0.0;
+    // offset, mu(v)}; mu(v) = 0 marks no element.  B elements per thread at a
+    // time: their records, then all MU entries of their inverse rows (the
+    // table's zero padding keeps the rows' reads in bounds), are requested
+    // before any is used, so the two dependent cache round trips are paid
+    // once per batch.
+    constexpr int B = sas_solve_batch<MU>();
+    for (uint32_t e0 = tid; e0 < k; e0 += B * THREADS) {
+      uint4 r[B];
 #pragma unroll
-      for (int jj = 0; jj < MU; ++jj) {
-        if ((uint32_t)jj < r.z) {
-          const float2 q = lds[jj * n_nodes + nv];
-          const cplx64 w = m[jj];
-          ar = fma(w.x, (double)q.x, fma(-w.y, (double)q.y, ar));
-          ai = fma(w.x, (double)q.y, fma(w.y, (double)q.x, ai));
-        }
+      for (int i = 0; i < B; ++i) {
+        const uint32_t e = e0 + i * THREADS;
+        r[i] = e < k ? rec[e] : make_uint4(0u, 0u, 0u, 0u);
       }
-      if (r.z != 0) res[r.x >> 16] = make_float2((float)ar, (float)ai);
+      cplx64 w[B][MU];
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+#pragma unroll
+        for (int jj = 0; jj < MU; ++jj) w[i][jj] = inv[r[i].y + jj];
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const uint32_t nv = r[i].x & 0xffffu;
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < MU; ++jj) {
+          if ((uint32_t)jj < r[i].z) {
+            const float2 q = lds[jj * n_nodes + nv];
+            ar = fma(w[i][jj].x, (double)q.x, fma(-w[i][jj].y, (double)q.y, ar));
+            ai = fma(w[i][jj].x, (double)q.y, fma(w[i][jj].y, (double)q.x, ai));
+          }
+        }
+        if (r[i].z != 0) res[r[i].x >> 16] = make_float2((float)ar, (float)ai);
+      }
     }
     lds_barrier();
     float2* ob = out + b * (uint64_t)ld_out;
@@ -2050,9 +2071,11 @@ static hipError_t launch_sas_fused_s(const float2* in, int64_t ld_in, float2* ou
                                      uint32_t k, const float2* tw, const uint16_t* src_node,
                                      float scale, const uint4* rec, const cplx64* inv,
                                      hipStream_t stream) {
-  if (sas_onepass_fits_s<S>(mu_star, n_nodes, k))
-    return launch_sas_onepass<S>(in, ld_in, out, ld_out, batch, mu_star, n_nodes, k, tw, src_node,
-                                 scale, rec, inv, stream);
+  if constexpr (sas_onepass_shape<S>()) {
+    if (sas_onepass_fits_s<S>(mu_star, n_nodes, k))
+      return launch_sas_onepass<S>(in, ld_in, out, ld_out, batch, mu_star, n_nodes, k, tw,
+                                   src_node, scale, rec, inv, stream);
+  }
   using Sh = typename SasFused<S>::Sh;
   const size_t lds = SasFused<S>::lds_bytes(mu_star, n_nodes, k);
   static OccupancyCache cache;
