@@ -202,7 +202,7 @@ void large_tables(uint32_t s, const std::vector<uint32_t>& pos, std::vector<uint
                   std::vector<uint32_t>* src32) {
   const uint64_t k = 1ULL << s, n_out = pos.size();
   const uint32_t s2 = large_split(s), s1 = s - s2;
-  const uint64_t K2 = 1ULL << s2, C = LARGE_CHUNK;
+  const uint64_t K2 = 1ULL << s2, C = large_chunk(s);
   const uint64_t chunks = (n_out + C - 1) / C;
   std::vector<std::vector<uint32_t>> L(1ULL << s1);
   for (uint64_t t = 0; t < n_out; ++t) L[pos[t] >> s2].push_back(static_cast<uint32_t>(t));

@@ -51,7 +51,7 @@ uint64_t device_tw_index(uint32_t s, uint32_t u, uint64_t n);
 //                subtree's gather, so its kept outputs come first, ordered by
 //                t; the other entries are 0);
 //   src16[2^s, 2^s + n) and src32[0, n), n = n_out rounded up to whole
-//                LARGE_CHUNKs: per output chunk, the chunk's values subtree
+//                chunks of large_chunk(s): per output chunk, the chunk's values subtree
 //                by subtree: the workspace index j 2^s2 + i of L_j[i] (src32)
 //                and its place L_j[i] - chunk start (src16[2^s + ...]).
 void large_tables(uint32_t s, const std::vector<uint32_t>& pos, std::vector<uint16_t>* src16,

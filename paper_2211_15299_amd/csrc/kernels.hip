@@ -2194,7 +2194,7 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
 //    table layout, one table per subtree, and the fused kernel's per-signal
 //    code runs each subtree in place.  Its gather writes the subtree's
 //    outputs ordered by their index t in the caller's order of J.
-//  * pass 3: output chunk c (LARGE_CHUNK consecutive t, of the n_out <= 2^s
+//  * pass 3: output chunk c (large_chunk(s) consecutive t, of the n_out <= 2^s
 //    outputs kept; the last chunk may be partial) takes from each
 //    subtree the contiguous run of its outputs whose t fall in the chunk,
 //    puts each value at its place in LDS, scales by N/k and stores the chunk
@@ -2203,7 +2203,6 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
 // Every stage's arithmetic is the single-pass kernel's, in the same order.
 // ---------------------------------------------------------------------------
 constexpr int LARGE_THREADS = 256;
-static_assert(LARGE_CHUNK <= 65536 && (LARGE_CHUNK << 3) <= (1u << 15), "chunk in LDS, 16-bit places");
 
 template <int S1>
 __global__ void __launch_bounds__(LARGE_THREADS)
@@ -2350,40 +2349,47 @@ large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint
                                                     unused, no_mfma);
 }
 
-// Placement of chunk c (outputs t in [c * LARGE_CHUNK, ...)): src3[t] is the
+// Placement of chunk c (outputs t in [c * CHUNK, ...)): src3[t] is the
 // output's index in the signal's workspace row (its subtree's run), dest3[t]
 // its slot in the chunk.  A whole chunk gives each thread LARGE_EPT outputs:
 // all of its table reads are issued first, then all of its row reads (through
 // a buffer descriptor, a 32-bit offset each), so that every thread keeps
-// LARGE_EPT reads in flight; the runs are short (about 16 outputs at s1 = 8).
+// LARGE_EPT reads in flight.  A chunk takes one run from each of the 2^s1
+// subtrees, CHUNK / 2^s1 outputs on average: chunks of 4096 (256 threads,
+// 32 KB of LDS) up to s1 = 6, of 16384 (1024 threads, 128 KB) above.
 constexpr int LARGE_EPT = 16;
-constexpr int PLACE_THREADS = (int)(LARGE_CHUNK / LARGE_EPT);
-static_assert(PLACE_THREADS * LARGE_EPT == (int)LARGE_CHUNK && PLACE_THREADS <= 1024,
-              "whole chunks per block");
+template <int CHUNK>
+constexpr int place_threads() {
+  static_assert(CHUNK % LARGE_EPT == 0 && CHUNK / LARGE_EPT <= 1024 && CHUNK <= 65536 &&
+                    CHUNK * 8 <= 128 * 1024,
+                "whole chunks per block, 16-bit places, the chunk in LDS");
+  return CHUNK / LARGE_EPT;
+}
 
-__global__ void __launch_bounds__(PLACE_THREADS)
+template <int CHUNK>
+__global__ void __launch_bounds__(place_threads<CHUNK>())
 large_place_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
                    uint64_t batch, uint32_t s, uint64_t n_out, const uint32_t* __restrict__ src3,
                    const uint16_t* __restrict__ dest3, float scale) {
-  __shared__ float2 chunk[LARGE_CHUNK];
+  constexpr int THREADS = place_threads<CHUNK>();
+  __shared__ float2 chunk[CHUNK];
   const uint64_t k = 1ULL << s;
-  const uint64_t chunks = (n_out + LARGE_CHUNK - 1) / LARGE_CHUNK;
+  const uint64_t chunks = (n_out + CHUNK - 1) / CHUNK;
   const int tid = (int)threadIdx.x;
   for (uint64_t unit = blockIdx.x; unit < batch * chunks; unit += gridDim.x) {
     const uint64_t b = unit / chunks, c = unit - b * chunks;
-    const uint32_t count = (uint32_t)(n_out - c * LARGE_CHUNK < LARGE_CHUNK
-                                          ? n_out - c * LARGE_CHUNK
-                                          : LARGE_CHUNK);
+    const uint32_t count =
+        (uint32_t)(n_out - c * CHUNK < (uint64_t)CHUNK ? n_out - c * CHUNK : (uint64_t)CHUNK);
     const float2* w = work + b * k;
-    const uint32_t* s3 = src3 + c * LARGE_CHUNK;
-    const uint16_t* d3 = dest3 + c * LARGE_CHUNK;
-    if (count == LARGE_CHUNK) {
+    const uint32_t* s3 = src3 + c * CHUNK;
+    const uint16_t* d3 = dest3 + c * CHUNK;
+    if (count == (uint32_t)CHUNK) {
       const __amdgpu_buffer_rsrc_t row = make_rsrc(w, (uint32_t)(k * sizeof(float2)));
       uint32_t si[LARGE_EPT], di[LARGE_EPT];
 #pragma unroll
       for (int i = 0; i < LARGE_EPT; ++i) {
-        si[i] = s3[tid + i * PLACE_THREADS];
-        di[i] = d3[tid + i * PLACE_THREADS];
+        si[i] = s3[tid + i * THREADS];
+        di[i] = d3[tid + i * THREADS];
       }
       float2 x[LARGE_EPT];
 #pragma unroll
@@ -2393,19 +2399,20 @@ large_place_kernel(const float2* __restrict__ work, float2* __restrict__ out, in
 #pragma unroll
       for (int i = 0; i < LARGE_EPT; ++i) chunk[di[i]] = make_float2(x[i].x * scale, x[i].y * scale);
     } else {
-      for (uint32_t e = tid; e < count; e += PLACE_THREADS) {
+      for (uint32_t e = tid; e < count; e += THREADS) {
         const float2 x = w[s3[e]];
         chunk[d3[e]] = make_float2(x.x * scale, x.y * scale);
       }
     }
     __syncthreads();
-    float2* o = out + b * (uint64_t)ld_out + c * LARGE_CHUNK;
-    for (uint32_t e = tid; e < count; e += PLACE_THREADS) store_stream(o + e, chunk[e]);
+    float2* o = out + b * (uint64_t)ld_out + c * CHUNK;
+    for (uint32_t e = tid; e < count; e += THREADS) store_stream(o + e, chunk[e]);
     __syncthreads();  // the next unit overwrites the chunk
   }
 }
 
 uint32_t large_split(uint32_t s) { return s > 20 ? s - 8 : 12; }
+uint32_t large_chunk(uint32_t s) { return s - large_split(s) >= 7 ? 16384u : 4096u; }
 
 static hipError_t stream_grid(uint64_t threads, unsigned* grid) {
   static OccupancyCache cache;
@@ -2427,19 +2434,34 @@ static hipError_t stream_grid(uint64_t threads, unsigned* grid) {
   return hipSuccess;
 }
 
-// Grid of a placement kernel: the blocks that are resident at once (by its
-// 32 KB of LDS), at most one per chunk.
-static hipError_t place_grid(const void* kernel, OccupancyCache& cache, uint64_t units,
-                             unsigned* grid) {
+// Grid of a placement kernel: the blocks that are resident at once (by the
+// chunk's LDS), at most one per chunk.
+static hipError_t place_grid(const void* kernel, int threads, OccupancyCache& cache,
+                             uint64_t units, unsigned* grid) {
   Occupancy occ;
   if (!cache.get(&occ)) {
-    hipError_t e = query_occupancy(kernel, PLACE_THREADS, 0, &occ);
+    hipError_t e = query_occupancy(kernel, threads, 0, &occ);
     if (e != hipSuccess) return e;
     cache.put(occ);
   }
   const uint64_t cap = (uint64_t)(occ.per_cu > 0 ? occ.per_cu : 1) * (uint64_t)occ.cus;
   *grid = (unsigned)(units < cap ? units : cap);
   return hipSuccess;
+}
+
+template <int CHUNK>
+static hipError_t launch_place(const float2* work, float2* out, int64_t ld_out, uint64_t batch,
+                               uint32_t s, uint64_t n_out, const uint32_t* src3,
+                               const uint16_t* dest3, float scale, hipStream_t stream) {
+  constexpr int THREADS = place_threads<CHUNK>();
+  static OccupancyCache cache;
+  unsigned grid = 0;
+  hipError_t e = place_grid((const void*)large_place_kernel<CHUNK>, THREADS, cache,
+                            batch * ((n_out + CHUNK - 1) / CHUNK), &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(large_place_kernel<CHUNK>, dim3(grid), dim3(THREADS), 0, stream, work, out,
+                     ld_out, batch, s, n_out, src3, dest3, scale);
+  return hipGetLastError();
 }
 
 // The two-group column kernel: the blocks resident at once, at most one per
@@ -2528,18 +2550,14 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  static OccupancyCache place_cache;
-  if ((e = place_grid((const void*)large_place_kernel, place_cache,
-                      batch * ((n_out + LARGE_CHUNK - 1) / LARGE_CHUNK), &grid)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(large_place_kernel, dim3(grid), dim3(PLACE_THREADS), 0, stream, work, out,
-                     ld_out, batch, s, n_out, src3, dest3, scale);
-  return hipGetLastError();
+  if (large_chunk(s) == 4096)
+    return launch_place<4096>(work, out, ld_out, batch, s, n_out, src3, dest3, scale, stream);
+  return launch_place<16384>(work, out, ld_out, batch, s, n_out, src3, dest3, scale, stream);
 }
 
 // ---------------------------------------------------------------------------
 // Inverse map above 2^14 points: the adjoint of the three passes, in reverse.
-//  * placement^H: chunk c of the coefficients (LARGE_CHUNK consecutive t) is
+//  * placement^H: chunk c of the coefficients (large_chunk(s) consecutive t) is
 //    read in order into LDS and written to the subtree runs of the workspace
 //    (the forward placement's tables, read the other way);
 //  * subtrees^H: each subtree runs the inverse kernel's per-signal code
@@ -2547,25 +2565,27 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
 //  * columns^H: the adjoint of stages s1..1 per column, scaled by `scale`
 //    (1/N), stored as the samples in ascending order of I_r.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(PLACE_THREADS)
+template <int CHUNK>
+__global__ void __launch_bounds__(place_threads<CHUNK>())
 large_unplace_kernel(const float2* __restrict__ coefs, int64_t ld_in, float2* __restrict__ work,
                      uint64_t batch, uint32_t s, const uint32_t* __restrict__ src3,
                      const uint16_t* __restrict__ dest3) {
-  __shared__ float2 chunk[LARGE_CHUNK];
+  constexpr int THREADS = place_threads<CHUNK>();
+  __shared__ float2 chunk[CHUNK];
   const uint64_t k = 1ULL << s;
-  const uint64_t chunks = k / LARGE_CHUNK;
+  const uint64_t chunks = k / CHUNK;
   const int tid = (int)threadIdx.x;
   for (uint64_t unit = blockIdx.x; unit < batch * chunks; unit += gridDim.x) {
     const uint64_t b = unit / chunks, c = unit - b * chunks;
-    const float2* x = coefs + b * (uint64_t)ld_in + c * LARGE_CHUNK;
-    const uint32_t* s3 = src3 + c * LARGE_CHUNK;
-    const uint16_t* d3 = dest3 + c * LARGE_CHUNK;
+    const float2* x = coefs + b * (uint64_t)ld_in + c * CHUNK;
+    const uint32_t* s3 = src3 + c * CHUNK;
+    const uint16_t* d3 = dest3 + c * CHUNK;
     uint32_t si[LARGE_EPT], di[LARGE_EPT];
 #pragma unroll
     for (int i = 0; i < LARGE_EPT; ++i) {
-      chunk[tid + i * PLACE_THREADS] = load_stream(x + tid + i * PLACE_THREADS);
-      si[i] = s3[tid + i * PLACE_THREADS];
-      di[i] = d3[tid + i * PLACE_THREADS];
+      chunk[tid + i * THREADS] = load_stream(x + tid + i * THREADS);
+      si[i] = s3[tid + i * THREADS];
+      di[i] = d3[tid + i * THREADS];
     }
     __syncthreads();
     const __amdgpu_buffer_rsrc_t row = make_rsrc(work + b * k, (uint32_t)(k * sizeof(float2)));
@@ -2706,6 +2726,21 @@ large_top2_inv_kernel(const float2* __restrict__ work, float2* __restrict__ out,
   }
 }
 
+template <int CHUNK>
+static hipError_t launch_unplace(const float2* coefs, int64_t ld_in, float2* work, uint64_t batch,
+                                 uint32_t s, const uint32_t* src3, const uint16_t* dest3,
+                                 hipStream_t stream) {
+  constexpr int THREADS = place_threads<CHUNK>();
+  static OccupancyCache cache;
+  unsigned grid = 0;
+  hipError_t e = place_grid((const void*)large_unplace_kernel<CHUNK>, THREADS, cache,
+                            batch * ((1ULL << s) / CHUNK), &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(large_unplace_kernel<CHUNK>, dim3(grid), dim3(THREADS), 0, stream, coefs,
+                     ld_in, work, batch, s, src3, dest3);
+  return hipGetLastError();
+}
+
 template <int S2, int SCHED>
 static hipError_t launch_large_sub_inv(float2* work, uint64_t units, uint32_t s1,
                                        const float2* tw2, const uint16_t* src2,
@@ -2737,16 +2772,12 @@ hipError_t launch_large_inverse(uint32_t s, const float2* coefs, int64_t ld_in, 
   if (batch == 0) return hipSuccess;
   if (s <= HIDFT_MAX_LOG2_K_DEVICE || s > HIDFT_MAX_LOG2_K_LARGE) return hipErrorInvalidValue;
   const uint32_t s2 = large_split(s), s1 = s - s2;
-  const uint64_t k = 1ULL << s;
   if (batch > (~0ULL >> (s + 1))) return hipErrorInvalidValue;
   unsigned grid = 0;
-  static OccupancyCache unplace_cache;
-  hipError_t e = place_grid((const void*)large_unplace_kernel, unplace_cache,
-                            batch * (k / LARGE_CHUNK), &grid);
+  hipError_t e = large_chunk(s) == 4096
+                     ? launch_unplace<4096>(coefs, ld_in, work, batch, s, src3, dest3, stream)
+                     : launch_unplace<16384>(coefs, ld_in, work, batch, s, src3, dest3, stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(large_unplace_kernel, dim3(grid), dim3(PLACE_THREADS), 0, stream, coefs,
-                     ld_in, work, batch, s, src3, dest3);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   const float2* tw2 = tw + ((1u << s1) - 1);
   const uint64_t units = batch << s1;
   switch (s2) {

@@ -54,14 +54,17 @@ hipError_t launch_fused(uint32_t s, const float2* in, int64_t ld_in, float2* out
 // or out): the top s1 = s - large_split(s) stages per column, the remaining
 // s2 stages per subtree of 2^s2 points, whose gather (src2: 2^s2 16-bit LDS
 // positions per subtree) puts first each subtree's kept outputs ordered by
-// their output index t, then the placement of chunks of LARGE_CHUNK outputs
-// (src3: for each chunk, the workspace index of each of its values, in runs
-// per subtree; dest3: the value's place t - chunk start) scaled by `scale`.
+// their output index t, then the placement of chunks of large_chunk(s)
+// outputs (src3: for each chunk, the workspace index of each of its values,
+// in runs per subtree; dest3: the value's place t - chunk start) scaled by
+// `scale`.
 // n_out: outputs per signal (0 = 2^s); output row b holds n_out values.  The
 // tables come from large_tables.  tw holds the twiddles in the split layout
 // of device_tw_index.  in may equal out.
-constexpr uint32_t LARGE_CHUNK = 4096;
 uint32_t large_split(uint32_t s);
+// Outputs per placement chunk: 4096, or 16384 from s1 = 7 on, where a
+// chunk of 4096 would take runs of 32 or fewer outputs from each subtree.
+uint32_t large_chunk(uint32_t s);
 hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out,
                         int64_t ld_out, uint64_t batch, float2* work, const float2* tw,
                         const uint16_t* src2, const uint32_t* src3, const uint16_t* dest3,
