@@ -616,11 +616,13 @@ hidft_status hidft_execute_inverse_ws(hidft_plan plan, const void* d_coefs, int6
  * call); when that size is 0 d_work may be NULL.  It is 0 when mu* = 1 (the
  * Hi-DFT output is the answer) with 2^s <= 2^14 -- above, the Hi-DFT runs in
  * the passes of hidft_execute_ws and needs 2^s complex64 values per signal --
- * and when the plan runs as one kernel: for
- * 2^s <= 2^13, mu* = 2..4 and node values that fit in LDS beside the
- * transform, the shifted Hi-DFTs gather their node values into LDS and the
- * leaf solves read them there (bit-identical results, no workspace
- * traffic), unless the plan was created with HIDFT_SAS_TWO_PASS.  Inputs,
+ * and when the plan runs as one kernel: for 2^s <= 2^13 and mu* = 2..4,
+ * when the node values fit in LDS (at 2^10 and 2^11 points, with all mu*
+ * shifted transforms of a signal in one block, over the transform area;
+ * otherwise beside it, with at most 8 elements per thread), the shifted
+ * Hi-DFTs gather their node values into LDS and the leaf solves read them
+ * there (bit-identical results, no workspace traffic), unless the plan was
+ * created with HIDFT_SAS_TWO_PASS.  Inputs,
  * outputs and the workspace must not overlap (INVALID_ARGUMENT).
  * The leaf solves: each node's dual Vandermonde matrix is inverted once, in
  * FP64 on the device, at plan creation (the plan holds sum_v mu(v)^2
