@@ -8,8 +8,9 @@ Checks, through the C ABI:
     coefficients the samples were synthesised from (FP64 full-length inverse
     DFT read at I_r), and seeded positions of the same rows against the FP64
     oracle;
-  * a batch: every row on 64 seeded positions of its own against the oracle
-    and on the energy identity ||c||^2 = (N^2/k) ||f_I||^2 (Lemma 1);
+  * batches (k = 2^15, 2^19, 2^20): every row on up to 64 seeded positions
+    of its own against the oracle and on the energy identity
+    ||c||^2 = (N^2/k) ||f_I||^2 (Lemma 1);
   * hidft_execute (stream-ordered workspace), hidft_execute_ws (caller's
     workspace), in place, strided rows and a captured graph give the same
     bits;
@@ -82,9 +83,11 @@ def test_large_recovers_every_coefficient(M, s):
     plan.close()
 
 
-def test_large_batch_every_row():
-    M, s, batch = 18, 15, 96
-    rng = rng_for(4102, 0)
+@pytest.mark.parametrize("M,s,batch", [(18, 15, 96), (22, 19, 6), (22, 20, 3)])
+def test_large_batch_every_row(M, s, batch):
+    """Chunks of 4096 outputs (s = 15) and of 16384 (s = 19, 20: s1 = 7, 8),
+    the column pass in registers (s1 = 3) and in tiles (s1 = 7, 8)."""
+    rng = rng_for(4102, s)
     sup = homogeneous_support(M, s, rng)
     J = sup.J.tolist()
     plan = native.Plan(M, J)
@@ -95,8 +98,10 @@ def test_large_batch_every_row():
     y = plan.execute(x)
     torch.cuda.synchronize()
     got = y.cpu().numpy()
-    pe = positions_vs_oracle(M, J, I, f, got, 64, rng_for(4103, 0), group=16)
-    _say(f"large batch: {batch} rows on 64 positions each, rel-L2 max {np.max(pe):.3e}")
+    n_pos = min(64, (1 << 25) // k)  # the oracle's submatrix stays within 512 MB
+    pe = positions_vs_oracle(M, J, I, f, got, n_pos, rng_for(4103, s), group=16)
+    _say(f"large batch: s={s}, {batch} rows on {n_pos} positions each, "
+         f"rel-L2 max {np.max(pe):.3e}")
     assert np.max(pe) <= TOL
     en = _energy_rel(got, f, M, k)
     assert np.max(en) <= 2 * TOL, np.max(en)
