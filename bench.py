@@ -429,10 +429,13 @@ def serve_run(native, srv, sups, vecs, rate, seconds, seed):
     done = np.zeros(n, dtype=bool)
     idx_of_rank = np.zeros(n, dtype=np.int64)
     lat, bsz = [], []
-    state = {"id0": None, "rank": 0, "rejected": 0, "failed": 0, "lag": 0.0}
+    state = {"id0": None, "rank": 0, "rejected": 0, "failed": 0, "lag": 0.0,
+             "submit_s": 0.0, "poll_s": 0.0}
 
     def collect(wait_us=0):
+        tp = time.perf_counter()
         res = srv.poll(wait_us)
+        state["poll_s"] += time.perf_counter() - tp
         if len(res):
             r = (res["id"].astype(np.int64) - state["id0"])
             done[idx_of_rank[r]] = True
@@ -455,7 +458,9 @@ def serve_run(native, srv, sups, vecs, rate, seconds, seed):
             if not seg.all():
                 j = lo + int(np.argmin(seg)) + pool_n
         if j > i:
+            ts = time.perf_counter()
             ids, sts = srv.submit_many(recs[i:j])
+            state["submit_s"] += time.perf_counter() - ts
             acc = sts == 0
             if state["id0"] is None and acc.any():
                 state["id0"] = int(ids[acc][0])
@@ -482,7 +487,8 @@ def serve_run(native, srv, sups, vecs, rate, seconds, seed):
             "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "max": float(lat.max())},
             "batch_size_mean": float(bsz.mean()), "batches": int(st["batches"] - st0["batches"]),
-            "max_client_lag_us": state["lag"] * 1e6}
+            "max_client_lag_us": state["lag"] * 1e6,
+            "client_time_s": {"submit_many": state["submit_s"], "poll": state["poll_s"]}}
 
 
 def serve_bench(args, native, seconds=None):
@@ -511,7 +517,8 @@ def serve_bench(args, native, seconds=None):
         r = serve_run(native, srv, sups, vecs, rate, 2.0, 2 * 10 ** 6 + q)
         curve.append({k: r[k] for k in ("offered_per_s", "transforms_per_s", "completed",
                                         "rejected", "failed", "latency_us", "batch_size_mean",
-                                        "data_GBps", "max_client_lag_us")})
+                                        "data_GBps", "max_client_lag_us", "wall_s",
+                                        "client_time_s")})
         print(f"serve sweep: offered {rate:.0f}/s sustained {r['transforms_per_s']:.0f}/s "
               f"p50 {r['latency_us']['p50']:.1f} us p99 {r['latency_us']['p99']:.1f} us "
               f"batch {r['batch_size_mean']:.1f}", file=sys.stderr, flush=True)

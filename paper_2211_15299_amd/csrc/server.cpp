@@ -93,10 +93,15 @@ struct Slot {
 // before it blocks on the request queue.
 constexpr std::chrono::microseconds kSpinWindow{100};
 
+// Hash of a support for the plan cache: M, k and at most 64 entries of J
+// spread over it (the first and the last included), so that a lookup costs
+// O(1) here; find() compares the whole of J, which decides.
 uint64_t hash_support(uint32_t M, const uint64_t* J, uint64_t k) {
   uint64_t h = 0x9e3779b97f4a7c15ULL ^ (M * 0x100000001b3ULL) ^ k;
-  for (uint64_t i = 0; i < k; ++i) {
-    h ^= J[i] + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
+  const uint64_t n = k < 64 ? k : 64;
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint64_t j = J[n > 1 ? i * (k - 1) / (n - 1) : 0];
+    h ^= j + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
   }
   return h;
 }
@@ -150,8 +155,8 @@ struct hidft_server_s {
   void admit(Request&& r);
   void fail_request(const Request& r, hidft_status st);
   void release(PlanEntry* e);
-  hidft_status submit_one(uint32_t M, const uint64_t* J, uint64_t k, const void* in, void* out,
-                          uint64_t* id);
+  hidft_status submit_batch(const hidft_server_request* reqs, uint64_t n, uint64_t* ids,
+                            int32_t* statuses);
 };
 
 // The resident plan of (M, J), or null.  plan_mu held.
@@ -159,7 +164,8 @@ PlanEntry* hidft_server_s::find(uint32_t M, const uint64_t* J, uint64_t k, uint6
   auto range = plans.equal_range(h);
   for (auto it = range.first; it != range.second; ++it) {
     PlanEntry* e = it->second.get();
-    if (e->M == M && e->J.size() == k && std::equal(e->J.begin(), e->J.end(), J)) return e;
+    if (e->M == M && e->J.size() == k && std::memcmp(e->J.data(), J, k * sizeof(uint64_t)) == 0)
+      return e;
   }
   return nullptr;
 }
@@ -446,47 +452,82 @@ void hidft_server_s::loop() {
   }
 }
 
-hidft_status hidft_server_s::submit_one(uint32_t M, const uint64_t* J, uint64_t k,
-                                        const void* in, void* out, uint64_t* id) {
-  if (!J || !in || !out || !id)
-    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: NULL argument");
-  if (k == 0 || k > slot_points) {
-    n_rejected++;
-    return hidft::set_error(HIDFT_ERR_OUT_OF_MEMORY,
-                            "hidft_server_submit: request larger than a batch slot's memory");
+// Submits n requests.  Per request: the checks that need no lock, then the
+// plan lookups of all of them under one hold of plan_mu, the support checks
+// of those without a resident plan, the queueing of all of them under one
+// hold of mu (ids in submission order) and one wake-up of the scheduler.
+// statuses[i] and ids[i] (0 when refused) are set per request; the return
+// value is the status of the last refused request (HIDFT_OK if none), and
+// its message is the thread's last error.
+hidft_status hidft_server_s::submit_batch(const hidft_server_request* reqs, uint64_t n,
+                                          uint64_t* ids, int32_t* statuses) {
+  struct Prep {
+    Request r;
+    uint64_t h = 0;
+    int32_t st = HIDFT_OK;
+    bool to_plan = false;  // accepted without a resident plan
+    std::string err;
+  };
+  std::vector<Prep> prep(n);
+  const auto now = Clock::now();
+  for (uint64_t i = 0; i < n; ++i) {
+    const hidft_server_request& q = reqs[i];
+    Prep& p = prep[i];
+    ids[i] = 0;
+    if (!q.J || !q.host_samples || !q.host_coefs) {
+      p.st = HIDFT_ERR_INVALID_ARGUMENT;
+      p.err = "hidft_server_submit: NULL argument";
+      continue;
+    }
+    if (q.k == 0 || q.k > slot_points) {
+      n_rejected++;
+      p.st = HIDFT_ERR_OUT_OF_MEMORY;
+      p.err = "hidft_server_submit: request larger than a batch slot's memory";
+      continue;
+    }
+    if (hidft::plan_table_bytes(q.k) > cfg.plan_bytes) {
+      n_rejected++;
+      p.st = HIDFT_ERR_OUT_OF_MEMORY;
+      p.err = "hidft_server_submit: the plan alone exceeds the plan-cache budget";
+      continue;
+    }
+    p.r.M = q.log2_n;
+    p.r.host_in = static_cast<const float2*>(q.host_samples);
+    p.r.host_out = static_cast<float2*>(q.host_coefs);
+    p.r.k = q.k;
+    p.r.t_submit = now;
+    p.h = hash_support(q.log2_n, q.J, q.k);
   }
-  if (hidft::plan_table_bytes(k) > cfg.plan_bytes) {
-    n_rejected++;
-    return hidft::set_error(HIDFT_ERR_OUT_OF_MEMORY,
-                            "hidft_server_submit: the plan alone exceeds the plan-cache budget");
-  }
-  Request r;
-  r.M = M;
-  r.host_in = static_cast<const float2*>(in);
-  r.host_out = static_cast<float2*>(out);
-  r.k = k;
-  r.t_submit = Clock::now();
-  const uint64_t h = hash_support(M, J, k);
   {
     std::lock_guard<std::mutex> lk(plan_mu);
-    if (PlanEntry* e = find(M, J, k, h)) {
-      ++e->refs;
-      lru.splice(lru.begin(), lru, e->lru);
-      n_plan_hits++;
-      r.entry = e;
-      r.s = e->plan->core.s;
+    for (uint64_t i = 0; i < n; ++i) {
+      Prep& p = prep[i];
+      if (p.st != HIDFT_OK) continue;
+      if (PlanEntry* e = find(reqs[i].log2_n, reqs[i].J, reqs[i].k, p.h)) {
+        ++e->refs;
+        lru.splice(lru.begin(), lru, e->lru);
+        n_plan_hits++;
+        p.r.entry = e;
+        p.r.s = e->plan->core.s;
+      }
     }
   }
-  if (!r.entry) {
+  for (uint64_t i = 0; i < n; ++i) {
+    Prep& p = prep[i];
+    if (p.st != HIDFT_OK || p.r.entry) continue;
     // Not resident: validate now, so that support errors return here; the
     // planner creates the plan.
+    const uint32_t M = reqs[i].log2_n;
+    const uint64_t* J = reqs[i].J;
+    const uint64_t k = reqs[i].k;
     uint64_t mask = 0;
     std::string err;
     hidft_status st = hidft::analyze_core(M, J, k, &mask, &err);
     if (st == HIDFT_OK && (k & (k - 1)) != 0) {
       st = HIDFT_ERR_SIZE_NOT_POW2;
       err = "k is not a power of two";
-    } else if (st == HIDFT_OK && (uint32_t)__builtin_popcountll(mask) != (uint32_t)__builtin_ctzll(k)) {
+    } else if (st == HIDFT_OK &&
+               (uint32_t)__builtin_popcountll(mask) != (uint32_t)__builtin_ctzll(k)) {
       st = HIDFT_ERR_NOT_HOMOGENEOUS;
       err = "J is not homogeneous";
     } else if (st == HIDFT_OK && __builtin_ctzll(k) > (int)HIDFT_MAX_LOG2_K_DEVICE) {
@@ -495,49 +536,70 @@ hidft_status hidft_server_s::submit_one(uint32_t M, const uint64_t* J, uint64_t 
     }
     if (st != HIDFT_OK) {
       n_rejected++;
-      return hidft::set_error(st, "hidft_server_submit: " + err);
+      p.st = st;
+      p.err = "hidft_server_submit: " + err;
+      continue;
     }
-    r.J.assign(J, J + k);
+    p.r.J.assign(J, J + k);
   }
-  const bool resident = r.entry != nullptr;
-  PlanEntry* held = r.entry;
-  bool stopping = false;
+  bool any_resident = false, any_planned = false;
+  uint64_t accepted = 0;
+  std::vector<PlanEntry*> to_release;
   {
     std::lock_guard<std::mutex> lk(mu);
-    if (stop) {
-      stopping = true;
-    } else {
-      r.id = next_id++;
-      *id = r.id;
+    for (uint64_t i = 0; i < n; ++i) {
+      Prep& p = prep[i];
+      if (p.st != HIDFT_OK) continue;
+      if (stop) {
+        if (p.r.entry) to_release.push_back(p.r.entry);
+        p.r.entry = nullptr;
+        p.st = HIDFT_ERR_INVALID_ARGUMENT;
+        p.err = "hidft_server_submit: server stopping";
+        continue;
+      }
+      p.r.id = next_id++;
+      ids[i] = p.r.id;
       in_system++;
-      if (resident) {
-        pending.push_back(std::move(r));
+      ++accepted;
+      if (p.r.entry) {
+        pending.push_back(std::move(p.r));
         n_pending.fetch_add(1, std::memory_order_release);
+        any_resident = true;
+      } else {
+        p.to_plan = true;
+        any_planned = true;
       }
     }
   }
-  if (stopping) {
-    if (held) release(held);
-    return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: server stopping");
+  for (PlanEntry* e : to_release) release(e);
+  n_submitted += accepted;
+  if (any_resident) cv_work.notify_one();
+  if (any_planned) {
+    std::vector<Request> refused;
+    {
+      std::lock_guard<std::mutex> lk(plan_mu);
+      for (uint64_t i = 0; i < n; ++i) {
+        Prep& p = prep[i];
+        if (!p.to_plan) continue;
+        if (!planner_stop)
+          need_plan.push_back(std::move(p.r));
+        else
+          refused.push_back(std::move(p.r));
+      }
+    }
+    cv_plan.notify_one();
+    for (const Request& r : refused) fail_request(r, HIDFT_ERR_INVALID_ARGUMENT);
   }
-  n_submitted++;
-  if (resident) {
-    cv_work.notify_one();
-    return hidft::set_error(HIDFT_OK, "");
-  }
-  bool queued = false;
-  {
-    std::lock_guard<std::mutex> lk(plan_mu);
-    if (!planner_stop) {
-      need_plan.push_back(std::move(r));
-      queued = true;
+  hidft_status last = HIDFT_OK;
+  const std::string* msg = nullptr;
+  for (uint64_t i = 0; i < n; ++i) {
+    statuses[i] = prep[i].st;
+    if (prep[i].st != HIDFT_OK) {
+      last = (hidft_status)prep[i].st;
+      msg = &prep[i].err;
     }
   }
-  if (queued)
-    cv_plan.notify_one();
-  else
-    fail_request(r, HIDFT_ERR_INVALID_ARGUMENT);  // the server stopped meanwhile
-  return hidft::set_error(HIDFT_OK, "");
+  return hidft::set_error(last, msg ? *msg : std::string());
 }
 
 extern "C" {
@@ -606,7 +668,10 @@ hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* o
 hidft_status hidft_server_submit(hidft_server s, uint32_t log2_n, const uint64_t* J, uint64_t k,
                                  const void* host_samples, void* host_coefs, uint64_t* id) {
   if (!s) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: NULL server");
-  return s->submit_one(log2_n, J, k, host_samples, host_coefs, id);
+  if (!id) return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT, "hidft_server_submit: NULL argument");
+  const hidft_server_request q{log2_n, J, k, host_samples, host_coefs};
+  int32_t st = HIDFT_OK;
+  return s->submit_batch(&q, 1, id, &st);
 }
 
 hidft_status hidft_server_submit_many(hidft_server s, const hidft_server_request* reqs,
@@ -615,14 +680,9 @@ hidft_status hidft_server_submit_many(hidft_server s, const hidft_server_request
   if (!s || (n > 0 && (!reqs || !ids || !statuses)))
     return hidft::set_error(HIDFT_ERR_INVALID_ARGUMENT,
                             "hidft_server_submit_many: NULL argument");
+  if (n > 0) (void)s->submit_batch(reqs, n, ids, statuses);
   uint64_t acc = 0;
-  for (uint64_t i = 0; i < n; ++i) {
-    const hidft_server_request& q = reqs[i];
-    ids[i] = 0;
-    statuses[i] = (int32_t)s->submit_one(q.log2_n, q.J, q.k, q.host_samples, q.host_coefs,
-                                         &ids[i]);
-    acc += statuses[i] == HIDFT_OK;
-  }
+  for (uint64_t i = 0; i < n; ++i) acc += statuses[i] == HIDFT_OK;
   if (n_accepted) *n_accepted = acc;
   return hidft::set_error(HIDFT_OK, "");
 }

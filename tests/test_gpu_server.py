@@ -214,10 +214,24 @@ def test_server_submit_many():
     ids, sts = srv.submit_many(recs)
     assert sts[4] == 5 and ids[4] == 0               # HIDFT_ERR_NOT_HOMOGENEOUS
     assert all(sts[i] == 0 and ids[i] > 0 for i in range(9) if i != 4)
+    acc = [int(ids[i]) for i in range(9) if i != 4]
+    assert acc == sorted(acc) and len(set(acc)) == len(acc)  # ids in submission order
     srv.drain()
     for i, (M, J, f, o) in enumerate(keep):
         if i != 4:
             assert np.array_equal(o, _alone(M, J, f[None, :])), i
+    # the same burst again, every plan now resident, with a NULL support in it
+    for _, _, _, o in keep:
+        o[:] = np.nan
+    recs[7]["J"] = 0
+    ids2, sts2 = srv.submit_many(recs)
+    assert sts2[4] == 5 and sts2[7] == 1 and ids2[4] == 0 and ids2[7] == 0  # INVALID_ARGUMENT
+    assert all(sts2[i] == 0 and ids2[i] > max(acc) for i in range(9) if i not in (4, 7))
+    srv.drain()
+    for i, (M, J, f, o) in enumerate(keep):
+        if i not in (4, 7):
+            assert np.array_equal(o, _alone(M, J, f[None, :])), i
+    assert np.isnan(keep[7][3]).all()
     srv.close()
 
 
