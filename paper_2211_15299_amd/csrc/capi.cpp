@@ -367,7 +367,7 @@ void pack_instances(const std::vector<std::pair<uint32_t, GroupSlot>>& inst, uin
     }
     wide.swap(alt);
   }
-  spread_packs(&narrow, (size_t)max_grid * GROUP_NARROW_PER_BLOCK);
+  spread_packs(&narrow, (size_t)max_grid * GROUP_NARROW_SPREAD);
   const size_t blocks = std::max(wide.size(), narrow.size());
   out->grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(max_grid, blocks));
   out->n_wide = (uint32_t)wide.size();

@@ -107,7 +107,7 @@ struct GroupSchedule {
 // the smallest remaining packs (a block with a long first pack gets a short
 // second one); else largest first.
 //
-// Narrow packs: split likewise until there are GROUP_NARROW_PER_BLOCK per
+// Narrow packs: split likewise until there are GROUP_NARROW_SPREAD per
 // block of max_grid (or single instances), then scheduled by a longest-first
 // greedy: each pack, largest first, goes to the block with the least
 // estimated time so far (a block starts from its wide packs), and a block's

@@ -122,6 +122,9 @@ constexpr uint32_t GROUP_WIDE_MIN_S = 13;
 constexpr uint32_t GROUP_NARROW_PER_BLOCK = 4;
 // The host schedule's fixed cost of a pack, in points (its latency).
 constexpr uint64_t GROUP_PACK_COST_POINTS = 2048;
+// Narrow packs are split until there are this many per block of the grid:
+// fewer, fuller packs than lanes, since a pack has a latency floor.
+constexpr uint32_t GROUP_NARROW_SPREAD = 2;
 
 // Instances of size 2^s that one pack holds.
 int grouped_slots_per_pack(uint32_t s);

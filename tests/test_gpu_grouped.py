@@ -46,8 +46,8 @@ def _expected_packs(ks, grid):
     """Pack count of the host packer: k >= 2^13 in wide packs of
     1024 / 2^(s-4) slots, whose partial last round of the grid is split until
     it has a pack per block or every pack holds one instance; smaller sizes in
-    narrow packs of 256 / 2^max(s-4, 0) slots, split likewise up to one per
-    quarter block (4 per block of the grid)."""
+    narrow packs of 256 / 2^max(s-4, 0) slots, split likewise up to 2 per
+    block of the grid."""
     sizes = {}
     for k in ks:
         s = int(k).bit_length() - 1
@@ -59,7 +59,7 @@ def _expected_packs(ks, grid):
         (wide if s >= 13 else narrow).extend(min(per, n - i) for i in range(0, n, per))
     full = len(wide) // grid * grid
     n_wide = len(wide) if full in (0, len(wide)) else full + min(grid, sum(wide[full:]))
-    n_narrow = len(narrow) if len(narrow) >= 4 * grid else min(4 * grid, sum(narrow))
+    n_narrow = len(narrow) if len(narrow) >= 2 * grid else min(2 * grid, sum(narrow))
     return n_wide + n_narrow
 
 
@@ -167,7 +167,7 @@ def test_grouped_last_round_spreading(s, full_rounds, tail_packs, ragged):
     """The packer's edge cases, one plan with many rows each.  Wide packs
     (a round is one pack per block): a partial last round of single-instance
     packs (2^14 points, nothing to split), and a partial round of 2-instance
-    packs split to single ones.  Narrow packs (a round is one pack per quarter
+    packs split to single ones.  Narrow packs (a round is two packs per
     block): exactly one round (nothing to spread), fewer packs than a round
     (split until every instance has its own), and more than a round (kept
     full).  Pack count as the model says; every row bit-identical to
@@ -178,7 +178,7 @@ def test_grouped_last_round_spreading(s, full_rounds, tail_packs, ragged):
     plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
     k = plan.k
     per = (1024 >> (s - 4)) if s >= 13 else (256 >> max(s - 4, 0))  # instances per full pack
-    round_packs = cus if s >= 13 else 4 * cus
+    round_packs = cus if s >= 13 else 2 * cus
     batch = (full_rounds * round_packs + tail_packs) * per + ragged
     _say(f"case s={s} batch={batch} cus={cus}")
     x = torch.from_numpy(sample_values(M, k, batch, rng)).cuda()
