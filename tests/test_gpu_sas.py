@@ -352,6 +352,14 @@ def test_sas_one_pass_form_whole_sets(s, extra, drop):
     assert torch.equal(y1.view(torch.float32), y2.view(torch.float32))
     err = oracle.rel_l2(y1.cpu().numpy().astype(np.complex128), c)
     assert np.max(err) <= one.err_bound <= 1e-5, (s, np.max(err), one.err_bound)
+    # strided rows give the same bits, and nothing is written past k
+    xs = torch.zeros((6, n + 3), dtype=torch.complex64, device="cuda")
+    xs[:, :n] = x
+    ys = torch.full((6, k + 5), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda")
+    one.execute_ptr(xs.data_ptr(), n + 3, ys.data_ptr(), k + 5, 6, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(ys[:, :k].view(torch.float32), y1.view(torch.float32))
+    assert torch.isnan(ys[:, k:]).all()
     one.close()
     two.close()
 
