@@ -1254,9 +1254,12 @@ static_assert(NARROW_SUBBLOCKS == (int)GROUP_NARROW_PER_BLOCK, "sub-blocks per b
 constexpr int NARROW_LDS_SLOTS = GROUPED_LDS_SLOTS / NARROW_SUBBLOCKS;  // 2^12 + 2^8
 static_assert(NARROW_LDS_SLOTS >= (1 << 12) + (1 << 8), "a narrow pack's LDS");
 // After the transform areas: the sub-blocks' barrier counters (one word
-// each), in float2 slots.
+// each), then the descriptor of a one-instance launch, in float2 slots.
 constexpr int GROUPED_CTL_SLOTS = NARROW_SUBBLOCKS / 2;
-constexpr size_t GROUPED_LDS_BYTES = (size_t)(GROUPED_LDS_SLOTS + GROUPED_CTL_SLOTS) * sizeof(float2);
+constexpr int GROUPED_ONE_SLOTS = (int)((sizeof(GroupSlot) + sizeof(float2) - 1) / sizeof(float2));
+static_assert(alignof(GroupSlot) <= sizeof(float2), "descriptor alignment in LDS");
+constexpr size_t GROUPED_LDS_BYTES =
+    (size_t)(GROUPED_LDS_SLOTS + GROUPED_CTL_SLOTS + GROUPED_ONE_SLOTS) * sizeof(float2);
 
 // Pointers into LDS, typed so: the compiler then emits LDS instructions
 // through them also in a function that is not inlined into the kernel (a
@@ -1399,85 +1402,107 @@ __device__ __attribute__((noinline)) void grouped_pack(const GroupSlot* __restri
   }
 }
 
+// The whole block runs wide pack `code` (a GroupPack::log2_k) of n slots.
+__device__ __forceinline__ void run_wide_pack(uint32_t code, const GroupSlot* sl, int n,
+                                              lds_ptr<float2> L, int tid) {
+  // Sizes with two schedules (S > 4, 4 does not divide S) have a body for
+  // each; the others ignore the flag.
+  const int skip = (code & GROUP_SKIP_IDLE) != 0;
+  switch (code & ~GROUP_SKIP_IDLE) {
+    case 13:
+      grouped_pack<13, SCHED_SHORT_LAST, GROUPED_THREADS>(sl, n, L, skip, tid, BlockSync());
+      break;
+    case 13 | GROUP_SHORT_FIRST:
+      grouped_pack<13, SCHED_SHORT_FIRST, GROUPED_THREADS>(sl, n, L, skip, tid, BlockSync());
+      break;
+    case 14:
+      grouped_pack<14, SCHED_SHORT_LAST, GROUPED_THREADS>(sl, n, L, skip, tid, BlockSync());
+      break;
+    case 14 | GROUP_SHORT_FIRST:
+      grouped_pack<14, SCHED_SHORT_FIRST, GROUPED_THREADS>(sl, n, L, skip, tid, BlockSync());
+      break;
+    default:
+      break;
+  }
+}
+
+// A narrow sub-block (thread stid of NARROW_THREADS, barrier `sync`) runs
+// narrow pack `code` of n slots.
+__device__ __forceinline__ void run_narrow_pack(uint32_t code, const GroupSlot* sl, int n,
+                                                lds_ptr<float2> L, int stid, SubSync sync) {
+  const int skip = (code & GROUP_SKIP_IDLE) != 0;
+  switch (code & ~GROUP_SKIP_IDLE) {
+#define HIDFT_ONE(S)                                                                          \
+  case S:                                                                                     \
+  case S | GROUP_SHORT_FIRST:                                                                 \
+    grouped_pack<S, SCHED_SHORT_FIRST, NARROW_THREADS>(sl, n, L, skip, stid, sync);          \
+    break;
+#define HIDFT_TWO(S)                                                                          \
+  case S:                                                                                     \
+    grouped_pack<S, SCHED_SHORT_LAST, NARROW_THREADS>(sl, n, L, skip, stid, sync);           \
+    break;                                                                                    \
+  case S | GROUP_SHORT_FIRST:                                                                 \
+    grouped_pack<S, SCHED_SHORT_FIRST, NARROW_THREADS>(sl, n, L, skip, stid, sync);          \
+    break;
+    HIDFT_ONE(0) HIDFT_ONE(1) HIDFT_ONE(2) HIDFT_ONE(3) HIDFT_ONE(4) HIDFT_TWO(5)
+    HIDFT_TWO(6) HIDFT_TWO(7) HIDFT_ONE(8) HIDFT_TWO(9) HIDFT_TWO(10) HIDFT_TWO(11)
+    HIDFT_ONE(12)
+#undef HIDFT_ONE
+#undef HIDFT_TWO
+    default:
+      break;
+  }
+}
+
+// one_code != GROUP_NO_ONE: a launch of one block for a single instance,
+// whose descriptor `one` and pack code come with the arguments, so the
+// transform starts without reading the pack, slot and lane tables (three
+// dependent reads, over the host link when those tables sit in mapped host
+// memory as the server's do).  The descriptor is copied to LDS for the pack
+// body, which reads its slots through a pointer.
 __global__ void __launch_bounds__(GROUPED_THREADS)
 hidft_grouped_kernel(const GroupPack* __restrict__ packs, uint32_t n_wide, uint32_t n_narrow,
                      const GroupSlot* __restrict__ slots, const uint32_t* __restrict__ lane_end,
                      uint32_t* done_count, uint32_t count_base, uint32_t* done_flag,
-                     uint32_t seq) {
+                     uint32_t seq, GroupSlot one, uint32_t one_code) {
   extern __shared__ float2 lds[];
-  // Wide phase: whole-block packs, grid stride.
-  for (uint32_t p = blockIdx.x; p < n_wide; p += gridDim.x) {
-    const GroupPack pk = packs[p];
-    const GroupSlot* sl = slots + pk.first_slot;
-    // Sizes with two schedules (S > 4, 4 does not divide S) have a body for
-    // each; the others ignore the flag.
-    const int skip = (pk.log2_k & GROUP_SKIP_IDLE) != 0;
-    const int tid = threadIdx.x;
-    const lds_ptr<float2> L = to_lds(lds);
-    switch (pk.log2_k & ~GROUP_SKIP_IDLE) {
-      case 13:
-        grouped_pack<13, SCHED_SHORT_LAST, GROUPED_THREADS>(sl, (int)pk.n_slots, L, skip, tid,
-                                                            BlockSync());
-        break;
-      case 13 | GROUP_SHORT_FIRST:
-        grouped_pack<13, SCHED_SHORT_FIRST, GROUPED_THREADS>(sl, (int)pk.n_slots, L, skip, tid,
-                                                             BlockSync());
-        break;
-      case 14:
-        grouped_pack<14, SCHED_SHORT_LAST, GROUPED_THREADS>(sl, (int)pk.n_slots, L, skip, tid,
-                                                            BlockSync());
-        break;
-      case 14 | GROUP_SHORT_FIRST:
-        grouped_pack<14, SCHED_SHORT_FIRST, GROUPED_THREADS>(sl, (int)pk.n_slots, L, skip, tid,
-                                                             BlockSync());
-        break;
-      default:
-        break;
-    }
-    lds_barrier();  // the next pack overwrites the LDS
-  }
-  if (n_narrow > 0) {
-    // Narrow phase: four lanes, each with its own LDS quarter and barrier
-    // counter, and its packs [lane_end[lane - 1], lane_end[lane]).
-    const lds_ptr<uint32_t> ctl = to_lds(reinterpret_cast<uint32_t*>(lds + GROUPED_LDS_SLOTS));
-    const int sub = __builtin_amdgcn_readfirstlane(threadIdx.x / NARROW_THREADS);
-    const int stid = threadIdx.x % NARROW_THREADS;
-    const uint32_t lane = blockIdx.x * NARROW_SUBBLOCKS + sub;
-    const uint32_t begin = lane == 0 ? 0u : lane_end[lane - 1];
-    const uint32_t end = lane_end[lane];
+  const lds_ptr<uint32_t> ctl = to_lds(reinterpret_cast<uint32_t*>(lds + GROUPED_LDS_SLOTS));
+  if (one_code != GROUP_NO_ONE) {
+    GroupSlot* od = reinterpret_cast<GroupSlot*>(lds + GROUPED_LDS_SLOTS + GROUPED_CTL_SLOTS);
+    if (threadIdx.x == 0) *od = one;
     if (threadIdx.x < NARROW_SUBBLOCKS) ctl[threadIdx.x] = 0u;
     lds_barrier();
-    const SubSync sync{ctl + sub};
-    const lds_ptr<float2> L = to_lds(lds + sub * NARROW_LDS_SLOTS);
-    for (uint32_t q = begin; q < end; ++q) {
-      const GroupPack pk = packs[n_wide + q];
-      const GroupSlot* sl = slots + pk.first_slot;
-      const int skip = (pk.log2_k & GROUP_SKIP_IDLE) != 0;
-      switch (pk.log2_k & ~GROUP_SKIP_IDLE) {
-#define HIDFT_ONE(S)                                                                 \
-  case S:                                                                            \
-  case S | GROUP_SHORT_FIRST:                                                        \
-    grouped_pack<S, SCHED_SHORT_FIRST, NARROW_THREADS>(sl, (int)pk.n_slots, L, skip, \
-                                                       stid, sync);                  \
-    break;
-#define HIDFT_TWO(S)                                                                 \
-  case S:                                                                            \
-    grouped_pack<S, SCHED_SHORT_LAST, NARROW_THREADS>(sl, (int)pk.n_slots, L, skip,  \
-                                                      stid, sync);                   \
-    break;                                                                           \
-  case S | GROUP_SHORT_FIRST:                                                        \
-    grouped_pack<S, SCHED_SHORT_FIRST, NARROW_THREADS>(sl, (int)pk.n_slots, L, skip, \
-                                                       stid, sync);                  \
-    break;
-        HIDFT_ONE(0) HIDFT_ONE(1) HIDFT_ONE(2) HIDFT_ONE(3) HIDFT_ONE(4) HIDFT_TWO(5)
-        HIDFT_TWO(6) HIDFT_TWO(7) HIDFT_ONE(8) HIDFT_TWO(9) HIDFT_TWO(10) HIDFT_TWO(11)
-        HIDFT_ONE(12)
-#undef HIDFT_ONE
-#undef HIDFT_TWO
-        default:
-          break;
+    if ((one_code & 0xffu) >= GROUP_WIDE_MIN_S) {
+      run_wide_pack(one_code, od, 1, to_lds(lds), (int)threadIdx.x);
+    } else if (threadIdx.x < NARROW_THREADS) {
+      // the first sub-block (whole wavefronts) and its barrier counter
+      run_narrow_pack(one_code, od, 1, to_lds(lds), (int)threadIdx.x, SubSync{ctl});
+    }
+  } else {
+    // Wide phase: whole-block packs, grid stride.
+    for (uint32_t p = blockIdx.x; p < n_wide; p += gridDim.x) {
+      const GroupPack pk = packs[p];
+      run_wide_pack(pk.log2_k, slots + pk.first_slot, (int)pk.n_slots, to_lds(lds),
+                    (int)threadIdx.x);
+      lds_barrier();  // the next pack overwrites the LDS
+    }
+    if (n_narrow > 0) {
+      // Narrow phase: four lanes, each with its own LDS quarter and barrier
+      // counter, and its packs [lane_end[lane - 1], lane_end[lane]).
+      const int sub = __builtin_amdgcn_readfirstlane(threadIdx.x / NARROW_THREADS);
+      const int stid = threadIdx.x % NARROW_THREADS;
+      const uint32_t lane = blockIdx.x * NARROW_SUBBLOCKS + sub;
+      const uint32_t begin = lane == 0 ? 0u : lane_end[lane - 1];
+      const uint32_t end = lane_end[lane];
+      if (threadIdx.x < NARROW_SUBBLOCKS) ctl[threadIdx.x] = 0u;
+      lds_barrier();
+      const SubSync sync{ctl + sub};
+      const lds_ptr<float2> L = to_lds(lds + sub * NARROW_LDS_SLOTS);
+      for (uint32_t q = begin; q < end; ++q) {
+        const GroupPack pk = packs[n_wide + q];
+        run_narrow_pack(pk.log2_k, slots + pk.first_slot, (int)pk.n_slots, L, stid, sync);
+        sync.sync();  // the next pack overwrites this lane's LDS
       }
-      sync.sync();  // the next pack overwrites this lane's LDS
     }
   }
   if (done_flag != nullptr) {
@@ -1539,9 +1564,26 @@ hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_wide, uint32_t n_
   hipLaunchKernelGGL(hidft_grouped_kernel, dim3(grid), dim3(GROUPED_THREADS), GROUPED_LDS_BYTES,
                      stream, d_packs, n_wide, n_narrow, d_slots, d_lane_end,
                      done ? done->d_count : nullptr, done ? *done->count_base : 0u,
-                     done ? done->d_flag : nullptr, done ? done->seq : 0u);
+                     done ? done->d_flag : nullptr, done ? done->seq : 0u, GroupSlot{},
+                     GROUP_NO_ONE);
   e = hipGetLastError();
   if (e == hipSuccess && done) *done->count_base += grid;
+  return e;
+}
+
+hipError_t launch_grouped_one(const GroupSlot& one, uint32_t code, hipStream_t stream,
+                              const GroupDone* done) {
+  const uint32_t s = code & 0xffu;
+  if (s > HIDFT_MAX_LOG2_K_DEVICE || code == GROUP_NO_ONE) return hipErrorInvalidValue;
+  uint32_t max_grid = 0;
+  hipError_t e = grouped_grid(&max_grid);  // sets the kernel's LDS limit
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(hidft_grouped_kernel, dim3(1), dim3(GROUPED_THREADS), GROUPED_LDS_BYTES,
+                     stream, nullptr, 0u, 0u, nullptr, nullptr,
+                     done ? done->d_count : nullptr, done ? *done->count_base : 0u,
+                     done ? done->d_flag : nullptr, done ? done->seq : 0u, one, code);
+  e = hipGetLastError();
+  if (e == hipSuccess && done) *done->count_base += 1;
   return e;
 }
 

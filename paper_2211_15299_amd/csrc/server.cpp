@@ -329,6 +329,19 @@ void hidft_server_s::launch(Slot& sl) {
     off += r.k;
   }
   sl.points = off;
+  hipError_t e;
+  const hidft::GroupDone done{sl.d_count, &sl.count_base, sl.d_flag, ++sl.seq};
+  if (inst.size() == 1) {
+    // A single request (most batches at moderate load): its descriptor goes
+    // with the launch, and no table is staged.
+    if ((e = hidft::launch_grouped_one(inst[0].second, inst[0].first | hidft::GROUP_SKIP_IDLE,
+                                       sl.stream, &done)) != hipSuccess ||
+        (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) {
+      worker_error = (int32_t)HIDFT_ERR_DEVICE;
+    }
+    n_batches++;
+    return;
+  }
   hidft::GroupSchedule sch;
   hidft::pack_instances(inst, grid, false, false, &sch);
   // A batch is often a single request: let the empty slots' wavefronts idle.
@@ -339,8 +352,6 @@ void hidft_server_s::launch(Slot& sl) {
   std::memcpy(sl.h_up + packs_at, sch.packs.data(), sch.packs.size() * sizeof(hidft::GroupPack));
   std::memcpy(sl.h_up + slots_at, sch.slots.data(), sch.slots.size() * sizeof(hidft::GroupSlot));
   std::memcpy(sl.h_up + lanes_at, sch.lane_end.data(), sch.lane_end.size() * sizeof(uint32_t));
-  hipError_t e;
-  const hidft::GroupDone done{sl.d_count, &sl.count_base, sl.d_flag, ++sl.seq};
   if ((e = hidft::launch_grouped(reinterpret_cast<const hidft::GroupPack*>(sl.d_up + packs_at),
                                  sch.n_wide, sch.n_narrow(),
                                  reinterpret_cast<const hidft::GroupSlot*>(sl.d_up + slots_at),
