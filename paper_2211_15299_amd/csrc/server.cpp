@@ -93,6 +93,92 @@ struct Slot {
 // before it blocks on the request queue.
 constexpr std::chrono::microseconds kSpinWindow{100};
 
+// Host threads that share the scheduler's staging copies of a large batch
+// (samples into the mapped region, coefficients out of it): one host thread
+// copies about 17-20 GB/s, which bounds the server at about 10^6 requests/s
+// when each of them is copied by the scheduler alone.  run() hands the
+// copies out one request at a time, takes part itself and returns once all
+// are done.  A helper registers (busy) under the lock under which run()
+// publishes a generation, and run() waits for every helper to leave the
+// previous one before it publishes the next, so a late helper never takes a
+// copy of a finished generation.
+class CopyPool {
+ public:
+  struct Job {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  };
+  void start(unsigned n_threads) {
+    for (unsigned i = 0; i < n_threads; ++i) threads_.emplace_back([this] { work(); });
+  }
+  void stop() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : threads_) t.join();
+    threads_.clear();
+  }
+  void run(const Job* jobs, size_t n) {
+    while (busy_.load(std::memory_order_acquire) != 0) __builtin_ia32_pause();
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      jobs_ = jobs;
+      n_ = n;
+      next_.store(0, std::memory_order_relaxed);
+      done_.store(0, std::memory_order_relaxed);
+      ++gen_;
+    }
+    cv_.notify_all();
+    take(jobs, n);
+    while (done_.load(std::memory_order_acquire) < n) __builtin_ia32_pause();
+  }
+  bool empty() const { return threads_.empty(); }
+
+ private:
+  void take(const Job* jobs, size_t n) {
+    for (size_t i; (i = next_.fetch_add(1, std::memory_order_relaxed)) < n;) {
+      std::memcpy(jobs[i].dst, jobs[i].src, jobs[i].bytes);
+      done_.fetch_add(1, std::memory_order_release);
+    }
+  }
+  void work() {
+    uint64_t seen = 0;
+    for (;;) {
+      const Job* jobs;
+      size_t n;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        jobs = jobs_;
+        n = n_;
+        busy_.fetch_add(1, std::memory_order_relaxed);
+      }
+      take(jobs, n);
+      busy_.fetch_sub(1, std::memory_order_release);
+    }
+  }
+  std::vector<std::thread> threads_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+  const Job* jobs_ = nullptr;
+  size_t n_ = 0;
+  std::atomic<size_t> next_{0}, done_{0};
+  std::atomic<unsigned> busy_{0};
+};
+
+// Batches whose copies in one direction total at least this many bytes go
+// through the pool; smaller ones (single requests at moderate load) are
+// copied by the scheduler, with no hand-off latency.
+constexpr size_t kPoolCopyBytes = 1u << 20;
+constexpr unsigned kCopyHelpers = 3;
+
 // Hash of a support for the plan cache: M, k and at most 64 entries of J
 // spread over it (the first and the last included), so that a lookup costs
 // O(1) here; find() compares the whole of J, which decides.
@@ -138,6 +224,8 @@ struct hidft_server_s {
 
   std::vector<Slot> slots;
   std::thread worker, planner;
+  CopyPool copies;                   // helpers of the scheduler's host copies
+  std::vector<CopyPool::Job> jobs;   // the scheduler's copy list
   std::atomic<bool> planner_done{false};
 
   std::atomic<uint64_t> n_submitted{0}, n_completed{0}, n_rejected{0}, n_batches{0};
@@ -151,6 +239,7 @@ struct hidft_server_s {
   void plan_loop();
   void launch(Slot& sl);
   void retire(Slot& sl);
+  void copy_all(size_t bytes);
   PlanEntry* find(uint32_t M, const uint64_t* J, uint64_t k, uint64_t h);
   void admit(Request&& r);
   void fail_request(const Request& r, hidft_status st);
@@ -306,6 +395,15 @@ void hidft_server_s::plan_loop() {
   cv_work.notify_all();
 }
 
+// Runs the copies of `jobs` (`bytes` in all): through the pool when large.
+void hidft_server_s::copy_all(size_t bytes) {
+  if (bytes >= kPoolCopyBytes && jobs.size() > 1 && !copies.empty()) {
+    copies.run(jobs.data(), jobs.size());
+    return;
+  }
+  for (const CopyPool::Job& j : jobs) std::memcpy(j.dst, j.src, j.bytes);
+}
+
 // Stages the batch in `sl` and issues the grouped transform.
 void hidft_server_s::launch(Slot& sl) {
   std::vector<std::pair<uint32_t, hidft::GroupSlot>> inst;
@@ -315,10 +413,11 @@ void hidft_server_s::launch(Slot& sl) {
   float2* d_in = reinterpret_cast<float2*>(sl.d_up);
   float2* d_out = sl.d_out;
   float2* h_in = reinterpret_cast<float2*>(sl.h_up);
+  jobs.clear();
   for (size_t i = 0; i < sl.batch.size(); ++i) {
     const Request& r = sl.batch[i];
     sl.offsets[i] = off;
-    std::memcpy(h_in + off, r.host_in, r.k * sizeof(float2));
+    jobs.push_back({h_in + off, r.host_in, r.k * sizeof(float2)});
     hidft::GroupSlot d;
     d.in = d_in + off;
     d.out = d_out + off;
@@ -329,6 +428,7 @@ void hidft_server_s::launch(Slot& sl) {
     off += r.k;
   }
   sl.points = off;
+  copy_all(off * sizeof(float2));
   hipError_t e;
   const hidft::GroupDone done{sl.d_count, &sl.count_base, sl.d_flag, ++sl.seq};
   if (inst.size() == 1) {
@@ -367,11 +467,18 @@ void hidft_server_s::launch(Slot& sl) {
 void hidft_server_s::retire(Slot& sl) {
   const int32_t st = worker_error.load() ? worker_error.load() : (int32_t)HIDFT_OK;
   const auto now = Clock::now();
+  if (st == HIDFT_OK) {
+    jobs.clear();
+    for (size_t i = 0; i < sl.batch.size(); ++i) {
+      const Request& r = sl.batch[i];
+      jobs.push_back({r.host_out, sl.h_out + sl.offsets[i], r.k * sizeof(float2)});
+    }
+    copy_all(sl.points * sizeof(float2));
+  }
   std::vector<hidft_server_result> done;
   done.reserve(sl.batch.size());
   for (size_t i = 0; i < sl.batch.size(); ++i) {
     const Request& r = sl.batch[i];
-    if (st == HIDFT_OK) std::memcpy(r.host_out, sl.h_out + sl.offsets[i], r.k * sizeof(float2));
     hidft_server_result res;
     res.id = r.id;
     res.status = st;
@@ -666,6 +773,7 @@ hidft_status hidft_server_create(const hidft_server_config* cfg, hidft_server* o
   for (Slot& sl : sv->slots) *sl.h_flag = 0;  // no batch has completed
   hidft_server s = sv.release();
   try {
+    s->copies.start(kCopyHelpers);
     s->planner = std::thread([s] { s->plan_loop(); });
     s->worker = std::thread([s] { s->loop(); });
   } catch (...) {
@@ -766,6 +874,7 @@ hidft_status hidft_server_destroy(hidft_server s) {
   s->planner_done.store(true, std::memory_order_release);
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  s->copies.stop();
   for (Slot& sl : s->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
     if (sl.done) (void)hipEventDestroy(sl.done);

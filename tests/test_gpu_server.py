@@ -235,6 +235,46 @@ def test_server_submit_many():
     srv.close()
 
 
+def test_server_large_batches_through_copy_helpers():
+    """Bursts large enough that a batch's copies (samples in, coefficients
+    out) pass the 1 MB at which the scheduler shares them with its helper
+    threads: 3 bursts of 240 requests over 8 supports of 2^11..2^13 points,
+    one submit_many each, batches of up to 512.  Every result equals the
+    request run alone, bit for bit."""
+    rng = rng_for(9, 99)
+    sups = []
+    for i, s in enumerate([11, 12, 13, 11, 12, 13, 12, 13]):
+        M = int(rng.integers(s + 2, 23))
+        sups.append((M, np.ascontiguousarray(homogeneous_support(M, s, rng_for(9, 100 + i)).J,
+                                             dtype=np.uint64)))
+    srv = native.Server(data_bytes=256 << 20, plan_bytes=64 << 20, slots=2, max_batch=512)
+    ref_of = {}
+    for burst in range(3):
+        recs = np.zeros(240, dtype=native.REQUEST_DTYPE)
+        keep = []
+        for i in range(240):
+            M, J = sups[(i + burst) % len(sups)]
+            f = sample_values(M, len(J), 1, rng)[0]
+            o = np.full(len(J), np.nan, dtype=np.complex64)
+            keep.append((M, J, f, o))
+            recs[i] = (M, J.ctypes.data, len(J), f.ctypes.data, o.ctypes.data)
+        ids, sts = srv.submit_many(recs)
+        assert (sts == 0).all() and (ids > 0).all()
+        srv.drain()
+        st = srv.stats()
+        _say(f"burst {burst}: {st['batches']} batches so far")
+        for i, (M, J, f, o) in enumerate(keep):
+            key = (M, J.ctypes.data)
+            if key not in ref_of:
+                ref_of[key] = native.Plan(M, J.tolist())
+            plan = ref_of[key]
+            want = plan.execute(torch.from_numpy(f[None, :]).cuda())[0].cpu().numpy()
+            assert np.array_equal(o, want), (burst, i)
+    for plan in ref_of.values():
+        plan.close()
+    srv.close()
+
+
 def test_server_concurrent_clients():
     sups = _supports(16, cfg=7)
     srv = native.Server(data_bytes=32 << 20, plan_bytes=64 << 20, slots=2, max_batch=64)
