@@ -235,6 +235,35 @@ def test_server_submit_many():
     srv.close()
 
 
+@pytest.mark.parametrize("s", [0, 5, 9, 12, 13, 14])
+def test_server_single_request_batches(s):
+    """A batch of one request runs as one block with its descriptor passed
+    with the launch (no table read): narrow sizes on the first quarter block,
+    2^13 and 2^14 points on the whole block.  Each request is drained before
+    the next, so every batch holds one; each equals the request alone, bit
+    for bit, and the FP64 oracle."""
+    rng = rng_for(9, 300 + s)
+    M = s + 6
+    J = np.ascontiguousarray(homogeneous_support(M, s, rng).J, dtype=np.uint64)
+    srv = native.Server(data_bytes=8 << 20, plan_bytes=8 << 20, slots=2, max_batch=8)
+    plan = native.Plan(M, J.tolist())
+    I = plan.samples().tolist()
+    for rep in range(3):
+        f = sample_values(M, len(J), 1, rng)
+        o = np.full(len(J), np.nan, dtype=np.complex64)
+        srv.submit(M, J, f[0], o)
+        srv.drain()
+        res = srv.poll()
+        assert len(res) == 1 and res["status"][0] == 0 and res["batch_size"][0] == 1
+        want = plan.execute(torch.from_numpy(f).cuda())[0].cpu().numpy()
+        assert np.array_equal(o, want), (s, rep)
+        ref = oracle.coefficients(M, J.tolist(), f.astype(np.complex128)) if s <= 9 else None
+        if ref is not None:
+            assert np.max(oracle.rel_l2(o[None, :].astype(np.complex128), ref)) <= 1e-5
+    plan.close()
+    srv.close()
+
+
 def test_server_large_batches_through_copy_helpers():
     """Bursts large enough that a batch's copies (samples in, coefficients
     out) pass the 1 MB at which the scheduler shares them with its helper
