@@ -200,6 +200,15 @@ def test_large_plans_refused_where_one_signal_must_fit():
                                               work.data_ptr() + 4, wb)) == "HIDFT_ERR_INVALID_ARGUMENT"
     assert status(lambda: plan.execute_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, 2,
                                               y.data_ptr(), wb)) == "HIDFT_ERR_INVALID_ARGUMENT"
+    # the inverse map's workspace is checked the same way
+    assert status(lambda: plan.inverse_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, 2,
+                                              work.data_ptr(), wb - 8)) == "HIDFT_ERR_INVALID_ARGUMENT"
+    assert status(lambda: plan.inverse_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, 2, 0, wb)) == \
+        "HIDFT_ERR_INVALID_ARGUMENT"
+    assert status(lambda: plan.inverse_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, 2,
+                                              work.data_ptr() + 4, wb)) == "HIDFT_ERR_INVALID_ARGUMENT"
+    assert status(lambda: plan.inverse_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, 2,
+                                              x.data_ptr(), wb)) == "HIDFT_ERR_INVALID_ARGUMENT"
     # the single-pass sizes need no workspace
     small = native.Plan(12, homogeneous_support(12, 10, rng).J.tolist())
     assert small.workspace_bytes(1000) == 0
