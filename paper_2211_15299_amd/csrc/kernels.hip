@@ -1454,8 +1454,8 @@ __device__ __forceinline__ void run_narrow_pack(uint32_t code, const GroupSlot* 
   }
 }
 
-// one_code != GROUP_NO_ONE: a launch of one block for a single instance,
-// whose descriptor `one` and pack code come with the arguments, so the
+// n_few > 0: a launch of n_few blocks for as many instances, block b taking
+// instance b, whose descriptor and pack code come with the arguments, so the
 // transform starts without reading the pack, slot and lane tables (three
 // dependent reads, over the host link when those tables sit in mapped host
 // memory as the server's do).  The descriptor is copied to LDS for the pack
@@ -1464,19 +1464,21 @@ __global__ void __launch_bounds__(GROUPED_THREADS)
 hidft_grouped_kernel(const GroupPack* __restrict__ packs, uint32_t n_wide, uint32_t n_narrow,
                      const GroupSlot* __restrict__ slots, const uint32_t* __restrict__ lane_end,
                      uint32_t* done_count, uint32_t count_base, uint32_t* done_flag,
-                     uint32_t seq, GroupSlot one, uint32_t one_code) {
+                     uint32_t seq, GroupFew few, uint32_t n_few) {
   extern __shared__ float2 lds[];
   const lds_ptr<uint32_t> ctl = to_lds(reinterpret_cast<uint32_t*>(lds + GROUPED_LDS_SLOTS));
-  if (one_code != GROUP_NO_ONE) {
+  if (n_few > 0) {
+    const uint32_t b = blockIdx.x;  // < n_few: the launch has n_few blocks
+    const uint32_t code = few.code[b];
     GroupSlot* od = reinterpret_cast<GroupSlot*>(lds + GROUPED_LDS_SLOTS + GROUPED_CTL_SLOTS);
-    if (threadIdx.x == 0) *od = one;
+    if (threadIdx.x == 0) *od = few.slot[b];
     if (threadIdx.x < NARROW_SUBBLOCKS) ctl[threadIdx.x] = 0u;
     lds_barrier();
-    if ((one_code & 0xffu) >= GROUP_WIDE_MIN_S) {
-      run_wide_pack(one_code, od, 1, to_lds(lds), (int)threadIdx.x);
+    if ((code & 0xffu) >= GROUP_WIDE_MIN_S) {
+      run_wide_pack(code, od, 1, to_lds(lds), (int)threadIdx.x);
     } else if (threadIdx.x < NARROW_THREADS) {
       // the first sub-block (whole wavefronts) and its barrier counter
-      run_narrow_pack(one_code, od, 1, to_lds(lds), (int)threadIdx.x, SubSync{ctl});
+      run_narrow_pack(code, od, 1, to_lds(lds), (int)threadIdx.x, SubSync{ctl});
     }
   } else {
     // Wide phase: whole-block packs, grid stride.
@@ -1564,26 +1566,26 @@ hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_wide, uint32_t n_
   hipLaunchKernelGGL(hidft_grouped_kernel, dim3(grid), dim3(GROUPED_THREADS), GROUPED_LDS_BYTES,
                      stream, d_packs, n_wide, n_narrow, d_slots, d_lane_end,
                      done ? done->d_count : nullptr, done ? *done->count_base : 0u,
-                     done ? done->d_flag : nullptr, done ? done->seq : 0u, GroupSlot{},
-                     GROUP_NO_ONE);
+                     done ? done->d_flag : nullptr, done ? done->seq : 0u, GroupFew{}, 0u);
   e = hipGetLastError();
   if (e == hipSuccess && done) *done->count_base += grid;
   return e;
 }
 
-hipError_t launch_grouped_one(const GroupSlot& one, uint32_t code, hipStream_t stream,
+hipError_t launch_grouped_few(const GroupFew& few, uint32_t n, hipStream_t stream,
                               const GroupDone* done) {
-  const uint32_t s = code & 0xffu;
-  if (s > HIDFT_MAX_LOG2_K_DEVICE || code == GROUP_NO_ONE) return hipErrorInvalidValue;
+  if (n == 0 || n > GROUP_FEW_MAX) return hipErrorInvalidValue;
+  for (uint32_t i = 0; i < n; ++i)
+    if ((few.code[i] & 0xffu) > HIDFT_MAX_LOG2_K_DEVICE) return hipErrorInvalidValue;
   uint32_t max_grid = 0;
   hipError_t e = grouped_grid(&max_grid);  // sets the kernel's LDS limit
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(hidft_grouped_kernel, dim3(1), dim3(GROUPED_THREADS), GROUPED_LDS_BYTES,
+  hipLaunchKernelGGL(hidft_grouped_kernel, dim3(n), dim3(GROUPED_THREADS), GROUPED_LDS_BYTES,
                      stream, nullptr, 0u, 0u, nullptr, nullptr,
                      done ? done->d_count : nullptr, done ? *done->count_base : 0u,
-                     done ? done->d_flag : nullptr, done ? done->seq : 0u, one, code);
+                     done ? done->d_flag : nullptr, done ? done->seq : 0u, few, n);
   e = hipGetLastError();
-  if (e == hipSuccess && done) *done->count_base += 1;
+  if (e == hipSuccess && done) *done->count_base += n;
   return e;
 }
 

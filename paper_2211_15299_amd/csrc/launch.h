@@ -152,11 +152,15 @@ struct GroupDone {
 hipError_t launch_grouped(const GroupPack* d_packs, uint32_t n_wide, uint32_t n_narrow,
                           const GroupSlot* d_slots, const uint32_t* d_lane_end, uint32_t grid,
                           hipStream_t stream, const GroupDone* done = nullptr);
-// The same kernel for a single instance: one block, the descriptor and the
-// pack code (a GroupPack::log2_k, flags included) passed by value, so no
-// table is read before the transform.
-constexpr uint32_t GROUP_NO_ONE = 0xffffffffu;
-hipError_t launch_grouped_one(const GroupSlot& one, uint32_t code, hipStream_t stream,
+// The same kernel for a few instances, one block each: their descriptors
+// and pack codes (a GroupPack::log2_k, flags included) passed by value, so
+// no table is read before the transforms.
+constexpr uint32_t GROUP_FEW_MAX = 4;
+struct GroupFew {
+  GroupSlot slot[GROUP_FEW_MAX];
+  uint32_t code[GROUP_FEW_MAX];
+};
+hipError_t launch_grouped_few(const GroupFew& few, uint32_t n, hipStream_t stream,
                               const GroupDone* done = nullptr);
 
 // Largest node (number of aliased coefficients) the leaf solves handle.

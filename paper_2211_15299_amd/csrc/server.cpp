@@ -431,11 +431,16 @@ void hidft_server_s::launch(Slot& sl) {
   copy_all(off * sizeof(float2));
   hipError_t e;
   const hidft::GroupDone done{sl.d_count, &sl.count_base, sl.d_flag, ++sl.seq};
-  if (inst.size() == 1) {
-    // A single request (most batches at moderate load): its descriptor goes
-    // with the launch, and no table is staged.
-    if ((e = hidft::launch_grouped_one(inst[0].second, inst[0].first | hidft::GROUP_SKIP_IDLE,
-                                       sl.stream, &done)) != hipSuccess ||
+  if (inst.size() <= hidft::GROUP_FEW_MAX) {
+    // A few requests (most batches at moderate load): one block each, their
+    // descriptors with the launch, no table staged.
+    hidft::GroupFew few{};
+    for (size_t i = 0; i < inst.size(); ++i) {
+      few.slot[i] = inst[i].second;
+      few.code[i] = inst[i].first | hidft::GROUP_SKIP_IDLE;
+    }
+    if ((e = hidft::launch_grouped_few(few, (uint32_t)inst.size(), sl.stream, &done)) !=
+            hipSuccess ||
         (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) {
       worker_error = (int32_t)HIDFT_ERR_DEVICE;
     }

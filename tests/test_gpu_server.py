@@ -237,11 +237,11 @@ def test_server_submit_many():
 
 @pytest.mark.parametrize("s", [0, 5, 9, 12, 13, 14])
 def test_server_single_request_batches(s):
-    """A batch of one request runs as one block with its descriptor passed
-    with the launch (no table read): narrow sizes on the first quarter block,
-    2^13 and 2^14 points on the whole block.  Each request is drained before
-    the next, so every batch holds one; each equals the request alone, bit
-    for bit, and the FP64 oracle."""
+    """A batch of up to four requests runs as one block per request with the
+    descriptors passed with the launch (no table read): narrow sizes on the
+    first quarter block, 2^13 and 2^14 points on the whole block.  Each
+    request is drained before the next, so every batch holds one; each
+    equals the request alone, bit for bit, and the FP64 oracle."""
     rng = rng_for(9, 300 + s)
     M = s + 6
     J = np.ascontiguousarray(homogeneous_support(M, s, rng).J, dtype=np.uint64)
@@ -261,6 +261,52 @@ def test_server_single_request_batches(s):
         if ref is not None:
             assert np.max(oracle.rel_l2(o[None, :].astype(np.complex128), ref)) <= 1e-5
     plan.close()
+    srv.close()
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_server_few_request_batches(n):
+    """n requests of mixed sizes (2^5..2^14 points) in one submit_many call,
+    all plans resident: the scheduler takes them as one batch (one block per
+    request up to four, the packed launch with tables from five).  Every
+    result equals the request alone, bit for bit; repeated with the requests
+    rotated."""
+    rng = rng_for(9, 400 + n)
+    sizes = [14, 5, 13, 9, 12][:n]
+    sups = []
+    for i, s in enumerate(sizes):
+        M = s + 4 + i
+        sups.append((M, np.ascontiguousarray(homogeneous_support(M, s, rng_for(9, 410 + i)).J,
+                                             dtype=np.uint64)))
+    plans = [native.Plan(M, J.tolist()) for M, J in sups]
+    srv = native.Server(data_bytes=16 << 20, plan_bytes=16 << 20, slots=2, max_batch=8)
+    warm = [np.zeros(len(J), dtype=np.complex64) for _, J in sups]
+    warm_out = [np.empty_like(w) for w in warm]  # alive until polled
+    for (M, J), w, wo in zip(sups, warm, warm_out):  # make every plan resident
+        srv.submit(M, J, w, wo)
+        srv.drain()
+    srv.poll()
+    for rot in range(2):
+        order = [(i + rot) % n for i in range(n)]
+        recs = np.zeros(n, dtype=native.REQUEST_DTYPE)
+        keep = []
+        for q, i in enumerate(order):
+            M, J = sups[i]
+            f = sample_values(M, len(J), 1, rng)[0]
+            o = np.full(len(J), np.nan, dtype=np.complex64)
+            keep.append((i, f, o))
+            recs[q] = (M, J.ctypes.data, len(J), f.ctypes.data, o.ctypes.data)
+        ids, sts = srv.submit_many(recs)
+        assert (sts == 0).all()
+        srv.drain()
+        res = srv.poll()
+        assert len(res) == n and (res["status"] == 0).all()
+        _say(f"n={n} rot={rot}: batch sizes {sorted(set(res['batch_size'].tolist()))}")
+        for i, f, o in keep:
+            want = plans[i].execute(torch.from_numpy(f[None, :]).cuda())[0].cpu().numpy()
+            assert np.array_equal(o, want), (n, rot, i)
+    for p in plans:
+        p.close()
     srv.close()
 
 
