@@ -173,8 +173,8 @@ hidft_status hidft_plan_device_bytes(hidft_plan plan, size_t* bytes);
  * k > 2^HIDFT_MAX_LOG2_K_DEVICE (up to 2^HIDFT_MAX_LOG2_K_LARGE): the stages
  * run in three passes through a workspace of hidft_plan_workspace_bytes
  * (Corollary 2: the recursion splits at any level): the top s1 = s - s2
- * stages (s1 <= 8) on the 2^s2 columns of each signal, the other s2 stages
- * (s2 = 12 up to k = 2^20, else s - 8) on each of the 2^s1 subtrees with the
+ * stages (s1 <= 9) on the 2^s2 columns of each signal, the other s2 stages
+ * (s2 = 12 up to k = 2^20, else s - 9) on each of the 2^s1 subtrees with the
  * fused kernel's per-signal code, then a placement into the caller's order
  * of J, scaled by N/k.  The stage arithmetic and order are those of one pass.  Here
  * hidft_execute takes the workspace from the stream-ordered allocator

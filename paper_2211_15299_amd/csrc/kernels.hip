@@ -2223,14 +2223,14 @@ hipError_t launch_sas_apply(const float2* y, uint32_t n_nodes, uint32_t mu_star,
 // Transforms of more than 2^14 points, in passes through a workspace.
 //
 // The recursion splits at any level (Corollary 2).  With s = s1 + s2
-// (s1 <= 8, 12 <= s2 <= 14):
+// (s2 = 12 up to s = 20, then s - 9; s1 <= 9):
 //  * pass 1: stages 1..s1 pair only the top s1 bits of the position a, and
 //    their twiddles depend on those bits alone, so for every value of the
 //    low s2 bits (a column) the 2^s1 values of the column form a transform
 //    with the same s1-stage twiddles.  Up to s1 = 4 a thread takes one
 //    column, in registers; above, a block takes a tile of columns through
-//    two groups (stages 1..4 on the top four bits, stages 5..s1 on the rest)
-//    with an exchange in LDS.
+//    two groups (stages 1..4 on the top four bits, stages 5..s1 on the rest,
+//    s1 <= 8) or three (s1 = 9) with exchanges in LDS.
 //  * pass 2: stages s1+1..s never mix values whose top s1 bits differ, so
 //    each subtree (2^s2 consecutive positions) is a transform of 2^s2 points
 //    whose stage-u' twiddles are the run of stage s1+u' starting at
@@ -2334,7 +2334,7 @@ large_top2_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restri
 #pragma unroll
       for (int c = 0; c < 16; ++c) L[col * PAD_H + c * RB + g] = v[c];
     }
-    __syncthreads();
+    lds_barrier();
     for (int unit = threadIdx.x; unit < COLS * 16; unit += THREADS) {
       const int col = unit % COLS, c = unit / COLS;
       float2 v[RB];
@@ -2354,7 +2354,100 @@ large_top2_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restri
 #pragma unroll
       for (int g = 0; g < RB; ++g) y[(uint64_t)(c * RB + g) * cols] = v[g];
     }
-    __syncthreads();  // the next tile overwrites L
+    lds_barrier();  // the next tile overwrites L
+  }
+}
+
+// Columns for s1 = 9, in three groups so that a thread holds 16 values: a
+// block of 512 threads takes 16 columns (h = row of the column, 0..511).
+//  * group A, stages 1..4 (bits 8..5 of h, uniform twiddles): thread (g, col)
+//    holds h = c * 32 + g, c < 16;
+//  * group B, stages 5..8 (bits 4..1), after an exchange in LDS: unit
+//    (hi, b0, col) holds h = hi * 32 + c * 2 + b0, c < 16;
+//  * group C, stage 9 (bit 0), after another exchange: each thread takes 8
+//    pairs (h, h + 1) and stores both.  Lanes l and l ^ 16 of group B hold
+//    rows h and h ^ 1 of one column; swapping their values through lane
+//    shuffles instead of this exchange made the pass 3-7 us slower (its
+//    adjoint 0-2 us).
+// Twiddles of stages 5..9 come from the table's first 511 entries, copied to
+// LDS.  A second group of five stages (32 values per thread) would need about
+// 210 registers and one block per CU.
+constexpr int TOP3_S1 = 9;
+constexpr int TOP3_THREADS = 512;
+constexpr int TOP3_COLS = 16;
+
+__global__ void __launch_bounds__(TOP3_THREADS, 4)
+large_top3_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __restrict__ work,
+                  uint64_t batch, uint32_t s2, const float2* __restrict__ tw) {
+  constexpr int H = 1 << TOP3_S1, PAD_H = H + 1, COLS = TOP3_COLS, THREADS = TOP3_THREADS;
+  static_assert(COLS * 32 == THREADS, "one thread per (g, col)");
+  __shared__ float2 L[COLS * PAD_H];
+  __shared__ float2 T[H - 1];
+  for (int i = threadIdx.x; i < H - 1; i += THREADS) T[i] = tw[i];
+  float2 w1[15];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) w1[i] = make_uniform(tw[i]);
+  __syncthreads();
+  const uint64_t cols = 1ULL << s2;
+  const uint64_t k = cols << TOP3_S1;
+  const uint64_t tiles_per_signal = cols / COLS;
+  const uint64_t tiles = batch * tiles_per_signal;
+  const int tid = (int)threadIdx.x;
+  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const uint64_t b = tile / tiles_per_signal;
+    const uint64_t col0 = (tile - b * tiles_per_signal) * COLS;
+    {  // group A
+      const int col = tid % COLS, g = tid / COLS;
+      const float2* x = in + b * (uint64_t)ld_in + col0 + col;
+      float2 v[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] = load_stream(x + (uint64_t)(c * 32 + g) * cols);
+#pragma unroll
+      for (int u = 1; u <= 4; ++u) {
+        const int bit = 4 - u;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c & (1 << bit)) continue;
+          butterfly(v[c], v[c | (1 << bit)], w1[(1 << (u - 1)) - 1 + (c >> (bit + 1))]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) L[col * PAD_H + c * 32 + g] = v[c];
+    }
+    lds_barrier();
+    {  // group B
+      const int col = tid % COLS, hb = tid / COLS;  // hb = hi * 2 + b0
+      const int hi = hb >> 1, b0 = hb & 1;
+      float2 v[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] = L[col * PAD_H + hi * 32 + c * 2 + b0];
+#pragma unroll
+      for (int u = 5; u <= 8; ++u) {
+        const int bit = 8 - u;  // of c; bit + 1 of h
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c & (1 << bit)) continue;
+          const int h = hi * 32 + c * 2 + b0;
+          butterfly(v[c], v[c | (1 << bit)], T[(1 << (u - 1)) - 1 + (h >> (bit + 2))]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) L[col * PAD_H + hi * 32 + c * 2 + b0] = v[c];
+    }
+    lds_barrier();
+    {  // group C: stage 9 on the pairs (h, h + 1), h even
+      float2* y = work + b * k + col0;
+#pragma unroll 2
+      for (int i = 0; i < 8; ++i) {
+        const int p = tid + i * THREADS;  // pair p: column p % 16, rows 2 (p / 16) + {0, 1}
+        const int col = p % COLS, h = 2 * (p / COLS);
+        float2 a = L[col * PAD_H + h], c = L[col * PAD_H + h + 1];
+        butterfly(a, c, T[(1 << (TOP3_S1 - 1)) - 1 + (h >> 1)]);
+        y[(uint64_t)h * cols + col] = a;
+        y[(uint64_t)(h + 1) * cols + col] = c;
+      }
+    }
+    lds_barrier();  // the next tile overwrites L
   }
 }
 
@@ -2369,6 +2462,24 @@ struct SubtreeMem {
   __device__ __forceinline__ void put(int uni, int lane, float2 x) const { out[uni + lane] = x; }
 };
 
+// Subtree units.  Each subtree reads its own twiddle and gather tables (10 B
+// per point, as much as its data) from the L2 of the XCD it runs on, and
+// blocks are dispatched to the eight XCDs in turn (block g to XCD g % 8).  In
+// signal-major order (unit g = signal * 2^s1 + subtree) an XCD serves 2^s1 / 8
+// subtrees' tables at once: 1.3 MB at s1 = 8 (2^12-point subtrees), which
+// fits its 4 MB L2 beside the streamed rows, but 2.6 and 5.2 MB at s1 = 9.
+// There block g takes subtree 8 (j / batch) + g % 8 of signal j % batch,
+// j = g / 8, so the batch's copies of one subtree run back to back on one XCD
+// and read its tables from that L2: 2^21 points 167 -> 159 us, 2^22 183 ->
+// 178 us.  Below s1 = 9 that order made the passes 5-12 us slower (the
+// blocks in flight read rows of many signals instead of consecutive rows).
+// A bijection on [0, units) since 8 divides 2^s1.
+__device__ __forceinline__ uint64_t subtree_unit(uint64_t g, uint32_t s1, uint64_t units) {
+  if (s1 < 9) return g;
+  const uint64_t batch = units >> s1, j = g >> 3, m = j / batch;
+  return ((j - m * batch) << s1) + (g & 7) + 8 * m;
+}
+
 template <int S2, int SCHED>
 __global__ void __launch_bounds__((FusedShape<S2, SCHED, 4>::THREADS))
 large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint32_t s1,
@@ -2378,8 +2489,9 @@ large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint
   constexpr int R = Sh::R, T = Sh::T;
   constexpr uint64_t K2 = 1ULL << S2;
   extern __shared__ float2 lds[];
-  const uint64_t unit = first + blockIdx.x;
-  if (unit >= units) return;  // uniform over the block
+  const uint64_t g = first + blockIdx.x;
+  if (g >= units) return;  // uniform over the block
+  const uint64_t unit = subtree_unit(g, s1, units);
   const uint64_t sub = unit & ((1ULL << s1) - 1);
   float2* row = work + unit * K2;  // unit = signal * 2^s1 + subtree
   float2 v[R];
@@ -2448,14 +2560,17 @@ large_place_kernel(const float2* __restrict__ work, float2* __restrict__ out, in
         chunk[d3[e]] = make_float2(x.x * scale, x.y * scale);
       }
     }
-    __syncthreads();
+    lds_barrier();
     float2* o = out + b * (uint64_t)ld_out + c * CHUNK;
     for (uint32_t e = tid; e < count; e += THREADS) store_stream(o + e, chunk[e]);
-    __syncthreads();  // the next unit overwrites the chunk
+    lds_barrier();  // the next unit overwrites the chunk
   }
 }
 
-uint32_t large_split(uint32_t s) { return s > 20 ? s - 8 : 12; }
+// s2: 12 up to 2^20 points (s1 <= 8), then s - 9 (s1 = 9, the three-group
+// column kernel): 2^21 points as 9 + 12 rather than 8 + 13 took the forward
+// pass sequence from 163 to 159 us and the inverse from 172 to 164 us.
+uint32_t large_split(uint32_t s) { return s > 20 ? s - TOP3_S1 : 12; }
 uint32_t large_chunk(uint32_t s) { return s - large_split(s) >= 7 ? 16384u : 4096u; }
 
 static hipError_t stream_grid(uint64_t threads, unsigned* grid) {
@@ -2530,6 +2645,22 @@ static hipError_t launch_top2(const float2* in, int64_t ld_in, float2* work, uin
   return hipGetLastError();
 }
 
+// The three-group column kernel (s1 = 9), or its adjoint: the blocks
+// resident at once, at most one per tile of 16 columns.
+static hipError_t top3_grid(const void* kernel, OccupancyCache& cache, uint64_t batch,
+                            uint32_t s2, unsigned* grid) {
+  Occupancy occ;
+  if (!cache.get(&occ)) {
+    hipError_t e = query_occupancy(kernel, TOP3_THREADS, 0, &occ);
+    if (e != hipSuccess) return e;
+    cache.put(occ);
+  }
+  const uint64_t tiles = (batch << s2) / TOP3_COLS;
+  const uint64_t cap = (uint64_t)occ.per_cu * (uint64_t)occ.cus;
+  *grid = (unsigned)(tiles < cap ? tiles : cap);
+  return hipSuccess;
+}
+
 template <int S2, int SCHED>
 static hipError_t launch_large_sub(float2* work, uint64_t units, uint32_t s1, const float2* tw2,
                                    const uint16_t* src2, hipStream_t stream) {
@@ -2581,6 +2712,16 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
     HIDFT_TOP2(5) HIDFT_TOP2(6) HIDFT_TOP2(7) HIDFT_TOP2(8)
 #undef HIDFT_TOP
 #undef HIDFT_TOP2
+    case TOP3_S1: {
+      static OccupancyCache cache3;
+      unsigned grid3 = 0;
+      if ((e = top3_grid((const void*)large_top3_kernel, cache3, batch, s2, &grid3)) !=
+          hipSuccess)
+        return e;
+      hipLaunchKernelGGL(large_top3_kernel, dim3(grid3), dim3(TOP3_THREADS), 0, stream, in,
+                         ld_in, work, batch, s2, tw);
+      break;
+    }
     default:
       return hipErrorInvalidValue;
   }
@@ -2631,14 +2772,14 @@ large_unplace_kernel(const float2* __restrict__ coefs, int64_t ld_in, float2* __
       si[i] = s3[tid + i * THREADS];
       di[i] = d3[tid + i * THREADS];
     }
-    __syncthreads();
+    lds_barrier();
     const __amdgpu_buffer_rsrc_t row = make_rsrc(work + b * k, (uint32_t)(k * sizeof(float2)));
 #pragma unroll
     for (int i = 0; i < LARGE_EPT; ++i)
       __builtin_amdgcn_raw_buffer_store_b64(
           __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, chunk[di[i]]), row,
           (int)(si[i] * sizeof(float2)), 0, 0);
-    __syncthreads();  // the next unit overwrites the chunk
+    lds_barrier();  // the next unit overwrites the chunk
   }
 }
 
@@ -2651,8 +2792,9 @@ large_sub_inv_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, 
   constexpr int R = Sh::R, T = Sh::T;
   constexpr uint64_t K2 = 1ULL << S2;
   extern __shared__ float2 lds[];
-  const uint64_t unit = first + blockIdx.x;
-  if (unit >= units) return;  // uniform over the block
+  const uint64_t g = first + blockIdx.x;
+  if (g >= units) return;  // uniform over the block
+  const uint64_t unit = subtree_unit(g, s1, units);
   const uint64_t sub = unit & ((1ULL << s1) - 1);
   float2* row = work + unit * K2;
   const int tau = (int)threadIdx.x;
@@ -2745,7 +2887,7 @@ large_top2_inv_kernel(const float2* __restrict__ work, float2* __restrict__ out,
 #pragma unroll
       for (int g = 0; g < RB; ++g) L[col * PAD_H + c * RB + g] = v[g];
     }
-    __syncthreads();
+    lds_barrier();
     {
       const int col = threadIdx.x % COLS, g = threadIdx.x / COLS;
       float2 v[16];
@@ -2766,7 +2908,7 @@ large_top2_inv_kernel(const float2* __restrict__ work, float2* __restrict__ out,
         store_stream(y + (uint64_t)(c * RB + g) * cols,
                      make_float2(v[c].x * scale, v[c].y * scale));
     }
-    __syncthreads();  // the next tile overwrites L
+    lds_barrier();  // the next tile overwrites L
   }
 }
 
@@ -2783,6 +2925,84 @@ static hipError_t launch_unplace(const float2* coefs, int64_t ld_in, float2* wor
   hipLaunchKernelGGL(large_unplace_kernel<CHUNK>, dim3(grid), dim3(THREADS), 0, stream, coefs,
                      ld_in, work, batch, s, src3, dest3);
   return hipGetLastError();
+}
+
+// The adjoint of large_top3_kernel: stage 9 on the pairs first, then group
+// B's stages 8..5, then group A's stages 4..1, scaled by `scale`.
+__global__ void __launch_bounds__(TOP3_THREADS, 4)
+large_top3_inv_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
+                      uint64_t batch, uint32_t s2, const float2* __restrict__ tw, float scale) {
+  constexpr int H = 1 << TOP3_S1, PAD_H = H + 1, COLS = TOP3_COLS, THREADS = TOP3_THREADS;
+  __shared__ float2 L[COLS * PAD_H];
+  __shared__ float2 T[H - 1];
+  for (int i = threadIdx.x; i < H - 1; i += THREADS) T[i] = tw[i];
+  float2 w1[15];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) w1[i] = make_uniform(tw[i]);
+  __syncthreads();
+  const uint64_t cols = 1ULL << s2;
+  const uint64_t k = cols << TOP3_S1;
+  const uint64_t tiles_per_signal = cols / COLS;
+  const uint64_t tiles = batch * tiles_per_signal;
+  const int tid = (int)threadIdx.x;
+  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const uint64_t b = tile / tiles_per_signal;
+    const uint64_t col0 = (tile - b * tiles_per_signal) * COLS;
+    {  // stage 9 on the pairs (h, h + 1), h even
+      const float2* x = work + b * k + col0;
+#pragma unroll 4
+      for (int i = 0; i < 8; ++i) {
+        const int p = tid + i * THREADS;
+        const int col = p % COLS, h = 2 * (p / COLS);
+        float2 a = x[(uint64_t)h * cols + col], c = x[(uint64_t)(h + 1) * cols + col];
+        butterfly_adj(a, c, T[(1 << (TOP3_S1 - 1)) - 1 + (h >> 1)]);
+        L[col * PAD_H + h] = a;
+        L[col * PAD_H + h + 1] = c;
+      }
+    }
+    lds_barrier();
+    {  // group B^H: stages 8..5
+      const int col = tid % COLS, hb = tid / COLS;
+      const int hi = hb >> 1, b0 = hb & 1;
+      float2 v[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] = L[col * PAD_H + hi * 32 + c * 2 + b0];
+#pragma unroll
+      for (int u = 8; u >= 5; --u) {
+        const int bit = 8 - u;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c & (1 << bit)) continue;
+          const int h = hi * 32 + c * 2 + b0;
+          butterfly_adj(v[c], v[c | (1 << bit)], T[(1 << (u - 1)) - 1 + (h >> (bit + 2))]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) L[col * PAD_H + hi * 32 + c * 2 + b0] = v[c];
+    }
+    lds_barrier();
+    {  // group A^H: stages 4..1, then the scaled store
+      const int col = tid % COLS, g = tid / COLS;
+      float2 v[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] = L[col * PAD_H + c * 32 + g];
+#pragma unroll
+      for (int u = 4; u >= 1; --u) {
+        const int bit = 4 - u;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c & (1 << bit)) continue;
+          butterfly_adj(v[c], v[c | (1 << bit)], w1[(1 << (u - 1)) - 1 + (c >> (bit + 1))]);
+        }
+      }
+      float2* y = out + b * (uint64_t)ld_out + col0 + col;
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        store_stream(y + (uint64_t)(c * 32 + g) * cols,
+                     make_float2(v[c].x * scale, v[c].y * scale));
+    }
+    lds_barrier();  // the next tile overwrites L
+  }
 }
 
 template <int S2, int SCHED>
@@ -2852,6 +3072,16 @@ hipError_t launch_large_inverse(uint32_t s, const float2* coefs, int64_t ld_in, 
     HIDFT_TOPI2(5) HIDFT_TOPI2(6) HIDFT_TOPI2(7) HIDFT_TOPI2(8)
 #undef HIDFT_TOPI
 #undef HIDFT_TOPI2
+    case TOP3_S1: {
+      static OccupancyCache cache3;
+      unsigned grid3 = 0;
+      if ((e = top3_grid((const void*)large_top3_inv_kernel, cache3, batch, s2, &grid3)) !=
+          hipSuccess)
+        return e;
+      hipLaunchKernelGGL(large_top3_inv_kernel, dim3(grid3), dim3(TOP3_THREADS), 0, stream, work,
+                         out, ld_out, batch, s2, tw, scale);
+      break;
+    }
     default:
       return hipErrorInvalidValue;
   }

@@ -83,10 +83,12 @@ def test_large_recovers_every_coefficient(M, s):
     plan.close()
 
 
-@pytest.mark.parametrize("M,s,batch", [(18, 15, 96), (22, 19, 6), (22, 20, 3)])
+@pytest.mark.parametrize("M,s,batch", [(18, 15, 96), (22, 19, 6), (22, 20, 3), (22, 21, 3)])
 def test_large_batch_every_row(M, s, batch):
-    """Chunks of 4096 outputs (s = 15) and of 16384 (s = 19, 20: s1 = 7, 8),
-    the column pass in registers (s1 = 3) and in tiles (s1 = 7, 8)."""
+    """Chunks of 4096 outputs (s = 15) and of 16384 (s = 19..21: s1 = 7..9),
+    the column pass in registers (s1 = 3), in two groups (s1 = 7, 8) and in
+    three (s1 = 9), where the subtree pass runs the batch's signals of one
+    subtree back to back (three signals: not a power of two)."""
     rng = rng_for(4102, s)
     sup = homogeneous_support(M, s, rng)
     J = sup.J.tolist()
@@ -216,7 +218,7 @@ def test_large_plans_refused_where_one_signal_must_fit():
     plan.close()
 
 
-@pytest.mark.parametrize("M,s", [(20, 15), (22, 17), (24, 20), (24, 22)])
+@pytest.mark.parametrize("M,s", [(20, 15), (22, 17), (24, 20), (24, 21), (24, 22)])
 def test_large_inverse_against_oracle(M, s):
     rng = rng_for(4107, s)
     plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
