@@ -30,6 +30,7 @@ HIDFT_SAS_WEIGHTS_ONLY = 0x4
 SAS_MAX_REL_ERR = 1e-5
 MAX_LOG2_K_DEVICE = 14
 MAX_LOG2_K_LARGE = 22
+SAS_SCRATCH_BYTES = 16 << 20  # hidft_sas_execute_noalloc: one signal's workspace at most
 
 # Execution variants (hidft_exec_config)
 PREC_FP32, PREC_F16X2, PREC_BF16X3 = 0, 1, 2

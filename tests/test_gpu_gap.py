@@ -91,12 +91,16 @@ def test_arithmetic_progressions(alpha):
 
 @pytest.mark.parametrize("kind,M,size,alpha", [("ap", 22, 20000, 1), ("ap", 22, 40000, 3),
                                               ("ap", 24, 100000, 5), ("gap", 24, [256, 64], 0),
-                                              ("gap", 24, [64, 64, 16], 0)])
+                                              ("gap", 24, [64, 64, 16], 0),
+                                              ("ap", 24, 1200000, 2), ("ap", 24, 3000000, 2)])
 def test_more_pivots_than_one_signal_in_lds(kind, M, size, alpha):
     """Lemma 5's Hi-DFT on all n > 14 pivots (2^n samples, mu* = 1) runs in
     passes through a workspace; every coefficient against the seeded ones
     the samples were synthesised from (FP64, full-length inverse DFT), and
-    hidft_sas_execute_noalloc gives the same bits."""
+    hidft_sas_execute_noalloc gives the same bits.  n = 21 and 22 (the last
+    two cases) take the three-group column pass and the subtree order that
+    runs both signals of one subtree back to back, with the placement
+    keeping 1.2 and 3 million of the 2^21 and 2^22 outputs."""
     rng = rng_for(932, M * 7 + (size if kind == "ap" else size[0]))
     J = (arithmetic_progression(M, size, rng, alpha) if kind == "ap"
          else gap_support(M, size, rng)).J.tolist()
@@ -115,9 +119,13 @@ def test_more_pivots_than_one_signal_in_lds(kind, M, size, alpha):
     assert np.max(err) <= plan.err_bound <= 1e-5
     x = torch.from_numpy(f.astype(np.complex64)).cuda()
     y = torch.empty((2, plan.k), dtype=torch.complex64, device="cuda")
-    plan.execute_noalloc_ptr(x.data_ptr(), len(S), y.data_ptr(), plan.k, 2)
-    torch.cuda.synchronize()
-    assert np.array_equal(y.cpu().numpy().astype(np.complex128), got)
+    if plan.workspace_bytes(1) <= native.SAS_SCRATCH_BYTES:
+        plan.execute_noalloc_ptr(x.data_ptr(), len(S), y.data_ptr(), plan.k, 2)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy().astype(np.complex128), got)
+    else:  # one signal's workspace exceeds the static scratch: refused, nothing run
+        with pytest.raises(native.HiDFTError, match="scratch"):
+            plan.execute_noalloc_ptr(x.data_ptr(), len(S), y.data_ptr(), plan.k, 2)
     # the induced weights stay within one signal in LDS
     with pytest.raises(native.HiDFTError):
         native.SASPlan(M, J, pivots=P, weights_only=True)
