@@ -83,12 +83,14 @@ def test_large_recovers_every_coefficient(M, s):
     plan.close()
 
 
-@pytest.mark.parametrize("M,s,batch", [(18, 15, 96), (22, 19, 6), (22, 20, 3), (22, 21, 3)])
+@pytest.mark.parametrize("M,s,batch", [(18, 15, 96), (22, 19, 6), (22, 20, 3), (22, 21, 3),
+                                         (22, 21, 1)])
 def test_large_batch_every_row(M, s, batch):
     """Chunks of 4096 outputs (s = 15) and of 16384 (s = 19..21: s1 = 7..9),
     the column pass in registers (s1 = 3), in two groups (s1 = 7, 8) and in
     three (s1 = 9), where the subtree pass runs the batch's signals of one
-    subtree back to back (three signals: not a power of two)."""
+    subtree back to back (three signals: not a power of two; one signal:
+    the signal-major order)."""
     rng = rng_for(4102, s)
     sup = homogeneous_support(M, s, rng)
     J = sup.J.tolist()
