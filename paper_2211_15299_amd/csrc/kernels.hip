@@ -541,23 +541,66 @@ struct FlatMemT {
 };
 using FlatMem = FlatMemT<false>;
 
-// Tables for the adjoint of one signal read per signal: its twiddles, and
-// the LDS places of the thread's R values (gather-table entries c * T + lane,
-// the scatter that starts the adjoint) in registers.  The places are read
-// before the signal's values, so that the scatter's first wait is not for
-// table reads queued behind the whole row (vector-memory counters retire in
-// order): the adjoint passes of 2^15..2^21 points took 4-5 us less per
-// launch; the 2^14-point inverse (one signal per block) is unchanged.
+// Twiddles of group g of the adjoint (stages t0(g)..RHO-1 of its window of
+// bits) for the thread at lane tau: entry (1 << t) - 1 + h is the h-th of the
+// window's stage t (entries of stages below t0(g) are left as they are).
+template <int S, int SCHED, int N, class Mem>
+__device__ __forceinline__ void adjoint_group_twiddles(float2 (&wq)[N], const Mem& mem, int tau,
+                                                       int g) {
+  using Sh = FusedShape<S, SCHED, 4>;
+  constexpr int RHO = Sh::RHO;
+  static_assert(N == (Sh::R > 1 ? Sh::R - 1 : 1), "one group's twiddles");
+  const int lo = Sh::lo(g), t0 = Sh::t0(g);
+  const int a_hi = tau >> lo;
+#pragma unroll
+  for (int t = 0; t < RHO; ++t) {
+    if (t < t0) continue;
+    const int u = S - lo - RHO + 1 + t;
+#pragma unroll
+    for (int h = 0; h < (1 << t); ++h)
+      wq[(1 << t) - 1 + h] = mem.tw_at(((1 << (u - 1)) - 1) + h, a_hi << t);
+  }
+}
+
+// Tables for the adjoint of one signal read per signal: its twiddles, the
+// LDS places of the thread's R values (gather-table entries c * T + lane, the
+// scatter that starts the adjoint) and the twiddles of its first group (the
+// last group G of the forward order), both in registers.  They are read
+// before the signal's values, so that the scatter and the first group do not
+// wait for table reads queued behind the whole row (vector-memory counters
+// retire in order).  The places ahead of the row took the adjoint passes of
+// 2^15..2^21 points 4-5 us less per launch; the first group's twiddles
+// ahead of it a further 1-1.4 us (3.8 us at 2^22), and the 2^14-point
+// inverse (one signal per block) from 78 to 75 us.
 template <int R, int T>
 struct AdjointMem {
+  static constexpr bool FIRST_TW = true;
   const float2* tw;
   int place[R];
+  float2 first_tw[R > 1 ? R - 1 : 1];
   __device__ __forceinline__ void read_places(const uint16_t* src, int lane) {
 #pragma unroll
     for (int c = 0; c < R; ++c) place[c] = src[c * T + lane];
   }
+  template <int S, int SCHED>
+  __device__ __forceinline__ void read_first_twiddles(int lane) {
+    static_assert(FusedShape<S, SCHED, 4>::R == R && FusedShape<S, SCHED, 4>::T == T,
+                  "the signal's shape");
+#pragma unroll
+    for (int i = 0; i < (R > 1 ? R - 1 : 1); ++i) first_tw[i] = make_float2(0.f, 0.f);
+    adjoint_group_twiddles<S, SCHED>(first_tw, *this, lane, FusedShape<S, SCHED, 4>::G);
+  }
   __device__ __forceinline__ float2 tw_at(int uni, int lane) const { return tw[uni + lane]; }
   __device__ __forceinline__ int src_at(int uni, int) const { return place[uni / T]; }
+};
+// Whether a table type holds its first group's twiddles (AdjointMem).
+template <class M, class = void>
+struct FirstTwOf {
+  static constexpr bool value = false;
+};
+template <class M>
+struct FirstTwOf<M, decltype((void)M::FIRST_TW)> {
+  static constexpr bool value = M::FIRST_TW;
 };
 
 constexpr int BUFFER_DWORD3 = 0x00020000;  // raw buffer, 32-bit data format
@@ -920,13 +963,15 @@ __device__ __forceinline__ void inverse_signal(SigVec<S, 4>& v, float2* L, int t
     const int base = a_lo + (a_hi << (lo + RHO));
     float2 wq[R > 1 ? R - 1 : 1];
     if constexpr (!(HOISTED && Sh::TW_REGS)) {
+      if constexpr (FirstTwOf<Mem>::value) {
+        if (g == G) {
 #pragma unroll
-      for (int t = 0; t < RHO; ++t) {
-        if (t < t0) continue;
-        const int u = S - lo - RHO + 1 + t;
-#pragma unroll
-        for (int h = 0; h < (1 << t); ++h)
-          wq[(1 << t) - 1 + h] = mem.tw_at(((1 << (u - 1)) - 1) + h, a_hi << t);
+          for (int i = 0; i < (R > 1 ? R - 1 : 1); ++i) wq[i] = mem.first_tw[i];
+        } else {
+          adjoint_group_twiddles<S, SCHED>(wq, mem, tau, g);
+        }
+      } else {
+        adjoint_group_twiddles<S, SCHED>(wq, mem, tau, g);
       }
     }
     lds_barrier();
@@ -1005,6 +1050,7 @@ hidft_inverse_kernel(const float2* __restrict__ in, int64_t ld_in, float2* __res
     AdjointMem<R, T> mem;
     mem.tw = tw;
     mem.read_places(src, tau);  // ahead of the signal
+    mem.template read_first_twiddles<S, SCHED>(tau);
     float2 v[R];
     __builtin_amdgcn_s_setprio(2);
     load_group1<S, SCHED, 4, PREC_FP32>(v, in, ld_in, sig, batch);
@@ -2822,6 +2868,7 @@ large_sub_inv_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, 
   AdjointMem<R, T> mem;
   mem.tw = tw2 + sub * (K2 - 1);
   mem.read_places(src2 + sub * K2, tau);  // ahead of the row
+  mem.template read_first_twiddles<S2, SCHED>(tau);
   float2 v[R];
   __builtin_amdgcn_s_setprio(2);
   load_row<R, T, false>(v, row, (uint32_t)K2);
