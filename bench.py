@@ -703,7 +703,7 @@ def inverse_bench(args, native, torch, stream, steps=50):
             "round_trip_rel_l2_max": rt, "steps": steps, "sets": sets}
 
 
-def large_bench(native, torch, stream, steps=20):
+def large_bench(native, torch, stream, steps=50):
     """Transforms of 2^15..2^22 points at N = 2^24, 256 MB of samples and
     coefficients per launch, 4 rotating (input, output) sets and one shared
     workspace (hidft_execute_ws: three passes, no allocation).  GB/s counts
@@ -743,7 +743,8 @@ def large_bench(native, torch, stream, steps=20):
             plan.inverse_ws_ptr(ys[i % sets].data_ptr(), k, xs[i % sets].data_ptr(), k, batch,
                                 work.data_ptr(), wb, stream)
 
-        run_inv(0)
+        for i in range(3):
+            run_inv(i)
         torch.cuda.synchronize()
         e0.record(stream)
         for i in range(steps):
