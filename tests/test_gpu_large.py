@@ -132,14 +132,21 @@ def test_large_batch_every_row(M, s, batch):
     plan.close()
 
 
-def test_large_in_a_graph():
-    M, s, batch = 19, 16, 8
-    rng = rng_for(4104, 0)
+@pytest.mark.parametrize("M,s,batch", [(19, 16, 8), (22, 21, 2)])
+def test_large_in_a_graph(M, s, batch):
+    """The caller-workspace forward and inverse passes captured in HIP graphs
+    (s = 16: the column pass in registers; s = 21: the three-group column
+    kernels and the subtree order of s1 = 9): every replay, with eager work
+    in between, equals the eager launch."""
+    rng = rng_for(4104, s)
     plan = native.Plan(M, homogeneous_support(M, s, rng).J.tolist())
     k = plan.k
     x = torch.from_numpy(sample_values(M, k, batch, rng)).cuda()
     ref = plan.execute(x)
+    ref_inv = torch.empty_like(x)
+    plan.inverse_ptr(ref.data_ptr(), k, ref_inv.data_ptr(), k, batch)
     y = torch.empty_like(x)
+    z = torch.empty_like(x)
     wb = plan.workspace_bytes(batch)
     work = torch.empty(wb // 8, dtype=torch.complex64, device="cuda")
     torch.cuda.synchronize()
@@ -147,13 +154,21 @@ def test_large_in_a_graph():
     with torch.cuda.graph(g):
         plan.execute_ws_ptr(x.data_ptr(), k, y.data_ptr(), k, batch, work.data_ptr(), wb,
                             stream=torch.cuda.current_stream())
+    gi = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gi):
+        plan.inverse_ws_ptr(ref.data_ptr(), k, z.data_ptr(), k, batch, work.data_ptr(), wb,
+                            stream=torch.cuda.current_stream())
     for rep in range(3):
         y.fill_(complex(np.nan, np.nan))
+        z.fill_(complex(np.nan, np.nan))
         work.fill_(0)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        assert torch.equal(y, ref), f"replay {rep}"
+        assert torch.equal(y, ref), f"forward replay {rep}"
+        gi.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(z, ref_inv), f"inverse replay {rep}"
     plan.close()
 
 
