@@ -2714,15 +2714,15 @@ static hipError_t launch_top2(const float2* in, int64_t ld_in, float2* work, uin
 
 // The three-group column kernel (s1 = 9), or its adjoint: the blocks
 // resident at once, at most one per tile of 16 columns.
-static hipError_t top3_grid(const void* kernel, OccupancyCache& cache, uint64_t batch,
-                            uint32_t s2, unsigned* grid) {
+static hipError_t top3_grid(const void* kernel, int threads, int cols, OccupancyCache& cache,
+                            uint64_t batch, uint32_t s2, unsigned* grid) {
   Occupancy occ;
   if (!cache.get(&occ)) {
-    hipError_t e = query_occupancy(kernel, TOP3_THREADS, 0, &occ);
+    hipError_t e = query_occupancy(kernel, threads, 0, &occ);
     if (e != hipSuccess) return e;
     cache.put(occ);
   }
-  const uint64_t tiles = (batch << s2) / TOP3_COLS;
+  const uint64_t tiles = (batch << s2) / (uint64_t)cols;
   const uint64_t cap = (uint64_t)occ.per_cu * (uint64_t)occ.cus;
   *grid = (unsigned)(tiles < cap ? tiles : cap);
   return hipSuccess;
@@ -2782,7 +2782,8 @@ hipError_t launch_large(uint32_t s, const float2* in, int64_t ld_in, float2* out
     case TOP3_S1: {
       static OccupancyCache cache3;
       unsigned grid3 = 0;
-      if ((e = top3_grid((const void*)large_top3_kernel, cache3, batch, s2, &grid3)) !=
+      if ((e = top3_grid((const void*)large_top3_kernel, TOP3_THREADS, TOP3_COLS, cache3, batch,
+                         s2, &grid3)) !=
           hipSuccess)
         return e;
       hipLaunchKernelGGL(large_top3_kernel, dim3(grid3), dim3(TOP3_THREADS), 0, stream, in,
@@ -2998,11 +2999,18 @@ static hipError_t launch_unplace(const float2* coefs, int64_t ld_in, float2* wor
 }
 
 // The adjoint of large_top3_kernel: stage 9 on the pairs first, then group
-// B's stages 8..5, then group A's stages 4..1, scaled by `scale`.
-__global__ void __launch_bounds__(TOP3_THREADS, 4)
+// B's stages 8..5, then group A's stages 4..1, scaled by `scale`.  Its tiles
+// are 32 columns wide (1024 threads, 135 KB of LDS, one block per CU): 2-3 us
+// less per pass than 16 columns at 2^21 and 2^22 points, where the forward
+// kernel was 4-5 us slower with them.
+constexpr int TOP3_INV_THREADS = 1024;
+constexpr int TOP3_INV_COLS = 32;
+__global__ void __launch_bounds__(TOP3_INV_THREADS, 4)
 large_top3_inv_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
                       uint64_t batch, uint32_t s2, const float2* __restrict__ tw, float scale) {
-  constexpr int H = 1 << TOP3_S1, PAD_H = H + 1, COLS = TOP3_COLS, THREADS = TOP3_THREADS;
+  constexpr int H = 1 << TOP3_S1, PAD_H = H + 1;
+  constexpr int COLS = TOP3_INV_COLS, THREADS = TOP3_INV_THREADS;
+  static_assert(COLS * 32 == THREADS, "one thread per (g, col)");
   __shared__ float2 L[COLS * PAD_H];
   __shared__ float2 T[H - 1];
   for (int i = threadIdx.x; i < H - 1; i += THREADS) T[i] = tw[i];
@@ -3145,11 +3153,11 @@ hipError_t launch_large_inverse(uint32_t s, const float2* coefs, int64_t ld_in, 
     case TOP3_S1: {
       static OccupancyCache cache3;
       unsigned grid3 = 0;
-      if ((e = top3_grid((const void*)large_top3_inv_kernel, cache3, batch, s2, &grid3)) !=
-          hipSuccess)
+      if ((e = top3_grid((const void*)large_top3_inv_kernel, TOP3_INV_THREADS, TOP3_INV_COLS,
+                         cache3, batch, s2, &grid3)) != hipSuccess)
         return e;
-      hipLaunchKernelGGL(large_top3_inv_kernel, dim3(grid3), dim3(TOP3_THREADS), 0, stream, work,
-                         out, ld_out, batch, s2, tw, scale);
+      hipLaunchKernelGGL(large_top3_inv_kernel, dim3(grid3), dim3(TOP3_INV_THREADS), 0, stream,
+                         work, out, ld_out, batch, s2, tw, scale);
       break;
     }
     default:
