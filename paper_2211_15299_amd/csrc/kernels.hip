@@ -2581,6 +2581,25 @@ large_sub_kernel(float2* __restrict__ work, uint64_t first, uint64_t units, uint
 // subtrees, CHUNK / 2^s1 outputs on average: chunks of 4096 (256 threads,
 // 32 KB of LDS) up to s1 = 6, of 16384 (1024 threads, 128 KB) above.
 constexpr int LARGE_EPT = 16;
+
+// Chunk units in XCD order.  A chunk's run from a subtree starts anywhere in
+// a 128-byte line, so the lines at a run's two ends are shared with the
+// neighbouring chunks' runs; blocks go to the eight XCDs in turn (block g to
+// XCD g % 8), which puts neighbouring chunks on different XCDs and moves
+// each shared line through two L2s.  In every full round of the grid, block
+// g takes unit (g % 8) * (grid / 8) + g / 8 of the round instead, so that
+// each XCD holds a contiguous range of chunks; the last, partial round keeps
+// the plain order.  A bijection on [0, units) for a grid that 8 divides.
+// Used at s1 = 9 (runs of 32 outputs), where it took the forward pass
+// sequence at 2^22 points from 178 to 167 us (2^21: 160 -> 157 us) and the
+// inverse at 2^22 from 171 to 166 us (2^21: 1.7 us slower); at s1 <= 8 the
+// forward was 8-10 us slower with it.
+__device__ __forceinline__ uint64_t chunk_unit(uint64_t u, uint64_t grid, uint64_t units,
+                                               uint32_t xcd_order) {
+  const uint64_t round = u / grid, g = u - round * grid;
+  if (!xcd_order || grid % 8 != 0 || (round + 1) * grid > units) return u;
+  return round * grid + (g % 8) * (grid / 8) + g / 8;
+}
 template <int CHUNK>
 constexpr int place_threads() {
   static_assert(CHUNK % LARGE_EPT == 0 && CHUNK / LARGE_EPT <= 1024 && CHUNK <= 65536 &&
@@ -2593,13 +2612,14 @@ template <int CHUNK>
 __global__ void __launch_bounds__(place_threads<CHUNK>())
 large_place_kernel(const float2* __restrict__ work, float2* __restrict__ out, int64_t ld_out,
                    uint64_t batch, uint32_t s, uint64_t n_out, const uint32_t* __restrict__ src3,
-                   const uint16_t* __restrict__ dest3, float scale) {
+                   const uint16_t* __restrict__ dest3, float scale, uint32_t xcd_order) {
   constexpr int THREADS = place_threads<CHUNK>();
   __shared__ float2 chunk[CHUNK];
   const uint64_t k = 1ULL << s;
   const uint64_t chunks = (n_out + CHUNK - 1) / CHUNK;
   const int tid = (int)threadIdx.x;
-  for (uint64_t unit = blockIdx.x; unit < batch * chunks; unit += gridDim.x) {
+  for (uint64_t u = blockIdx.x; u < batch * chunks; u += gridDim.x) {
+    const uint64_t unit = chunk_unit(u, gridDim.x, batch * chunks, xcd_order);
     const uint64_t b = unit / chunks, c = unit - b * chunks;
     const uint32_t count =
         (uint32_t)(n_out - c * CHUNK < (uint64_t)CHUNK ? n_out - c * CHUNK : (uint64_t)CHUNK);
@@ -2686,7 +2706,8 @@ static hipError_t launch_place(const float2* work, float2* out, int64_t ld_out, 
                             batch * ((n_out + CHUNK - 1) / CHUNK), &grid);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(large_place_kernel<CHUNK>, dim3(grid), dim3(THREADS), 0, stream, work, out,
-                     ld_out, batch, s, n_out, src3, dest3, scale);
+                     ld_out, batch, s, n_out, src3, dest3, scale,
+                     (uint32_t)(s - large_split(s) >= TOP3_S1));
   return hipGetLastError();
 }
 
@@ -2822,13 +2843,14 @@ template <int CHUNK>
 __global__ void __launch_bounds__(place_threads<CHUNK>())
 large_unplace_kernel(const float2* __restrict__ coefs, int64_t ld_in, float2* __restrict__ work,
                      uint64_t batch, uint32_t s, const uint32_t* __restrict__ src3,
-                     const uint16_t* __restrict__ dest3) {
+                     const uint16_t* __restrict__ dest3, uint32_t xcd_order) {
   constexpr int THREADS = place_threads<CHUNK>();
   __shared__ float2 chunk[CHUNK];
   const uint64_t k = 1ULL << s;
   const uint64_t chunks = k / CHUNK;
   const int tid = (int)threadIdx.x;
-  for (uint64_t unit = blockIdx.x; unit < batch * chunks; unit += gridDim.x) {
+  for (uint64_t u = blockIdx.x; u < batch * chunks; u += gridDim.x) {
+    const uint64_t unit = chunk_unit(u, gridDim.x, batch * chunks, xcd_order);
     const uint64_t b = unit / chunks, c = unit - b * chunks;
     const float2* x = coefs + b * (uint64_t)ld_in + c * CHUNK;
     const uint32_t* s3 = src3 + c * CHUNK;
@@ -2994,7 +3016,8 @@ static hipError_t launch_unplace(const float2* coefs, int64_t ld_in, float2* wor
                             batch * ((1ULL << s) / CHUNK), &grid);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(large_unplace_kernel<CHUNK>, dim3(grid), dim3(THREADS), 0, stream, coefs,
-                     ld_in, work, batch, s, src3, dest3);
+                     ld_in, work, batch, s, src3, dest3,
+                     (uint32_t)(s - large_split(s) >= TOP3_S1));
   return hipGetLastError();
 }
 
